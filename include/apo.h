@@ -1,0 +1,187 @@
+/*
+ * libapo -- repeated-fragment mining over task-hash token windows on MI355X.
+ *
+ * Implements FindRepeats, Algorithm 2 ("Non-overlapping repeated
+ * sub-strings") of Yadav et al., "Automatic Tracing in Task-Based Runtime
+ * Systems", ASPLOS 2025, Section 4.2, including the O(n log n) realisation of
+ * the section's implementation paragraph.  A window S of tokens (one hash per
+ * issued task, Section 4.1) goes through: order-preserving rank compression,
+ * suffix array by prefix doubling, LCP array (Phi/PLCP), candidate generation
+ * over adjacent suffix-array pairs, the (length desc, substring asc, start
+ * asc) sort, and greedy selection of non-overlapping occurrences.  Every stage
+ * runs as HIP kernels on the GPU; there is no CPU fallback.
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - tokens compare as unsigned integers, substrings lexicographically, and a
+ *     suffix that is a proper prefix of another sorts first;
+ *   - candidates shorter than min_len are dropped (min_len >= 1, inclusive);
+ *   - an accepted occurrence is (start, length); the result lists one row per
+ *     distinct accepted substring -- first accepted start, length, number of
+ *     accepted occurrences -- in order of first acceptance, i.e. by length
+ *     descending, then substring ascending.
+ * The result is a pure function of (tokens, min_len): identical for a window
+ * analysed alone, in a batch, or through the server.
+ *
+ * Ownership: the caller owns every buffer passed in (host or device).  The
+ * context owns its device workspace, streams and threads.  Calls on one
+ * context must come from one thread, except apo_submit / apo_poll /
+ * apo_fetch, which are thread-safe.
+ *
+ * Errors (all entry points return an int):
+ *   APO_OK       success
+ *   APO_EINVAL   null pointer, min_len == 0, n > APO_MAX_N, bad offsets
+ *   APO_ENOMEM   device memory for the workspace could not be obtained, or
+ *                the request exceeds the context's memory budget
+ *   APO_ERANGE   an output buffer is too small; the *_n outputs then hold the
+ *                required counts and nothing else is written.  floor(n/min_len)
+ *                rows and occurrences always suffice.
+ *   APO_EDEVICE  a HIP call failed or a device-side capacity check tripped;
+ *                the context stays valid and can be destroyed or reused
+ *   APO_EAGAIN   server queue full
+ *   APO_ENOTFOUND unknown server ticket
+ */
+#ifndef APO_H
+#define APO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APO_MAX_N (1u << 26)
+
+enum {
+  APO_OK = 0,
+  APO_EINVAL = -1,
+  APO_ENOMEM = -2,
+  APO_ERANGE = -3,
+  APO_EDEVICE = -4,
+  APO_EAGAIN = -5,
+  APO_ENOTFOUND = -6
+};
+
+typedef struct apo_ctx apo_ctx;
+
+/* One distinct accepted substring (a candidate trace): first accepted start
+ * (relative to its window), length in tokens, number of accepted
+ * non-overlapping occurrences. */
+typedef struct {
+  uint32_t start, length, count;
+} apo_candidate;
+
+/* One accepted occurrence, in acceptance order; `cand` indexes the row of
+ * its substring in the apo_candidate output. */
+typedef struct {
+  uint32_t start, length, cand;
+} apo_occurrence;
+
+/* Create a context on HIP device `hip_device`.  `device_mem_budget_bytes`
+ * caps the workspace (0 = no cap).  Returns APO_EINVAL for out == NULL,
+ * APO_EDEVICE if the device cannot be selected. */
+int apo_create(apo_ctx **out, int hip_device, size_t device_mem_budget_bytes);
+
+/* Stops the server if running, frees all device memory.  NULL is a no-op. */
+int apo_destroy(apo_ctx *ctx);
+
+/* Static string for an error code. */
+const char *apo_strerror(int code);
+
+/* FindRepeats (Section 4.2, Algorithm 2) on one window of host tokens.
+ * Blocking.  tokens: n values (n <= APO_MAX_N; n < 2 gives 0 rows).
+ * out: room for out_cap rows; *out_n receives the row count.  occ may be
+ * NULL; otherwise room for occ_cap occurrences, *occ_n receives their count. */
+int apo_analyze_window(apo_ctx *ctx, const uint64_t *tokens, uint32_t n, uint32_t min_len,
+                       apo_candidate *out, uint32_t out_cap, uint32_t *out_n,
+                       apo_occurrence *occ, uint32_t occ_cap, uint32_t *occ_n);
+
+/* Same for 32-bit tokens. */
+int apo_analyze_window_u32(apo_ctx *ctx, const uint32_t *tokens, uint32_t n, uint32_t min_len,
+                           apo_candidate *out, uint32_t out_cap, uint32_t *out_n,
+                           apo_occurrence *occ, uint32_t occ_cap, uint32_t *occ_n);
+
+/* Device-resident variant: d_tokens is a device array of n tokens of
+ * `token_bits` (32 or 64) bits; outputs are device arrays (d_occ may be
+ * NULL) and *h_out_n / *h_occ_n are written on the host.  Work is ordered on
+ * `hip_stream` (NULL = the context's stream); the call returns when the
+ * outputs are complete. */
+int apo_analyze_window_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                           uint32_t min_len, apo_candidate *d_out, uint32_t out_cap,
+                           uint32_t *h_out_n, apo_occurrence *d_occ, uint32_t occ_cap,
+                           uint32_t *h_occ_n, void *hip_stream);
+
+/* Many windows at once: window w is tokens[offsets[w] .. offsets[w+1]) of a
+ * host array.  Rows of window w are out[out_offsets[w] .. out_offsets[w+1]);
+ * out_offsets has num_windows+1 entries.  Each window's rows equal what
+ * apo_analyze_window returns for it alone. */
+int apo_analyze_batch(apo_ctx *ctx, const uint64_t *tokens, const uint64_t *offsets,
+                      uint32_t num_windows, uint32_t min_len, apo_candidate *out,
+                      uint64_t out_cap, uint64_t *out_offsets);
+
+/* Device-resident batch: d_tokens (64-bit) and h_offsets (host) as above;
+ * d_out device rows, h_out_offsets host. */
+int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t *h_offsets,
+                          uint32_t num_windows, uint32_t min_len, apo_candidate *d_out,
+                          uint64_t out_cap, uint64_t *h_out_offsets, void *hip_stream);
+
+/* ---- stage outputs, for checking each stage against a reference ---- */
+
+/* Suffix array of one device window (Section 4.2, SuffixArray(S)):
+ * d_sa[i] = start of the i-th smallest suffix.  *h_rounds (nullable) gets the
+ * number of doubling rounds. */
+int apo_suffix_array_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                         uint32_t *d_sa, uint32_t *h_rounds, void *hip_stream);
+
+/* Suffix array plus LCP: d_lcp[i] = common prefix of suffixes d_sa[i] and
+ * d_sa[i+1] for i < n-1 (the indexing of Algorithm 2's loop); d_lcp[n-1] = 0. */
+int apo_lcp_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t *d_sa,
+                uint32_t *d_lcp, void *hip_stream);
+
+/* Candidates of length >= min_len after Sort(C), exact duplicates removed:
+ * d_len/d_start/d_id (substring ID = suffix-array left boundary of the
+ * l-interval of the generating pair).  *h_count gets the count; APO_ERANGE if
+ * cap is too small (2n always suffices). */
+int apo_candidates_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                       uint32_t min_len, uint32_t *d_len, uint32_t *d_start, uint32_t *d_id,
+                       uint32_t cap, uint32_t *h_count, void *hip_stream);
+
+/* Per-stage device times of the last analysis (ms): token ranks, suffix
+ * array, LCP, candidates, candidate sort, selection, output.  Returns the
+ * number of stages written (<= nstages). */
+int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
+
+/* Counters of the last analysis: rounds of doubling, candidates generated,
+ * candidates after dedup, selection rounds, accepted occurrences, rows,
+ * sum over rounds of active suffixes, distinct tokens. */
+int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
+
+/* ---- continuous-batching server ---- */
+
+/* Start the server: up to max_slots analyses in flight on the device at once,
+ * admitted while the memory budget allows.  queue_cap bounds waiting
+ * requests (0 = 65536). */
+int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue_cap);
+
+/* Enqueue a window (tokens are copied before return).  *ticket identifies it.
+ * APO_EAGAIN when the queue is full. */
+int apo_submit(apo_ctx *ctx, uint32_t stream_id, const uint64_t *tokens, uint32_t n,
+               uint32_t min_len, uint64_t *ticket);
+
+/* *done = 1 once the result of `ticket` is ready. */
+int apo_poll(apo_ctx *ctx, uint64_t ticket, int *done);
+
+/* Copy the rows of a finished ticket and release it.  APO_EAGAIN if not done;
+ * APO_ERANGE (with *out_n set, ticket kept) if out_cap is too small.
+ * *lat_ns (nullable) gets submit-to-ready latency in ns. */
+int apo_fetch(apo_ctx *ctx, uint64_t ticket, apo_candidate *out, uint32_t out_cap,
+              uint32_t *out_n, uint64_t *lat_ns);
+
+/* Drain in-flight work, stop the server threads. */
+int apo_server_stop(apo_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* APO_H */

@@ -1,0 +1,275 @@
+"""ctypes binding of libapo (include/apo.h): argument marshalling only.
+
+Every step of the analysis runs in the HIP library.  If the library is not
+built, :func:`load` raises; there is no fallback path.  PyTorch is used only to
+hand over device memory (``tensor.data_ptr()``) and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libapo.so")
+
+APO_OK, APO_EINVAL, APO_ENOMEM, APO_ERANGE, APO_EDEVICE, APO_EAGAIN, APO_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+APO_MAX_N = 1 << 26
+
+ROW_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("count", "<u4")])
+OCC_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("cand", "<u4")])
+
+STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
+COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
+            "active_sum", "sigma")
+
+# name -> (restype, argtypes); mirrors include/apo.h
+_P, _U32, _U64, _I, _SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+SIGNATURES = {
+    "apo_create": (_I, [ctypes.POINTER(_P), _I, _SZ]),
+    "apo_destroy": (_I, [_P]),
+    "apo_strerror": (ctypes.c_char_p, [_I]),
+    "apo_analyze_window": (_I, [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _P]),
+    "apo_analyze_window_u32": (_I, [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _P]),
+    "apo_analyze_window_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _U32, _P, _P, _U32, _P, _P]),
+    "apo_analyze_batch": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P]),
+    "apo_analyze_batch_dev": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P, _P]),
+    "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
+    "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
+    "apo_candidates_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
+    "apo_last_stage_ms": (_I, [_P, _P, _I]),
+    "apo_last_counters": (_I, [_P, _P, _I]),
+    "apo_server_start": (_I, [_P, _U32, _U32]),
+    "apo_submit": (_I, [_P, _U32, _P, _U32, _U32, _P]),
+    "apo_poll": (_I, [_P, _U64, _P]),
+    "apo_fetch": (_I, [_P, _U64, _P, _U32, _P, _P]),
+    "apo_server_stop": (_I, [_P]),
+}
+
+_lib = None
+
+
+class ApoError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _lib.apo_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__("%s: %s (%d)" % (what, msg, code))
+
+
+def load() -> ctypes.CDLL:
+    """Load libapo.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libapo.so is not built (%s); run python -m paper_2406_18111_amd.build" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != APO_OK:
+        raise ApoError(rc, what)
+
+
+def _np_ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev_ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream) -> Optional[ctypes.c_void_p]:
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _host_tokens(tokens):
+    t = np.ascontiguousarray(np.asarray(tokens))
+    if t.dtype == np.uint32:
+        return t, 32
+    if t.dtype != np.uint64:
+        if t.dtype.kind == "i" and t.size and int(t.min()) < 0:
+            raise ValueError("tokens must be non-negative")
+        t = np.ascontiguousarray(t.astype(np.uint64))
+    return t, 64
+
+
+class Context:
+    """One libapo context on a HIP device (owns a device workspace and stream)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.apo_create(ctypes.byref(h), int(device), int(budget_bytes)), "apo_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.apo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---------------------------------------------------------- host API
+    def analyze(self, tokens, min_len: int, occurrences: bool = False):
+        """FindRepeats on one host window.  Returns rows (ROW_DTYPE) and, if
+        asked, occurrences (OCC_DTYPE)."""
+        t, bits = _host_tokens(tokens)
+        n = len(t)
+        cap = max(n // max(int(min_len), 1), 1) if min_len > 0 else 1
+        rows = np.zeros(cap, dtype=ROW_DTYPE)
+        occ = np.zeros(cap, dtype=OCC_DTYPE) if occurrences else None
+        rn, on = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        fn = self._lib.apo_analyze_window if bits == 64 else self._lib.apo_analyze_window_u32
+        rc = fn(self._h, _np_ptr(t) if n else None, n, int(min_len), _np_ptr(rows), cap, ctypes.byref(rn),
+                _np_ptr(occ) if occurrences else None, cap if occurrences else 0,
+                ctypes.byref(on) if occurrences else None)
+        _check(rc, "apo_analyze_window")
+        rows = rows[: rn.value].copy()
+        return (rows, occ[: on.value].copy()) if occurrences else rows
+
+    def analyze_batch(self, tokens, offsets, min_len: int):
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        W = len(off) - 1
+        total = int(off[-1] - off[0]) if W >= 1 else 0
+        cap = max(total // max(int(min_len), 1), 1)
+        rows = np.zeros(cap, dtype=ROW_DTYPE)
+        oo = np.zeros(W + 1, dtype=np.uint64)
+        rc = self._lib.apo_analyze_batch(self._h, _np_ptr(t) if len(t) else None, _np_ptr(off), W, int(min_len),
+                                         _np_ptr(rows), cap, _np_ptr(oo))
+        _check(rc, "apo_analyze_batch")
+        return rows[: int(oo[-1])].copy(), oo
+
+    # -------------------------------------------------------- device API
+    def analyze_dev(self, tokens, min_len: int, stream=None, occurrences: bool = False):
+        """tokens: 1-D torch tensor on the GPU (uint64 as int64 view, or int32/uint32 bits).
+        Returns (rows_u32[k,3] tensor, occ_u32[m,3] tensor or None)."""
+        import torch
+        bits = 64 if tokens.element_size() == 8 else 32
+        n = tokens.numel()
+        cap = max(n // max(int(min_len), 1), 1)
+        rows = torch.empty((cap, 3), dtype=torch.int32, device=tokens.device)
+        occ = torch.empty((cap, 3), dtype=torch.int32, device=tokens.device) if occurrences else None
+        rn, on = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        rc = self._lib.apo_analyze_window_dev(self._h, _dev_ptr(tokens), bits, n, int(min_len), _dev_ptr(rows), cap,
+                                              ctypes.byref(rn), _dev_ptr(occ) if occurrences else None,
+                                              cap if occurrences else 0,
+                                              ctypes.byref(on) if occurrences else None, _stream_ptr(stream))
+        _check(rc, "apo_analyze_window_dev")
+        return rows[: rn.value], (occ[: on.value] if occurrences else None)
+
+    def analyze_batch_dev(self, tokens, offsets, min_len: int, stream=None):
+        import torch
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        W = len(off) - 1
+        total = int(off[-1] - off[0])
+        cap = max(total // max(int(min_len), 1), 1)
+        rows = torch.empty((cap, 3), dtype=torch.int32, device=tokens.device)
+        oo = np.zeros(W + 1, dtype=np.uint64)
+        rc = self._lib.apo_analyze_batch_dev(self._h, _dev_ptr(tokens), _np_ptr(off), W, int(min_len),
+                                             _dev_ptr(rows), cap, _np_ptr(oo), _stream_ptr(stream))
+        _check(rc, "apo_analyze_batch_dev")
+        return rows[: int(oo[-1])], oo
+
+    def suffix_array_dev(self, tokens, stream=None):
+        import torch
+        bits = 64 if tokens.element_size() == 8 else 32
+        n = tokens.numel()
+        sa = torch.empty(n, dtype=torch.int32, device=tokens.device)
+        rounds = ctypes.c_uint32(0)
+        _check(self._lib.apo_suffix_array_dev(self._h, _dev_ptr(tokens), bits, n, _dev_ptr(sa), ctypes.byref(rounds),
+                                              _stream_ptr(stream)), "apo_suffix_array_dev")
+        return sa, rounds.value
+
+    def lcp_dev(self, tokens, stream=None):
+        import torch
+        bits = 64 if tokens.element_size() == 8 else 32
+        n = tokens.numel()
+        sa = torch.empty(n, dtype=torch.int32, device=tokens.device)
+        lcp = torch.empty(n, dtype=torch.int32, device=tokens.device)
+        _check(self._lib.apo_lcp_dev(self._h, _dev_ptr(tokens), bits, n, _dev_ptr(sa), _dev_ptr(lcp),
+                                     _stream_ptr(stream)), "apo_lcp_dev")
+        return sa, lcp
+
+    def candidates_dev(self, tokens, min_len: int, stream=None):
+        import torch
+        bits = 64 if tokens.element_size() == 8 else 32
+        n = tokens.numel()
+        cap = max(2 * n, 1)
+        ln = torch.empty(cap, dtype=torch.int32, device=tokens.device)
+        st = torch.empty(cap, dtype=torch.int32, device=tokens.device)
+        ids = torch.empty(cap, dtype=torch.int32, device=tokens.device)
+        cnt = ctypes.c_uint32(0)
+        _check(self._lib.apo_candidates_dev(self._h, _dev_ptr(tokens), bits, n, int(min_len), _dev_ptr(ln),
+                                            _dev_ptr(st), _dev_ptr(ids), cap, ctypes.byref(cnt), _stream_ptr(stream)),
+               "apo_candidates_dev")
+        m = cnt.value
+        return {"len": ln[:m], "start": st[:m], "id": ids[:m]}
+
+    # ------------------------------------------------------ diagnostics
+    def stage_ms(self):
+        a = (ctypes.c_double * len(STAGES))()
+        k = self._lib.apo_last_stage_ms(self._h, a, len(STAGES))
+        return dict(zip(STAGES[:k], list(a)[:k]))
+
+    def counters(self):
+        a = (ctypes.c_uint64 * len(COUNTERS))()
+        k = self._lib.apo_last_counters(self._h, a, len(COUNTERS))
+        return dict(zip(COUNTERS[:k], list(a)[:k]))
+
+    # ---------------------------------------------------------- server
+    def server_start(self, slots: int = 2, queue_cap: int = 0):
+        _check(self._lib.apo_server_start(self._h, int(slots), int(queue_cap)), "apo_server_start")
+
+    def submit(self, tokens, min_len: int, stream_id: int = 0) -> int:
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        tk = ctypes.c_uint64(0)
+        rc = self._lib.apo_submit(self._h, int(stream_id), _np_ptr(t) if len(t) else None, len(t), int(min_len),
+                                  ctypes.byref(tk))
+        _check(rc, "apo_submit")
+        return tk.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int(0)
+        _check(self._lib.apo_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(d)), "apo_poll")
+        return bool(d.value)
+
+    def fetch(self, ticket: int, cap: int = 1 << 16):
+        """Rows of a finished ticket and its submit-to-ready latency (s); None if not ready."""
+        while True:
+            rows = np.zeros(max(cap, 1), dtype=ROW_DTYPE)
+            n = ctypes.c_uint32(0)
+            lat = ctypes.c_uint64(0)
+            rc = self._lib.apo_fetch(self._h, ctypes.c_uint64(ticket), _np_ptr(rows), len(rows), ctypes.byref(n),
+                                     ctypes.byref(lat))
+            if rc == APO_EAGAIN:
+                return None
+            if rc == APO_ERANGE:
+                cap = n.value
+                continue
+            _check(rc, "apo_fetch")
+            return rows[: n.value].copy(), lat.value * 1e-9
+
+    def server_stop(self):
+        _check(self._lib.apo_server_stop(self._h), "apo_server_stop")

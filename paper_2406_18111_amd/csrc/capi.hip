@@ -1,0 +1,551 @@
+// C ABI of libapo (include/apo.h): argument checking, staging of host
+// buffers, and the continuous-batching server.
+#include "apo.h"
+#include "pipeline.h"
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace apo {
+
+struct Request {
+  uint64_t ticket = 0;
+  uint32_t stream_id = 0;
+  uint32_t min_len = 1;
+  std::vector<uint64_t> tokens;
+  std::vector<apo_candidate> rows;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  int status = 0;
+  bool done = false;
+};
+
+struct Slot {
+  Workspace ws;
+  hipStream_t stream = nullptr;
+  std::thread th;
+  uint64_t *pinned = nullptr;  // staging for packed tokens
+  uint64_t pinned_cap = 0;
+};
+
+struct Server {
+  std::mutex mu;
+  std::condition_variable cv_work;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+  std::vector<std::unique_ptr<Slot>> slots;
+  uint64_t next_ticket = 1;
+  uint32_t queue_cap = 65536;
+  uint64_t slot_token_cap = 0;
+  size_t slot_budget = 0;
+  bool stopping = false;
+  int device = 0;
+  std::atomic<uint64_t> batches{0}, windows{0};
+};
+
+}  // namespace apo
+
+struct apo_ctx {
+  int device = 0;
+  size_t budget = 0;
+  hipStream_t stream = nullptr;
+  apo::Workspace ws;
+  apo::RunInfo info;
+  std::unique_ptr<apo::Server> server;
+};
+
+using namespace apo;
+
+static int set_dev(apo_ctx *c) { return hipSetDevice(c->device) == hipSuccess ? APO_OK : APO_EDEVICE; }
+
+extern "C" const char *apo_strerror(int code) {
+  switch (code) {
+    case APO_OK: return "ok";
+    case APO_EINVAL: return "invalid argument";
+    case APO_ENOMEM: return "out of device memory or over budget";
+    case APO_ERANGE: return "output buffer too small";
+    case APO_EDEVICE: return "device error";
+    case APO_EAGAIN: return "try again (queue full or result not ready)";
+    case APO_ENOTFOUND: return "unknown ticket";
+    default: return "unknown error";
+  }
+}
+
+extern "C" int apo_create(apo_ctx **out, int hip_device, size_t budget) {
+  if (!out) return APO_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+    (void)hipGetLastError();
+    return APO_EDEVICE;
+  }
+  auto *c = new apo_ctx();
+  c->device = hip_device;
+  c->budget = budget;
+  if (hipSetDevice(hip_device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess) {
+    delete c;
+    return APO_EDEVICE;
+  }
+  *out = c;
+  return APO_OK;
+}
+
+extern "C" int apo_server_stop(apo_ctx *ctx);
+
+extern "C" int apo_destroy(apo_ctx *ctx) {
+  if (!ctx) return APO_OK;
+  (void)hipSetDevice(ctx->device);
+  apo_server_stop(ctx);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->ws.release();
+  (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return APO_OK;
+}
+
+static int map_rc(int rc) {
+  if (rc == 0) return APO_OK;
+  if (rc == -2) return APO_ENOMEM;
+  return APO_EDEVICE;
+}
+
+// Runs one analysis on the context workspace, tokens already on the device.
+static int run_ctx(apo_ctx *c, const void *d_tok, int bits, uint32_t n, uint32_t min_len, Stop stop,
+                   hipStream_t s) {
+  int rc = c->ws.ensure(n, 1, c->budget);
+  if (rc) return map_rc(rc);
+  const uint64_t off[2] = {0, n};
+  rc = run_pipeline(c->ws, d_tok, bits, n, off, 1, min_len, stop, s, c->info);
+  return map_rc(rc);
+}
+
+static int analyze_host(apo_ctx *ctx, const void *tokens, int bits, uint32_t n, uint32_t min_len,
+                        apo_candidate *out, uint32_t out_cap, uint32_t *out_n, apo_occurrence *occ,
+                        uint32_t occ_cap, uint32_t *occ_n) {
+  if (!ctx || !out_n || (!tokens && n) || (!out && out_cap) || min_len == 0 || n > APO_MAX_N) return APO_EINVAL;
+  if (occ && !occ_n) return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  *out_n = 0;
+  if (occ_n) *occ_n = 0;
+  ctx->info = RunInfo{};
+  if (n < 2) return APO_OK;
+  int rc = ctx->ws.ensure(n, 1, ctx->budget);
+  if (rc) return map_rc(rc);
+  const size_t bytes = (size_t)n * (bits / 8);
+  if (hipMemcpyAsync(ctx->ws.tok64, tokens, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return APO_EDEVICE;
+  }
+  rc = run_ctx(ctx, ctx->ws.tok64, bits, n, min_len, Stop::FULL, ctx->stream);
+  if (rc) return rc;
+  const uint32_t rows = ctx->info.rows, acc = ctx->info.accepted;
+  *out_n = rows;
+  if (occ_n) *occ_n = acc;
+  if (rows > out_cap || (occ && acc > occ_cap)) return APO_ERANGE;
+  if (rows && hipMemcpy(out, ctx->ws.rows, (size_t)rows * sizeof(apo_candidate), hipMemcpyDeviceToHost) != hipSuccess)
+    return APO_EDEVICE;
+  if (occ && acc &&
+      hipMemcpy(occ, ctx->ws.occ, (size_t)acc * sizeof(apo_occurrence), hipMemcpyDeviceToHost) != hipSuccess)
+    return APO_EDEVICE;
+  return APO_OK;
+}
+
+extern "C" int apo_analyze_window(apo_ctx *ctx, const uint64_t *tokens, uint32_t n, uint32_t min_len,
+                                  apo_candidate *out, uint32_t out_cap, uint32_t *out_n, apo_occurrence *occ,
+                                  uint32_t occ_cap, uint32_t *occ_n) {
+  return analyze_host(ctx, tokens, 64, n, min_len, out, out_cap, out_n, occ, occ_cap, occ_n);
+}
+
+extern "C" int apo_analyze_window_u32(apo_ctx *ctx, const uint32_t *tokens, uint32_t n, uint32_t min_len,
+                                      apo_candidate *out, uint32_t out_cap, uint32_t *out_n, apo_occurrence *occ,
+                                      uint32_t occ_cap, uint32_t *occ_n) {
+  return analyze_host(ctx, tokens, 32, n, min_len, out, out_cap, out_n, occ, occ_cap, occ_n);
+}
+
+static hipStream_t pick_stream(apo_ctx *c, void *s) { return s ? static_cast<hipStream_t>(s) : c->stream; }
+
+extern "C" int apo_analyze_window_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                                      uint32_t min_len, apo_candidate *d_out, uint32_t out_cap, uint32_t *h_out_n,
+                                      apo_occurrence *d_occ, uint32_t occ_cap, uint32_t *h_occ_n, void *stream) {
+  if (!ctx || !h_out_n || (!d_tokens && n) || (!d_out && out_cap) || min_len == 0 || n > APO_MAX_N ||
+      (token_bits != 32 && token_bits != 64) || (d_occ && !h_occ_n))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  *h_out_n = 0;
+  if (h_occ_n) *h_occ_n = 0;
+  ctx->info = RunInfo{};
+  if (n < 2) return APO_OK;
+  hipStream_t s = pick_stream(ctx, stream);
+  int rc = run_ctx(ctx, d_tokens, token_bits, n, min_len, Stop::FULL, s);
+  if (rc) return rc;
+  const uint32_t rows = ctx->info.rows, acc = ctx->info.accepted;
+  *h_out_n = rows;
+  if (h_occ_n) *h_occ_n = acc;
+  if (rows > out_cap || (d_occ && acc > occ_cap)) return APO_ERANGE;
+  if (rows && hipMemcpyAsync(d_out, ctx->ws.rows, (size_t)rows * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return APO_EDEVICE;
+  if (d_occ && acc && hipMemcpyAsync(d_occ, ctx->ws.occ, (size_t)acc * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return APO_EDEVICE;
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+static int check_offsets(const uint64_t *off, uint32_t W, uint64_t &total) {
+  if (!off || W == 0) return APO_EINVAL;
+  for (uint32_t w = 0; w < W; w++) {
+    if (off[w + 1] < off[w]) return APO_EINVAL;
+    if (off[w + 1] - off[w] > APO_MAX_N) return APO_EINVAL;
+  }
+  total = off[W] - off[0];
+  if (total >= (1ull << 31)) return APO_EINVAL;
+  return APO_OK;
+}
+
+static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
+                        hipStream_t s, uint64_t total) {
+  std::vector<uint64_t> norm(W + 1);
+  for (uint32_t w = 0; w <= W; w++) norm[w] = off[w] - off[0];
+  int rc = ctx->ws.ensure(std::max<uint64_t>(total, 2), W, ctx->budget);
+  if (rc) return map_rc(rc);
+  rc = run_pipeline(ctx->ws, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info);
+  return map_rc(rc);
+}
+
+static int batch_offsets(apo_ctx *ctx, uint32_t W, uint64_t *out_offsets, uint64_t out_cap) {
+  std::vector<uint32_t> cnt(W, 0);
+  const uint32_t rows = ctx->info.rows;
+  if (W > 1 && rows) {
+    if (hipMemcpy(cnt.data(), ctx->ws.win_rows, W * 4, hipMemcpyDeviceToHost) != hipSuccess) return APO_EDEVICE;
+  } else if (W == 1) {
+    cnt[0] = rows;
+  }
+  out_offsets[0] = 0;
+  for (uint32_t w = 0; w < W; w++) out_offsets[w + 1] = out_offsets[w] + cnt[w];
+  return rows > out_cap ? APO_ERANGE : APO_OK;
+}
+
+extern "C" int apo_analyze_batch(apo_ctx *ctx, const uint64_t *tokens, const uint64_t *offsets, uint32_t W,
+                                 uint32_t min_len, apo_candidate *out, uint64_t out_cap, uint64_t *out_offsets) {
+  if (!ctx || !out_offsets || min_len == 0 || (!out && out_cap)) return APO_EINVAL;
+  uint64_t total = 0;
+  int rc = check_offsets(offsets, W, total);
+  if (rc) return rc;
+  if (total && !tokens) return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  ctx->info = RunInfo{};
+  if (total < 2) {
+    for (uint32_t w = 0; w <= W; w++) out_offsets[w] = 0;
+    return APO_OK;
+  }
+  rc = ctx->ws.ensure(total, W, ctx->budget);
+  if (rc) return map_rc(rc);
+  if (hipMemcpyAsync(ctx->ws.tok64, tokens + offsets[0], total * 8, hipMemcpyHostToDevice, ctx->stream) !=
+      hipSuccess)
+    return APO_EDEVICE;
+  rc = batch_common(ctx, ctx->ws.tok64, offsets, W, min_len, ctx->stream, total);
+  if (rc) return rc;
+  rc = batch_offsets(ctx, W, out_offsets, out_cap);
+  if (rc) return rc;
+  if (ctx->info.rows &&
+      hipMemcpy(out, ctx->ws.rows, (size_t)ctx->info.rows * sizeof(apo_candidate), hipMemcpyDeviceToHost) !=
+          hipSuccess)
+    return APO_EDEVICE;
+  return APO_OK;
+}
+
+extern "C" int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t *h_offsets, uint32_t W,
+                                     uint32_t min_len, apo_candidate *d_out, uint64_t out_cap,
+                                     uint64_t *h_out_offsets, void *stream) {
+  if (!ctx || !h_out_offsets || min_len == 0 || (!d_out && out_cap)) return APO_EINVAL;
+  uint64_t total = 0;
+  int rc = check_offsets(h_offsets, W, total);
+  if (rc) return rc;
+  if (total && !d_tokens) return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  ctx->info = RunInfo{};
+  if (total < 2) {
+    for (uint32_t w = 0; w <= W; w++) h_out_offsets[w] = 0;
+    return APO_OK;
+  }
+  hipStream_t s = pick_stream(ctx, stream);
+  rc = batch_common(ctx, d_tokens + h_offsets[0], h_offsets, W, min_len, s, total);
+  if (rc) return rc;
+  rc = batch_offsets(ctx, W, h_out_offsets, out_cap);
+  if (rc) return rc;
+  if (ctx->info.rows &&
+      hipMemcpyAsync(d_out, ctx->ws.rows, (size_t)ctx->info.rows * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return APO_EDEVICE;
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_suffix_array_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t *d_sa,
+                                    uint32_t *h_rounds, void *stream) {
+  if (!ctx || !d_tokens || !d_sa || n == 0 || n > APO_MAX_N || (token_bits != 32 && token_bits != 64))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  hipStream_t s = pick_stream(ctx, stream);
+  int rc = run_ctx(ctx, d_tokens, token_bits, n, 1, Stop::SA, s);
+  if (rc) return rc;
+  if (h_rounds) *h_rounds = ctx->info.rounds;
+  if (hipMemcpyAsync(d_sa, ctx->ws.sa, (size_t)n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return APO_EDEVICE;
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_lcp_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t *d_sa,
+                           uint32_t *d_lcp, void *stream) {
+  if (!ctx || !d_tokens || !d_lcp || n == 0 || n > APO_MAX_N || (token_bits != 32 && token_bits != 64))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  hipStream_t s = pick_stream(ctx, stream);
+  int rc = run_ctx(ctx, d_tokens, token_bits, n, 1, Stop::LCP, s);
+  if (rc) return rc;
+  if (d_sa && hipMemcpyAsync(d_sa, ctx->ws.sa, (size_t)n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return APO_EDEVICE;
+  if (hipMemcpyAsync(d_lcp, ctx->ws.lcp, (size_t)n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return APO_EDEVICE;
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_candidates_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t min_len,
+                                  uint32_t *d_len, uint32_t *d_start, uint32_t *d_id, uint32_t cap, uint32_t *h_count,
+                                  void *stream) {
+  if (!ctx || !d_tokens || !h_count || min_len == 0 || n == 0 || n > APO_MAX_N ||
+      (token_bits != 32 && token_bits != 64) || ((!d_len || !d_start || !d_id) && cap))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  *h_count = 0;
+  if (n < 2) return APO_OK;
+  hipStream_t s = pick_stream(ctx, stream);
+  int rc = run_ctx(ctx, d_tokens, token_bits, n, min_len, Stop::CANDS, s);
+  if (rc) return rc;
+  const uint32_t m = ctx->info.cands_dedup;
+  *h_count = m;
+  if (m > cap) return APO_ERANGE;
+  if (m) {
+    if (hipMemcpyAsync(d_len, ctx->ws.s_len, (size_t)m * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d_start, ctx->ws.s_start, (size_t)m * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(d_id, ctx->ws.s_id, (size_t)m * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return APO_EDEVICE;
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_last_stage_ms(apo_ctx *ctx, double *ms, int nstages) {
+  if (!ctx || !ms || nstages < 0) return APO_EINVAL;
+  const int k = std::min(nstages, kStages);
+  for (int i = 0; i < k; i++) ms[i] = ctx->info.stage_ms[i];
+  return k;
+}
+
+extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
+  if (!ctx || !v || nvals < 0) return APO_EINVAL;
+  const RunInfo &I = ctx->info;
+  const uint64_t all[8] = {I.rounds, I.cands, I.cands_dedup, I.sel_rounds, I.accepted, I.rows, I.active_sum, I.sigma};
+  const int k = std::min(nvals, 8);
+  for (int i = 0; i < k; i++) v[i] = all[i];
+  return k;
+}
+
+// ===================================================================== server
+// Each slot owns a resident workspace and stream.  A free slot takes every
+// queued request that shares the oldest request's min_len and fits its token
+// budget, packs them into one batch (windows never interact), runs it, and
+// publishes each window's rows.  Slots run concurrently on their streams, so
+// requests arriving while others are on the GPU are admitted as soon as a
+// slot frees up, and their work overlaps on the device.
+static void slot_loop(Server *S, Slot *sl) {
+  (void)hipSetDevice(S->device);
+  std::vector<std::shared_ptr<Request>> batch;
+  std::vector<uint64_t> off;
+  std::vector<uint64_t> outoff;
+  std::vector<apo_candidate> rows;
+  RunInfo info;
+  while (true) {
+    batch.clear();
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
+      if (S->queue.empty() && S->stopping) return;
+      const uint32_t ml = S->queue.front()->min_len;
+      uint64_t tot = 0;
+      for (auto it = S->queue.begin(); it != S->queue.end();) {
+        const uint64_t n = (*it)->tokens.size();
+        if ((*it)->min_len == ml && (batch.empty() || tot + n <= S->slot_token_cap)) {
+          tot += n;
+          batch.push_back(*it);
+          it = S->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    const uint32_t W = (uint32_t)batch.size();
+    off.assign(W + 1, 0);
+    for (uint32_t w = 0; w < W; w++) off[w + 1] = off[w] + batch[w]->tokens.size();
+    const uint64_t total = off[W];
+    int rc = 0;
+    if (total > sl->pinned_cap) {
+      if (sl->pinned) (void)hipHostFree(sl->pinned);
+      sl->pinned = nullptr;
+      sl->pinned_cap = 0;
+      uint64_t cap = 1;
+      while (cap < total) cap <<= 1;
+      if (hipHostMalloc((void **)&sl->pinned, cap * 8, hipHostMallocDefault) == hipSuccess) sl->pinned_cap = cap;
+      else rc = APO_ENOMEM;
+    }
+    if (!rc) {
+      for (uint32_t w = 0; w < W; w++)
+        if (!batch[w]->tokens.empty())
+          memcpy(sl->pinned + off[w], batch[w]->tokens.data(), batch[w]->tokens.size() * 8);
+      rc = map_rc(sl->ws.ensure(std::max<uint64_t>(total, 2), W, S->slot_budget));
+    }
+    outoff.assign(W + 1, 0);
+    if (!rc && total >= 2) {
+      if (hipMemcpyAsync(sl->ws.tok64, sl->pinned, total * 8, hipMemcpyHostToDevice, sl->stream) != hipSuccess)
+        rc = APO_EDEVICE;
+      if (!rc) rc = map_rc(run_pipeline(sl->ws, sl->ws.tok64, 64, total, off.data(), W, batch[0]->min_len, Stop::FULL,
+                                        sl->stream, info));
+      if (!rc) {
+        std::vector<uint32_t> cnt(W, 0);
+        if (W > 1 && info.rows) {
+          if (hipMemcpy(cnt.data(), sl->ws.win_rows, W * 4, hipMemcpyDeviceToHost) != hipSuccess) rc = APO_EDEVICE;
+        } else if (W == 1) {
+          cnt[0] = info.rows;
+        }
+        for (uint32_t w = 0; w < W; w++) outoff[w + 1] = outoff[w] + cnt[w];
+        rows.resize(info.rows);
+        if (!rc && info.rows &&
+            hipMemcpy(rows.data(), sl->ws.rows, (size_t)info.rows * sizeof(apo_candidate), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+          rc = APO_EDEVICE;
+      }
+    }
+    const auto now = std::chrono::steady_clock::now();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (uint32_t w = 0; w < W; w++) {
+        Request &R = *batch[w];
+        R.status = rc;
+        if (!rc && total >= 2) R.rows.assign(rows.begin() + outoff[w], rows.begin() + outoff[w + 1]);
+        R.tokens.clear();
+        R.tokens.shrink_to_fit();
+        R.t_done = now;
+        R.done = true;
+      }
+    }
+    S->batches++;
+    S->windows += W;
+  }
+}
+
+extern "C" int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue_cap) {
+  if (!ctx || max_slots == 0 || max_slots > 16) return APO_EINVAL;
+  if (ctx->server) return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  auto S = std::make_unique<Server>();
+  S->device = ctx->device;
+  S->queue_cap = queue_cap ? queue_cap : 65536;
+  // per-slot memory share; token budget = largest N whose workspace fits
+  size_t budget = ctx->budget;
+  if (!budget) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return APO_EDEVICE;
+    budget = fr / 2;
+  }
+  S->slot_budget = budget / max_slots;
+  uint64_t cap = 1024;
+  while (Workspace::bytes_for(cap * 2, 4096) <= S->slot_budget && cap < (1ull << 30)) cap *= 2;
+  S->slot_token_cap = cap;
+  for (uint32_t i = 0; i < max_slots; i++) {
+    auto sl = std::make_unique<Slot>();
+    if (hipStreamCreate(&sl->stream) != hipSuccess) return APO_EDEVICE;
+    S->slots.push_back(std::move(sl));
+  }
+  Server *raw = S.get();
+  for (auto &sl : S->slots) sl->th = std::thread(slot_loop, raw, sl.get());
+  ctx->server = std::move(S);
+  return APO_OK;
+}
+
+extern "C" int apo_submit(apo_ctx *ctx, uint32_t stream_id, const uint64_t *tokens, uint32_t n, uint32_t min_len,
+                          uint64_t *ticket) {
+  if (!ctx || !ticket || (!tokens && n) || min_len == 0 || n > APO_MAX_N) return APO_EINVAL;
+  Server *S = ctx->server.get();
+  if (!S) return APO_EINVAL;
+  if ((uint64_t)n > S->slot_token_cap) return APO_ENOMEM;
+  auto R = std::make_shared<Request>();
+  R->stream_id = stream_id;
+  R->min_len = min_len;
+  R->tokens.assign(tokens, tokens + n);
+  R->t_submit = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stopping) return APO_EINVAL;
+    if (S->queue.size() >= S->queue_cap) return APO_EAGAIN;
+    R->ticket = S->next_ticket++;
+    S->tickets[R->ticket] = R;
+    S->queue.push_back(R);
+    *ticket = R->ticket;
+  }
+  S->cv_work.notify_one();
+  return APO_OK;
+}
+
+extern "C" int apo_poll(apo_ctx *ctx, uint64_t ticket, int *done) {
+  if (!ctx || !done || !ctx->server) return APO_EINVAL;
+  Server *S = ctx->server.get();
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return APO_ENOTFOUND;
+  *done = it->second->done ? 1 : 0;
+  return APO_OK;
+}
+
+extern "C" int apo_fetch(apo_ctx *ctx, uint64_t ticket, apo_candidate *out, uint32_t out_cap, uint32_t *out_n,
+                         uint64_t *lat_ns) {
+  if (!ctx || !out_n || (!out && out_cap) || !ctx->server) return APO_EINVAL;
+  Server *S = ctx->server.get();
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return APO_ENOTFOUND;
+  Request &R = *it->second;
+  if (!R.done) return APO_EAGAIN;
+  if (R.status) {
+    const int st = R.status;
+    S->tickets.erase(it);
+    return st;
+  }
+  *out_n = (uint32_t)R.rows.size();
+  if (R.rows.size() > out_cap) return APO_ERANGE;
+  if (!R.rows.empty()) memcpy(out, R.rows.data(), R.rows.size() * sizeof(apo_candidate));
+  if (lat_ns)
+    *lat_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(R.t_done - R.t_submit).count();
+  S->tickets.erase(it);
+  return APO_OK;
+}
+
+extern "C" int apo_server_stop(apo_ctx *ctx) {
+  if (!ctx) return APO_EINVAL;
+  Server *S = ctx->server.get();
+  if (!S) return APO_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stopping = true;
+  }
+  S->cv_work.notify_all();
+  for (auto &sl : S->slots) {
+    if (sl->th.joinable()) sl->th.join();
+    (void)hipSetDevice(S->device);
+    (void)hipStreamSynchronize(sl->stream);
+    sl->ws.release();
+    if (sl->pinned) (void)hipHostFree(sl->pinned);
+    (void)hipStreamDestroy(sl->stream);
+  }
+  ctx->server.reset();
+  return APO_OK;
+}

@@ -1,0 +1,80 @@
+// Small device helpers (wave64 scans, hashing) shared by the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apo {
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x = x > y ? x : y;
+  }
+  return x;
+}
+
+// Block-wide exclusive sum over NT threads.  `sh` needs NT/64 words.  Returns
+// the exclusive prefix of the calling thread; *total receives the block sum.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t x, uint32_t *sh, uint32_t *total) {
+  const uint32_t inc = wave_incl_sum(x);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; i++) {
+    const uint32_t v = sh[i];
+    before += (i < w) ? v : 0u;
+    tot += v;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inc - x;
+}
+
+// Block-wide inclusive max over NT threads.
+template <int NT>
+__device__ __forceinline__ uint32_t block_incl_max(uint32_t x, uint32_t *sh) {
+  const uint32_t inc = wave_incl_max(x);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) sh[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; i++) {
+    const uint32_t v = sh[i];
+    if (i < w) before = before > v ? before : v;
+  }
+  __syncthreads();
+  return before > inc ? before : inc;
+}
+
+// SplitMix64 finaliser (Steele/Lea/Flood; constants by Vigna), used as a hash.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int class_of(uint32_t len) {
+  // 1-based class c with len in (2^(c-1), 2^c], len==1 -> c=1; returns c-1
+  int c = 32 - __clz((int)(len - 1u));  // ceil(log2(len)) for len>=2, 0 for len==1
+  if (len <= 1u) c = 0;
+  c = c < 1 ? 1 : c;
+  return c - 1;
+}
+
+}  // namespace apo

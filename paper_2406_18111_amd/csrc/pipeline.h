@@ -1,0 +1,78 @@
+// Host-side pipeline: workspace ownership and the stage sequence of one
+// analysis (a single window or a packed batch of windows).
+#pragma once
+#include "apo_internal.h"
+#include "segsort.h"
+#include <vector>
+
+namespace apo {
+
+enum class Stop { SA, LCP, CANDS, FULL };
+
+enum Cnt {
+  CNT_ND = 0, CNT_C, CNT_MAXL, CNT_M, CNT_NLIVE0, CNT_NLIVE1, CNT_UNDEC, CNT_A, CNT_NROWS,
+  CNT_RANGE = 10,  // two 64-bit words, 8-byte aligned
+  CNT_COUNT = 32
+};
+
+constexpr int kStages = 7;
+constexpr int kSelRoundCap = 64;
+
+struct RunInfo {
+  uint32_t rounds = 0;        // doubling rounds incl. the token sort
+  uint64_t active_sum = 0;    // sum over rounds of processed suffixes
+  uint32_t sigma = 0;         // distinct tokens (64-bit input)
+  uint32_t cands = 0;         // candidates generated (length >= min_len)
+  uint32_t cands_dedup = 0;   // after removing exact duplicates
+  uint32_t maxl = 0;
+  uint32_t sel_rounds = 0;
+  uint32_t sel_sequential = 0;
+  uint32_t accepted = 0;
+  uint32_t rows = 0;
+  double stage_ms[kStages] = {0};
+};
+
+struct Workspace {
+  uint64_t capN = 0;
+  uint32_t capW = 0;
+  int nsnap = 0, nT = 0, nlev = 0;
+  uint64_t hcap = 0;
+  SortEngine eng;
+  void *mem = nullptr;
+  size_t bytes = 0;
+
+  uint64_t *tok64 = nullptr;
+  uint32_t *tokrank = nullptr, *htab = nullptr, *hrank = nullptr, *dist_idx = nullptr, *dist_slot = nullptr;
+  uint32_t *dhi = nullptr, *dlo = nullptr;
+  uint64_t *d_off = nullptr;
+  uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;
+  uint32_t *rank = nullptr, *snap = nullptr, *sa = nullptr;
+  uint8_t *fin = nullptr;
+  uint32_t *phi = nullptr, *plcp = nullptr, *lcp = nullptr;
+  uint32_t *lvl[8] = {nullptr};
+  uint32_t *c_len = nullptr, *c_start = nullptr, *c_id = nullptr;
+  uint8_t *keep = nullptr;
+  uint32_t *s_len = nullptr, *s_start = nullptr, *s_id = nullptr;
+  uint32_t *tmp_a = nullptr, *tmp_b = nullptr, *tmp_c = nullptr, *tmp_d = nullptr, *tile_tmp = nullptr;
+  uint32_t *T = nullptr, *live[2] = {nullptr, nullptr};
+  uint8_t *state = nullptr, *mark = nullptr;
+  uint32_t *o_len = nullptr, *o_start = nullptr, *o_id = nullptr;
+  void *rows = nullptr, *occ = nullptr;
+  uint32_t *row_first = nullptr, *rowidx = nullptr;
+  uint32_t *dcnt = nullptr;
+  uint32_t *hcnt = nullptr;        // pinned host mirror of dcnt
+  SortCounters *hctr = nullptr;    // pinned host mirror of engine counters
+  hipEvent_t ev[kStages + 1] = {};
+
+  static size_t bytes_for(uint64_t N, uint32_t W);
+  int ensure(uint64_t N, uint32_t W, size_t budget);
+  void release();
+};
+
+// Runs the stages of one analysis on stream s.  d_tok: device tokens of
+// `bits` (32/64) bits, windows given by host offsets h_off[0..W] (global,
+// ascending, h_off[0] == 0).  Results stay in the workspace.
+int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
+                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info);
+
+}  // namespace apo

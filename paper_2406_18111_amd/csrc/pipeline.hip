@@ -1,0 +1,371 @@
+// Stage sequence of one analysis (Section 4.2, Algorithm 2), host side.
+#include "pipeline.h"
+#include "stages.h"
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+namespace apo {
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line) {
+  fprintf(stderr, "[apo] %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+  (void)hipGetLastError();
+  return e == hipErrorOutOfMemory ? -2 : -4;
+}
+
+__global__ void k_set_range(uint64_t *r, uint32_t count) {
+  if (threadIdx.x == 0) { r[0] = 0; r[1] = count; }
+}
+
+static uint64_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// ---------------------------------------------------------------- layout
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t n) { size_t o = total; total += (n + 255) & ~(size_t)255; return o; }
+};
+
+static void plan(uint64_t N, uint32_t W, int &nsnap, int &nT, int &nlev, uint64_t &hcap) {
+  nsnap = ceil_log2_u64(N) + 2;
+  nT = ceil_log2_u64(N) + 1;
+  nlev = 1;
+  for (uint64_t sz = N; sz > 1 && nlev < 6; sz = (sz + 63) / 64) nlev++;
+  hcap = pow2_at_least(2 * N);
+  (void)W;
+}
+
+size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
+  int ns, nt, nl;
+  uint64_t hc;
+  plan(N, W, ns, nt, nl, hc);
+  const uint64_t C2 = 2 * N;
+  size_t b = 0;
+  b += N * 8 + N * 4 * 8 + hc * 8 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
+  b += C2 * (4 * 8 + 2) + (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
+  b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / kLdsTile + 64) * (kBins * 8 + 8 * 16);  // sort engine
+  return b;
+}
+
+void Workspace::release() {
+  eng.release();
+  if (mem) (void)hipFree(mem);
+  mem = nullptr;
+  if (hcnt) (void)hipHostFree(hcnt);
+  hcnt = nullptr;
+  if (hctr) (void)hipHostFree(hctr);
+  hctr = nullptr;
+  for (auto &e : ev)
+    if (e) { (void)hipEventDestroy(e); e = nullptr; }
+  capN = 0;
+  capW = 0;
+}
+
+int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
+  if (N <= capN && W <= capW && mem) return 0;
+  const uint64_t wantN = std::max<uint64_t>(pow2_at_least(std::max<uint64_t>(N, 1024)), capN);
+  const uint32_t wantW = std::max<uint32_t>((uint32_t)pow2_at_least(std::max<uint32_t>(W, 1)), capW);
+  if (budget && bytes_for(wantN, wantW) > budget) return -2;
+  release();
+  plan(wantN, wantW, nsnap, nT, nlev, hcap);
+  const uint64_t N_ = wantN, C2 = 2 * wantN;
+  Layout L;
+  size_t o_tok64 = L.take(N_ * 8), o_tokrank = L.take(N_ * 4), o_htab = L.take(hcap * 4), o_hrank = L.take(hcap * 4);
+  size_t o_di = L.take(N_ * 4), o_ds = L.take(N_ * 4), o_dhi = L.take(N_ * 4), o_dlo = L.take(N_ * 4);
+  size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
+  size_t o_wr = L.take((wantW + 1) * 4);
+  size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_fin = L.take(N_), o_sa = L.take(N_ * 4);
+  size_t o_phi = L.take(N_ * 4), o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
+  size_t o_lvl[8] = {0};
+  {
+    uint64_t sz = N_;
+    for (int k = 1; k < nlev; k++) { sz = (sz + 63) / 64; o_lvl[k] = L.take(sz * 4 + 4); }
+  }
+  size_t o_cl = L.take(C2 * 4), o_cs = L.take(C2 * 4), o_ci = L.take(C2 * 4), o_keep = L.take(C2);
+  size_t o_sl = L.take(C2 * 4), o_ss = L.take(C2 * 4), o_si = L.take(C2 * 4);
+  size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
+  size_t o_tile = L.take((C2 / 4096 + 4) * 4);
+  size_t o_T = L.take((size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
+  size_t o_state = L.take(C2), o_mark = L.take(N_);
+  size_t o_ol = L.take(N_ * 4), o_os = L.take(N_ * 4), o_oi = L.take(N_ * 4);
+  size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
+  size_t o_cnt = L.take(CNT_COUNT * 4);
+  hipError_t e = hipMalloc(&mem, L.total);
+  if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
+  bytes = L.total;
+  char *m = static_cast<char *>(mem);
+  tok64 = (uint64_t *)(m + o_tok64);
+  tokrank = (uint32_t *)(m + o_tokrank);
+  htab = (uint32_t *)(m + o_htab);
+  hrank = (uint32_t *)(m + o_hrank);
+  dist_idx = (uint32_t *)(m + o_di);
+  dist_slot = (uint32_t *)(m + o_ds);
+  dhi = (uint32_t *)(m + o_dhi);
+  dlo = (uint32_t *)(m + o_dlo);
+  d_off = (uint64_t *)(m + o_off);
+  wbeg = (uint32_t *)(m + o_wb);
+  wend = (uint32_t *)(m + o_we);
+  wid = (uint32_t *)(m + o_wid);
+  win_rows = (uint32_t *)(m + o_wr);
+  rank = (uint32_t *)(m + o_rank);
+  snap = (uint32_t *)(m + o_snap);
+  fin = (uint8_t *)(m + o_fin);
+  sa = (uint32_t *)(m + o_sa);
+  phi = (uint32_t *)(m + o_phi);
+  plcp = (uint32_t *)(m + o_plcp);
+  lcp = (uint32_t *)(m + o_lcp);
+  for (int k = 1; k < nlev; k++) lvl[k] = (uint32_t *)(m + o_lvl[k]);
+  c_len = (uint32_t *)(m + o_cl);
+  c_start = (uint32_t *)(m + o_cs);
+  c_id = (uint32_t *)(m + o_ci);
+  keep = (uint8_t *)(m + o_keep);
+  s_len = (uint32_t *)(m + o_sl);
+  s_start = (uint32_t *)(m + o_ss);
+  s_id = (uint32_t *)(m + o_si);
+  tmp_a = (uint32_t *)(m + o_ta);
+  tmp_b = (uint32_t *)(m + o_tb);
+  tmp_c = (uint32_t *)(m + o_tc);
+  tmp_d = (uint32_t *)(m + o_td);
+  tile_tmp = (uint32_t *)(m + o_tile);
+  T = (uint32_t *)(m + o_T);
+  live[0] = (uint32_t *)(m + o_live0);
+  live[1] = (uint32_t *)(m + o_live1);
+  state = (uint8_t *)(m + o_state);
+  mark = (uint8_t *)(m + o_mark);
+  o_len = (uint32_t *)(m + o_ol);
+  o_start = (uint32_t *)(m + o_os);
+  o_id = (uint32_t *)(m + o_oi);
+  rows = (void *)(m + o_rows);
+  occ = (void *)(m + o_occ);
+  row_first = (uint32_t *)(m + o_rf);
+  rowidx = (uint32_t *)(m + o_ri);
+  dcnt = (uint32_t *)(m + o_cnt);
+  int rc = eng.alloc(C2);
+  if (rc) { release(); return rc; }
+  APO_HIP_TRY(hipHostMalloc((void **)&hcnt, CNT_COUNT * 4, hipHostMallocDefault));
+  APO_HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(SortCounters), hipHostMallocDefault));
+  for (auto &ev_ : ev) APO_HIP_TRY(hipEventCreate(&ev_));
+  APO_HIP_TRY(hipMemset(dcnt, 0, CNT_COUNT * 4));
+  capN = N_;
+  capW = wantW;
+  return 0;
+}
+
+// ------------------------------------------------------------- helpers
+static int read_counters(Workspace &w, hipStream_t s) {
+  APO_HIP_TRY(hipMemcpyAsync(w.hcnt, w.dcnt, CNT_COUNT * 4, hipMemcpyDeviceToHost, s));
+  APO_HIP_TRY(hipMemcpyAsync(w.hctr, w.eng.bufs().ctr, sizeof(SortCounters), hipMemcpyDeviceToHost, s));
+  APO_HIP_TRY(hipStreamSynchronize(s));
+  if (w.hctr->err) {
+    fprintf(stderr, "[apo] device capacity check failed (code %u)\n", w.hctr->err);
+    return -4;
+  }
+  return 0;
+}
+
+// Multi-key sort of `count` items whose ids are 0..count-1: level k orders by
+// fields[k][id] (c - field when subs[k]) within the groups of level k-1.  The
+// final order is left in eng.val[0]; keep[slot] = 0 marks exact duplicates
+// of the previous slot at the last level (when keep != nullptr).
+static int sort_plain(Workspace &w, uint32_t count, const uint32_t *const *fields, const int *subs,
+                      const uint32_t *consts, const int *bits, int nlevels, uint8_t *keep, hipStream_t s) {
+  SortEngine &E = w.eng;
+  int cur = 0;
+  E.reset_counters(s);
+  E.round_begin(cur, s);
+  E.iota_val(count, s);
+  E.gather_field(cur, fields[0], count, subs[0], consts[0], count, s);
+  uint64_t *rng = reinterpret_cast<uint64_t *>(w.dcnt + CNT_RANGE);
+  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, s, rng, count);
+  E.init_units(cur, rng, 1, 0, (uint32_t)bits[0], s);
+  if (keep) fill_u8(keep, count, 1, s);
+  for (int L = 0; L < nlevels; L++) {
+    const int last = (L == nlevels - 1);
+    const uint32_t nb = last ? 0u : (uint32_t)bits[L + 1];
+    E.msd(cur, count, s);
+    E.lds_plain(cur, nb, last, keep ? keep : w.keep, count, s);
+    E.bulk_plain(cur, nb, last, keep ? keep : w.keep, count, s);
+    if (!last) {
+      cur ^= 1;
+      E.round_begin(cur, s);
+      E.gather_field(cur, fields[L + 1], 0, subs[L + 1], consts[L + 1], count, s);
+    }
+  }
+  return 0;
+}
+
+static void stamp(Workspace &w, int k, hipStream_t s) { (void)hipEventRecord(w.ev[k], s); }
+
+int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
+                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info) {
+  info = RunInfo{};
+  SortEngine &E = w.eng;
+  SortBufs &B = E.bufs();
+  int rc;
+  stamp(w, 0, s);
+  APO_HIP_TRY(hipMemcpyAsync(w.d_off, h_off, (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  const bool batch = W > 1;
+  const uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr;
+  if (batch) {
+    window_bounds(w.d_off, W, w.wbeg, w.wend, w.wid, s);
+    wbeg = w.wbeg;
+    wend = w.wend;
+    wid = w.wid;
+  }
+  fill_u32(w.dcnt, CNT_RANGE, 0, s);
+
+  // ---- order-preserving token ranks
+  const uint32_t *key0;
+  uint32_t bits0;
+  if (bits == 64) {
+    const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
+    const uint64_t hc = pow2_at_least(2 * N);
+    fill_u32(w.htab, hc, kNone, s);
+    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, w.dcnt + CNT_ND, s);
+    if ((rc = read_counters(w, s))) return rc;
+    const uint32_t nd = w.hcnt[CNT_ND];
+    info.sigma = nd;
+    hash_fields(tok, w.dist_idx, w.dcnt + CNT_ND, w.dhi, w.dlo, nd, s);
+    const uint32_t *f[2] = {w.dhi, w.dlo};
+    const int sub[2] = {0, 0};
+    const uint32_t cs[2] = {0, 0};
+    const int bb[2] = {32, 32};
+    sort_plain(w, nd, f, sub, cs, bb, 2, nullptr, s);
+    hash_assign(B.val[0], w.dcnt + CNT_ND, w.dist_slot, w.hrank, nd, s);
+    hash_lookup(tok, N, w.htab, hc - 1, w.hrank, w.tokrank, s);
+    key0 = w.tokrank;
+    bits0 = (uint32_t)bit_length_u64(nd);
+  } else {
+    key0 = static_cast<const uint32_t *>(d_tok);
+    bits0 = 32;
+  }
+  stamp(w, 1, s);
+
+  // ---- suffix array by prefix doubling
+  const uint32_t rank_bits = (uint32_t)bit_length_u64(N);
+  int cur = 0;
+  E.reset_counters(s);
+  E.round_begin(cur, s);
+  E.gather_identity(key0, (uint32_t)N, s);
+  E.init_units(cur, w.d_off, W, 0, bits0, s);
+  uint64_t act = N;
+  int r = 0;
+  while (true) {
+    if (r >= w.nsnap) return -4;
+    RankOut R{w.rank, w.snap + (size_t)r * N, w.fin, (uint32_t)r};
+    E.msd(cur, act, s);
+    E.lds_sa(cur, R, rank_bits, act, s);
+    E.bulk_sa(cur, R, rank_bits, act, s);
+    if ((rc = read_counters(w, s))) return rc;
+    info.active_sum += act;
+    const uint32_t nxt_act = w.hctr->act_cnt[cur ^ 1];
+    if (nxt_act == 0) break;
+    cur ^= 1;
+    r++;
+    E.round_begin(cur, s);
+    E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), nxt_act, s);
+    act = nxt_act;
+  }
+  info.rounds = (uint32_t)r + 1;
+  APO_HIP_TRY(hipMemcpyAsync(w.sa, B.val[0], N * 4, hipMemcpyDeviceToDevice, s));
+  stamp(w, 2, s);
+  if (stop == Stop::SA) return read_counters(w, s);
+
+  // ---- LCP via Phi / PLCP
+  build_lcp(w.sa, N, wbeg, wend, w.snap, w.fin, r - 1, w.phi, w.plcp, w.lcp, s);
+  stamp(w, 3, s);
+  if (stop == Stop::LCP) return read_counters(w, s);
+
+  // ---- candidates
+  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.c_len, w.c_start, w.c_id, w.dcnt + CNT_C,
+                 w.dcnt + CNT_MAXL, s);
+  if ((rc = read_counters(w, s))) return rc;
+  const uint32_t C = w.hcnt[CNT_C], maxl = w.hcnt[CNT_MAXL];
+  info.cands = C;
+  info.maxl = maxl;
+  stamp(w, 4, s);
+  uint32_t M = 0;
+  if (C > 0) {
+    const uint32_t *f[3] = {w.c_len, w.c_id, w.c_start};
+    const int sub[3] = {1, 0, 0};
+    const uint32_t cs[3] = {maxl, 0, 0};
+    const int bb[3] = {bit_length_u64(maxl), (int)rank_bits, (int)rank_bits};
+    sort_plain(w, C, f, sub, cs, bb, 3, w.keep, s);
+    compact_sorted(B.val[0], w.keep, C, w.c_len, w.c_start, w.c_id, w.s_len, w.s_start, w.s_id, w.tmp_a, w.tmp_b,
+                   w.tile_tmp, w.dcnt + CNT_M, s);
+    if ((rc = read_counters(w, s))) return rc;
+    M = w.hcnt[CNT_M];
+  }
+  info.cands_dedup = M;
+  stamp(w, 5, s);
+  if (stop == Stop::CANDS) return 0;
+
+  // ---- greedy selection
+  if (M > 0) {
+    const int top = 31 - __builtin_clz(maxl);
+    fill_u32(w.dcnt + CNT_NLIVE0, 1, M, s);
+    sel_init(w.live[0], w.dcnt + CNT_NLIVE0, w.state, M, s);
+    int li = 0;
+    uint64_t hint = M;
+    while (true) {
+      fill_u32(w.dcnt + CNT_NLIVE0 + (li ^ 1), 1, 0, s);
+      fill_u32(w.dcnt + CNT_UNDEC, 1, 0, s);
+      sel_round(w.live[li], w.dcnt + CNT_NLIVE0 + li, hint, w.s_len, w.s_start, w.T, top, N, w.state, w.live[li ^ 1],
+                w.dcnt + CNT_NLIVE0 + (li ^ 1), w.dcnt + CNT_UNDEC, s);
+      info.sel_rounds++;
+      if ((rc = read_counters(w, s))) return rc;
+      if (w.hcnt[CNT_UNDEC] == 0) break;
+      if (info.sel_rounds >= (uint32_t)kSelRoundCap) {
+        sel_sequential(w.state, w.s_len, w.s_start, M, w.mark, N, s);
+        info.sel_sequential = 1;
+        break;
+      }
+      li ^= 1;
+      hint = w.hcnt[CNT_NLIVE0 + li];
+    }
+  }
+  stamp(w, 6, s);
+
+  // ---- accepted occurrences and rows
+  uint32_t A = 0;
+  if (M > 0) {
+    gather_accepted(w.state, M, w.s_len, w.s_start, w.s_id, w.o_len, w.o_start, w.o_id, w.tmp_a, w.tmp_b,
+                    w.tile_tmp, w.dcnt + CNT_A, s);
+    if ((rc = read_counters(w, s))) return rc;
+    A = w.hcnt[CNT_A];
+  }
+  info.accepted = A;
+  const uint32_t *order = nullptr;
+  if (batch && A > 0) {
+    window_of_occ(w.o_start, w.wid, A, w.tmp_c, s);
+    iota_u32(w.tmp_d, A, s);
+    const uint32_t *f[2] = {w.tmp_c, w.tmp_d};
+    const int sub[2] = {0, 0};
+    const uint32_t cs[2] = {0, 0};
+    const int bb[2] = {bit_length_u64(W), bit_length_u64(A)};
+    sort_plain(w, A, f, sub, cs, bb, 2, nullptr, s);
+    order = B.val[0];
+  }
+  if (batch) fill_u32(w.win_rows, W + 1, 0, s);
+  uint32_t nrows = 0;
+  if (A > 0) {
+    emit_rows(order, A, w.o_len, w.o_start, w.o_id, wid, wbeg, w.tmp_a, w.rowidx, w.row_first, w.rows, w.occ,
+              batch ? w.win_rows : nullptr, w.tile_tmp, w.dcnt + CNT_NROWS, s);
+    if ((rc = read_counters(w, s))) return rc;
+    nrows = w.hcnt[CNT_NROWS];
+    row_counts(w.row_first, nrows, A, w.rows, s);
+  }
+  info.rows = nrows;
+  stamp(w, 7, s);
+  APO_HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < kStages; k++) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) info.stage_ms[k] = ms;
+  }
+  return 0;
+}
+
+}  // namespace apo

@@ -1,0 +1,40 @@
+// Host interface of the segmented refine-sort engine (see segsort.hip).
+#pragma once
+#include "apo_internal.h"
+
+namespace apo {
+
+class SortEngine {
+ public:
+  int alloc(uint64_t capacity);
+  void release();
+  SortBufs &bufs() { return b_; }
+  uint64_t capacity() const { return cap_; }
+  size_t bytes() const { return bytes_; }
+
+  void reset_counters(hipStream_t s);
+  void round_begin(int cur, hipStream_t s);
+  void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
+                  hipStream_t s);
+  void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
+  void gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n, uint32_t h,
+                 uint32_t act_hint, hipStream_t s);
+  void gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c, uint32_t hint,
+                    hipStream_t s);
+  void iota_val(uint32_t n, hipStream_t s);
+  void msd(int cur, uint64_t work_hint, hipStream_t s);
+  void lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s);
+  void lds_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep, uint64_t work_hint,
+                 hipStream_t s);
+  void bulk_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s);
+  void bulk_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep, uint64_t work_hint,
+                  hipStream_t s);
+
+ private:
+  SortBufs b_{};
+  void *mem_ = nullptr;
+  size_t bytes_ = 0;
+  uint64_t cap_ = 0;
+};
+
+}  // namespace apo

@@ -1,0 +1,646 @@
+// Segmented refine-sort engine.
+//
+// State: slots [0, cap) hold (key, val) pairs; a set of "units" (contiguous
+// slot ranges) must each be sorted by key, after which every run of equal keys
+// becomes a group.  Groups of size >= 2 become the units of the next level
+// (next doubling round, or the next key of a multi-key sort).  Order among
+// equal keys is left unspecified: every consumer only depends on group
+// membership, and the final order is fully determined once all groups are
+// singletons or exact duplicates.
+//
+// Units of length <= kLdsTile are sorted in LDS by bitonic networks (one
+// workgroup sorts 2^(12-c) units of class c side by side).  Longer units are
+// split by MSD bucketing passes on kDigitBits-bit digits (histogram, scan,
+// scatter into the alternate buffer) until the pieces fit the LDS path or all
+// key bits are consumed (the piece then is one group).
+#include "apo_internal.h"
+#include "device_util.h"
+#include "segsort.h"
+#include <algorithm>
+
+namespace apo {
+
+enum { MODE_SA = 0, MODE_PLAIN = 1 };
+
+// ------------------------------------------------------------------ resets
+__global__ void k_round_begin(SortCounters *c, int cur) {
+  const int nxt = cur ^ 1;
+  const int t = threadIdx.x;
+  if (t < kClasses) c->cls_cnt[nxt][t] = 0;
+  if (t < 4) {
+    c->chunk_total[t] = 0;
+    if (t >= 1) c->big_cnt[cur][t] = 0;
+  }
+  if (t == 0) {
+    c->big_cnt[nxt][0] = 0;
+    c->bulk_cnt = 0;
+    c->act_cnt[nxt] = 0;
+  }
+}
+
+__global__ void k_counters_reset(SortCounters *c) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(c);
+  const int nw = sizeof(SortCounters) / 4;
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0;
+}
+
+// -------------------------------------------------------------- unit setup
+// Routes the ranges [off[w], off[w+1]) to the class lists or the level-0 big
+// list of list `cur`.  Empty ranges are skipped.
+__global__ void k_init_units(SortBufs B, int cur, const uint64_t *off, uint32_t nranges,
+                             uint32_t base, uint32_t key_bits) {
+  const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= nranges) return;
+  const uint32_t s = (uint32_t)(off[w] - off[0]) + base;
+  const uint32_t len = (uint32_t)(off[w + 1] - off[w]);
+  if (len == 0) return;
+  if (len <= (uint32_t)kLdsTile) {
+    const int ci = class_of(len);
+    const uint32_t k = atomicAdd(&B.ctr->cls_cnt[cur][ci], 1u);
+    const uint32_t capc = B.cls_off[ci + 1] - B.cls_off[ci];
+    if (k >= capc) { atomicOr(&B.ctr->err, 1u); return; }
+    B.cls[cur][B.cls_off[ci] + k] = Unit{s, len};
+  } else {
+    const uint32_t k = atomicAdd(&B.ctr->big_cnt[cur][0], 1u);
+    if (k >= B.big_cap) { atomicOr(&B.ctr->err, 2u); return; }
+    B.big[cur][0][k] = BigUnit{s, len, key_bits, 0u};
+  }
+}
+
+// ------------------------------------------------------------------ gathers
+// Round 0 of suffix sorting: slot p holds suffix p, keyed by its first token
+// (its dense rank or, for 32-bit input, the token itself).
+__global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n) {
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    B.key[0][p] = src[p];
+    B.val[0][p] = p;
+  }
+}
+
+// Doubling round with offset h: key = rank of the suffix h positions later,
+// 0 when that lies past the end of the suffix's window.
+__global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uint32_t *slot_wend,
+                            uint32_t n, uint32_t h) {
+  const uint32_t cnt = B.ctr->act_cnt[cur];
+  const uint32_t *act = B.act[cur];
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const uint32_t p = act[q];
+    const uint32_t x = B.val[0][p] + h;
+    const uint32_t we = slot_wend ? slot_wend[p] : n;
+    B.key[0][p] = x < we ? rank[x] : 0u;
+  }
+}
+
+// Multi-key sort: key = field[val] (or c - field[val] when `sub`), over the
+// active list, or over slots [0, all) when all > 0.
+__global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, uint32_t all,
+                               int sub, uint32_t c) {
+  const uint32_t cnt = all ? all : B.ctr->act_cnt[cur];
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
+    const uint32_t p = all ? q : B.act[cur][q];
+    const uint32_t f = field[B.val[0][p]];
+    B.key[0][p] = sub ? c - f : f;
+  }
+}
+
+__global__ void k_iota_val(SortBufs B, uint32_t n) {
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    B.val[0][p] = p;
+}
+
+// -------------------------------------------------------------- LDS sorting
+template <int MODE>
+__global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, RankOut R,
+                                                          uint32_t next_bits, int last_level,
+                                                          uint8_t *keep) {
+  constexpr int NT = kLdsThreads;
+  constexpr int PER = kLdsTile / NT;  // 16 consecutive slots per thread
+  __shared__ uint64_t d[kLdsTile];
+  __shared__ uint32_t hd[kLdsTile];
+  __shared__ Unit ud[kLdsTile / 2];
+  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t cls_loc[kClasses], cls_base[kClasses];
+  __shared__ uint32_t act_base;
+  __shared__ uint32_t item_c, item_b, items_total;
+  __shared__ uint32_t cnt_c[kClasses];
+
+  const int nxt = cur ^ 1;
+  const int tid = threadIdx.x;
+  if (tid < kClasses) cnt_c[tid] = B.ctr->cls_cnt[cur][tid];
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int ci = 0; ci < kClasses; ci++) {
+      const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
+      tot += (cnt_c[ci] + per - 1) / per;
+    }
+    items_total = tot;
+  }
+  __syncthreads();
+  const uint32_t total = items_total;
+
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    if (tid == 0) {
+      uint32_t it = item;
+      int ci = 0;
+      for (; ci < kClasses; ci++) {
+        const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
+        const uint32_t ni = (cnt_c[ci] + per - 1) / per;
+        if (it < ni) break;
+        it -= ni;
+      }
+      item_c = (uint32_t)ci;
+      item_b = it;
+    }
+    if (tid < kClasses) cls_loc[tid] = 0;
+    __syncthreads();
+    const int ci = (int)item_c;
+    const int c = ci + 1;
+    const uint32_t sub = 1u << c;
+    const uint32_t per = (uint32_t)kLdsTile >> c;
+    const uint32_t first = item_b * per;
+    const uint32_t nb = min(per, cnt_c[ci] - first);
+    const Unit *src = B.cls[cur] + B.cls_off[ci] + first;
+    for (uint32_t j = tid; j < nb; j += NT) ud[j] = src[j];
+    __syncthreads();
+
+    // load (key, val) pairs; pad with all-ones
+    for (int s = tid; s < kLdsTile; s += NT) {
+      const uint32_t j = (uint32_t)s >> c, idx = (uint32_t)s & (sub - 1);
+      uint64_t v = ~0ull;
+      if (j < nb) {
+        const Unit u = ud[j];
+        const uint32_t len = u.len & ~kBufBit;
+        if (idx < len) {
+          const int b = (u.len & kBufBit) ? 1 : 0;
+          const uint32_t p = u.start + idx;
+          v = ((uint64_t)B.key[b][p] << 32) | B.val[b][p];
+        }
+      }
+      d[s] = v;
+    }
+    __syncthreads();
+
+    // bitonic sort of every sub-block of size `sub`, ascending
+    for (uint32_t k = 2; k <= sub; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t t = tid; t < (uint32_t)kLdsTile / 2; t += NT) {
+          const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+          const uint32_t l = i | jj;
+          const bool asc = (k == sub) || ((i & k) == 0);
+          const uint64_t a = d[i], b = d[l];
+          if ((a > b) == asc) { d[i] = b; d[l] = a; }
+        }
+        __syncthreads();
+      }
+    }
+
+    // group heads: hd[s] = last boundary slot <= s.  Every sub-block starts
+    // with a boundary, so the running maximum never leaves the sub-block.
+    const int s0 = tid * PER;
+    uint32_t run = 0;  // last boundary + 1 seen in this thread's chunk (0: none)
+    for (int q = 0; q < PER; q++) {
+      const int s = s0 + q;
+      const uint32_t idx = (uint32_t)s & (sub - 1);
+      const bool bnd = (idx == 0) || ((uint32_t)(d[s] >> 32) != (uint32_t)(d[s - 1] >> 32));
+      if (bnd) run = (uint32_t)s + 1;
+      hd[s] = run;
+    }
+    __shared__ uint32_t tmax[NT];
+    tmax[tid] = block_incl_max<NT>(run, sh);
+    __syncthreads();
+    const uint32_t carry = tid > 0 ? tmax[tid - 1] : 0u;
+    for (int q = 0; q < PER; q++) {
+      const int s = s0 + q;
+      const uint32_t h = hd[s];
+      hd[s] = (h ? h : carry) - 1u;
+    }
+    __syncthreads();
+
+    // regroup
+    uint32_t my_act = 0;
+    for (int q = 0; q < PER; q++) {
+      const int s = s0 + q;
+      const uint32_t j = (uint32_t)s >> c, idx = (uint32_t)s & (sub - 1);
+      if (j >= nb) continue;
+      const Unit u = ud[j];
+      const uint32_t len = u.len & ~kBufBit;
+      if (idx >= len) continue;
+      const uint32_t hs = hd[s];
+      const bool bnd = hs == (uint32_t)s;
+      const bool last = (idx + 1 == len) || ((uint32_t)(d[s + 1] >> 32) != (uint32_t)(d[s] >> 32));
+      const bool single = bnd && last;
+      const uint32_t v = (uint32_t)d[s];
+      const uint32_t gpos = u.start + (hs - (j << c));
+      const uint32_t p = u.start + idx;
+      B.val[0][p] = v;
+      if (MODE == MODE_SA) {
+        R.rank[v] = gpos + 1;
+        R.snap[v] = gpos + 1;
+        if (single) R.fin[v] = (uint8_t)R.round;
+      }
+      if (last_level) {
+        keep[p] = bnd ? 1 : 0;
+      } else {
+        if (!single) my_act++;
+        if (last && !bnd) {
+          const uint32_t size = (uint32_t)s - hs + 1;
+          atomicAdd(&cls_loc[class_of(size)], 1u);
+        }
+      }
+    }
+    if (!last_level) {
+      uint32_t tot;
+      const uint32_t off = block_excl_sum<NT>(my_act, sh, &tot);
+      if (tid == 0) act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      if (tid < kClasses) {
+        const uint32_t m = cls_loc[tid];
+        cls_base[tid] = m ? atomicAdd(&B.ctr->cls_cnt[nxt][tid], m) : 0u;
+        cls_loc[tid] = 0;
+      }
+      __syncthreads();
+      uint32_t w = act_base + off;
+      for (int q = 0; q < PER; q++) {
+        const int s = s0 + q;
+        const uint32_t j = (uint32_t)s >> c, idx = (uint32_t)s & (sub - 1);
+        if (j >= nb) continue;
+        const Unit u = ud[j];
+        const uint32_t len = u.len & ~kBufBit;
+        if (idx >= len) continue;
+        const uint32_t hs = hd[s];
+        const bool bnd = hs == (uint32_t)s;
+        const bool last = (idx + 1 == len) || ((uint32_t)(d[s + 1] >> 32) != (uint32_t)(d[s] >> 32));
+        if (!(bnd && last)) {
+          if (w < B.cap) B.act[nxt][w] = u.start + idx;
+          else atomicOr(&B.ctr->err, 4u);
+          w++;
+        }
+        if (last && !bnd) {
+          const uint32_t size = (uint32_t)s - hs + 1;
+          const int cc = class_of(size);
+          const uint32_t k = cls_base[cc] + atomicAdd(&cls_loc[cc], 1u);
+          const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
+          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (hs - (j << c)), size};
+          else atomicOr(&B.ctr->err, 8u);
+        }
+      }
+    }
+    (void)next_bits;
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- MSD bucketing
+__global__ void k_msd_chunkify(SortBufs B, int cur, int level) {
+  constexpr int NT = 1024;
+  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t carry;
+  const uint32_t units = B.ctr->big_cnt[cur][level];
+  const BigUnit *U = B.big[cur][level];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < units; b0 += NT) {
+    const uint32_t u = b0 + threadIdx.x;
+    const uint32_t ch = u < units ? (U[u].len + kChunk - 1) / kChunk : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum<NT>(ch, sh, &tot);
+    if (u < units) B.chunk_base[u] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    B.chunk_base[units] = carry;
+    B.ctr->chunk_total[level] = carry;
+  }
+}
+
+__device__ __forceinline__ uint32_t find_unit(const uint32_t *base, uint32_t units, uint32_t ch) {
+  uint32_t lo = 0, hi = units;  // largest u with base[u] <= ch
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= ch) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void digit_params(uint32_t bits, uint32_t &shift, uint32_t &mask) {
+  const uint32_t d = bits < (uint32_t)kDigitBits ? bits : (uint32_t)kDigitBits;
+  shift = bits - d;
+  mask = (d >= 32) ? 0xFFFFFFFFu : ((1u << d) - 1u);
+}
+
+__global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level) {
+  __shared__ uint32_t h[kBins];
+  const uint32_t units = B.ctr->big_cnt[cur][level];
+  const uint32_t total = B.ctr->chunk_total[level];
+  const BigUnit *U = B.big[cur][level];
+  for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const uint32_t u = find_unit(B.chunk_base, units, ch);
+    const BigUnit bu = U[u];
+    uint32_t shift, mask;
+    digit_params(bu.bits, shift, mask);
+    const uint32_t lo = bu.start + (ch - B.chunk_base[u]) * kChunk;
+    const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
+    const uint32_t *key = B.key[bu.flags & 1u];
+    for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
+      atomicAdd(&h[(key[p] >> shift) & mask], 1u);
+    __syncthreads();
+    uint32_t *gh = B.hist + (size_t)u * kBins;
+    for (int b = threadIdx.x; b <= (int)mask; b += blockDim.x)
+      if (h[b]) atomicAdd(&gh[b], h[b]);
+    __syncthreads();
+  }
+}
+
+__device__ void route_piece(SortBufs &B, int cur, int level, uint32_t start, uint32_t len,
+                            uint32_t bits_left, uint32_t buf) {
+  if (len <= (uint32_t)kLdsTile) {
+    const int ci = class_of(len);
+    const uint32_t k = atomicAdd(&B.ctr->cls_cnt[cur][ci], 1u);
+    const uint32_t capc = B.cls_off[ci + 1] - B.cls_off[ci];
+    if (k < capc) B.cls[cur][B.cls_off[ci] + k] = Unit{start, len | (buf ? kBufBit : 0u)};
+    else atomicOr(&B.ctr->err, 16u);
+  } else if (bits_left == 0 || level >= 3) {
+    const uint32_t k = atomicAdd(&B.ctr->bulk_cnt, 1u);
+    if (k < B.big_cap) B.bulk[k] = BigUnit{start, len, 0u, buf};
+    else atomicOr(&B.ctr->err, 32u);
+  } else {
+    const uint32_t k = atomicAdd(&B.ctr->big_cnt[cur][level + 1], 1u);
+    if (k < B.big_cap) B.big[cur][level + 1][k] = BigUnit{start, len, bits_left, buf};
+    else atomicOr(&B.ctr->err, 64u);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_msd_scan(SortBufs B, int cur, int level) {
+  constexpr int NT = 256;
+  constexpr int PER = kBins / NT;
+  __shared__ uint32_t sh[NT / 64];
+  const uint32_t units = B.ctr->big_cnt[cur][level];
+  BigUnit *U = B.big[cur][level];
+  for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const BigUnit bu = U[u];
+    uint32_t shift, mask;
+    digit_params(bu.bits, shift, mask);
+    uint32_t *gh = B.hist + (size_t)u * kBins;
+    uint32_t *cu = B.cursor + (size_t)u * kBins;
+    uint32_t v[PER];
+    uint32_t loc = 0;
+    for (int q = 0; q < PER; q++) {
+      const uint32_t b = threadIdx.x * PER + q;
+      v[q] = b <= mask ? gh[b] : 0u;
+      loc += v[q];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);
+    // single bucket: keep data in place, continue with the remaining bits
+    bool single = false;
+    for (int q = 0; q < PER; q++) single |= (v[q] == bu.len);
+    __shared__ int any_single;
+    if (threadIdx.x == 0) any_single = 0;
+    __syncthreads();
+    if (single) any_single = 1;
+    __syncthreads();
+    const bool one = any_single != 0;
+    for (int q = 0; q < PER; q++) {
+      const uint32_t b = threadIdx.x * PER + q;
+      if (b <= mask) {
+        cu[b] = bu.start + ex;
+        if (v[q]) {
+          if (one) route_piece(B, cur, level, bu.start, bu.len, shift, bu.flags & 1u);
+          else route_piece(B, cur, level, bu.start + ex, v[q], shift, (bu.flags & 1u) ^ 1u);
+        }
+        gh[b] = 0;
+      }
+      ex += v[q];
+    }
+    if (threadIdx.x == 0 && one) U[u].flags = bu.flags | 2u;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int level) {
+  constexpr int NT = 256;
+  constexpr int PER = kChunk / NT;
+  __shared__ uint32_t cnt[kBins];
+  const uint32_t units = B.ctr->big_cnt[cur][level];
+  const uint32_t total = B.ctr->chunk_total[level];
+  const BigUnit *U = B.big[cur][level];
+  for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+    const uint32_t u = find_unit(B.chunk_base, units, ch);
+    const BigUnit bu = U[u];
+    if (bu.flags & 2u) continue;  // uniform across the block
+    for (int b = threadIdx.x; b < kBins; b += NT) cnt[b] = 0;
+    __syncthreads();
+    uint32_t shift, mask;
+    digit_params(bu.bits, shift, mask);
+    const uint32_t lo = bu.start + (ch - B.chunk_base[u]) * kChunk;
+    const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
+    const int sb = bu.flags & 1u, db = sb ^ 1;
+    uint32_t kk[PER], vv[PER], oo[PER];
+    for (int q = 0; q < PER; q++) {
+      const uint32_t p = lo + threadIdx.x + q * NT;
+      if (p < hi) {
+        kk[q] = B.key[sb][p];
+        vv[q] = B.val[sb][p];
+        oo[q] = atomicAdd(&cnt[(kk[q] >> shift) & mask], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t *cu = B.cursor + (size_t)u * kBins;
+    for (int b = threadIdx.x; b <= (int)mask; b += NT) {
+      const uint32_t m = cnt[b];
+      cnt[b] = m ? atomicAdd(&cu[b], m) : 0u;
+    }
+    __syncthreads();
+    for (int q = 0; q < PER; q++) {
+      const uint32_t p = lo + threadIdx.x + q * NT;
+      if (p < hi) {
+        const uint32_t dst = cnt[(kk[q] >> shift) & mask] + oo[q];
+        B.key[db][dst] = kk[q];
+        B.val[db][dst] = vv[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------- bulk (one-group) units
+template <int MODE>
+__global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, uint32_t next_bits,
+                                              int last_level, uint8_t *keep) {
+  constexpr int NT = 256;
+  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t base;
+  const int nxt = cur ^ 1;
+  const uint32_t units = B.ctr->bulk_cnt;
+  for (uint32_t u = 0; u < units; u++) {
+    const BigUnit bu = B.bulk[u];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !last_level) {
+      const uint32_t k = atomicAdd(&B.ctr->big_cnt[nxt][0], 1u);
+      if (k < B.big_cap) B.big[nxt][0][k] = BigUnit{bu.start, bu.len, next_bits, 0u};
+      else atomicOr(&B.ctr->err, 128u);
+    }
+    const uint32_t stride = gridDim.x * NT;
+    for (uint32_t e0 = blockIdx.x * NT; e0 < bu.len; e0 += stride) {
+      const uint32_t e = e0 + threadIdx.x;
+      const bool ok = e < bu.len;
+      const uint32_t p = bu.start + e;
+      if (ok) {
+        const uint32_t v = B.val[bu.flags & 1u][p];
+        if (bu.flags & 1u) B.val[0][p] = v;
+        if (MODE == MODE_SA) {
+          R.rank[v] = bu.start + 1;
+          R.snap[v] = bu.start + 1;
+        }
+        if (last_level) keep[p] = (e == 0) ? 1 : 0;
+      }
+      if (!last_level) {
+        uint32_t tot;
+        const uint32_t off = block_excl_sum<NT>(ok ? 1u : 0u, sh, &tot);
+        if (threadIdx.x == 0) base = atomicAdd(&B.ctr->act_cnt[nxt], tot);
+        __syncthreads();
+        if (ok) {
+          const uint32_t w = base + off;
+          if (w < B.cap) B.act[nxt][w] = p;
+          else atomicOr(&B.ctr->err, 256u);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// =================================================================== host
+static inline dim3 grid_for(uint64_t n, int threads, int cap_blocks) {
+  uint64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)cap_blocks) b = cap_blocks;
+  return dim3((unsigned)b);
+}
+
+int SortEngine::alloc(uint64_t capacity) {
+  cap_ = capacity;
+  SortBufs &B = b_;
+  B.cap = capacity;
+  // class regions: class c (1-based) holds at most cap >> (c-1) units (+1 slack)
+  uint32_t off = 0;
+  for (int ci = 0; ci < kClasses; ci++) {
+    B.cls_off[ci] = off;
+    off += (uint32_t)((capacity >> ci) + 1);
+  }
+  B.cls_off[kClasses] = off;
+  B.big_cap = (uint32_t)(capacity / kLdsTile + 64);
+  size_t bytes = 0;
+  auto take = [&](size_t n) { size_t o = bytes; bytes += (n + 255) & ~(size_t)255; return o; };
+  size_t o_key0 = take(capacity * 4), o_key1 = take(capacity * 4);
+  size_t o_val0 = take(capacity * 4), o_val1 = take(capacity * 4);
+  size_t o_cls0 = take((size_t)off * sizeof(Unit)), o_cls1 = take((size_t)off * sizeof(Unit));
+  size_t o_big[2][4];
+  for (int l = 0; l < 2; l++)
+    for (int v = 0; v < 4; v++) o_big[l][v] = take((size_t)B.big_cap * sizeof(BigUnit));
+  size_t o_bulk = take((size_t)B.big_cap * sizeof(BigUnit));
+  size_t o_hist = take((size_t)B.big_cap * kBins * 4);
+  size_t o_cur = take((size_t)B.big_cap * kBins * 4);
+  size_t o_cb = take((size_t)(B.big_cap + 1) * 4);
+  size_t o_act0 = take(capacity * 4), o_act1 = take(capacity * 4);
+  size_t o_ctr = take(sizeof(SortCounters));
+  APO_HIP_TRY(hipMalloc(&mem_, bytes));
+  bytes_ = bytes;
+  char *m = static_cast<char *>(mem_);
+  B.key[0] = (uint32_t *)(m + o_key0); B.key[1] = (uint32_t *)(m + o_key1);
+  B.val[0] = (uint32_t *)(m + o_val0); B.val[1] = (uint32_t *)(m + o_val1);
+  B.cls[0] = (Unit *)(m + o_cls0); B.cls[1] = (Unit *)(m + o_cls1);
+  for (int l = 0; l < 2; l++)
+    for (int v = 0; v < 4; v++) B.big[l][v] = (BigUnit *)(m + o_big[l][v]);
+  B.bulk = (BigUnit *)(m + o_bulk);
+  B.hist = (uint32_t *)(m + o_hist);
+  B.cursor = (uint32_t *)(m + o_cur);
+  B.chunk_base = (uint32_t *)(m + o_cb);
+  B.act[0] = (uint32_t *)(m + o_act0); B.act[1] = (uint32_t *)(m + o_act1);
+  B.ctr = (SortCounters *)(m + o_ctr);
+  APO_HIP_TRY(hipMemset(B.hist, 0, (size_t)B.big_cap * kBins * 4));
+  APO_HIP_TRY(hipMemset(B.ctr, 0, sizeof(SortCounters)));
+  return 0;
+}
+
+void SortEngine::release() {
+  if (mem_) (void)hipFree(mem_);
+  mem_ = nullptr;
+}
+
+void SortEngine::reset_counters(hipStream_t s) {
+  hipLaunchKernelGGL(k_counters_reset, dim3(1), dim3(64), 0, s, b_.ctr);
+}
+
+void SortEngine::round_begin(int cur, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, b_.ctr, cur);
+}
+
+void SortEngine::init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base,
+                            uint32_t key_bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_units, grid_for(nranges, 256, 1 << 16), dim3(256), 0, s, b_, cur, d_off,
+                     nranges, base, key_bits);
+}
+
+void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_identity, grid_for(n, 256, 4096), dim3(256), 0, s, b_, src, n);
+}
+
+void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n,
+                           uint32_t h, uint32_t act_hint, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sa, grid_for(act_hint, 256, 4096), dim3(256), 0, s, b_, cur, rank,
+                     slot_wend, n, h);
+}
+
+void SortEngine::gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c,
+                              uint32_t hint, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_field, grid_for(all ? all : hint, 256, 4096), dim3(256), 0, s, b_,
+                     cur, field, all, sub, c);
+}
+
+void SortEngine::iota_val(uint32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota_val, grid_for(n, 256, 4096), dim3(256), 0, s, b_, n);
+}
+
+void SortEngine::msd(int cur, uint64_t work_hint, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<uint64_t>(4096, std::max<uint64_t>(256, work_hint / kChunk + 1));
+  for (int level = 0; level < 3; level++) {
+    hipLaunchKernelGGL(k_msd_chunkify, dim3(1), dim3(1024), 0, s, b_, cur, level);
+    hipLaunchKernelGGL(k_msd_hist, dim3(g), dim3(256), 0, s, b_, cur, level);
+    hipLaunchKernelGGL(k_msd_scan, dim3(256), dim3(256), 0, s, b_, cur, level);
+    hipLaunchKernelGGL(k_msd_scatter, dim3(g), dim3(256), 0, s, b_, cur, level);
+  }
+}
+
+void SortEngine::lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / kLdsTile + 16));
+  hipLaunchKernelGGL(k_lds_sort<MODE_SA>, dim3(g), dim3(kLdsThreads), 0, s, b_, cur, R, next_bits, 0,
+                     (uint8_t *)nullptr);
+}
+
+void SortEngine::lds_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep,
+                           uint64_t work_hint, hipStream_t s) {
+  RankOut R{};
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / kLdsTile + 16));
+  hipLaunchKernelGGL(k_lds_sort<MODE_PLAIN>, dim3(g), dim3(kLdsThreads), 0, s, b_, cur, R, next_bits,
+                     last_level, keep);
+}
+
+void SortEngine::bulk_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s) {
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / 1024 + 1));
+  hipLaunchKernelGGL(k_bulk<MODE_SA>, dim3(g), dim3(256), 0, s, b_, cur, R, next_bits, 0,
+                     (uint8_t *)nullptr);
+}
+
+void SortEngine::bulk_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep,
+                            uint64_t work_hint, hipStream_t s) {
+  RankOut R{};
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / 1024 + 1));
+  hipLaunchKernelGGL(k_bulk<MODE_PLAIN>, dim3(g), dim3(256), 0, s, b_, cur, R, next_bits, last_level,
+                     keep);
+}
+
+}  // namespace apo

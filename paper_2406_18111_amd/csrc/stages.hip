@@ -1,0 +1,637 @@
+// Stage kernels of the repeat-finding path (everything except the segmented
+// sort engine): token ranking, LCP construction, candidate generation,
+// greedy selection and output compaction.
+#include "apo_internal.h"
+#include "device_util.h"
+#include "stages.h"
+#include <algorithm>
+
+namespace apo {
+
+static inline dim3 grid_for(uint64_t n, int threads, int cap_blocks) {
+  uint64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)cap_blocks) b = cap_blocks;
+  return dim3((unsigned)b);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) { GRID_STRIDE(i, n) p[i] = v; }
+__global__ void k_fill_u8(uint8_t *p, uint64_t n, uint8_t v) { GRID_STRIDE(i, n) p[i] = v; }
+
+void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u32, grid_for(n, 256, 8192), dim3(256), 0, s, p, n, v);
+}
+void fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_fill_u8, grid_for(n, 256, 8192), dim3(256), 0, s, p, n, v);
+}
+
+// ------------------------------------------------------ device-wide scan
+// Exclusive prefix sum of u32 values (sums fit in u32).  Three phases:
+// per-tile sums, one-workgroup scan of the tile sums, per-tile rescan.
+constexpr int kScanNT = 256, kScanPer = 16, kScanTile = kScanNT * kScanPer;
+
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const uint32_t *in, uint64_t n, uint32_t *tile_sum) {
+  __shared__ uint32_t sh[kScanNT / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t loc = 0;
+  for (int q = 0; q < kScanPer; q++) {
+    const uint64_t i = base + (uint64_t)q * kScanNT + threadIdx.x;
+    loc += i < n ? in[i] : 0u;
+  }
+  uint32_t tot;
+  (void)block_excl_sum<kScanNT>(loc, sh, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *tile_sum, uint32_t ntiles, uint32_t *total) {
+  __shared__ uint32_t sh[1024 / 64];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < ntiles; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t v = i < ntiles ? tile_sum[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_sum<1024>(v, sh, &tot);
+    if (i < ntiles) tile_sum[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_apply(const uint32_t *in, uint64_t n, const uint32_t *tile_sum,
+                                                        uint32_t *out) {
+  __shared__ uint32_t sh[kScanNT / 64];
+  // thread owns kScanPer consecutive elements
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+  uint32_t v[kScanPer];
+  uint32_t loc = 0;
+  for (int q = 0; q < kScanPer; q++) {
+    const uint64_t i = base + q;
+    v[q] = i < n ? in[i] : 0u;
+    loc += v[q];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_sum<kScanNT>(loc, sh, &tot) + tile_sum[blockIdx.x];
+  for (int q = 0; q < kScanPer; q++) {
+    const uint64_t i = base + q;
+    if (i < n) out[i] = ex;
+    ex += v[q];
+  }
+}
+
+void scan_excl(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tile_tmp, uint32_t *total,
+               hipStream_t s) {
+  const uint32_t tiles = (uint32_t)((n + kScanTile - 1) / kScanTile);
+  if (tiles == 0) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0u);
+    return;
+  }
+  // k_scan_tiles reads elements strided by kScanNT within the tile; any
+  // partition of the tile gives the same tile sum.
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanNT), 0, s, in, n, tile_tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tile_tmp, tiles, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanNT), 0, s, in, n, tile_tmp, out);
+}
+
+// ------------------------------------------------------ token ranking (u64)
+// Open-addressing table of first-occurrence indices.  A thread inserts its
+// token; the one whose CAS claims an empty slot records a new distinct value.
+__global__ void k_hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask,
+                              uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd) {
+  GRID_STRIDE(i, n) {
+    const uint64_t key = tok[i];
+    uint64_t h = mix64(key) & mask;
+    while (true) {
+      uint32_t cur = tab[h];
+      if (cur == kNone) {
+        const uint32_t prev = atomicCAS(&tab[h], kNone, (uint32_t)i);
+        if (prev == kNone) {
+          const uint32_t d = atomicAdd(nd, 1u);
+          dist_idx[d] = (uint32_t)i;
+          dist_slot[d] = (uint32_t)h;
+          break;
+        }
+        cur = prev;
+      }
+      if (tok[cur] == key) break;
+      h = (h + 1) & mask;
+    }
+  }
+}
+
+__global__ void k_hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd,
+                              uint32_t *hi, uint32_t *lo) {
+  const uint32_t m = *nd;
+  GRID_STRIDE(d, m) {
+    const uint64_t t = tok[dist_idx[d]];
+    hi[d] = (uint32_t)(t >> 32);
+    lo[d] = (uint32_t)t;
+  }
+}
+
+__global__ void k_hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot,
+                              uint32_t *slot_rank) {
+  const uint32_t m = *nd;
+  GRID_STRIDE(q, m) slot_rank[dist_slot[sorted_d[q]]] = (uint32_t)q + 1u;
+}
+
+__global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *tab, uint64_t mask,
+                              const uint32_t *slot_rank, uint32_t *out) {
+  GRID_STRIDE(i, n) {
+    const uint64_t key = tok[i];
+    uint64_t h = mix64(key) & mask;
+    while (true) {
+      const uint32_t cur = tab[h];
+      if (cur != kNone && tok[cur] == key) { out[i] = slot_rank[h]; break; }
+      h = (h + 1) & mask;
+    }
+  }
+}
+
+void hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask, uint32_t *dist_idx,
+                 uint32_t *dist_slot, uint32_t *nd, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_insert, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n, tab, mask, dist_idx,
+                     dist_slot, nd);
+}
+void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
+                 uint32_t *lo, uint64_t hint, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_fields, grid_for(hint, 256, 8192), dim3(256), 0, s, tok, dist_idx, nd, hi, lo);
+}
+void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot, uint32_t *slot_rank,
+                 uint64_t hint, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_assign, grid_for(hint, 256, 8192), dim3(256), 0, s, sorted_d, nd, dist_slot,
+                     slot_rank);
+}
+void hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *tab, uint64_t mask, const uint32_t *slot_rank,
+                 uint32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_lookup, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n, tab, mask, slot_rank, out);
+}
+
+// -------------------------------------------------------------- windows
+// Per-slot window bounds for batched input (offsets are global, ascending).
+__global__ void k_window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend,
+                                uint32_t *wid) {
+  const uint32_t w = blockIdx.x;
+  if (w >= nw) return;
+  const uint32_t b = (uint32_t)(off[w] - off[0]), e = (uint32_t)(off[w + 1] - off[0]);
+  for (uint32_t p = b + threadIdx.x; p < e; p += blockDim.x) {
+    wbeg[p] = b;
+    wend[p] = e;
+    wid[p] = w;
+  }
+}
+
+void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
+                   hipStream_t s) {
+  if (nw) hipLaunchKernelGGL(k_window_bounds, dim3(nw), dim3(256), 0, s, off, nw, wbeg, wend, wid);
+}
+
+// ------------------------------------------------------------------- LCP
+__global__ void k_phi(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, uint32_t *phi) {
+  GRID_STRIDE(i, n) {
+    const uint32_t b = wbeg ? wbeg[i] : 0u;
+    phi[sa[i]] = (i > b) ? sa[i - 1] : kNone;
+  }
+}
+
+// lcp(x, y) >= acc known; extend by binary lifting over the per-round rank
+// snapshots: 2^j-prefixes at x+acc and y+acc are equal iff both suffixes were
+// still in a shared group after round j and carried the same rank then.
+__device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t acc, uint32_t we, int top,
+                                             const uint32_t *snap, uint64_t n, const uint8_t *fin) {
+  for (int j = top; j >= 0; j--) {
+    const uint32_t a = x + acc, b = y + acc;
+    if (a >= we || b >= we) break;
+    if (fin[a] > j && fin[b] > j && snap[(uint64_t)j * n + a] == snap[(uint64_t)j * n + b]) acc += 1u << j;
+  }
+  return acc;
+}
+
+constexpr int kKasaiChunk = 32;
+constexpr int kKasaiCap = 64;
+
+// Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of consecutive
+// positions; each chunk (and each window start) is seeded exactly by lifting,
+// and an extension longer than kKasaiCap tokens switches to lifting.
+__global__ void k_plcp(const uint32_t *phi, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
+                       const uint32_t *snap, const uint8_t *fin, int top, uint32_t *plcp) {
+  const uint64_t nchunks = (n + kKasaiChunk - 1) / kKasaiChunk;
+  GRID_STRIDE(t, nchunks) {
+    const uint64_t j0 = t * kKasaiChunk, j1 = min(j0 + kKasaiChunk, n);
+    uint32_t h = 0;
+    bool fresh = true;
+    for (uint64_t j = j0; j < j1; j++) {
+      const uint32_t y = phi[j];
+      const uint32_t b = wbeg ? wbeg[j] : 0u;
+      if (j == b) fresh = true;
+      if (y == kNone) { plcp[j] = 0; h = 0; fresh = true; continue; }
+      const uint32_t we = wend ? wend[j] : (uint32_t)n;
+      if (fresh) {
+        h = lcp_lift((uint32_t)j, y, 0u, we, top, snap, n, fin);
+        fresh = false;
+      } else {
+        h = h > 0 ? h - 1 : 0;
+        int steps = 0;
+        while ((uint32_t)j + h < we && y + h < we && snap[(uint32_t)j + h] == snap[y + h]) {
+          h++;
+          if (++steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin); break; }
+        }
+      }
+      plcp[j] = h;
+    }
+  }
+}
+
+__global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, const uint32_t *plcp, uint32_t *lcp) {
+  GRID_STRIDE(i, n) {
+    const uint32_t we = wend ? wend[i] : (uint32_t)n;
+    lcp[i] = (i + 1 < we) ? plcp[sa[i + 1]] : 0u;
+  }
+}
+
+void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
+               const uint8_t *fin, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp, hipStream_t s) {
+  hipLaunchKernelGGL(k_phi, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wbeg, phi);
+  const uint64_t nch = (n + kKasaiChunk - 1) / kKasaiChunk;
+  hipLaunchKernelGGL(k_plcp, grid_for(nch, 256, 8192), dim3(256), 0, s, phi, n, wbeg, wend, snap, fin, top, plcp);
+  hipLaunchKernelGGL(k_lcp, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
+}
+
+// ------------------------------------------------------------ candidates
+// Block minima of LCP (64-ary levels) for previous-smaller-value queries.
+__global__ void k_blockmin(const uint32_t *src, uint64_t nsrc, uint32_t *dst, uint64_t ndst) {
+  GRID_STRIDE(k, ndst) {
+    uint32_t m = 0xFFFFFFFFu;
+    const uint64_t b = k * 64, e = min(b + 64, nsrc);
+    for (uint64_t i = b; i < e; i++) m = min(m, src[i]);
+    dst[k] = m;
+  }
+}
+
+struct MinLevels {
+  const uint32_t *lv[kMinLevels];
+  uint64_t sz[kMinLevels];
+  int nlev;
+};
+
+// Largest j < i with lcp[j] < l, or -1.  Scans the block of i at level 0,
+// climbs 64-ary minimum levels until an entry below l appears, then descends
+// to its rightmost qualifying leaf.
+__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
+  uint64_t pos = i;  // exclusive bound at the current level
+  int lev = 0;
+  int64_t found = -1;
+  while (pos > 0) {
+    // the top level has no parent: scan it down to entry 0
+    const uint64_t bs = (lev + 1 >= M.nlev) ? 0 : ((pos - 1) >> 6) << 6;
+    const uint32_t *L = M.lv[lev];
+    for (uint64_t e = pos; e > bs; e--) {
+      if (L[e - 1] < l) { found = (int64_t)(e - 1); break; }
+    }
+    if (found >= 0) break;
+    if (lev + 1 >= M.nlev) return -1;
+    pos = bs >> 6;
+    lev++;
+  }
+  if (found < 0) return -1;
+  while (lev > 0) {
+    lev--;
+    const uint32_t *L = M.lv[lev];
+    const uint64_t b = (uint64_t)found * 64;
+    const uint64_t e = min(b + 64, M.sz[lev]);
+    int64_t f = -1;
+    for (uint64_t q = e; q > b; q--) {
+      if (L[q - 1] < l) { f = (int64_t)(q - 1); break; }
+    }
+    found = f;  // always found: the parent minimum is < l
+    if (found < 0) return -1;
+  }
+  return found;
+}
+
+// Loop body of the paper's candidate pass for every adjacent pair i (both
+// suffixes in one window): disjoint branch -> (p, s1), (p, s2); overlap branch
+// -> l = floor((p+d)/2) - remainder mod d, at base and base+l.  Candidates
+// with l >= min_len are appended with their substring ID.
+__global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
+                                                    const uint32_t *wend, uint32_t min_len, MinLevels M,
+                                                    uint32_t *c_len, uint32_t *c_start, uint32_t *c_id,
+                                                    uint32_t *cnt, uint32_t *maxl) {
+  __shared__ uint32_t sh[4];
+  __shared__ uint32_t base;
+  __shared__ uint32_t bmax;
+  if (threadIdx.x == 0) bmax = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
+    uint32_t l = 0, a = 0, b = 0, id = 0;
+    bool emit = false;
+    if (i + 1 < n) {
+      const uint32_t we = wend ? wend[i] : (uint32_t)n;
+      if (i + 1 < we) {
+        const uint32_t s1 = sa[i], s2 = sa[i + 1], p = lcp[i];
+        const uint32_t lo = min(s1, s2), hi = max(s1, s2);
+        if (lo + p <= hi) {
+          l = p; a = s1; b = s2;
+        } else {
+          const uint32_t d = hi - lo;
+          l = (p + d) / 2;
+          l -= l % d;
+          a = lo; b = lo + l;
+        }
+        if (l >= min_len) {
+          emit = true;
+          id = (uint32_t)(psv_query(M, i, l) + 1);
+        }
+      }
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_sum<256>(emit ? 2u : 0u, sh, &tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(cnt, tot) : 0u;
+    if (emit) atomicMax(&bmax, l);
+    __syncthreads();
+    if (emit) {
+      const uint32_t w = base + off;
+      c_len[w] = l; c_start[w] = a; c_id[w] = id;
+      c_len[w + 1] = l; c_start[w + 1] = b; c_id[w + 1] = id;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && bmax) atomicMax(maxl, bmax);
+}
+
+void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend, uint32_t min_len,
+                    uint32_t *const *levels, int nlev, uint32_t *c_len, uint32_t *c_start, uint32_t *c_id,
+                    uint32_t *cnt, uint32_t *maxl, hipStream_t s) {
+  MinLevels M{};
+  uint64_t sz = n;
+  M.lv[0] = lcp;
+  M.sz[0] = n;
+  M.nlev = 1;
+  for (int k = 1; k < nlev && k < kMinLevels; k++) {
+    const uint64_t nd = (sz + 63) / 64;
+    hipLaunchKernelGGL(k_blockmin, grid_for(nd, 256, 8192), dim3(256), 0, s, M.lv[k - 1], sz, levels[k], nd);
+    M.lv[k] = levels[k];
+    M.sz[k] = nd;
+    M.nlev = k + 1;
+    sz = nd;
+    if (nd <= 1) break;
+  }
+  hipLaunchKernelGGL(k_candidates, grid_for(n, 256, 8192), dim3(256), 0, s, sa, lcp, n, wend, min_len, M, c_len,
+                     c_start, c_id, cnt, maxl);
+}
+
+// Keep the first of each run of identical candidates, in sorted order.
+__global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *pos, uint64_t m,
+                                const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id,
+                                uint32_t *s_len, uint32_t *s_start, uint32_t *s_id) {
+  GRID_STRIDE(k, m) {
+    if (keep[k]) {
+      const uint32_t c = order[k], o = pos[k];
+      s_len[o] = c_len[c]; s_start[o] = c_start[c]; s_id[o] = c_id[c];
+    }
+  }
+}
+
+__global__ void k_u8_to_u32(const uint8_t *a, uint64_t n, uint32_t *b) { GRID_STRIDE(i, n) b[i] = a[i]; }
+
+void compact_sorted(const uint32_t *order, const uint8_t *keep, uint64_t m, const uint32_t *c_len,
+                    const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len, uint32_t *s_start,
+                    uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_u8_to_u32, grid_for(m, 256, 8192), dim3(256), 0, s, keep, m, tmp_flags);
+  scan_excl(tmp_flags, tmp_pos, m, tile_tmp, total, s);
+  hipLaunchKernelGGL(k_gather_sorted, grid_for(m, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m, c_len,
+                     c_start, c_id, s_len, s_start, s_id);
+}
+
+// ------------------------------------------------------------- selection
+// Round-based exact evaluation of the greedy: a candidate is accepted once no
+// live (undecided or accepted) candidate of higher priority covers its first
+// or last position, and rejected once an accepted one does.  Coverage minima
+// come from a sparse table: every live interval writes its priority into the
+// two power-of-two blocks that tile it, then minima are pushed down level by
+// level to single positions.
+__global__ void k_sel_insert(const uint32_t *live, const uint32_t *nlive, const uint32_t *len,
+                             const uint32_t *start, uint32_t *T, uint64_t n) {
+  const uint32_t m = *nlive;
+  GRID_STRIDE(q, m) {
+    const uint32_t k = live[q];
+    const uint32_t l = len[k], s = start[k];
+    const int j = 31 - __clz((int)l);
+    uint32_t *Tj = T + (uint64_t)j * n;
+    atomicMin(&Tj[s], k);
+    atomicMin(&Tj[s + l - (1u << j)], k);
+  }
+}
+
+__global__ void k_sel_push(uint32_t *T, uint64_t n, int j) {
+  const uint32_t *Tj = T + (uint64_t)j * n;
+  uint32_t *Td = T + (uint64_t)(j - 1) * n;
+  const uint64_t half = 1ull << (j - 1);
+  GRID_STRIDE(x, n) {
+    uint32_t v = Td[x];
+    v = min(v, Tj[x]);
+    if (x >= half) v = min(v, Tj[x - half]);
+    Td[x] = v;
+  }
+}
+
+__global__ void k_sel_decide(const uint32_t *live, const uint32_t *nlive, const uint32_t *len,
+                             const uint32_t *start, const uint32_t *T0, uint8_t *state, uint32_t *live_next,
+                             uint32_t *nlive_next, uint32_t *n_undec) {
+  __shared__ uint32_t sh[4];
+  __shared__ uint32_t base;
+  __shared__ uint32_t und;
+  if (threadIdx.x == 0) und = 0;
+  __syncthreads();
+  const uint32_t m = *nlive;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
+    const uint64_t q = q0 + threadIdx.x;
+    bool keep_live = false;
+    if (q < m) {
+      const uint32_t k = live[q];
+      uint8_t st = state[k];
+      if (st == 0) {
+        const uint32_t l = len[k], s = start[k];
+        const uint32_t t1 = T0[s], t2 = T0[s + l - 1];
+        if (t1 >= k && t2 >= k) {
+          st = 1;
+        } else if ((t1 < k && state[t1] == 1) || (t2 < k && state[t2] == 1)) {
+          st = 2;
+        }
+        if (st != 0) state[k] = st;
+        else atomicAdd(&und, 1u);
+      }
+      keep_live = st != 2;
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_sum<256>(keep_live ? 1u : 0u, sh, &tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(nlive_next, tot) : 0u;
+    __syncthreads();
+    if (keep_live) live_next[base + off] = live[q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && und) atomicAdd(n_undec, und);
+}
+
+__global__ void k_iota(uint32_t *p, const uint32_t *n) {
+  const uint32_t m = *n;
+  GRID_STRIDE(i, m) p[i] = (uint32_t)i;
+}
+
+void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t m, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, grid_for(m, 256, 8192), dim3(256), 0, s, live, nlive_dev);
+  fill_u8(state, m, 0, s);
+}
+
+void sel_round(const uint32_t *live, const uint32_t *nlive, uint64_t live_hint, const uint32_t *len,
+               const uint32_t *start, uint32_t *T, int top, uint64_t n, uint8_t *state, uint32_t *live_next,
+               uint32_t *nlive_next, uint32_t *n_undec, hipStream_t s) {
+  fill_u32(T, (uint64_t)(top + 1) * n, 0xFFFFFFFFu, s);
+  hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, live, nlive, len, start, T, n);
+  for (int j = top; j >= 1; j--)
+    hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, T, n, j);
+  hipLaunchKernelGGL(k_sel_decide, grid_for(live_hint, 256, 8192), dim3(256), 0, s, live, nlive, len, start, T,
+                     state, live_next, nlive_next, n_undec);
+}
+
+// Exact sequential completion for whatever is still undecided after the
+// round cap: one thread walks the sorted list with a mark array.
+__global__ void k_sel_paint(const uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
+                            uint8_t *mark) {
+  GRID_STRIDE(k, m) {
+    if (state[k] == 1) {
+      const uint32_t s = start[k], l = len[k];
+      for (uint32_t x = s; x < s + l; x++) mark[x] = 1;
+    }
+  }
+}
+
+__global__ void k_sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
+                                 uint8_t *mark) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (uint64_t k = 0; k < m; k++) {
+    if (state[k] != 0) continue;
+    const uint32_t s = start[k], l = len[k];
+    if (mark[s] || mark[s + l - 1]) { state[k] = 2; continue; }
+    state[k] = 1;
+    for (uint32_t x = s; x < s + l; x++) mark[x] = 1;
+  }
+}
+
+void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m, uint8_t *mark,
+                    uint64_t n, hipStream_t s) {
+  fill_u8(mark, n, 0, s);
+  hipLaunchKernelGGL(k_sel_paint, grid_for(m, 256, 8192), dim3(256), 0, s, state, len, start, m, mark);
+  hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m, mark);
+}
+
+// ---------------------------------------------------------------- output
+__global__ void k_acc_flags(const uint8_t *state, uint64_t m, uint32_t *f) { GRID_STRIDE(k, m) f[k] = state[k] == 1; }
+
+__global__ void k_acc_gather(const uint8_t *state, const uint32_t *pos, uint64_t m, const uint32_t *len,
+                             const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start,
+                             uint32_t *o_id) {
+  GRID_STRIDE(k, m) {
+    if (state[k] == 1) {
+      const uint32_t o = pos[k];
+      o_len[o] = len[k]; o_start[o] = start[k]; o_id[o] = id[k];
+    }
+  }
+}
+
+void gather_accepted(const uint8_t *state, uint64_t m, const uint32_t *len, const uint32_t *start,
+                     const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id, uint32_t *tmp_f,
+                     uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
+  hipLaunchKernelGGL(k_acc_flags, grid_for(m, 256, 8192), dim3(256), 0, s, state, m, tmp_f);
+  scan_excl(tmp_f, tmp_pos, m, tile_tmp, total, s);
+  hipLaunchKernelGGL(k_acc_gather, grid_for(m, 256, 8192), dim3(256), 0, s, state, tmp_pos, m, len, start, id,
+                     o_len, o_start, o_id);
+}
+
+// Occurrence o (in final order: window, then priority) opens a row when its
+// window, length or substring ID differs from occurrence o-1.
+__global__ void k_row_flags(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
+                            const uint32_t *o_id, const uint32_t *wid, uint32_t *f) {
+  GRID_STRIDE(o, a) {
+    const uint32_t c = order ? order[o] : (uint32_t)o;
+    bool nr = (o == 0);
+    if (!nr) {
+      const uint32_t p = order ? order[o - 1] : (uint32_t)(o - 1);
+      nr = o_len[c] != o_len[p] || o_id[c] != o_id[p] ||
+           (wid && wid[o_start[c]] != wid[o_start[p]]);
+    }
+    f[o] = nr ? 1u : 0u;
+  }
+}
+
+struct OutRow { uint32_t start, length, count; };
+struct OutOcc { uint32_t start, length, cand; };
+
+__global__ void k_emit(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
+                       const uint32_t *wid, const uint32_t *wbeg_of_pos, const uint32_t *f, const uint32_t *rowidx,
+                       uint32_t *row_first, OutRow *rows, OutOcc *occ, uint32_t *win_rows) {
+  GRID_STRIDE(o, a) {
+    const uint32_t c = order ? order[o] : (uint32_t)o;
+    const uint32_t r = rowidx[o];
+    const uint32_t st = o_start[c];
+    const uint32_t rel = st - (wbeg_of_pos ? wbeg_of_pos[st] : 0u);
+    if (f[o]) {
+      row_first[r] = (uint32_t)o;
+      rows[r].start = rel;
+      rows[r].length = o_len[c];
+      if (win_rows) atomicAdd(&win_rows[wid ? wid[st] : 0u], 1u);
+    }
+    if (occ) { occ[o].start = rel; occ[o].length = o_len[c]; occ[o].cand = r; }
+  }
+}
+
+__global__ void k_row_counts(const uint32_t *row_first, uint32_t nrows, uint32_t a, OutRow *rows) {
+  GRID_STRIDE(r, nrows) {
+    const uint32_t e = (r + 1 < nrows) ? row_first[r + 1] : a;
+    rows[r].count = e - row_first[r];
+  }
+}
+
+void emit_rows(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
+               const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f, uint32_t *rowidx,
+               uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
+               uint32_t *nrows, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_flags, grid_for(a, 256, 8192), dim3(256), 0, s, order, a, o_len, o_start, o_id, wid, f);
+  scan_excl(f, rowidx, a, tile_tmp, nrows, s);
+  hipLaunchKernelGGL(k_emit, grid_for(a, 256, 8192), dim3(256), 0, s, order, a, o_len, o_start, wid, wbeg, f,
+                     rowidx, row_first, (OutRow *)rows, (OutOcc *)occ, win_rows);
+}
+
+void row_counts(const uint32_t *row_first, uint32_t nrows, uint32_t a, void *rows, hipStream_t s) {
+  if (nrows)
+    hipLaunchKernelGGL(k_row_counts, grid_for(nrows, 256, 8192), dim3(256), 0, s, row_first, nrows, a,
+                       (OutRow *)rows);
+}
+
+}  // namespace apo
+
+namespace apo {
+
+__global__ void k_window_of_occ(const uint32_t *o_start, const uint32_t *wid, uint64_t a, uint32_t *out) {
+  GRID_STRIDE(o, a) out[o] = wid[o_start[o]];
+}
+__global__ void k_iota_n(uint32_t *p, uint64_t n) { GRID_STRIDE(i, n) p[i] = (uint32_t)i; }
+
+void window_of_occ(const uint32_t *o_start, const uint32_t *wid, uint64_t a, uint32_t *out, hipStream_t s) {
+  if (a) hipLaunchKernelGGL(k_window_of_occ, grid_for(a, 256, 8192), dim3(256), 0, s, o_start, wid, a, out);
+}
+void iota_u32(uint32_t *p, uint64_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_iota_n, grid_for(n, 256, 8192), dim3(256), 0, s, p, n);
+}
+
+}  // namespace apo

@@ -156,6 +156,16 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
  * sum over rounds of active suffixes, distinct tokens. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
 
+/* Live timing of one kernel family with HIP events around each of its
+ * launches (on the stream the kernel runs on): tag 1 = the LDS sort-and-regroup
+ * kernel of the suffix-array doubling rounds; 0 = off.  Costs one event pair
+ * per timed launch. */
+int apo_profile_kernel(apo_ctx *ctx, int tag);
+
+/* For the last analysis: number of timed launches that had work, their total
+ * device time (ms) and the number of entries they processed. */
+int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double *total_ms, uint64_t *elems);
+
 /* ---- continuous-batching server ---- */
 
 /* Start the server: up to max_slots analyses in flight on the device at once,

@@ -41,6 +41,8 @@ SIGNATURES = {
     "apo_candidates_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
     "apo_last_stage_ms": (_I, [_P, _P, _I]),
     "apo_last_counters": (_I, [_P, _P, _I]),
+    "apo_profile_kernel": (_I, [_P, _I]),
+    "apo_last_kernel_profile": (_I, [_P, _P, _P, _P]),
     "apo_server_start": (_I, [_P, _U32, _U32]),
     "apo_submit": (_I, [_P, _U32, _P, _U32, _U32, _P]),
     "apo_poll": (_I, [_P, _U64, _P]),
@@ -237,6 +239,16 @@ class Context:
         a = (ctypes.c_uint64 * len(COUNTERS))()
         k = self._lib.apo_last_counters(self._h, a, len(COUNTERS))
         return dict(zip(COUNTERS[:k], list(a)[:k]))
+
+    def profile_kernel(self, tag: int):
+        """Time one kernel family with HIP events (1: LDS sort of the doubling rounds; 0: off)."""
+        _check(self._lib.apo_profile_kernel(self._h, int(tag)), "apo_profile_kernel")
+
+    def kernel_profile(self):
+        la, ms, el = ctypes.c_uint64(0), ctypes.c_double(0), ctypes.c_uint64(0)
+        _check(self._lib.apo_last_kernel_profile(self._h, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(el)),
+               "apo_last_kernel_profile")
+        return {"launches": la.value, "ms": ms.value, "elems": el.value}
 
     # ---------------------------------------------------------- server
     def server_start(self, slots: int = 2, queue_cap: int = 0):

@@ -42,7 +42,8 @@ struct SortCounters {
   uint32_t act_cnt[2];            // active slot list lengths
   uint32_t chunk_total[4];        // chunks per MSD level
   uint32_t err;                   // nonzero: capacity overflow detected on device
-  uint32_t pad[3];
+  uint32_t lds_elems;             // entries sorted by the LDS path this round
+  uint32_t pad[2];
 };
 
 // Pointers of one segmented-sort "engine" (arrays of capacity cap elements).

@@ -351,6 +351,20 @@ extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   return k;
 }
 
+extern "C" int apo_profile_kernel(apo_ctx *ctx, int tag) {
+  if (!ctx || tag < KT_NONE || tag > KT_LDS_SA) return APO_EINVAL;
+  ctx->ws.ktag = tag;
+  return APO_OK;
+}
+
+extern "C" int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double *total_ms, uint64_t *elems) {
+  if (!ctx || !launches || !total_ms || !elems) return APO_EINVAL;
+  *launches = ctx->info.k_launches;
+  *total_ms = ctx->info.k_ms;
+  *elems = ctx->info.k_elems;
+  return APO_OK;
+}
+
 // ===================================================================== server
 // Each slot owns a resident workspace and stream.  A free slot takes every
 // queued request that shares the oldest request's min_len and fits its token

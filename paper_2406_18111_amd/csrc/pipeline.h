@@ -30,7 +30,13 @@ struct RunInfo {
   uint32_t accepted = 0;
   uint32_t rows = 0;
   double stage_ms[kStages] = {0};
+  // live timing of one kernel family (Workspace::ktag), launches with work only
+  uint64_t k_launches = 0, k_elems = 0;
+  double k_ms = 0;
 };
+
+enum KernelTag { KT_NONE = 0, KT_LDS_SA = 1 };
+constexpr int kMaxTimed = 64;
 
 struct Workspace {
   uint64_t capN = 0;
@@ -60,9 +66,15 @@ struct Workspace {
   void *rows = nullptr, *occ = nullptr;
   uint32_t *row_first = nullptr, *rowidx = nullptr;
   uint32_t *dcnt = nullptr;
+  uint32_t *rhist = nullptr;       // per doubling round: active slots, large units after it
+  uint32_t *hrhist = nullptr;      // pinned host mirror of rhist
   uint32_t *hcnt = nullptr;        // pinned host mirror of dcnt
   SortCounters *hctr = nullptr;    // pinned host mirror of engine counters
   hipEvent_t ev[kStages + 1] = {};
+  int ktag = KT_NONE;              // kernel family timed with events around each launch
+  hipEvent_t kev[2 * kMaxTimed] = {};
+  int kround[kMaxTimed] = {0};
+  int kev_n = 0;
 
   static size_t bytes_for(uint64_t N, uint32_t W);
   int ensure(uint64_t N, uint32_t W, size_t budget);

@@ -58,7 +58,11 @@ void Workspace::release() {
   hcnt = nullptr;
   if (hctr) (void)hipHostFree(hctr);
   hctr = nullptr;
+  if (hrhist) (void)hipHostFree(hrhist);
+  hrhist = nullptr;
   for (auto &e : ev)
+    if (e) { (void)hipEventDestroy(e); e = nullptr; }
+  for (auto &e : kev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   capN = 0;
   capW = 0;
@@ -93,6 +97,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_ol = L.take(N_ * 4), o_os = L.take(N_ * 4), o_oi = L.take(N_ * 4);
   size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
   size_t o_cnt = L.take(CNT_COUNT * 4);
+  size_t o_rh = L.take(4 * 64 * 4);
   hipError_t e = hipMalloc(&mem, L.total);
   if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
   bytes = L.total;
@@ -143,11 +148,14 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   row_first = (uint32_t *)(m + o_rf);
   rowidx = (uint32_t *)(m + o_ri);
   dcnt = (uint32_t *)(m + o_cnt);
+  rhist = (uint32_t *)(m + o_rh);
   int rc = eng.alloc(C2);
   if (rc) { release(); return rc; }
   APO_HIP_TRY(hipHostMalloc((void **)&hcnt, CNT_COUNT * 4, hipHostMallocDefault));
   APO_HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(SortCounters), hipHostMallocDefault));
+  APO_HIP_TRY(hipHostMalloc((void **)&hrhist, 4 * 64 * 4, hipHostMallocDefault));
   for (auto &ev_ : ev) APO_HIP_TRY(hipEventCreate(&ev_));
+  for (auto &ev_ : kev) APO_HIP_TRY(hipEventCreate(&ev_));
   APO_HIP_TRY(hipMemset(dcnt, 0, CNT_COUNT * 4));
   capN = N_;
   capW = wantW;
@@ -185,7 +193,7 @@ static int sort_plain(Workspace &w, uint32_t count, const uint32_t *const *field
   for (int L = 0; L < nlevels; L++) {
     const int last = (L == nlevels - 1);
     const uint32_t nb = last ? 0u : (uint32_t)bits[L + 1];
-    E.msd(cur, count, s);
+    if (count > (uint32_t)kLdsTile) E.msd(cur, count, s);
     E.lds_plain(cur, nb, last, keep ? keep : w.keep, count, s);
     E.bulk_plain(cur, nb, last, keep ? keep : w.keep, count, s);
     if (!last) {
@@ -245,30 +253,60 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   stamp(w, 1, s);
 
   // ---- suffix array by prefix doubling
+  // Rounds are launched `spec` at a time and the host reads their outcomes
+  // once per batch.  A round launched after the last active suffix became
+  // unique finds empty lists everywhere and changes nothing, so speculation
+  // never alters the result.  Large units only arise from large units of the
+  // previous round, so once none are left the MSD passes are skipped.
   const uint32_t rank_bits = (uint32_t)bit_length_u64(N);
   int cur = 0;
   E.reset_counters(s);
   E.round_begin(cur, s);
   E.gather_identity(key0, (uint32_t)N, s);
   E.init_units(cur, w.d_off, W, 0, bits0, s);
+  uint64_t maxwin = 0;
+  for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
+  bool big = maxwin > (uint64_t)kLdsTile;
   uint64_t act = N;
-  int r = 0;
-  while (true) {
+  int r = 0, synced = 0, done_round = -1;
+  w.kev_n = 0;
+  int spec = 2;
+  fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
+  while (done_round < 0) {
     if (r >= w.nsnap) return -4;
+    if (r > 0) {
+      E.round_begin(cur, s);
+      E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, s);
+    }
     RankOut R{w.rank, w.snap + (size_t)r * N, w.fin, (uint32_t)r};
-    E.msd(cur, act, s);
+    if (big) E.msd(cur, act, s);
+    const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
+    if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
     E.lds_sa(cur, R, rank_bits, act, s);
+    if (timed) {
+      APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n + 1], s));
+      w.kround[w.kev_n++] = r;
+    }
     E.bulk_sa(cur, R, rank_bits, act, s);
-    if ((rc = read_counters(w, s))) return rc;
-    info.active_sum += act;
-    const uint32_t nxt_act = w.hctr->act_cnt[cur ^ 1];
-    if (nxt_act == 0) break;
+    E.round_end(cur, r, w.rhist, s);
     cur ^= 1;
     r++;
-    E.round_begin(cur, s);
-    E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), nxt_act, s);
-    act = nxt_act;
+    if (r - synced >= spec || r >= w.nsnap) {
+      APO_HIP_TRY(hipMemcpyAsync(w.hrhist, w.rhist, 4 * w.nsnap * 4, hipMemcpyDeviceToHost, s));
+      if ((rc = read_counters(w, s))) return rc;
+      for (int k = synced; k < r; k++) {
+        info.active_sum += (k == 0) ? N : w.hrhist[4 * (k - 1)];
+        if (w.hrhist[4 * k] == 0) { done_round = k; break; }
+      }
+      if (done_round < 0) {
+        act = w.hrhist[4 * (r - 1)];
+        big = w.hrhist[4 * (r - 1) + 1] > 0;
+        synced = r;
+        spec = std::min(spec * 2, 8);
+      }
+    }
   }
+  r = done_round;
   info.rounds = (uint32_t)r + 1;
   APO_HIP_TRY(hipMemcpyAsync(w.sa, B.val[0], N * 4, hipMemcpyDeviceToDevice, s));
   stamp(w, 2, s);
@@ -364,6 +402,15 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   for (int k = 0; k < kStages; k++) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) info.stage_ms[k] = ms;
+  }
+  for (int k = 0; k < w.kev_n; k++) {
+    const uint32_t elems = w.hrhist[4 * w.kround[k] + 2];
+    float ms = 0;
+    if (elems && hipEventElapsedTime(&ms, w.kev[2 * k], w.kev[2 * k + 1]) == hipSuccess) {
+      info.k_launches++;
+      info.k_elems += elems;
+      info.k_ms += ms;
+    }
   }
   return 0;
 }

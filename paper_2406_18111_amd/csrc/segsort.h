@@ -14,6 +14,7 @@ class SortEngine {
 
   void reset_counters(hipStream_t s);
   void round_begin(int cur, hipStream_t s);
+  void round_end(int cur, int r, uint32_t *hist, hipStream_t s);
   void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
                   hipStream_t s);
   void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);

@@ -35,6 +35,17 @@ __global__ void k_round_begin(SortCounters *c, int cur) {
     c->big_cnt[nxt][0] = 0;
     c->bulk_cnt = 0;
     c->act_cnt[nxt] = 0;
+    c->lds_elems = 0;
+  }
+}
+
+// Records the outcome of round `r` (active slots and large units handed to
+// the next round) so the host can read several rounds at once.
+__global__ void k_round_end(const SortCounters *c, int cur, int r, uint32_t *hist) {
+  if (threadIdx.x == 0) {
+    hist[4 * r] = c->act_cnt[cur ^ 1];
+    hist[4 * r + 1] = c->big_cnt[cur ^ 1][0];
+    hist[4 * r + 2] = c->lds_elems;
   }
 }
 
@@ -163,6 +174,11 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
     const Unit *src = B.cls[cur] + B.cls_off[ci] + first;
     for (uint32_t j = tid; j < nb; j += NT) ud[j] = src[j];
     __syncthreads();
+    if (tid == 0) {
+      uint32_t tot = 0;
+      for (uint32_t j = 0; j < nb; j++) tot += ud[j].len & ~kBufBit;
+      atomicAdd(&B.ctr->lds_elems, tot);
+    }
 
     // load (key, val) pairs; pad with all-ones
     for (int s = tid; s < kLdsTile; s += NT) {
@@ -577,6 +593,10 @@ void SortEngine::reset_counters(hipStream_t s) {
 
 void SortEngine::round_begin(int cur, hipStream_t s) {
   hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(64), 0, s, b_.ctr, cur);
+}
+
+void SortEngine::round_end(int cur, int r, uint32_t *hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_end, dim3(1), dim3(64), 0, s, b_.ctr, cur, r, hist);
 }
 
 void SortEngine::init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base,

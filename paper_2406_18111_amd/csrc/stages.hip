@@ -582,7 +582,7 @@ __global__ void k_emit(const uint32_t *order, uint64_t a, const uint32_t *o_len,
                        uint32_t *row_first, OutRow *rows, OutOcc *occ, uint32_t *win_rows) {
   GRID_STRIDE(o, a) {
     const uint32_t c = order ? order[o] : (uint32_t)o;
-    const uint32_t r = rowidx[o];
+    const uint32_t r = rowidx[o] + f[o] - 1u;  // row of this occurrence (inclusive count - 1)
     const uint32_t st = o_start[c];
     const uint32_t rel = st - (wbeg_of_pos ? wbeg_of_pos[st] : 0u);
     if (f[o]) {

@@ -1,0 +1,153 @@
+"""Batched and served analyses: each window's result is identical alone, in a
+batch, and in the server mix (exact, integer results), and matches the oracle."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_18111_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2406_18111_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _rows_ref(t, m):
+    r = oracle.find_repeats(t, m)
+    return np.stack([r["row_start"], r["row_len"], r["row_count"]], 1).astype(np.int64).reshape(-1, 3)
+
+
+def _as3(rows):
+    return np.stack([rows["start"], rows["length"], rows["count"]], 1).astype(np.int64).reshape(-1, 3)
+
+
+def _pack(wins):
+    off = np.zeros(len(wins) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(w) for w in wins])
+    toks = np.concatenate(wins).astype(np.uint64) if wins else np.zeros(0, np.uint64)
+    return toks, off
+
+
+def _mixed_windows(seed, count):
+    rng = np.random.default_rng(seed)
+    wins = []
+    for k in range(count):
+        kind = k % 5
+        L = int(rng.choice([0, 1, 2, 3, 100, 4095, 4096, 4097, 9000, 30000]))
+        if kind == 0:
+            w = rng.integers(0, 3, L)
+        elif kind == 1:
+            w = np.full(L, 5)
+        elif kind == 2:
+            w = synth.loop_stream(int(rng.integers(1 << 30)), L, int(rng.integers(10, 60)), 64, 0.05) if L else np.zeros(0)
+        elif kind == 3:
+            w = np.tile(np.arange(7), L // 7 + 1)[:L]
+        else:
+            w = rng.integers(0, 1 << 40, L)
+        wins.append(np.asarray(w, dtype=np.uint64))
+    return wins
+
+
+def test_batch_equals_alone_and_oracle(ctx):
+    wins = _mixed_windows(5, 40)
+    toks, off = _pack(wins)
+    for m in (1, 4, 8):
+        print("batch min_len", m, flush=True)
+        rows, oo = ctx.analyze_batch(toks, off, m)
+        for w, win in enumerate(wins):
+            got = _as3(rows[int(oo[w]):int(oo[w + 1])])
+            alone = _as3(ctx.analyze(win, m))
+            assert np.array_equal(got, alone), (w, len(win))
+            assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
+
+
+def test_batch_device_api(ctx):
+    import torch
+    wins, m = synth.config3(num_windows=24)
+    toks, off = _pack(wins)
+    dev = torch.from_numpy(toks.view(np.int64)).cuda()
+    rows_d, oo_d = ctx.analyze_batch_dev(dev, off, m)
+    rows_h, oo_h = ctx.analyze_batch(toks, off, m)
+    assert np.array_equal(oo_d, oo_h)
+    assert np.array_equal(rows_d.cpu().numpy().astype(np.int64), _as3(rows_h))
+    for w, win in enumerate(wins):
+        assert np.array_equal(_as3(rows_h[int(oo_h[w]):int(oo_h[w + 1])]), _rows_ref(win, m))
+
+
+def test_config3_full_batch_sampled(ctx):
+    """All 4096 windows of the batched workload in one call; 48 sampled windows
+    checked against the oracle and against their own single-window analysis."""
+    wins, m = synth.config3()
+    toks, off = _pack(wins)
+    print("config3 tokens", len(toks), flush=True)
+    rows, oo = ctx.analyze_batch(toks, off, m)
+    rng = np.random.default_rng(11)
+    sample = sorted(set(rng.integers(0, len(wins), 44).tolist()) | {0, len(wins) - 1,
+                    int(np.argmax([len(w) for w in wins])), int(np.argmin([len(w) for w in wins]))})
+    for w in sample:
+        got = _as3(rows[int(oo[w]):int(oo[w + 1])])
+        assert np.array_equal(got, _rows_ref(wins[w], m)), w
+        assert np.array_equal(got, _as3(ctx.analyze(wins[w], m))), w
+
+
+def test_server_mix_equals_alone(ctx):
+    from paper_2406_18111_amd import Context
+    reqs = list(synth.config4_trace(duration=0.03, hi=1 << 16))
+    reqs += [synth.Request(0.0, 0, np.zeros(0, np.uint64)), synth.Request(0.0, 0, np.array([3], np.uint64))]
+    with Context(0) as srv:
+        srv.server_start(slots=3)
+        tickets = []
+        for i, r in enumerate(reqs):
+            m = 16 if i % 3 else 8  # two min lengths in flight at once
+            tickets.append((srv.submit(r.tokens, m, r.stream), r.tokens, m))
+        results = []
+        deadline = time.time() + 120
+        pending = list(tickets)
+        while pending and time.time() < deadline:
+            nxt = []
+            for tk, toks, m in pending:
+                got = srv.fetch(tk)
+                if got is None:
+                    nxt.append((tk, toks, m))
+                else:
+                    results.append((got[0], toks, m, got[1]))
+            pending = nxt
+            time.sleep(0.002)
+        assert not pending
+        srv.server_stop()
+    for rows, toks, m, lat in results:
+        assert lat >= 0
+        assert np.array_equal(_as3(rows), _as3(ctx.analyze(toks, m)))
+    for rows, toks, m, _ in results[:10]:
+        assert np.array_equal(_as3(rows), _rows_ref(toks, m))
+
+
+def test_server_errors(ctx):
+    from paper_2406_18111_amd import ApoError, Context
+    from paper_2406_18111_amd import _lib
+    with Context(0) as srv:
+        with pytest.raises(ApoError):
+            srv.submit(np.arange(10, dtype=np.uint64), 2)  # server not started
+        srv.server_start(slots=1)
+        with pytest.raises(ApoError) as e:
+            srv.fetch(987654)
+        assert e.value.code == _lib.APO_ENOTFOUND
+        tk = srv.submit(np.tile(np.arange(5, dtype=np.uint64), 400), 2)
+        t0 = time.time()
+        got = None
+        while got is None and time.time() - t0 < 60:
+            got = srv.fetch(tk, cap=0)  # too small at first: binding retries with the needed size
+            time.sleep(0.001)
+        assert got is not None and len(got[0]) >= 1
+        srv.server_stop()
+        with pytest.raises(ApoError):
+            srv.submit(np.arange(10, dtype=np.uint64), 2)

@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps, no baseline (for profilers)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 4096-window batch: one packed launch sequence vs per-window calls")
+    ap.add_argument("--serve", action="store_true",
+                    help="also replay the Poisson serving trace through the server and the plain FIFO path")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-slots", type=int, default=3)
     return ap.parse_args()
 
 
@@ -71,6 +77,118 @@ def cpu_baseline(t, m, seconds):
             break
     return {"value": reps * len(t) / el, "unit": "tokens/s", "cores": 1, "kind": "oracle",
             "sample": "%d full analyses of the same window by the single-threaded C oracle (%.1f s)" % (reps, el)}
+
+
+def batched_leg(ctx, reps=3):
+    """4096 windows (log-uniform 256..65536, loop bodies 10..500, alphabet 2^12,
+    5% substitutions, min_len 8): one packed launch sequence vs one plain
+    per-window analysis per window, tokens resident on the device."""
+    import torch
+    from paper_2406_18111_amd import synth
+    wins, m = synth.config3()
+    off = np.zeros(len(wins) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(w) for w in wins])
+    toks = np.concatenate(wins)
+    dev = torch.from_numpy(toks.view(np.int64)).cuda()
+    total = int(off[-1])
+    ctx.analyze_batch_dev(dev, off, m)  # warm-up (workspace growth)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rows, oo = ctx.analyze_batch_dev(dev, off, m)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    views = [dev[int(off[w]):int(off[w + 1])] for w in range(len(wins))]
+    ctx.analyze_dev(views[0], m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrows = 0
+    for v in views:
+        r, _ = ctx.analyze_dev(v, m)
+        nrows += int(r.shape[0])
+    torch.cuda.synchronize()
+    tw = time.perf_counter() - t0
+    return {"workload": "config3", "windows": len(wins), "tokens": total, "min_len": m,
+            "batched_tokens_per_s": total / tb, "batched_ms": tb * 1e3,
+            "per_window_tokens_per_s": total / tw, "per_window_ms": tw * 1e3,
+            "speedup": tw / tb, "rows": int(oo[-1]), "rows_per_window_path": nrows}
+
+
+def serve_leg(seconds, slots):
+    """Open-loop replay of the serving trace (64 nested-loop streams, Poisson
+    arrivals at 2000/s, windows log-uniform 1024..2^20, min_len 16): the
+    continuous-batching server vs the plain one-window-at-a-time FIFO path."""
+    import threading
+    import torch
+    from paper_2406_18111_amd import Context, synth
+    reqs = list(synth.config4_trace(duration=seconds))
+    offered = sum(len(r.tokens) for r in reqs)
+
+    def replay_server():
+        srv = Context(0)
+        srv.server_start(slots=slots)
+        # warm the slots' workspaces
+        for r in reqs[: slots * 2]:
+            tk = srv.submit(r.tokens, 16, r.stream)
+            while srv.fetch(tk) is None:
+                time.sleep(0.0005)
+        lat = [None] * len(reqs)
+        done_t = [0.0] * len(reqs)
+        tickets = [None] * len(reqs)
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, r in enumerate(reqs):
+                now = time.perf_counter() - t0
+                if r.arrival > now:
+                    time.sleep(r.arrival - now)
+                tickets[i] = srv.submit(r.tokens, 16, r.stream)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        pending = set()
+        i_next = 0
+        while i_next < len(reqs) or pending:
+            while i_next < len(reqs) and tickets[i_next] is not None:
+                pending.add(i_next)
+                i_next += 1
+            for i in list(pending):
+                got = srv.fetch(tickets[i])
+                if got is not None:
+                    lat[i] = got[1]
+                    done_t[i] = time.perf_counter() - t0
+                    pending.discard(i)
+            time.sleep(0.0002)
+        th.join()
+        srv.server_stop()
+        srv.close()
+        span = max(done_t) - reqs[0].arrival
+        return lat, span
+
+    def replay_fifo():
+        ctx = Context(0)
+        ctx.analyze(reqs[0].tokens, 16)
+        lat = []
+        t0 = time.perf_counter()
+        last = 0.0
+        for r in reqs:
+            now = time.perf_counter() - t0
+            if r.arrival > now:
+                time.sleep(r.arrival - now)
+            ctx.analyze(r.tokens, 16)
+            last = time.perf_counter() - t0
+            lat.append(last - r.arrival)
+        ctx.close()
+        return lat, last - reqs[0].arrival
+
+    out = {"workload": "config4", "requests": len(reqs), "trace_seconds": seconds,
+           "offered_tokens_per_s": offered / seconds, "slots": slots}
+    for name, fn in (("server", replay_server), ("fifo", replay_fifo)):
+        lat, span = fn()
+        lat = np.array(lat, dtype=np.float64)
+        out[name] = {"tokens_per_s": offered / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3), "span_s": span}
+    return out
 
 
 def main():
@@ -138,6 +256,10 @@ def main():
                            "kernel": "k_lds_sort<MODE_SA> (doubling rounds)",
                            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
                            "launches_per_step": kprof["launches"] / steps}
+    if args.batched and not args.profile_steps:
+        out["batched"] = batched_leg(ctx)
+    if args.serve and not args.profile_steps:
+        out["serving"] = serve_leg(args.serve_seconds, args.serve_slots)
     if not args.profile_steps and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(t, m, args.cpu_seconds)
     print(json.dumps(out), flush=True)

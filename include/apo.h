@@ -166,6 +166,25 @@ int apo_profile_kernel(apo_ctx *ctx, int tag);
  * device time (ms) and the number of entries they processed. */
 int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double *total_ms, uint64_t *elems);
 
+/* ---- autotuning of kernel parameters ---- */
+
+/* Times every (LDS sort tile 2^11..2^13, MSD digit width 8/10/11/12) pair on
+ * the device window d_tokens (median of `reps` runs after one warm-up) and
+ * keeps the fastest for windows of the same size bucket (ceil(log2 n)); later
+ * analyses, batches and server slots use the nearest tuned bucket.  Outputs
+ * (nullable) receive the chosen pair and its median time in ms.  Parameters
+ * change speed only, never results. */
+int apo_tune(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t min_len, int reps,
+             int *best_tile_log, int *best_digit_bits, double *best_ms);
+
+/* Fix the pair for all sizes (tile_log 11..13, digit_bits 8..12); negative
+ * values return to the tuned table. */
+int apo_set_params(apo_ctx *ctx, int tile_log, int digit_bits);
+
+/* Persist / restore the tuned table (text: "log2n tile_log digit_bits" lines). */
+int apo_tune_save(apo_ctx *ctx, const char *path);
+int apo_tune_load(apo_ctx *ctx, const char *path);
+
 /* ---- continuous-batching server ---- */
 
 /* Start the server: up to max_slots analyses in flight on the device at once,

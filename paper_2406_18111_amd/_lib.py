@@ -43,6 +43,10 @@ SIGNATURES = {
     "apo_last_counters": (_I, [_P, _P, _I]),
     "apo_profile_kernel": (_I, [_P, _I]),
     "apo_last_kernel_profile": (_I, [_P, _P, _P, _P]),
+    "apo_tune": (_I, [_P, _P, _I, _U32, _U32, _I, _P, _P, _P]),
+    "apo_set_params": (_I, [_P, _I, _I]),
+    "apo_tune_save": (_I, [_P, ctypes.c_char_p]),
+    "apo_tune_load": (_I, [_P, ctypes.c_char_p]),
     "apo_server_start": (_I, [_P, _U32, _U32]),
     "apo_submit": (_I, [_P, _U32, _P, _U32, _U32, _P]),
     "apo_poll": (_I, [_P, _U64, _P]),
@@ -249,6 +253,24 @@ class Context:
         _check(self._lib.apo_last_kernel_profile(self._h, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(el)),
                "apo_last_kernel_profile")
         return {"launches": la.value, "ms": ms.value, "elems": el.value}
+
+    # ------------------------------------------------------- autotuner
+    def tune(self, tokens, min_len: int, reps: int = 3):
+        """Autotune (LDS tile, digit width) on a device window; returns (tile_log, digit_bits, ms)."""
+        bits = 64 if tokens.element_size() == 8 else 32
+        t, d, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        _check(self._lib.apo_tune(self._h, _dev_ptr(tokens), bits, tokens.numel(), int(min_len), int(reps),
+                                  ctypes.byref(t), ctypes.byref(d), ctypes.byref(ms)), "apo_tune")
+        return t.value, d.value, ms.value
+
+    def set_params(self, tile_log: int, digit_bits: int):
+        _check(self._lib.apo_set_params(self._h, int(tile_log), int(digit_bits)), "apo_set_params")
+
+    def tune_save(self, path: str):
+        _check(self._lib.apo_tune_save(self._h, path.encode()), "apo_tune_save")
+
+    def tune_load(self, path: str):
+        _check(self._lib.apo_tune_load(self._h, path.encode()), "apo_tune_load")
 
     # ---------------------------------------------------------- server
     def server_start(self, slots: int = 2, queue_cap: int = 0):

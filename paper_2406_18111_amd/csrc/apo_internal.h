@@ -8,13 +8,16 @@
 namespace apo {
 
 // ---------------------------------------------------------------- tuning
-constexpr int kLdsTileLog = 12;             // LDS sort tile: 4096 64-bit entries (32 KB)
-constexpr int kLdsTile = 1 << kLdsTileLog;
-constexpr int kClasses = kLdsTileLog;       // size class c holds units of length (2^(c-1), 2^c]
+// The LDS sort tile (2^tile_log 64-bit entries) and the MSD digit width are
+// chosen per run (defaults below, or the autotuner's table).
+constexpr int kMinTileLog = 11, kMaxTileLog = 13, kDefaultTileLog = 12;
+constexpr int kClasses = kMaxTileLog;       // size class c holds units of length (2^(c-1), 2^c]
 constexpr int kLdsThreads = 256;
-constexpr int kDigitBits = 11;              // MSD bucket pass digit width
-constexpr int kBins = 1 << kDigitBits;
-constexpr int kChunk = 8192;                // elements per workgroup in MSD passes
+constexpr int kMinDigitBits = 8, kMaxDigitBits = 12, kDefaultDigitBits = 11;
+constexpr int kBins = 1 << kMaxDigitBits;   // histogram stride per large unit
+constexpr int kMaxMsdLevels = 4;            // 32-bit keys / 8-bit digits
+constexpr int kMsdLists = kMaxMsdLevels + 1;
+constexpr int kChunk = 8192;                // elements per workgroup in MSD / bulk passes
 constexpr int kMaxRounds = 32;              // doubling rounds (n <= 2^26 needs <= 28)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kBufBit = 0x80000000u;   // unit data lives in the alternate buffer
@@ -25,25 +28,27 @@ struct Unit {
   uint32_t len;     // low 31 bits length, top bit = alternate buffer
 };
 
-// Large unit for MSD bucketing passes.
+// Large unit for MSD bucketing passes.  Units of one list are appended with a
+// packed (units << 32 | chunks) atomic, so chunk bases grow with the unit
+// index and a chunk finds its unit by binary search.
 struct BigUnit {
   uint32_t start;
   uint32_t len;
-  uint32_t bits;    // key bits still unsorted (from the top)
-  uint32_t flags;   // bit0: data in alternate buffer, bit1: skip scatter (single bucket)
+  uint32_t cbase;   // index of the unit's first kChunk-sized chunk in its list
+  uint32_t meta;    // bits 0-7: key bits still unsorted (from the top);
+                    // bit 8: data in the alternate buffer; bit 9: skip scatter
 };
+constexpr uint32_t kMetaAlt = 1u << 8, kMetaSkip = 1u << 9;
 
 // Device-side counters of one segmented-sort level/round.  Lives in device
 // memory; the host reads it back between rounds.
 struct SortCounters {
-  uint32_t cls_cnt[2][kClasses];  // per class unit counts, [list][class]
-  uint32_t big_cnt[2][4];         // large units: [list][level]  (level 0 = from previous round)
-  uint32_t bulk_cnt;              // units with all key bits consumed (single group)
-  uint32_t act_cnt[2];            // active slot list lengths
-  uint32_t chunk_total[4];        // chunks per MSD level
-  uint32_t err;                   // nonzero: capacity overflow detected on device
-  uint32_t lds_elems;             // entries sorted by the LDS path this round
-  uint32_t pad[2];
+  unsigned long long big_pk[2][kMsdLists];  // large units [list][level]: (units << 32) | chunks
+  unsigned long long bulk_pk;       // single-group units of this round, packed likewise
+  uint32_t cls_cnt[2][kClasses];    // per class unit counts, [list][class]
+  uint32_t act_cnt[2];              // active slot list lengths
+  uint32_t err;                     // nonzero: capacity overflow detected on device
+  uint32_t lds_elems;               // entries sorted by the LDS path this round
 };
 
 // Pointers of one segmented-sort "engine" (arrays of capacity cap elements).
@@ -52,12 +57,13 @@ struct SortBufs {
   uint32_t *val[2];
   Unit *cls[2];         // class lists, [list] each with per-class regions
   uint32_t cls_off[kClasses + 1];   // region offsets (in units) within one list
-  BigUnit *big[2][4];   // [list][level]
+  BigUnit *big[2][kMsdLists];   // [list][level]
   uint32_t big_cap;
   BigUnit *bulk;
+  uint32_t tile_log;    // LDS tile = 2^tile_log entries
+  uint32_t digit_bits;  // MSD digit width
   uint32_t *hist;       // big_cap * kBins
   uint32_t *cursor;     // big_cap * kBins
-  uint32_t *chunk_base; // big_cap + 1
   uint32_t *act[2];
   SortCounters *ctr;
   uint64_t cap;

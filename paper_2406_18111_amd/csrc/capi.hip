@@ -2,7 +2,10 @@
 // buffers, and the continuous-batching server.
 #include "apo.h"
 #include "pipeline.h"
+#include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <map>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -34,6 +37,31 @@ struct Slot {
   uint64_t pinned_cap = 0;
 };
 
+// Autotuned kernel parameters per input-size bucket (ceil(log2 n)).
+struct TuneTable {
+  std::map<int, std::pair<int, int>> best;  // bucket -> (tile_log, digit_bits)
+  int fixed_tile = -1, fixed_digit = -1;     // manual override when >= 0
+  void pick(uint64_t n, int &tile, int &digit) const {
+    tile = kDefaultTileLog;
+    digit = kDefaultDigitBits;
+    if (fixed_tile >= 0) {
+      tile = fixed_tile;
+      digit = fixed_digit;
+      return;
+    }
+    if (best.empty()) return;
+    const int b = ceil_log2_u64(std::max<uint64_t>(n, 2));
+    auto it = best.lower_bound(b);  // nearest tuned bucket
+    if (it == best.end()) it = std::prev(best.end());
+    else if (it->first != b && it != best.begin()) {
+      auto lo = std::prev(it);
+      if (b - lo->first < it->first - b) it = lo;
+    }
+    tile = it->second.first;
+    digit = it->second.second;
+  }
+};
+
 struct Server {
   std::mutex mu;
   std::condition_variable cv_work;
@@ -46,6 +74,7 @@ struct Server {
   size_t slot_budget = 0;
   bool stopping = false;
   int device = 0;
+  TuneTable tune;
   std::atomic<uint64_t> batches{0}, windows{0};
 };
 
@@ -57,6 +86,7 @@ struct apo_ctx {
   hipStream_t stream = nullptr;
   apo::Workspace ws;
   apo::RunInfo info;
+  apo::TuneTable tune;
   std::unique_ptr<apo::Server> server;
 };
 
@@ -121,6 +151,9 @@ static int run_ctx(apo_ctx *c, const void *d_tok, int bits, uint32_t n, uint32_t
   int rc = c->ws.ensure(n, 1, c->budget);
   if (rc) return map_rc(rc);
   const uint64_t off[2] = {0, n};
+  int tl, db;
+  c->tune.pick(n, tl, db);
+  c->ws.eng.set_params(tl, db);
   rc = run_pipeline(c->ws, d_tok, bits, n, off, 1, min_len, stop, s, c->info);
   return map_rc(rc);
 }
@@ -212,6 +245,9 @@ static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
   for (uint32_t w = 0; w <= W; w++) norm[w] = off[w] - off[0];
   int rc = ctx->ws.ensure(std::max<uint64_t>(total, 2), W, ctx->budget);
   if (rc) return map_rc(rc);
+  int tl, db;
+  ctx->tune.pick(total, tl, db);
+  ctx->ws.eng.set_params(tl, db);
   rc = run_pipeline(ctx->ws, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info);
   return map_rc(rc);
 }
@@ -365,6 +401,86 @@ extern "C" int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double 
   return APO_OK;
 }
 
+// ================================================================== autotuner
+// Times every (LDS tile, digit width) pair on the caller's window and keeps the
+// fastest for the window's size bucket.  Results never depend on the choice.
+extern "C" int apo_tune(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t min_len, int reps,
+                        int *best_tile_log, int *best_digit_bits, double *best_ms) {
+  if (!ctx || !d_tokens || n < 2 || n > APO_MAX_N || min_len == 0 || (token_bits != 32 && token_bits != 64))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  reps = std::max(1, std::min(reps, 50));
+  int rc = ctx->ws.ensure(n, 1, ctx->budget);
+  if (rc) return map_rc(rc);
+  const uint64_t off[2] = {0, n};
+  double best = 1e30;
+  int bt = kDefaultTileLog, bd = kDefaultDigitBits;
+  for (int tl = kMinTileLog; tl <= kMaxTileLog; tl++) {
+    for (int db : {8, 10, 11, 12}) {
+      ctx->ws.eng.set_params(tl, db);
+      std::vector<double> t;
+      for (int k = 0; k <= reps; k++) {
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = map_rc(run_pipeline(ctx->ws, d_tokens, token_bits, n, off, 1, min_len, Stop::FULL, ctx->stream,
+                                 ctx->info));
+        if (rc) return rc;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (k > 0) t.push_back(ms);
+      }
+      std::sort(t.begin(), t.end());
+      const double med = t[t.size() / 2];
+      if (med < best) { best = med; bt = tl; bd = db; }
+    }
+  }
+  ctx->tune.best[ceil_log2_u64(n)] = {bt, bd};
+  if (best_tile_log) *best_tile_log = bt;
+  if (best_digit_bits) *best_digit_bits = bd;
+  if (best_ms) *best_ms = best;
+  return APO_OK;
+}
+
+extern "C" int apo_set_params(apo_ctx *ctx, int tile_log, int digit_bits) {
+  if (!ctx) return APO_EINVAL;
+  if (tile_log < 0 || digit_bits < 0) {
+    ctx->tune.fixed_tile = ctx->tune.fixed_digit = -1;
+    return APO_OK;
+  }
+  if (tile_log < kMinTileLog || tile_log > kMaxTileLog || digit_bits < kMinDigitBits || digit_bits > kMaxDigitBits)
+    return APO_EINVAL;
+  ctx->tune.fixed_tile = tile_log;
+  ctx->tune.fixed_digit = digit_bits;
+  return APO_OK;
+}
+
+extern "C" int apo_tune_save(apo_ctx *ctx, const char *path) {
+  if (!ctx || !path) return APO_EINVAL;
+  FILE *f = fopen(path, "w");
+  if (!f) return APO_EINVAL;
+  fprintf(f, "# log2n tile_log digit_bits\n");
+  for (auto &kv : ctx->tune.best) fprintf(f, "%d %d %d\n", kv.first, kv.second.first, kv.second.second);
+  fclose(f);
+  return APO_OK;
+}
+
+extern "C" int apo_tune_load(apo_ctx *ctx, const char *path) {
+  if (!ctx || !path) return APO_EINVAL;
+  FILE *f = fopen(path, "r");
+  if (!f) return APO_EINVAL;
+  char line[256];
+  TuneTable t = ctx->tune;
+  t.best.clear();
+  while (fgets(line, sizeof line, f)) {
+    int b, tl, db;
+    if (line[0] == '#') continue;
+    if (sscanf(line, "%d %d %d", &b, &tl, &db) == 3 && b >= 1 && b <= 40 && tl >= kMinTileLog &&
+        tl <= kMaxTileLog && db >= kMinDigitBits && db <= kMaxDigitBits)
+      t.best[b] = {tl, db};
+  }
+  fclose(f);
+  ctx->tune = t;
+  return APO_OK;
+}
+
 // ===================================================================== server
 // Each slot owns a resident workspace and stream.  A free slot takes every
 // queued request that shares the oldest request's min_len and fits its token
@@ -422,8 +538,13 @@ static void slot_loop(Server *S, Slot *sl) {
     if (!rc && total >= 2) {
       if (hipMemcpyAsync(sl->ws.tok64, sl->pinned, total * 8, hipMemcpyHostToDevice, sl->stream) != hipSuccess)
         rc = APO_EDEVICE;
-      if (!rc) rc = map_rc(run_pipeline(sl->ws, sl->ws.tok64, 64, total, off.data(), W, batch[0]->min_len, Stop::FULL,
-                                        sl->stream, info));
+      if (!rc) {
+        int tl, db;
+        S->tune.pick(total, tl, db);
+        sl->ws.eng.set_params(tl, db);
+        rc = map_rc(run_pipeline(sl->ws, sl->ws.tok64, 64, total, off.data(), W, batch[0]->min_len, Stop::FULL,
+                                 sl->stream, info));
+      }
       if (!rc) {
         std::vector<uint32_t> cnt(W, 0);
         if (W > 1 && info.rows) {
@@ -463,6 +584,7 @@ extern "C" int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue
   if (set_dev(ctx)) return APO_EDEVICE;
   auto S = std::make_unique<Server>();
   S->device = ctx->device;
+  S->tune = ctx->tune;
   S->queue_cap = queue_cap ? queue_cap : 65536;
   // per-slot memory share; token budget = largest N whose workspace fits
   size_t budget = ctx->budget;

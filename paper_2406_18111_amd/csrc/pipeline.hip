@@ -46,7 +46,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   size_t b = 0;
   b += N * 8 + N * 4 * 8 + hc * 8 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
   b += C2 * (4 * 8 + 2) + (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
-  b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / kLdsTile + 64) * (kBins * 8 + 8 * 16);  // sort engine
+  b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
 }
 
@@ -193,7 +193,7 @@ static int sort_plain(Workspace &w, uint32_t count, const uint32_t *const *field
   for (int L = 0; L < nlevels; L++) {
     const int last = (L == nlevels - 1);
     const uint32_t nb = last ? 0u : (uint32_t)bits[L + 1];
-    if (count > (uint32_t)kLdsTile) E.msd(cur, count, s);
+    if (count > (1u << E.tile_log())) E.msd(cur, count, bits[L], s);
     E.lds_plain(cur, nb, last, keep ? keep : w.keep, count, s);
     E.bulk_plain(cur, nb, last, keep ? keep : w.keep, count, s);
     if (!last) {
@@ -266,11 +266,11 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   E.init_units(cur, w.d_off, W, 0, bits0, s);
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
-  bool big = maxwin > (uint64_t)kLdsTile;
+  bool big = maxwin > (1ull << E.tile_log());
   uint64_t act = N;
   int r = 0, synced = 0, done_round = -1;
   w.kev_n = 0;
-  int spec = 2;
+  const int spec = 4;
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
@@ -279,7 +279,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, s);
     }
     RankOut R{w.rank, w.snap + (size_t)r * N, w.fin, (uint32_t)r};
-    if (big) E.msd(cur, act, s);
+    if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rank_bits, s);
     const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
     if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
     E.lds_sa(cur, R, rank_bits, act, s);
@@ -302,7 +302,6 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
         act = w.hrhist[4 * (r - 1)];
         big = w.hrhist[4 * (r - 1) + 1] > 0;
         synced = r;
-        spec = std::min(spec * 2, 8);
       }
     }
   }

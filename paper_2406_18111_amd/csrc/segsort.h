@@ -13,6 +13,9 @@ class SortEngine {
   size_t bytes() const { return bytes_; }
 
   void reset_counters(hipStream_t s);
+  void set_params(int tile_log, int digit_bits);
+  int tile_log() const { return (int)b_.tile_log; }
+  int digit_bits() const { return (int)b_.digit_bits; }
   void round_begin(int cur, hipStream_t s);
   void round_end(int cur, int r, uint32_t *hist, hipStream_t s);
   void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
@@ -23,7 +26,7 @@ class SortEngine {
   void gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c, uint32_t hint,
                     hipStream_t s);
   void iota_val(uint32_t n, hipStream_t s);
-  void msd(int cur, uint64_t work_hint, hipStream_t s);
+  void msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s);
   void lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s);
   void lds_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep, uint64_t work_hint,
                  hipStream_t s);

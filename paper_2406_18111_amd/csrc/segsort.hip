@@ -8,9 +8,9 @@
 // membership, and the final order is fully determined once all groups are
 // singletons or exact duplicates.
 //
-// Units of length <= kLdsTile are sorted in LDS by bitonic networks (one
-// workgroup sorts 2^(12-c) units of class c side by side).  Longer units are
-// split by MSD bucketing passes on kDigitBits-bit digits (histogram, scan,
+// Units of length <= 2^tile_log are sorted in LDS by bitonic networks (one
+// workgroup sorts 2^(tile_log-c) units of class c side by side).  Longer units
+// are split by MSD bucketing passes on digit_bits-bit digits (histogram, scan,
 // scatter into the alternate buffer) until the pieces fit the LDS path or all
 // key bits are consumed (the piece then is one group).
 #include "apo_internal.h"
@@ -27,26 +27,51 @@ __global__ void k_round_begin(SortCounters *c, int cur) {
   const int nxt = cur ^ 1;
   const int t = threadIdx.x;
   if (t < kClasses) c->cls_cnt[nxt][t] = 0;
-  if (t < 4) {
-    c->chunk_total[t] = 0;
-    if (t >= 1) c->big_cnt[cur][t] = 0;
-  }
+  if (t >= 1 && t < kMsdLists) c->big_pk[cur][t] = 0;
   if (t == 0) {
-    c->big_cnt[nxt][0] = 0;
-    c->bulk_cnt = 0;
+    c->big_pk[nxt][0] = 0;
+    c->bulk_pk = 0;
     c->act_cnt[nxt] = 0;
     c->lds_elems = 0;
   }
 }
 
 // Records the outcome of round `r` (active slots and large units handed to
-// the next round) so the host can read several rounds at once.
+// the next round, entries sorted in LDS) so the host can read several rounds
+// at once.
 __global__ void k_round_end(const SortCounters *c, int cur, int r, uint32_t *hist) {
   if (threadIdx.x == 0) {
     hist[4 * r] = c->act_cnt[cur ^ 1];
-    hist[4 * r + 1] = c->big_cnt[cur ^ 1][0];
+    hist[4 * r + 1] = (uint32_t)(c->big_pk[cur ^ 1][0] >> 32);
     hist[4 * r + 2] = c->lds_elems;
   }
+}
+
+__device__ __forceinline__ uint32_t chunks_of(uint32_t len) { return (len + kChunk - 1) / kChunk; }
+
+// Appends one large unit to a list with its chunk base.
+__device__ __forceinline__ void append_big(BigUnit *list, unsigned long long *pk, uint32_t cap, uint32_t start,
+                                           uint32_t len, uint32_t meta, uint32_t *err) {
+  const unsigned long long old = atomicAdd(pk, (1ull << 32) | chunks_of(len));
+  const uint32_t k = (uint32_t)(old >> 32);
+  if (k < cap) list[k] = BigUnit{start, len, (uint32_t)old, meta};
+  else atomicOr(err, 2u);
+}
+
+// Number of units of a list (clamped to its capacity) and of their chunks.
+__device__ __forceinline__ void list_size(unsigned long long pk, uint32_t cap, uint32_t &units, uint32_t &chunks) {
+  units = min((uint32_t)(pk >> 32), cap);
+  chunks = (uint32_t)pk;
+}
+
+// Largest u < units with U[u].cbase <= ch.
+__device__ __forceinline__ uint32_t find_unit(const BigUnit *U, uint32_t units, uint32_t ch) {
+  uint32_t lo = 0, hi = units;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (U[mid].cbase <= ch) lo = mid; else hi = mid;
+  }
+  return lo;
 }
 
 __global__ void k_counters_reset(SortCounters *c) {
@@ -65,16 +90,14 @@ __global__ void k_init_units(SortBufs B, int cur, const uint64_t *off, uint32_t 
   const uint32_t s = (uint32_t)(off[w] - off[0]) + base;
   const uint32_t len = (uint32_t)(off[w + 1] - off[w]);
   if (len == 0) return;
-  if (len <= (uint32_t)kLdsTile) {
+  if (len <= (1u << B.tile_log)) {
     const int ci = class_of(len);
     const uint32_t k = atomicAdd(&B.ctr->cls_cnt[cur][ci], 1u);
     const uint32_t capc = B.cls_off[ci + 1] - B.cls_off[ci];
     if (k >= capc) { atomicOr(&B.ctr->err, 1u); return; }
     B.cls[cur][B.cls_off[ci] + k] = Unit{s, len};
   } else {
-    const uint32_t k = atomicAdd(&B.ctr->big_cnt[cur][0], 1u);
-    if (k >= B.big_cap) { atomicOr(&B.ctr->err, 2u); return; }
-    B.big[cur][0][k] = BigUnit{s, len, key_bits, 0u};
+    append_big(B.big[cur][0], &B.ctr->big_pk[cur][0], B.big_cap, s, len, key_bits, &B.ctr->err);
   }
 }
 
@@ -120,12 +143,14 @@ __global__ void k_iota_val(SortBufs B, uint32_t n) {
 }
 
 // -------------------------------------------------------------- LDS sorting
-template <int MODE>
+template <int MODE, int TL>
 __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, RankOut R,
                                                           uint32_t next_bits, int last_level,
                                                           uint8_t *keep) {
   constexpr int NT = kLdsThreads;
-  constexpr int PER = kLdsTile / NT;  // 16 consecutive slots per thread
+  constexpr int kLdsTile = 1 << TL;
+  constexpr int kTileClasses = TL;
+  constexpr int PER = kLdsTile / NT;  // consecutive slots per thread
   __shared__ uint64_t d[kLdsTile];
   __shared__ uint32_t hd[kLdsTile];
   __shared__ Unit ud[kLdsTile / 2];
@@ -141,7 +166,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
   __syncthreads();
   if (tid == 0) {
     uint32_t tot = 0;
-    for (int ci = 0; ci < kClasses; ci++) {
+    for (int ci = 0; ci < kTileClasses; ci++) {
       const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
       tot += (cnt_c[ci] + per - 1) / per;
     }
@@ -154,7 +179,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
     if (tid == 0) {
       uint32_t it = item;
       int ci = 0;
-      for (; ci < kClasses; ci++) {
+      for (; ci < kTileClasses; ci++) {
         const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
         const uint32_t ni = (cnt_c[ci] + per - 1) / per;
         if (it < ni) break;
@@ -307,60 +332,27 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
 }
 
 // ----------------------------------------------------------- MSD bucketing
-__global__ void k_msd_chunkify(SortBufs B, int cur, int level) {
-  constexpr int NT = 1024;
-  __shared__ uint32_t sh[NT / 64];
-  __shared__ uint32_t carry;
-  const uint32_t units = B.ctr->big_cnt[cur][level];
-  const BigUnit *U = B.big[cur][level];
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t b0 = 0; b0 < units; b0 += NT) {
-    const uint32_t u = b0 + threadIdx.x;
-    const uint32_t ch = u < units ? (U[u].len + kChunk - 1) / kChunk : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_sum<NT>(ch, sh, &tot);
-    if (u < units) B.chunk_base[u] = carry + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    B.chunk_base[units] = carry;
-    B.ctr->chunk_total[level] = carry;
-  }
-}
-
-__device__ __forceinline__ uint32_t find_unit(const uint32_t *base, uint32_t units, uint32_t ch) {
-  uint32_t lo = 0, hi = units;  // largest u with base[u] <= ch
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (base[mid] <= ch) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ void digit_params(uint32_t bits, uint32_t &shift, uint32_t &mask) {
-  const uint32_t d = bits < (uint32_t)kDigitBits ? bits : (uint32_t)kDigitBits;
+__device__ __forceinline__ void digit_params(uint32_t bits, uint32_t dbits, uint32_t &shift, uint32_t &mask) {
+  const uint32_t d = bits < dbits ? bits : dbits;
   shift = bits - d;
   mask = (d >= 32) ? 0xFFFFFFFFu : ((1u << d) - 1u);
 }
 
 __global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level) {
   __shared__ uint32_t h[kBins];
-  const uint32_t units = B.ctr->big_cnt[cur][level];
-  const uint32_t total = B.ctr->chunk_total[level];
+  uint32_t units, total;
+  list_size(B.ctr->big_pk[cur][level], B.big_cap, units, total);
   const BigUnit *U = B.big[cur][level];
   for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+    for (int b = threadIdx.x; b < (1 << B.digit_bits); b += blockDim.x) h[b] = 0;
     __syncthreads();
-    const uint32_t u = find_unit(B.chunk_base, units, ch);
+    const uint32_t u = find_unit(U, units, ch);
     const BigUnit bu = U[u];
     uint32_t shift, mask;
-    digit_params(bu.bits, shift, mask);
-    const uint32_t lo = bu.start + (ch - B.chunk_base[u]) * kChunk;
+    digit_params(bu.meta & 0xFFu, B.digit_bits, shift, mask);
+    const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
-    const uint32_t *key = B.key[bu.flags & 1u];
+    const uint32_t *key = B.key[(bu.meta & kMetaAlt) ? 1 : 0];
     for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
       atomicAdd(&h[(key[p] >> shift) & mask], 1u);
     __syncthreads();
@@ -371,37 +363,40 @@ __global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level
   }
 }
 
-__device__ void route_piece(SortBufs &B, int cur, int level, uint32_t start, uint32_t len,
-                            uint32_t bits_left, uint32_t buf) {
-  if (len <= (uint32_t)kLdsTile) {
-    const int ci = class_of(len);
-    const uint32_t k = atomicAdd(&B.ctr->cls_cnt[cur][ci], 1u);
-    const uint32_t capc = B.cls_off[ci + 1] - B.cls_off[ci];
-    if (k < capc) B.cls[cur][B.cls_off[ci] + k] = Unit{start, len | (buf ? kBufBit : 0u)};
-    else atomicOr(&B.ctr->err, 16u);
-  } else if (bits_left == 0 || level >= 3) {
-    const uint32_t k = atomicAdd(&B.ctr->bulk_cnt, 1u);
-    if (k < B.big_cap) B.bulk[k] = BigUnit{start, len, 0u, buf};
-    else atomicOr(&B.ctr->err, 32u);
-  } else {
-    const uint32_t k = atomicAdd(&B.ctr->big_cnt[cur][level + 1], 1u);
-    if (k < B.big_cap) B.big[cur][level + 1][k] = BigUnit{start, len, bits_left, buf};
-    else atomicOr(&B.ctr->err, 64u);
-  }
+// Destinations of a bucket: LDS class lists (0..kClasses-1), the bulk list,
+// the next MSD level.
+enum { kDestBulk = kClasses, kDestNext = kClasses + 1, kDests = kClasses + 2 };
+
+__device__ __forceinline__ int dest_of(const SortBufs &B, uint32_t len, uint32_t bits_left, int level) {
+  if (len <= (1u << B.tile_log)) return class_of(len);
+  if (bits_left == 0 || level + 1 >= kMaxMsdLevels) return kDestBulk;
+  return kDestNext;
 }
 
+// One workgroup per large unit: exclusive scan of its digit histogram into
+// scatter cursors, then every non-empty bucket becomes a piece routed to a
+// class list, the bulk list or the next level.  Appends are aggregated per
+// workgroup (one global atomic per destination).  A unit whose digit puts
+// everything into one bucket is not scattered: it continues in place.
 __global__ __launch_bounds__(256) void k_msd_scan(SortBufs B, int cur, int level) {
   constexpr int NT = 256;
   constexpr int PER = kBins / NT;
   __shared__ uint32_t sh[NT / 64];
-  const uint32_t units = B.ctr->big_cnt[cur][level];
+  __shared__ unsigned long long dl[kDests];  // per destination: (units << 32) | chunks, local
+  __shared__ unsigned long long dg[kDests];  // global base of this workgroup's range
+  __shared__ int one;
+  uint32_t units, total;
+  list_size(B.ctr->big_pk[cur][level], B.big_cap, units, total);
   BigUnit *U = B.big[cur][level];
   for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
     const BigUnit bu = U[u];
+    const uint32_t buf = (bu.meta & kMetaAlt) ? 1u : 0u;
     uint32_t shift, mask;
-    digit_params(bu.bits, shift, mask);
+    digit_params(bu.meta & 0xFFu, B.digit_bits, shift, mask);
     uint32_t *gh = B.hist + (size_t)u * kBins;
     uint32_t *cu = B.cursor + (size_t)u * kBins;
+    if (threadIdx.x < kDests) dl[threadIdx.x] = 0;
+    if (threadIdx.x == 0) one = 0;
     uint32_t v[PER];
     uint32_t loc = 0;
     for (int q = 0; q < PER; q++) {
@@ -410,29 +405,65 @@ __global__ __launch_bounds__(256) void k_msd_scan(SortBufs B, int cur, int level
       loc += v[q];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);
-    // single bucket: keep data in place, continue with the remaining bits
-    bool single = false;
-    for (int q = 0; q < PER; q++) single |= (v[q] == bu.len);
-    __shared__ int any_single;
-    if (threadIdx.x == 0) any_single = 0;
+    const uint32_t ex0 = block_excl_sum<NT>(loc, sh, &tot);  // (has barriers)
+    for (int q = 0; q < PER; q++)
+      if (v[q] == bu.len) one = 1;
     __syncthreads();
-    if (single) any_single = 1;
-    __syncthreads();
-    const bool one = any_single != 0;
+    const bool single = one != 0;
+    // pass 1: local offsets per destination
+    unsigned long long lo[PER];
+    uint32_t ex = ex0;
     for (int q = 0; q < PER; q++) {
       const uint32_t b = threadIdx.x * PER + q;
+      lo[q] = 0;
       if (b <= mask) {
         cu[b] = bu.start + ex;
-        if (v[q]) {
-          if (one) route_piece(B, cur, level, bu.start, bu.len, shift, bu.flags & 1u);
-          else route_piece(B, cur, level, bu.start + ex, v[q], shift, (bu.flags & 1u) ^ 1u);
-        }
         gh[b] = 0;
+        if (v[q]) {
+          const int d = dest_of(B, v[q], shift, level);
+          const unsigned long long inc = (d >= kDestBulk) ? ((1ull << 32) | chunks_of(v[q])) : (1ull << 32);
+          lo[q] = atomicAdd(&dl[d], inc);
+        }
       }
       ex += v[q];
     }
-    if (threadIdx.x == 0 && one) U[u].flags = bu.flags | 2u;
+    __syncthreads();
+    if (threadIdx.x < kDests) {
+      const int d = threadIdx.x;
+      const unsigned long long m = dl[d];
+      unsigned long long g = 0;
+      if (m) {
+        if (d < kClasses) g = (unsigned long long)atomicAdd(&B.ctr->cls_cnt[cur][d], (uint32_t)(m >> 32)) << 32;
+        else if (d == kDestBulk) g = atomicAdd(&B.ctr->bulk_pk, m);
+        else g = atomicAdd(&B.ctr->big_pk[cur][level + 1], m);
+      }
+      dg[d] = g;
+    }
+    __syncthreads();
+    // pass 2: write the pieces
+    ex = ex0;
+    for (int q = 0; q < PER; q++) {
+      const uint32_t b = threadIdx.x * PER + q;
+      if (b <= mask && v[q]) {
+        const uint32_t pstart = single ? bu.start : bu.start + ex;
+        const uint32_t pbuf = single ? buf : buf ^ 1u;
+        const int d = dest_of(B, v[q], shift, level);
+        const uint32_t k = (uint32_t)(dg[d] >> 32) + (uint32_t)(lo[q] >> 32);
+        const uint32_t cb = (uint32_t)dg[d] + (uint32_t)lo[q];
+        if (d < kClasses) {
+          const uint32_t capc = B.cls_off[d + 1] - B.cls_off[d];
+          if (k < capc) B.cls[cur][B.cls_off[d] + k] = Unit{pstart, v[q] | (pbuf ? kBufBit : 0u)};
+          else atomicOr(&B.ctr->err, 16u);
+        } else if (k < B.big_cap) {
+          BigUnit *L = (d == kDestBulk) ? B.bulk : B.big[cur][level + 1];
+          L[k] = BigUnit{pstart, v[q], cb, shift | (pbuf ? kMetaAlt : 0u)};
+        } else {
+          atomicOr(&B.ctr->err, 32u);
+        }
+      }
+      ex += v[q];
+    }
+    if (threadIdx.x == 0 && single) U[u].meta = bu.meta | kMetaSkip;
     __syncthreads();
   }
 }
@@ -441,20 +472,20 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
   constexpr int NT = 256;
   constexpr int PER = kChunk / NT;
   __shared__ uint32_t cnt[kBins];
-  const uint32_t units = B.ctr->big_cnt[cur][level];
-  const uint32_t total = B.ctr->chunk_total[level];
+  uint32_t units, total;
+  list_size(B.ctr->big_pk[cur][level], B.big_cap, units, total);
   const BigUnit *U = B.big[cur][level];
   for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
-    const uint32_t u = find_unit(B.chunk_base, units, ch);
+    const uint32_t u = find_unit(U, units, ch);
     const BigUnit bu = U[u];
-    if (bu.flags & 2u) continue;  // uniform across the block
-    for (int b = threadIdx.x; b < kBins; b += NT) cnt[b] = 0;
+    if (bu.meta & kMetaSkip) continue;  // uniform across the block
+    for (int b = threadIdx.x; b < (1 << B.digit_bits); b += NT) cnt[b] = 0;
     __syncthreads();
     uint32_t shift, mask;
-    digit_params(bu.bits, shift, mask);
-    const uint32_t lo = bu.start + (ch - B.chunk_base[u]) * kChunk;
+    digit_params(bu.meta & 0xFFu, B.digit_bits, shift, mask);
+    const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
-    const int sb = bu.flags & 1u, db = sb ^ 1;
+    const int sb = (bu.meta & kMetaAlt) ? 1 : 0, db = sb ^ 1;
     uint32_t kk[PER], vv[PER], oo[PER];
     for (int q = 0; q < PER; q++) {
       const uint32_t p = lo + threadIdx.x + q * NT;
@@ -484,49 +515,53 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
 }
 
 // --------------------------------------------------- bulk (one-group) units
+// Pieces whose key bits are used up are one group each.  Processed chunk by
+// chunk: SA-mode ranks/snapshots, copy-back from the alternate buffer, the
+// next level's active slots, and (by the unit's first chunk) the unit itself
+// as a large unit of the next level.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, uint32_t next_bits,
                                               int last_level, uint8_t *keep) {
   constexpr int NT = 256;
+  constexpr int PER = kChunk / NT;
   __shared__ uint32_t sh[NT / 64];
   __shared__ uint32_t base;
   const int nxt = cur ^ 1;
-  const uint32_t units = B.ctr->bulk_cnt;
-  for (uint32_t u = 0; u < units; u++) {
+  uint32_t units, total;
+  list_size(B.ctr->bulk_pk, B.big_cap, units, total);
+  for (uint32_t ch = blockIdx.x; ch < total; ch += gridDim.x) {
+    const uint32_t u = find_unit(B.bulk, units, ch);
     const BigUnit bu = B.bulk[u];
-    if (blockIdx.x == 0 && threadIdx.x == 0 && !last_level) {
-      const uint32_t k = atomicAdd(&B.ctr->big_cnt[nxt][0], 1u);
-      if (k < B.big_cap) B.big[nxt][0][k] = BigUnit{bu.start, bu.len, next_bits, 0u};
-      else atomicOr(&B.ctr->err, 128u);
-    }
-    const uint32_t stride = gridDim.x * NT;
-    for (uint32_t e0 = blockIdx.x * NT; e0 < bu.len; e0 += stride) {
-      const uint32_t e = e0 + threadIdx.x;
-      const bool ok = e < bu.len;
-      const uint32_t p = bu.start + e;
-      if (ok) {
-        const uint32_t v = B.val[bu.flags & 1u][p];
-        if (bu.flags & 1u) B.val[0][p] = v;
+    const bool alt = (bu.meta & kMetaAlt) != 0;
+    const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
+    const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
+    if (threadIdx.x == 0 && !last_level && ch == bu.cbase)
+      append_big(B.big[nxt][0], &B.ctr->big_pk[nxt][0], B.big_cap, bu.start, bu.len, next_bits, &B.ctr->err);
+    for (int q = 0; q < PER; q++) {
+      const uint32_t p = lo + threadIdx.x + q * NT;
+      if (p < hi) {
+        const uint32_t v = B.val[alt ? 1 : 0][p];
+        if (alt) B.val[0][p] = v;
         if (MODE == MODE_SA) {
           R.rank[v] = bu.start + 1;
           R.snap[v] = bu.start + 1;
         }
-        if (last_level) keep[p] = (e == 0) ? 1 : 0;
-      }
-      if (!last_level) {
-        uint32_t tot;
-        const uint32_t off = block_excl_sum<NT>(ok ? 1u : 0u, sh, &tot);
-        if (threadIdx.x == 0) base = atomicAdd(&B.ctr->act_cnt[nxt], tot);
-        __syncthreads();
-        if (ok) {
-          const uint32_t w = base + off;
-          if (w < B.cap) B.act[nxt][w] = p;
-          else atomicOr(&B.ctr->err, 256u);
-        }
-        __syncthreads();
+        if (last_level) keep[p] = (p == bu.start) ? 1 : 0;
       }
     }
+    if (!last_level) {
+      const uint32_t cnt = hi - lo;
+      if (threadIdx.x == 0) base = atomicAdd(&B.ctr->act_cnt[nxt], cnt);
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+        const uint32_t w = base + e;
+        if (w < B.cap) B.act[nxt][w] = lo + e;
+        else atomicOr(&B.ctr->err, 256u);
+      }
+      __syncthreads();
+    }
   }
+  (void)sh;
 }
 
 // =================================================================== host
@@ -548,19 +583,20 @@ int SortEngine::alloc(uint64_t capacity) {
     off += (uint32_t)((capacity >> ci) + 1);
   }
   B.cls_off[kClasses] = off;
-  B.big_cap = (uint32_t)(capacity / kLdsTile + 64);
+  B.big_cap = (uint32_t)(capacity / (1u << kMinTileLog) + 64);
+  B.tile_log = kDefaultTileLog;
+  B.digit_bits = kDefaultDigitBits;
   size_t bytes = 0;
   auto take = [&](size_t n) { size_t o = bytes; bytes += (n + 255) & ~(size_t)255; return o; };
   size_t o_key0 = take(capacity * 4), o_key1 = take(capacity * 4);
   size_t o_val0 = take(capacity * 4), o_val1 = take(capacity * 4);
   size_t o_cls0 = take((size_t)off * sizeof(Unit)), o_cls1 = take((size_t)off * sizeof(Unit));
-  size_t o_big[2][4];
+  size_t o_big[2][kMsdLists];
   for (int l = 0; l < 2; l++)
-    for (int v = 0; v < 4; v++) o_big[l][v] = take((size_t)B.big_cap * sizeof(BigUnit));
+    for (int v = 0; v < kMsdLists; v++) o_big[l][v] = take((size_t)B.big_cap * sizeof(BigUnit));
   size_t o_bulk = take((size_t)B.big_cap * sizeof(BigUnit));
   size_t o_hist = take((size_t)B.big_cap * kBins * 4);
   size_t o_cur = take((size_t)B.big_cap * kBins * 4);
-  size_t o_cb = take((size_t)(B.big_cap + 1) * 4);
   size_t o_act0 = take(capacity * 4), o_act1 = take(capacity * 4);
   size_t o_ctr = take(sizeof(SortCounters));
   APO_HIP_TRY(hipMalloc(&mem_, bytes));
@@ -570,11 +606,10 @@ int SortEngine::alloc(uint64_t capacity) {
   B.val[0] = (uint32_t *)(m + o_val0); B.val[1] = (uint32_t *)(m + o_val1);
   B.cls[0] = (Unit *)(m + o_cls0); B.cls[1] = (Unit *)(m + o_cls1);
   for (int l = 0; l < 2; l++)
-    for (int v = 0; v < 4; v++) B.big[l][v] = (BigUnit *)(m + o_big[l][v]);
+    for (int v = 0; v < kMsdLists; v++) B.big[l][v] = (BigUnit *)(m + o_big[l][v]);
   B.bulk = (BigUnit *)(m + o_bulk);
   B.hist = (uint32_t *)(m + o_hist);
   B.cursor = (uint32_t *)(m + o_cur);
-  B.chunk_base = (uint32_t *)(m + o_cb);
   B.act[0] = (uint32_t *)(m + o_act0); B.act[1] = (uint32_t *)(m + o_act1);
   B.ctr = (SortCounters *)(m + o_ctr);
   APO_HIP_TRY(hipMemset(B.hist, 0, (size_t)B.big_cap * kBins * 4));
@@ -625,32 +660,54 @@ void SortEngine::iota_val(uint32_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_iota_val, grid_for(n, 256, 4096), dim3(256), 0, s, b_, n);
 }
 
-void SortEngine::msd(int cur, uint64_t work_hint, hipStream_t s) {
+void SortEngine::msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s) {
   const unsigned g = (unsigned)std::min<uint64_t>(4096, std::max<uint64_t>(256, work_hint / kChunk + 1));
-  for (int level = 0; level < 3; level++) {
-    hipLaunchKernelGGL(k_msd_chunkify, dim3(1), dim3(1024), 0, s, b_, cur, level);
+  const int levels = std::min(kMaxMsdLevels, (max_bits + (int)b_.digit_bits - 1) / (int)b_.digit_bits);
+  for (int level = 0; level < levels; level++) {
     hipLaunchKernelGGL(k_msd_hist, dim3(g), dim3(256), 0, s, b_, cur, level);
     hipLaunchKernelGGL(k_msd_scan, dim3(256), dim3(256), 0, s, b_, cur, level);
     hipLaunchKernelGGL(k_msd_scatter, dim3(g), dim3(256), 0, s, b_, cur, level);
   }
 }
 
+template <int MODE>
+static void launch_lds(const SortBufs &b, int cur, RankOut R, uint32_t next_bits, int last_level, uint8_t *keep,
+                       uint64_t work_hint, hipStream_t s) {
+  const uint64_t tile = 1ull << b.tile_log;
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / tile + 16));
+  switch (b.tile_log) {
+    case 11:
+      hipLaunchKernelGGL((k_lds_sort<MODE, 11>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
+                         keep);
+      break;
+    case 13:
+      hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
+                         keep);
+      break;
+    default:
+      hipLaunchKernelGGL((k_lds_sort<MODE, 12>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
+                         keep);
+      break;
+  }
+}
+
+void SortEngine::set_params(int tile_log, int digit_bits) {
+  b_.tile_log = (uint32_t)std::min(std::max(tile_log, kMinTileLog), kMaxTileLog);
+  b_.digit_bits = (uint32_t)std::min(std::max(digit_bits, kMinDigitBits), kMaxDigitBits);
+}
+
 void SortEngine::lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s) {
-  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / kLdsTile + 16));
-  hipLaunchKernelGGL(k_lds_sort<MODE_SA>, dim3(g), dim3(kLdsThreads), 0, s, b_, cur, R, next_bits, 0,
-                     (uint8_t *)nullptr);
+  launch_lds<MODE_SA>(b_, cur, R, next_bits, 0, nullptr, work_hint, s);
 }
 
 void SortEngine::lds_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep,
                            uint64_t work_hint, hipStream_t s) {
   RankOut R{};
-  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / kLdsTile + 16));
-  hipLaunchKernelGGL(k_lds_sort<MODE_PLAIN>, dim3(g), dim3(kLdsThreads), 0, s, b_, cur, R, next_bits,
-                     last_level, keep);
+  launch_lds<MODE_PLAIN>(b_, cur, R, next_bits, last_level, keep, work_hint, s);
 }
 
 void SortEngine::bulk_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s) {
-  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / 1024 + 1));
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / kChunk + 1));
   hipLaunchKernelGGL(k_bulk<MODE_SA>, dim3(g), dim3(256), 0, s, b_, cur, R, next_bits, 0,
                      (uint8_t *)nullptr);
 }
@@ -658,7 +715,7 @@ void SortEngine::bulk_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_h
 void SortEngine::bulk_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep,
                             uint64_t work_hint, hipStream_t s) {
   RankOut R{};
-  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / 1024 + 1));
+  const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, work_hint / kChunk + 1));
   hipLaunchKernelGGL(k_bulk<MODE_PLAIN>, dim3(g), dim3(256), 0, s, b_, cur, R, next_bits, last_level,
                      keep);
 }

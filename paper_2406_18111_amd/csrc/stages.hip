@@ -101,28 +101,57 @@ void scan_excl(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tile_tmp
 }
 
 // ------------------------------------------------------ token ranking (u64)
-// Open-addressing table of first-occurrence indices.  A thread inserts its
-// token; the one whose CAS claims an empty slot records a new distinct value.
-__global__ void k_hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask,
-                              uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd) {
-  GRID_STRIDE(i, n) {
-    const uint64_t key = tok[i];
-    uint64_t h = mix64(key) & mask;
-    while (true) {
-      uint32_t cur = tab[h];
-      if (cur == kNone) {
-        const uint32_t prev = atomicCAS(&tab[h], kNone, (uint32_t)i);
-        if (prev == kNone) {
-          const uint32_t d = atomicAdd(nd, 1u);
-          dist_idx[d] = (uint32_t)i;
-          dist_slot[d] = (uint32_t)h;
+// Open-addressing table of first-occurrence indices.  Each workgroup first
+// removes duplicates within its tile of tokens with a table in LDS, so only
+// one thread per distinct value and tile touches the global table (loop
+// streams repeat a few hundred hashes thousands of times).  The thread whose
+// CAS claims an empty global slot records a new distinct value.
+constexpr int kHashTile = 2048, kHashLds = 4096;
+
+__device__ __forceinline__ void global_insert(const uint64_t *tok, uint32_t i, uint64_t key, uint32_t *tab,
+                                              uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
+                                              uint32_t *nd) {
+  uint64_t h = mix64(key) & mask;
+  while (true) {
+    uint32_t cur = tab[h];
+    if (cur == kNone) {
+      const uint32_t prev = atomicCAS(&tab[h], kNone, i);
+      if (prev == kNone) {
+        const uint32_t d = atomicAdd(nd, 1u);
+        dist_idx[d] = i;
+        dist_slot[d] = (uint32_t)h;
+        return;
+      }
+      cur = prev;
+    }
+    if (tok[cur] == key) return;
+    h = (h + 1) & mask;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask,
+                                                     uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd) {
+  __shared__ uint64_t lt[kHashTile];   // the tile's tokens
+  __shared__ uint32_t ls[kHashLds];    // local table: tile index + 1 (0 = empty)
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kHashTile; t0 < n; t0 += (uint64_t)gridDim.x * kHashTile) {
+    const uint32_t m = (uint32_t)min((uint64_t)kHashTile, n - t0);
+    for (uint32_t k = threadIdx.x; k < kHashLds; k += blockDim.x) ls[k] = 0;
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) lt[k] = tok[t0 + k];
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+      const uint64_t key = lt[k];
+      uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
+      while (true) {
+        const uint32_t prev = atomicCAS(&ls[h], 0u, k + 1);
+        if (prev == 0u) {  // first in this tile
+          global_insert(tok, (uint32_t)(t0 + k), key, tab, mask, dist_idx, dist_slot, nd);
           break;
         }
-        cur = prev;
+        if (lt[prev - 1] == key) break;
+        h = (h + 1) & (kHashLds - 1);
       }
-      if (tok[cur] == key) break;
-      h = (h + 1) & mask;
     }
+    __syncthreads();
   }
 }
 
@@ -157,8 +186,9 @@ __global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *t
 
 void hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask, uint32_t *dist_idx,
                  uint32_t *dist_slot, uint32_t *nd, hipStream_t s) {
-  hipLaunchKernelGGL(k_hash_insert, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n, tab, mask, dist_idx,
-                     dist_slot, nd);
+  const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
+  hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
+                     0, s, tok, n, tab, mask, dist_idx, dist_slot, nd);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -214,7 +244,7 @@ __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t ac
   return acc;
 }
 
-constexpr int kKasaiChunk = 32;
+constexpr int kKasaiChunk = 16;
 constexpr int kKasaiCap = 64;
 
 // Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of consecutive

@@ -204,3 +204,33 @@ def test_config2_full_size(ctx):
             assert x[p] < y[p]
         else:
             assert la < lb
+
+
+@pytest.mark.parametrize("tile_log", [11, 12, 13])
+@pytest.mark.parametrize("digit_bits", [8, 10, 11, 12])
+def test_kernel_params_do_not_change_results(ctx, tile_log, digit_bits):
+    """Every LDS tile / MSD digit width gives the oracle's result (units longer
+    than the tile exercise the MSD path)."""
+    ctx.set_params(tile_log, digit_bits)
+    try:
+        rng = np.random.default_rng(tile_log * 100 + digit_bits)
+        cases = [rng.integers(0, 3, 20000).astype(np.uint64), _u64([4] * 9000 + [1, 2] * 3000),
+                 synth.config1(n=1 << 15)[0]]
+        for t in cases:
+            for m in (2, 16):
+                _check_full(ctx, t, m)
+        sa, _ = ctx.suffix_array_dev(_dev(cases[1]))
+        assert np.array_equal(sa.cpu().numpy().astype(np.int64), oracle.suffix_array(cases[1]))
+    finally:
+        ctx.set_params(-1, -1)
+
+
+def test_tune_table_roundtrip(ctx, tmp_path):
+    t, m = synth.config1(n=1 << 14)
+    tl, db, ms = ctx.tune(_dev(t), m, reps=1)
+    assert 11 <= tl <= 13 and db in (8, 10, 11, 12) and ms > 0
+    path = str(tmp_path / "tune.txt")
+    ctx.tune_save(path)
+    assert open(path).read().split("\n")[1].split() == ["14", str(tl), str(db)]
+    ctx.tune_load(path)
+    _check_full(ctx, t, m)

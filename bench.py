@@ -253,7 +253,7 @@ def main():
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "k_lds_sort<MODE_SA> (doubling rounds)",
+                           "kernel": "LDS sort + LDS grouping kernels of the doubling rounds (k_lds_sort<0>, k_lds_group<0>)",
                            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
                            "launches_per_step": kprof["launches"] / steps}
     if args.batched and not args.profile_steps:

@@ -68,6 +68,8 @@ struct Workspace {
   uint32_t *dcnt = nullptr;
   uint32_t *rhist = nullptr;       // per doubling round: active slots, large units after it
   uint32_t *hrhist = nullptr;      // pinned host mirror of rhist
+  uint32_t *selcnt = nullptr;      // selection rounds: live counts, undecided counts
+  uint32_t *hsel = nullptr;        // pinned host mirror of selcnt
   uint32_t *hcnt = nullptr;        // pinned host mirror of dcnt
   SortCounters *hctr = nullptr;    // pinned host mirror of engine counters
   hipEvent_t ev[kStages + 1] = {};

@@ -45,7 +45,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   const uint64_t C2 = 2 * N;
   size_t b = 0;
   b += N * 8 + N * 4 * 8 + hc * 8 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
-  b += C2 * (4 * 8 + 2) + (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
+  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
   b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
 }
@@ -60,6 +60,8 @@ void Workspace::release() {
   hctr = nullptr;
   if (hrhist) (void)hipHostFree(hrhist);
   hrhist = nullptr;
+  if (hsel) (void)hipHostFree(hsel);
+  hsel = nullptr;
   for (auto &e : ev)
     if (e) { (void)hipEventDestroy(e); e = nullptr; }
   for (auto &e : kev)
@@ -92,12 +94,13 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_sl = L.take(C2 * 4), o_ss = L.take(C2 * 4), o_si = L.take(C2 * 4);
   size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
   size_t o_tile = L.take((C2 / 4096 + 4) * 4);
-  size_t o_T = L.take((size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
+  size_t o_T = L.take(2 * (size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
   size_t o_state = L.take(C2), o_mark = L.take(N_);
   size_t o_ol = L.take(N_ * 4), o_os = L.take(N_ * 4), o_oi = L.take(N_ * 4);
   size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
   size_t o_cnt = L.take(CNT_COUNT * 4);
   size_t o_rh = L.take(4 * 64 * 4);
+  size_t o_sc = L.take(2 * (kSelRoundCap + 2) * 4);
   hipError_t e = hipMalloc(&mem, L.total);
   if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
   bytes = L.total;
@@ -149,11 +152,13 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   rowidx = (uint32_t *)(m + o_ri);
   dcnt = (uint32_t *)(m + o_cnt);
   rhist = (uint32_t *)(m + o_rh);
+  selcnt = (uint32_t *)(m + o_sc);
   int rc = eng.alloc(C2);
   if (rc) { release(); return rc; }
   APO_HIP_TRY(hipHostMalloc((void **)&hcnt, CNT_COUNT * 4, hipHostMallocDefault));
   APO_HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(SortCounters), hipHostMallocDefault));
   APO_HIP_TRY(hipHostMalloc((void **)&hrhist, 4 * 64 * 4, hipHostMallocDefault));
+  APO_HIP_TRY(hipHostMalloc((void **)&hsel, 2 * (kSelRoundCap + 2) * 4, hipHostMallocDefault));
   for (auto &ev_ : ev) APO_HIP_TRY(hipEventCreate(&ev_));
   for (auto &ev_ : kev) APO_HIP_TRY(hipEventCreate(&ev_));
   APO_HIP_TRY(hipMemset(dcnt, 0, CNT_COUNT * 4));
@@ -274,10 +279,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
-    if (r > 0) {
-      E.round_begin(cur, s);
-      E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, s);
-    }
+    if (r > 0) E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, w.rhist, r, s);
     RankOut R{w.rank, w.snap + (size_t)r * N, w.fin, (uint32_t)r};
     if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rank_bits, s);
     const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
@@ -288,10 +290,10 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       w.kround[w.kev_n++] = r;
     }
     E.bulk_sa(cur, R, rank_bits, act, s);
-    E.round_end(cur, r, w.rhist, s);
     cur ^= 1;
     r++;
     if (r - synced >= spec || r >= w.nsnap) {
+      E.round_end(cur ^ 1, r - 1, w.rhist, s);
       APO_HIP_TRY(hipMemcpyAsync(w.hrhist, w.rhist, 4 * w.nsnap * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
       for (int k = synced; k < r; k++) {
@@ -340,28 +342,34 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   stamp(w, 5, s);
   if (stop == Stop::CANDS) return 0;
 
-  // ---- greedy selection
+  // ---- greedy selection (rounds launched two at a time, see sel_round)
   if (M > 0) {
     const int top = 31 - __builtin_clz(maxl);
-    fill_u32(w.dcnt + CNT_NLIVE0, 1, M, s);
-    sel_init(w.live[0], w.dcnt + CNT_NLIVE0, w.state, M, s);
-    int li = 0;
+    uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
+    uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2);
+    fill_u32(Ta, (uint64_t)(top + 1) * N, 0xFFFFFFFFu, s);
+    fill_u32(w.selcnt, 2 * (kSelRoundCap + 2), 0, s);
+    fill_u32(nlive, 1, M, s);
+    sel_init(w.live[0], nlive, w.state, M, s);
+    int r = 0, done = -1;
+    const int ahead = 2;
     uint64_t hint = M;
-    while (true) {
-      fill_u32(w.dcnt + CNT_NLIVE0 + (li ^ 1), 1, 0, s);
-      fill_u32(w.dcnt + CNT_UNDEC, 1, 0, s);
-      sel_round(w.live[li], w.dcnt + CNT_NLIVE0 + li, hint, w.s_len, w.s_start, w.T, top, N, w.state, w.live[li ^ 1],
-                w.dcnt + CNT_NLIVE0 + (li ^ 1), w.dcnt + CNT_UNDEC, s);
-      info.sel_rounds++;
+    while (done < 0 && r < kSelRoundCap) {
+      for (int q = r; q < r + ahead && q < kSelRoundCap; q++)
+        sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[q & 1],
+                  w.live[(q + 1) & 1], nlive, undec, q, hint, s);
+      const int hi = std::min(r + ahead, kSelRoundCap);
+      APO_HIP_TRY(hipMemcpyAsync(w.hsel, w.selcnt, 2 * (kSelRoundCap + 2) * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
-      if (w.hcnt[CNT_UNDEC] == 0) break;
-      if (info.sel_rounds >= (uint32_t)kSelRoundCap) {
-        sel_sequential(w.state, w.s_len, w.s_start, M, w.mark, N, s);
-        info.sel_sequential = 1;
-        break;
-      }
-      li ^= 1;
-      hint = w.hcnt[CNT_NLIVE0 + li];
+      for (int q = r; q < hi; q++)
+        if (w.hsel[(kSelRoundCap + 2) + q] == 0) { done = q; break; }
+      if (done < 0) hint = w.hsel[hi];
+      r = hi;
+    }
+    info.sel_rounds = done >= 0 ? (uint32_t)done + 1 : (uint32_t)kSelRoundCap;
+    if (done < 0) {
+      sel_sequential(w.state, w.s_len, w.s_start, M, w.mark, N, s);
+      info.sel_sequential = 1;
     }
   }
   stamp(w, 6, s);

@@ -22,7 +22,7 @@ class SortEngine {
                   hipStream_t s);
   void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
   void gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n, uint32_t h,
-                 uint32_t act_hint, hipStream_t s);
+                 uint32_t act_hint, uint32_t *hist, int r, hipStream_t s);
   void gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c, uint32_t hint,
                     hipStream_t s);
   void iota_val(uint32_t n, hipStream_t s);

@@ -113,8 +113,23 @@ __global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n) {
 
 // Doubling round with offset h: key = rank of the suffix h positions later,
 // 0 when that lies past the end of the suffix's window.
+// Block 0 also closes the previous round (records its outcome in hist[r-1])
+// and clears the counters of this round (what k_round_end / k_round_begin do).
 __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uint32_t *slot_wend,
-                            uint32_t n, uint32_t h) {
+                            uint32_t n, uint32_t h, uint32_t *hist, int r) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SortCounters *c = B.ctr;
+    const int nxt = cur ^ 1;
+    hist[4 * (r - 1)] = c->act_cnt[cur];
+    hist[4 * (r - 1) + 1] = (uint32_t)(c->big_pk[cur][0] >> 32);
+    hist[4 * (r - 1) + 2] = c->lds_elems;
+    for (int t = 0; t < kClasses; t++) c->cls_cnt[nxt][t] = 0;
+    for (int t = 1; t < kMsdLists; t++) c->big_pk[cur][t] = 0;
+    c->big_pk[nxt][0] = 0;
+    c->bulk_pk = 0;
+    c->act_cnt[nxt] = 0;
+    c->lds_elems = 0;
+  }
   const uint32_t cnt = B.ctr->act_cnt[cur];
   const uint32_t *act = B.act[cur];
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
@@ -146,7 +161,7 @@ __global__ void k_iota_val(SortBufs B, uint32_t n) {
 template <int MODE, int TL>
 __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, RankOut R,
                                                           uint32_t next_bits, int last_level,
-                                                          uint8_t *keep) {
+                                                          uint8_t *keep, int ci_lo, int ci_hi) {
   constexpr int NT = kLdsThreads;
   constexpr int kLdsTile = 1 << TL;
   constexpr int kTileClasses = TL;
@@ -166,7 +181,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
   __syncthreads();
   if (tid == 0) {
     uint32_t tot = 0;
-    for (int ci = 0; ci < kTileClasses; ci++) {
+    for (int ci = ci_lo; ci < ci_hi && ci < kTileClasses; ci++) {
       const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
       tot += (cnt_c[ci] + per - 1) / per;
     }
@@ -178,8 +193,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
     if (tid == 0) {
       uint32_t it = item;
-      int ci = 0;
-      for (; ci < kTileClasses; ci++) {
+      int ci = ci_lo;
+      for (; ci < ci_hi && ci < kTileClasses; ci++) {
         const uint32_t per = (uint32_t)kLdsTile >> (ci + 1);
         const uint32_t ni = (cnt_c[ci] + per - 1) / per;
         if (it < ni) break;
@@ -327,6 +342,238 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       }
     }
     (void)next_bits;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------- LDS grouping (large units)
+// For units of 65..2^TLG entries: count the entries of every distinct
+// (unit, key) pair in an LDS hash table, sort only the distinct pairs, turn
+// their counts into offsets and drop every entry into its group's range.  Work
+// per entry is a few LDS operations plus a share of the distinct-pair sort,
+// instead of a full bitonic network; loop-structured streams have few
+// distinct keys per group.
+constexpr int kGroupMinCi = 6;  // 0-based class 6 = lengths 65..128
+constexpr int kGroupThreads = 512;
+
+template <int MODE, int TLG>
+__global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur, RankOut R, int last_level,
+                                                            uint8_t *keep) {
+  constexpr int NT = kGroupThreads;
+  constexpr int T = 1 << TLG;
+  constexpr int HT = 2 * T;            // hash slots (load <= 1/2)
+  constexpr int PER = T / NT;
+  constexpr int MAXU = T >> (kGroupMinCi + 1);  // units per tile of the smallest handled class
+  __shared__ uint32_t K[T], V[T];
+  __shared__ uint16_t EJ[T];           // unit of each entry
+  __shared__ uint32_t tab[HT];         // insert: (count << 16) | (entry + 1); after scan: (count << 16) | base
+  __shared__ uint64_t D[T];            // distinct (unit, key, slot); after scan: fill cursors (u32[HT])
+  __shared__ Unit ud[MAXU];
+  __shared__ uint32_t uoff[MAXU + 1];
+  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t nd, act_base, items_total, item_c, item_b;
+  __shared__ uint32_t cls_loc[kClasses], cls_base[kClasses], cnt_c[kClasses];
+  uint32_t *cursor = reinterpret_cast<uint32_t *>(D);
+  const int nxt = cur ^ 1;
+  const int tid = threadIdx.x;
+  const int ci_hi = min((int)B.tile_log, TLG);
+  if (tid < kClasses) cnt_c[tid] = B.ctr->cls_cnt[cur][tid];
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int ci = kGroupMinCi; ci < ci_hi; ci++) {
+      const uint32_t per = (uint32_t)T >> (ci + 1);
+      tot += (cnt_c[ci] + per - 1) / per;
+    }
+    items_total = tot;
+  }
+  __syncthreads();
+  const uint32_t total_items = items_total;
+  for (uint32_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+    if (tid == 0) {
+      uint32_t it = item;
+      int ci = kGroupMinCi;
+      for (; ci < ci_hi; ci++) {
+        const uint32_t per = (uint32_t)T >> (ci + 1);
+        const uint32_t ni = (cnt_c[ci] + per - 1) / per;
+        if (it < ni) break;
+        it -= ni;
+      }
+      item_c = (uint32_t)ci;
+      item_b = it;
+      nd = 0;
+    }
+    if (tid < kClasses) cls_loc[tid] = 0;
+    for (int h = tid; h < HT; h += NT) tab[h] = 0;
+    __syncthreads();
+    const int ci = (int)item_c;
+    const uint32_t per = (uint32_t)T >> (ci + 1);
+    const uint32_t first = item_b * per;
+    const uint32_t nb = min(per, cnt_c[ci] - first);
+    const Unit *src = B.cls[cur] + B.cls_off[ci] + first;
+    // unit descriptors and compact offsets (nb <= MAXU <= NT)
+    {
+      uint32_t len = 0;
+      if (tid < (int)nb) {
+        ud[tid] = src[tid];
+        len = src[tid].len & ~kBufBit;
+      }
+      uint32_t tot;
+      const uint32_t ex = block_excl_sum<NT>(len, sh, &tot);
+      if (tid < (int)nb) uoff[tid] = ex;
+      if (tid == 0) uoff[nb] = tot;
+      if (tid == 0) atomicAdd(&B.ctr->lds_elems, tot);
+    }
+    __syncthreads();
+    const uint32_t total = uoff[nb];
+    // load entries
+    for (uint32_t p = tid; p < total; p += NT) {
+      uint32_t lo = 0, hi = nb;  // unit j: uoff[j] <= p < uoff[j+1]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (uoff[mid] <= p) lo = mid; else hi = mid;
+      }
+      const Unit u = ud[lo];
+      const int b = (u.len & kBufBit) ? 1 : 0;
+      const uint32_t g = u.start + (p - uoff[lo]);
+      K[p] = B.key[b][g];
+      V[p] = B.val[b][g];
+      EJ[p] = (uint16_t)lo;
+    }
+    __syncthreads();
+    // insert into the hash table
+    uint32_t eslot[PER];
+    for (int q = 0; q < PER; q++) {
+      const uint32_t p = tid + q * NT;
+      eslot[q] = 0;
+      if (p < total) {
+        const uint32_t key = K[p], j = EJ[p];
+        uint32_t h = (uint32_t)(mix64(((uint64_t)j << 32) | key) >> 20) & (HT - 1);
+        while (true) {
+          const uint32_t prev = atomicCAS(&tab[h], 0u, (1u << 16) | (p + 1));
+          if (prev == 0u) {
+            const uint32_t d = atomicAdd(&nd, 1u);
+            D[d] = ((uint64_t)j << 46) | ((uint64_t)key << 14) | h;
+            break;
+          }
+          const uint32_t e = (prev & 0xFFFFu) - 1;
+          if (K[e] == key && EJ[e] == j) {
+            atomicAdd(&tab[h], 1u << 16);
+            break;
+          }
+          h = (h + 1) & (HT - 1);
+        }
+        eslot[q] = h;
+      }
+    }
+    __syncthreads();
+    // sort the distinct pairs (bitonic over the next power of two)
+    const uint32_t m = nd;
+    uint32_t m2 = 1;
+    while (m2 < m) m2 <<= 1;
+    for (uint32_t i = m + tid; i < m2; i += NT) D[i] = ~0ull;
+    __syncthreads();
+    for (uint32_t k = 2; k <= m2; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        for (uint32_t t = tid; t < m2 / 2; t += NT) {
+          const uint32_t i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+          const uint32_t l = i | jj;
+          const bool asc = (i & k) == 0;
+          const uint64_t a = D[i], b = D[l];
+          if ((a > b) == asc) { D[i] = b; D[l] = a; }
+        }
+        __syncthreads();
+      }
+    }
+    // offsets: exclusive scan of counts in (unit, key) order
+    {
+      const uint32_t chunk = (m + NT - 1) / NT;
+      const uint32_t d0 = tid * chunk, d1 = min(d0 + chunk, m);
+      uint32_t loc = 0;
+      for (uint32_t d = d0; d < d1; d++) loc += tab[(uint32_t)D[d] & (HT - 1)] >> 16;
+      uint32_t tot;
+      uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);
+      uint32_t slots[8];
+      uint32_t bases[8];
+      int nsl = 0;
+      for (uint32_t d = d0; d < d1; d++) {
+        const uint32_t h = (uint32_t)D[d] & (HT - 1);
+        const uint32_t c = tab[h] >> 16;
+        if (nsl < 8) { slots[nsl] = h; bases[nsl] = ex; nsl++; }
+        else { tab[h] = (c << 16) | ex; }  // only when chunk > 8 (m > 8 * NT): never for T <= 4096
+        ex += c;
+      }
+      __syncthreads();  // every D read done before D is reused as cursors
+      for (int z = 0; z < nsl; z++) {
+        const uint32_t c = tab[slots[z]] >> 16;
+        tab[slots[z]] = (c << 16) | bases[z];
+        cursor[slots[z]] = bases[z];
+      }
+    }
+    __syncthreads();
+    // place entries and regroup
+    uint32_t my_act = 0;
+    uint32_t pos_q[PER];
+    for (int q = 0; q < PER; q++) {
+      const uint32_t p = tid + q * NT;
+      pos_q[q] = 0;
+      if (p < total) {
+        const uint32_t h = eslot[q];
+        const uint32_t info = tab[h];
+        const uint32_t gbase = info & 0xFFFFu, gcnt = info >> 16;
+        const uint32_t pos = atomicAdd(&cursor[h], 1u);
+        pos_q[q] = pos;
+        const uint32_t j = EJ[p];
+        const Unit u = ud[j];
+        const uint32_t slot = u.start + (pos - uoff[j]);
+        const uint32_t head = u.start + (gbase - uoff[j]);
+        const uint32_t v = V[p];
+        B.val[0][slot] = v;
+        if (MODE == MODE_SA) {
+          R.rank[v] = head + 1;
+          R.snap[v] = head + 1;
+          if (gcnt == 1) R.fin[v] = (uint8_t)R.round;
+        }
+        if (last_level) {
+          keep[slot] = (pos == gbase) ? 1 : 0;
+        } else if (gcnt >= 2) {
+          my_act++;
+          if (pos == gbase) atomicAdd(&cls_loc[class_of(gcnt)], 1u);
+        }
+      }
+    }
+    if (!last_level) {
+      uint32_t tot;
+      const uint32_t off = block_excl_sum<NT>(my_act, sh, &tot);
+      if (tid == 0) act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      if (tid < kClasses) {
+        const uint32_t mm = cls_loc[tid];
+        cls_base[tid] = mm ? atomicAdd(&B.ctr->cls_cnt[nxt][tid], mm) : 0u;
+        cls_loc[tid] = 0;
+      }
+      __syncthreads();
+      uint32_t w = act_base + off;
+      for (int q = 0; q < PER; q++) {
+        const uint32_t p = tid + q * NT;
+        if (p >= total) continue;
+        const uint32_t info = tab[eslot[q]];
+        const uint32_t gbase = info & 0xFFFFu, gcnt = info >> 16;
+        if (gcnt < 2) continue;
+        const uint32_t j = EJ[p];
+        const Unit u = ud[j];
+        const uint32_t slot = u.start + (pos_q[q] - uoff[j]);
+        if (w < B.cap) B.act[nxt][w] = slot;
+        else atomicOr(&B.ctr->err, 4u);
+        w++;
+        if (pos_q[q] == gbase) {
+          const int cc = class_of(gcnt);
+          const uint32_t k = cls_base[cc] + atomicAdd(&cls_loc[cc], 1u);
+          const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
+          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (gbase - uoff[j]), gcnt};
+          else atomicOr(&B.ctr->err, 8u);
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -645,9 +892,9 @@ void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s)
 }
 
 void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n,
-                           uint32_t h, uint32_t act_hint, hipStream_t s) {
+                           uint32_t h, uint32_t act_hint, uint32_t *hist, int r, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_sa, grid_for(act_hint, 256, 4096), dim3(256), 0, s, b_, cur, rank,
-                     slot_wend, n, h);
+                     slot_wend, n, h, hist, r);
 }
 
 void SortEngine::gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c,
@@ -675,19 +922,31 @@ static void launch_lds(const SortBufs &b, int cur, RankOut R, uint32_t next_bits
                        uint64_t work_hint, hipStream_t s) {
   const uint64_t tile = 1ull << b.tile_log;
   const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / tile + 16));
-  switch (b.tile_log) {
+  const int tl = (int)b.tile_log;
+  // classes below kGroupMinCi: bitonic sub-block sort; kGroupMinCi..min(tl,12)-1:
+  // hash grouping; class 13 (tile 2^13 only): bitonic
+  const int grp_hi = std::min(tl, 12);
+  switch (tl) {
     case 11:
       hipLaunchKernelGGL((k_lds_sort<MODE, 11>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep);
+                         keep, 0, kGroupMinCi);
       break;
     case 13:
       hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep);
+                         keep, 0, kGroupMinCi);
+      hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
+                         keep, 12, 13);
       break;
     default:
       hipLaunchKernelGGL((k_lds_sort<MODE, 12>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep);
+                         keep, 0, kGroupMinCi);
       break;
+  }
+  if (grp_hi > kGroupMinCi) {
+    if (tl == 11)
+      hipLaunchKernelGGL((k_lds_group<MODE, 11>), dim3(g), dim3(kGroupThreads), 0, s, b, cur, R, last_level, keep);
+    else
+      hipLaunchKernelGGL((k_lds_group<MODE, 12>), dim3(g), dim3(kGroupThreads), 0, s, b, cur, R, last_level, keep);
   }
 }
 

@@ -37,9 +37,9 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, uint64_t m, cons
                     uint32_t *total, hipStream_t s);
 
 void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t m, hipStream_t s);
-void sel_round(const uint32_t *live, const uint32_t *nlive, uint64_t live_hint, const uint32_t *len,
-               const uint32_t *start, uint32_t *T, int top, uint64_t n, uint8_t *state,
-               uint32_t *live_next, uint32_t *nlive_next, uint32_t *n_undec, hipStream_t s);
+void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
+               uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
+               uint64_t live_hint, hipStream_t s);
 void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
                     uint8_t *mark, uint64_t n, hipStream_t s);
 

@@ -314,7 +314,9 @@ struct MinLevels {
 // Largest j < i with lcp[j] < l, or -1.  Scans the block of i at level 0,
 // climbs 64-ary minimum levels until an entry below l appears, then descends
 // to its rightmost qualifying leaf.
-__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
+// `win` holds lcp[wlo, wlo + wn) in LDS (level-0 reads inside it come from LDS).
+__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l, const uint32_t *win, uint64_t wlo,
+                             uint64_t wn) {
   uint64_t pos = i;  // exclusive bound at the current level
   int lev = 0;
   int64_t found = -1;
@@ -323,7 +325,9 @@ __device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
     const uint64_t bs = (lev + 1 >= M.nlev) ? 0 : ((pos - 1) >> 6) << 6;
     const uint32_t *L = M.lv[lev];
     for (uint64_t e = pos; e > bs; e--) {
-      if (L[e - 1] < l) { found = (int64_t)(e - 1); break; }
+      const uint64_t x = e - 1;
+      const uint32_t v = (lev == 0 && x >= wlo && x - wlo < wn) ? win[x - wlo] : L[x];
+      if (v < l) { found = (int64_t)x; break; }
     }
     if (found >= 0) break;
     if (lev + 1 >= M.nlev) return -1;
@@ -357,10 +361,16 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t bmax;
+  __shared__ uint32_t win[256 + 64];
   if (threadIdx.x == 0) bmax = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
+    // pairs [i0, i0+256) scan at most 64 entries to their left at level 0
+    const uint64_t wlo = i0 >= 64 ? i0 - 64 : 0;
+    const uint64_t wn = min((uint64_t)(256 + 64), n - wlo);
+    for (uint64_t x = threadIdx.x; x < wn; x += blockDim.x) win[x] = lcp[wlo + x];
+    __syncthreads();
     uint32_t l = 0, a = 0, b = 0, id = 0;
     bool emit = false;
     if (i + 1 < n) {
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
         }
         if (l >= min_len) {
           emit = true;
-          id = (uint32_t)(psv_query(M, i, l) + 1);
+          id = (uint32_t)(psv_query(M, i, l, win, wlo, wn) + 1);
         }
       }
     }
@@ -448,69 +458,136 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, uint64_t m, cons
 // or last position, and rejected once an accepted one does.  Coverage minima
 // come from a sparse table: every live interval writes its priority into the
 // two power-of-two blocks that tile it, then minima are pushed down level by
-// level to single positions.
-__global__ void k_sel_insert(const uint32_t *live, const uint32_t *nlive, const uint32_t *len,
-                             const uint32_t *start, uint32_t *T, uint64_t n) {
-  const uint32_t m = *nlive;
+// level to single positions (levels above kSelSmall one pass each, the rest
+// inside one tiled LDS kernel).  Two tables alternate between rounds; each
+// round clears the other one as it goes.  Round r runs only if round r-1 left
+// undecided candidates, so rounds can be launched ahead of the host.
+constexpr int kSelSmall = 8;
+constexpr int kPushTile = 1024;
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+struct SelArgs {
+  const uint32_t *len, *start;
+  uint32_t *Tc, *To;        // this round's table and the other one; level j at + j*n
+  uint64_t n;
+  int top;
+  uint8_t *state;
+  const uint32_t *live;
+  uint32_t *live_next;
+  uint32_t *nlive;          // nlive[r]: live count of round r
+  uint32_t *undec;          // undec[r]: undecided after round r
+  int r;
+};
+
+__device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.undec[a.r - 1] > 0; }
+
+__global__ void k_sel_insert(SelArgs a) {
+  if (!sel_active(a)) return;
+  const uint32_t m = a.nlive[a.r];
   GRID_STRIDE(q, m) {
-    const uint32_t k = live[q];
-    const uint32_t l = len[k], s = start[k];
+    const uint32_t k = a.live[q];
+    const uint32_t l = a.len[k], s = a.start[k];
     const int j = 31 - __clz((int)l);
-    uint32_t *Tj = T + (uint64_t)j * n;
+    uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
     atomicMin(&Tj[s], k);
     atomicMin(&Tj[s + l - (1u << j)], k);
   }
 }
 
-__global__ void k_sel_push(uint32_t *T, uint64_t n, int j) {
-  const uint32_t *Tj = T + (uint64_t)j * n;
-  uint32_t *Td = T + (uint64_t)(j - 1) * n;
+// Level j -> j-1 for the large levels; clears level j of the other table.
+__global__ void k_sel_push(SelArgs a, int j) {
+  if (!sel_active(a)) return;
+  const uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
+  uint32_t *Td = a.Tc + (uint64_t)(j - 1) * a.n;
+  uint32_t *Oj = a.To + (uint64_t)j * a.n;
   const uint64_t half = 1ull << (j - 1);
-  GRID_STRIDE(x, n) {
+  GRID_STRIDE(x, a.n) {
     uint32_t v = Td[x];
     v = min(v, Tj[x]);
     if (x >= half) v = min(v, Tj[x - half]);
     Td[x] = v;
+    Oj[x] = kInf;
   }
 }
 
-__global__ void k_sel_decide(const uint32_t *live, const uint32_t *nlive, const uint32_t *len,
-                             const uint32_t *start, const uint32_t *T0, uint8_t *state, uint32_t *live_next,
-                             uint32_t *nlive_next, uint32_t *n_undec) {
+// Levels min(top, kSelSmall)..0 for one tile of positions, halos included;
+// writes level 0 and clears levels 0..J of the other table on the tile.
+__global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
+  if (!sel_active(a)) return;
+  constexpr int HMAX = 1 << kSelSmall;
+  __shared__ uint32_t buf[2][kPushTile + HMAX];
+  const int J = min(a.top, kSelSmall);
+  const uint64_t ntiles = (a.n + kPushTile - 1) / kPushTile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t x0 = (int64_t)t * kPushTile;
+    const int64_t x1 = min((int64_t)a.n, x0 + kPushTile);
+    // level J over [x0 - 2^J + 1, x1)
+    int64_t lo = x0 - (1ll << J) + 1;
+    const uint32_t *TJ = a.Tc + (uint64_t)J * a.n;
+    for (int64_t x = lo + threadIdx.x; x < x1; x += blockDim.x) buf[0][x - lo] = x >= 0 ? TJ[x] : kInf;
+    __syncthreads();
+    int c = 0;
+    for (int j = J; j >= 1; j--) {
+      const int64_t half = 1ll << (j - 1);
+      const int64_t nlo = x0 - half + 1;  // level j-1 range [nlo, x1)
+      const uint32_t *Td = a.Tc + (uint64_t)(j - 1) * a.n;
+      for (int64_t x = nlo + threadIdx.x; x < x1; x += blockDim.x) {
+        uint32_t v = x >= 0 ? Td[x] : kInf;
+        v = min(v, buf[c][x - lo]);
+        if (x - half >= lo) v = min(v, buf[c][x - half - lo]);
+        buf[c ^ 1][x - nlo] = v;
+      }
+      __syncthreads();
+      c ^= 1;
+      lo = nlo;
+    }
+    uint32_t *T0 = a.Tc;
+    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+      T0[x] = buf[c][x - lo];
+      for (int j = 0; j <= J; j++) a.To[(uint64_t)j * a.n + x] = kInf;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_sel_decide(SelArgs a) {
+  if (!sel_active(a)) return;
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t und;
   if (threadIdx.x == 0) und = 0;
   __syncthreads();
-  const uint32_t m = *nlive;
+  const uint32_t m = a.nlive[a.r];
+  const uint32_t *T0 = a.Tc;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
     const uint64_t q = q0 + threadIdx.x;
     bool keep_live = false;
+    uint32_t k = 0;
     if (q < m) {
-      const uint32_t k = live[q];
-      uint8_t st = state[k];
+      k = a.live[q];
+      uint8_t st = a.state[k];
       if (st == 0) {
-        const uint32_t l = len[k], s = start[k];
+        const uint32_t l = a.len[k], s = a.start[k];
         const uint32_t t1 = T0[s], t2 = T0[s + l - 1];
         if (t1 >= k && t2 >= k) {
           st = 1;
-        } else if ((t1 < k && state[t1] == 1) || (t2 < k && state[t2] == 1)) {
+        } else if ((t1 < k && a.state[t1] == 1) || (t2 < k && a.state[t2] == 1)) {
           st = 2;
         }
-        if (st != 0) state[k] = st;
+        if (st != 0) a.state[k] = st;
         else atomicAdd(&und, 1u);
       }
       keep_live = st != 2;
     }
     uint32_t tot;
     const uint32_t off = block_excl_sum<256>(keep_live ? 1u : 0u, sh, &tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(nlive_next, tot) : 0u;
+    if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
     __syncthreads();
-    if (keep_live) live_next[base + off] = live[q];
+    if (keep_live) a.live_next[base + off] = k;
     __syncthreads();
   }
-  if (threadIdx.x == 0 && und) atomicAdd(n_undec, und);
+  if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
 }
 
 __global__ void k_iota(uint32_t *p, const uint32_t *n) {
@@ -523,15 +600,16 @@ void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_
   fill_u8(state, m, 0, s);
 }
 
-void sel_round(const uint32_t *live, const uint32_t *nlive, uint64_t live_hint, const uint32_t *len,
-               const uint32_t *start, uint32_t *T, int top, uint64_t n, uint8_t *state, uint32_t *live_next,
-               uint32_t *nlive_next, uint32_t *n_undec, hipStream_t s) {
-  fill_u32(T, (uint64_t)(top + 1) * n, 0xFFFFFFFFu, s);
-  hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, live, nlive, len, start, T, n);
-  for (int j = top; j >= 1; j--)
-    hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, T, n, j);
-  hipLaunchKernelGGL(k_sel_decide, grid_for(live_hint, 256, 8192), dim3(256), 0, s, live, nlive, len, start, T,
-                     state, live_next, nlive_next, n_undec);
+void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
+               uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
+               uint64_t live_hint, hipStream_t s) {
+  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r};
+  hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
+  for (int j = top; j > kSelSmall; j--)
+    hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, a, j);
+  const uint64_t ntiles = (n + kPushTile - 1) / kPushTile;
+  hipLaunchKernelGGL(k_sel_push_tile, dim3((unsigned)std::min<uint64_t>(ntiles, 4096)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sel_decide, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
 }
 
 // Exact sequential completion for whatever is still undecided after the

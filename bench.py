@@ -1,14 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark: tokens analysed per second by the HIP FindRepeats path.
 
-Workload (default): one window of n = 2^20 uint64 task-hash tokens, a nested
-loop stream (outer body 200 tokens with an inner body of 30 tokens repeated
-10 times, alphabet 2^16, 1% substitutions, 0.5% insertions), min repeat length
-16.  One step = one complete analysis of the window (rank compression, suffix
-array, LCP, candidates, sort, greedy selection, output) with the tokens
-already resident in device memory.
+Default workload (batched): 4096 independent windows, lengths log-uniform in
+[256, 65536] (48.8 M tokens in total), each a loop stream (body length
+uniform in [10, 500] from an alphabet of 2^12 hashes, 5% substitutions), min
+repeat length 8.  One step = one complete analysis of every window (rank
+compression, suffix array, LCP, candidates, sort, greedy selection, output)
+as one packed launch sequence, replayed as a HIP graph, tokens resident in
+device memory.  Reported beside it: the same windows through one plain
+per-window analysis each, the single-window n = 2^20 nested-loop workload,
+and the continuous-batching server on a Poisson trace (p50/p99 latency).
 
-Prints one JSON line (rank 0).  Runs on one GPU only.
+Prints one JSON line.  Runs on one GPU only.
 """
 from __future__ import annotations
 
@@ -24,9 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per entry of the doubling rounds' LDS sort-and-regroup
-# kernel: read key + suffix (8), write the sorted suffix (4), write its new rank
-# (4) and its rank snapshot for the LCP stage (4).
+# Algorithmic bytes per entry of the doubling rounds' LDS sort / grouping
+# kernels: read key + suffix (8), write the sorted suffix (4), write its new
+# rank (4) and its rank snapshot for the LCP stage (4).
 LDS_SA_BYTES_PER_ENTRY = 20
 LDS_SA_TAG = 1
 
@@ -36,21 +39,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="config1", choices=["config0", "config1", "config2"])
+    ap.add_argument("--workload", default="config3", choices=["config0", "config1", "config2", "config3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--profile-steps", type=int, default=0,
-                    help="only run this many steps, no baseline (for profilers)")
-    ap.add_argument("--batched", action="store_true",
-                    help="also time the 4096-window batch: one packed launch sequence vs per-window calls")
-    ap.add_argument("--serve", action="store_true",
-                    help="also replay the Poisson serving trace through the server and the plain FIFO path")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-window, single-window and serving legs")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many steps of the main workload (for profilers)")
     return ap.parse_args()
 
 
-def workload(name):
+def single_workload(name):
     from paper_2406_18111_amd import synth
     if name == "config0":
         t, m = synth.config0()
@@ -65,40 +67,80 @@ def workload(name):
     return t, m, desc
 
 
-def cpu_baseline(t, m, seconds):
+def pack(wins):
+    off = np.zeros(len(wins) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(w) for w in wins])
+    return np.concatenate(wins), off
+
+
+def cpu_baseline_windows(wins, m, seconds):
+    """The oracle over the windows in order until `seconds` of CPU work."""
+    import oracle
+    tok = 0
+    k = 0
+    t0 = time.perf_counter()
+    while k < len(wins):
+        oracle.find_repeats(wins[k], m)
+        tok += len(wins[k])
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": tok / el, "unit": "tokens/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of the %d windows (%d tokens) by the single-threaded C oracle, %.1f s"
+                      % (k, len(wins), tok, el)}
+
+
+def cpu_baseline_single(t, m, seconds):
     import oracle
     reps = 0
     t0 = time.perf_counter()
     while True:
         oracle.find_repeats(t, m)
         reps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
+        if time.perf_counter() - t0 >= seconds:
             break
+    el = time.perf_counter() - t0
     return {"value": reps * len(t) / el, "unit": "tokens/s", "cores": 1, "kind": "oracle",
             "sample": "%d full analyses of the same window by the single-threaded C oracle (%.1f s)" % (reps, el)}
 
 
-def batched_leg(ctx, reps=3):
-    """4096 windows (log-uniform 256..65536, loop bodies 10..500, alphabet 2^12,
-    5% substitutions, min_len 8): one packed launch sequence vs one plain
-    per-window analysis per window, tokens resident on the device."""
+def timed_steps(ctx, step, steps):
+    """Runs `steps` steps with live kernel timing; returns seconds/step, kernel
+    totals, per-stage device ms and the last step's output."""
     import torch
-    from paper_2406_18111_amd import synth
-    wins, m = synth.config3()
-    off = np.zeros(len(wins) + 1, dtype=np.uint64)
-    off[1:] = np.cumsum([len(w) for w in wins])
-    toks = np.concatenate(wins)
-    dev = torch.from_numpy(toks.view(np.int64)).cuda()
-    total = int(off[-1])
-    ctx.analyze_batch_dev(dev, off, m)  # warm-up (workspace growth)
+    kprof = {"launches": 0, "ms": 0.0, "elems": 0}
+    stage_tot = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        rows, oo = ctx.analyze_batch_dev(dev, off, m)
+    for _ in range(steps):
+        out = step()
+        kp = ctx.kernel_profile()
+        for k in kprof:
+            kprof[k] += kp[k]
+        st = ctx.stage_ms()
+        stage_tot = st if stage_tot is None else {k: stage_tot[k] + v for k, v in st.items()}
     torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
-    views = [dev[int(off[w]):int(off[w + 1])] for w in range(len(wins))]
+    el = (time.perf_counter() - t0) / steps
+    return el, kprof, {k: v / steps for k, v in stage_tot.items()}, out
+
+
+def roofline(kprof, steps):
+    if not kprof["launches"]:
+        return None
+    avg_ms = kprof["ms"] / kprof["launches"]
+    bytes_per_launch = kprof["elems"] * LDS_SA_BYTES_PER_ENTRY / kprof["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "LDS sort + LDS grouping kernels of the doubling rounds (k_lds_sort<0>, k_lds_group<0>)",
+            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
+            "launches_per_step": kprof["launches"] / steps}
+
+
+def per_window_leg(ctx, dev, off, m):
+    import torch
+    views = [dev[int(off[w]):int(off[w + 1])] for w in range(len(off) - 1)]
     ctx.analyze_dev(views[0], m)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -107,11 +149,7 @@ def batched_leg(ctx, reps=3):
         r, _ = ctx.analyze_dev(v, m)
         nrows += int(r.shape[0])
     torch.cuda.synchronize()
-    tw = time.perf_counter() - t0
-    return {"workload": "config3", "windows": len(wins), "tokens": total, "min_len": m,
-            "batched_tokens_per_s": total / tb, "batched_ms": tb * 1e3,
-            "per_window_tokens_per_s": total / tw, "per_window_ms": tw * 1e3,
-            "speedup": tw / tb, "rows": int(oo[-1]), "rows_per_window_path": nrows}
+    return time.perf_counter() - t0, nrows
 
 
 def serve_leg(seconds, slots):
@@ -119,7 +157,6 @@ def serve_leg(seconds, slots):
     arrivals at 2000/s, windows log-uniform 1024..2^20, min_len 16): the
     continuous-batching server vs the plain one-window-at-a-time FIFO path."""
     import threading
-    import torch
     from paper_2406_18111_amd import Context, synth
     reqs = list(synth.config4_trace(duration=seconds))
     offered = sum(len(r.tokens) for r in reqs)
@@ -127,8 +164,7 @@ def serve_leg(seconds, slots):
     def replay_server():
         srv = Context(0)
         srv.server_start(slots=slots)
-        # warm the slots' workspaces
-        for r in reqs[: slots * 2]:
+        for r in reqs[: slots * 2]:  # warm the slots' workspaces
             tk = srv.submit(r.tokens, 16, r.stream)
             while srv.fetch(tk) is None:
                 time.sleep(0.0005)
@@ -162,8 +198,7 @@ def serve_leg(seconds, slots):
         th.join()
         srv.server_stop()
         srv.close()
-        span = max(done_t) - reqs[0].arrival
-        return lat, span
+        return lat, max(done_t) - reqs[0].arrival
 
     def replay_fifo():
         ctx = Context(0)
@@ -198,70 +233,66 @@ def main():
               "(see DESIGN.md, 'Sharding').", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2406_18111_amd import Context
+    from paper_2406_18111_amd import Context, synth
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    t, m, desc = workload(args.workload)
-    n = len(t)
-    dev = torch.from_numpy(t.view(np.int64) if t.dtype == np.uint64 else t.view(np.int32)).cuda()
     ctx = Context(0)
+    ctx.set_graphs(not args.no_graphs)
     steps = args.profile_steps or args.steps
     warm = 1 if args.profile_steps else args.warmup
-    for _ in range(warm):
-        ctx.analyze_dev(dev, m)
-    torch.cuda.synchronize()
-    stage_tot = None
-    kprof = {"launches": 0, "ms": 0.0, "elems": 0}
-    ctx.profile_kernel(LDS_SA_TAG)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        rows, _ = ctx.analyze_dev(dev, m)
-        st = ctx.stage_ms()
-        stage_tot = st if stage_tot is None else {k: stage_tot[k] + v for k, v in st.items()}
-        kp = ctx.kernel_profile()
-        for k in kprof:
-            kprof[k] += kp[k]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ctx.profile_kernel(0)
-    ms = el * 1e3 / steps
-    value = n * steps / el
-    counters = ctx.counters()
-    out = {
-        "metric": "tokens analyzed/sec (SA+LCP+repeat mining)",
-        "value": value,
-        "unit": "tokens/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warm,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32" if t.dtype == np.uint32 else "u64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "n": n, "min_len": m,
-                   "windows": 1},
-        "stage_ms": {k: v / steps for k, v in stage_tot.items()},
-        "counters": counters,
-        "rows": int(rows.shape[0]),
-    }
-    if kprof["launches"]:
-        avg_ms = kprof["ms"] / kprof["launches"]
-        bytes_per_launch = kprof["elems"] * LDS_SA_BYTES_PER_ENTRY / kprof["launches"]
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "LDS sort + LDS grouping kernels of the doubling rounds (k_lds_sort<0>, k_lds_group<0>)",
-                           "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
-                           "launches_per_step": kprof["launches"] / steps}
-    if args.batched and not args.profile_steps:
-        out["batched"] = batched_leg(ctx)
-    if args.serve and not args.profile_steps:
-        out["serving"] = serve_leg(args.serve_seconds, args.serve_slots)
-    if not args.profile_steps and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(t, m, args.cpu_seconds)
+    out = {"metric": "tokens analyzed/sec (SA+LCP+repeat mining)", "unit": "tokens/s", "n_gpus": 1,
+           "steps": steps, "warmup": warm, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic"}
+    if args.workload == "config3":
+        wins, m = synth.config3()
+        toks, off = pack(wins)
+        dev = torch.from_numpy(toks.view(np.int64)).cuda()
+        total = int(off[-1])
+        ctx.profile_kernel(LDS_SA_TAG)
+        for _ in range(warm):
+            ctx.analyze_batch_dev(dev, off, m)
+        sec, kprof, stages, res = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), steps)
+        ctx.profile_kernel(0)
+        out.update({"value": total / sec, "ms_per_step": sec * 1e3, "dtype": "u64",
+                    "config": {"workload": "config3", "windows": len(wins), "tokens": total, "min_len": m,
+                               "description": "4096 windows, lengths log-uniform 256..65536, loop bodies 10..500, "
+                                              "alphabet 2^12, 5% substitutions; one packed launch sequence "
+                                              "replayed as a HIP graph" + (" (graphs off)" if args.no_graphs else "")},
+                    "counters": ctx.counters(), "rows": int(res[1][-1]), "graph": ctx.graph_stats()})
+        rf = roofline(kprof, steps)
+        if rf:
+            out["roofline"] = rf
+        if not args.profile_steps and not args.no_extras:
+            tw, nrows = per_window_leg(ctx, dev, off, m)
+            out["per_window"] = {"tokens_per_s": total / tw, "ms": tw * 1e3, "rows": nrows,
+                                 "batched_speedup": tw / sec}
+        if not args.profile_steps and not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_windows(wins, m, args.cpu_seconds)
+        if not args.profile_steps and not args.no_extras:
+            t1, m1, _ = single_workload("config1")
+            d1 = torch.from_numpy(t1.view(np.int64)).cuda()
+            ctx.analyze_dev(d1, m1)
+            s1, _, st1, _ = timed_steps(ctx, lambda: ctx.analyze_dev(d1, m1), 10)
+            out["single_window_config1"] = {"tokens_per_s": len(t1) / s1, "ms": s1 * 1e3, "stage_ms": st1}
+            out["serving"] = serve_leg(args.serve_seconds, args.serve_slots)
+    else:
+        t, m, desc = single_workload(args.workload)
+        n = len(t)
+        dev = torch.from_numpy(t.view(np.int64) if t.dtype == np.uint64 else t.view(np.int32)).cuda()
+        for _ in range(warm):
+            ctx.analyze_dev(dev, m)
+        ctx.profile_kernel(LDS_SA_TAG)
+        sec, kprof, stages, res = timed_steps(ctx, lambda: ctx.analyze_dev(dev, m), steps)
+        ctx.profile_kernel(0)
+        out.update({"value": n / sec, "ms_per_step": sec * 1e3, "dtype": "u32" if t.dtype == np.uint32 else "u64",
+                    "config": {"workload": args.workload, "description": desc, "n": n, "min_len": m, "windows": 1},
+                    "stage_ms": stages, "counters": ctx.counters(), "rows": int(res[0].shape[0])})
+        rf = roofline(kprof, steps)
+        if rf:
+            out["roofline"] = rf
+        if not args.profile_steps and not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_single(t, m, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -125,6 +125,17 @@ int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t
                           uint32_t num_windows, uint32_t min_len, apo_candidate *d_out,
                           uint64_t out_cap, uint64_t *h_out_offsets, void *hip_stream);
 
+/* Batched analyses enqueue their whole launch sequence without host
+ * synchronisation (round counts bounded by the longest window) and, when
+ * enabled (default), record it as a HIP graph that is replayed for later
+ * batches of the same shape (same token pointer, total length, window count,
+ * longest window, min_len and kernel parameters); window offsets are uploaded
+ * outside the graph.  on = 0 disables capture. */
+int apo_set_graphs(apo_ctx *ctx, int on);
+
+/* Number of graph captures and replays made by this context. */
+int apo_graph_stats(apo_ctx *ctx, uint64_t *captures, uint64_t *replays);
+
 /* ---- stage outputs, for checking each stage against a reference ---- */
 
 /* Suffix array of one device window (Section 4.2, SuffixArray(S)):
@@ -206,8 +217,41 @@ int apo_poll(apo_ctx *ctx, uint64_t ticket, int *done);
 int apo_fetch(apo_ctx *ctx, uint64_t ticket, apo_candidate *out, uint32_t out_cap,
               uint32_t *out_n, uint64_t *lat_ns);
 
+/* Give up a ticket: its result is dropped now if ready, else when it is. */
+int apo_release(apo_ctx *ctx, uint64_t ticket);
+
 /* Drain in-flight work, stop the server threads. */
 int apo_server_stop(apo_ctx *ctx);
+
+/* ---- trace finder: history buffer + ruler-function sampling ---- */
+
+/* Section 4.4: after the i-th block (i >= 1) of block_tokens tokens, the
+ * analysed slice is the last block_tokens * 2^v(i) tokens, v(i) the number of
+ * trailing zero bits of i, capped at `capacity`.  Returns that length (0 for
+ * i == 0). */
+uint64_t apo_ruler_slice(uint64_t block_index, uint32_t block_tokens, uint64_t capacity);
+
+typedef struct apo_tracer apo_tracer;
+
+/* A trace finder for one task stream (Algorithm 1's TraceFinder): keeps the
+ * last `capacity` tokens and, after every block of `block_tokens` new tokens,
+ * submits the ruler slice of the history to ctx's server (apo_server_start
+ * must have been called) as an asynchronous FindRepeats with min_len. */
+int apo_tracer_create(apo_ctx *ctx, uint32_t stream_id, uint32_t block_tokens, uint32_t capacity,
+                      uint32_t min_len, apo_tracer **out);
+
+/* Appends n tokens (copied); *submitted (nullable) gets the number of
+ * analyses submitted.  Errors of apo_submit are passed through. */
+int apo_tracer_push(apo_tracer *t, const uint64_t *tokens, uint32_t n, uint32_t *submitted);
+
+/* Oldest finished analysis in submission order: slice start (in stream
+ * positions) and length, and its rows (start relative to the slice).
+ * APO_EAGAIN if it is not ready or none is pending. */
+int apo_tracer_poll(apo_tracer *t, uint64_t *slice_begin, uint64_t *slice_len, apo_candidate *out,
+                    uint32_t out_cap, uint32_t *out_n);
+
+/* Frees the tracer (results still queued are dropped). */
+int apo_tracer_destroy(apo_tracer *t);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,8 @@ SIGNATURES = {
     "apo_analyze_window_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _U32, _P, _P, _U32, _P, _P]),
     "apo_analyze_batch": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P]),
     "apo_analyze_batch_dev": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P, _P]),
+    "apo_set_graphs": (_I, [_P, _I]),
+    "apo_graph_stats": (_I, [_P, _P, _P]),
     "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_candidates_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
@@ -52,6 +54,12 @@ SIGNATURES = {
     "apo_poll": (_I, [_P, _U64, _P]),
     "apo_fetch": (_I, [_P, _U64, _P, _U32, _P, _P]),
     "apo_server_stop": (_I, [_P]),
+    "apo_release": (_I, [_P, _U64]),
+    "apo_ruler_slice": (_U64, [_U64, _U32, _U64]),
+    "apo_tracer_create": (_I, [_P, _U32, _U32, _U32, _U32, ctypes.POINTER(_P)]),
+    "apo_tracer_push": (_I, [_P, _P, _U32, _P]),
+    "apo_tracer_poll": (_I, [_P, _P, _P, _P, _U32, _P]),
+    "apo_tracer_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -198,6 +206,14 @@ class Context:
         _check(rc, "apo_analyze_batch_dev")
         return rows[: int(oo[-1])], oo
 
+    def set_graphs(self, on: bool):
+        _check(self._lib.apo_set_graphs(self._h, int(bool(on))), "apo_set_graphs")
+
+    def graph_stats(self):
+        c, r = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(self._lib.apo_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r)), "apo_graph_stats")
+        return {"captures": c.value, "replays": r.value}
+
     def suffix_array_dev(self, tokens, stream=None):
         import torch
         bits = 64 if tokens.element_size() == 8 else 32
@@ -307,3 +323,52 @@ class Context:
 
     def server_stop(self):
         _check(self._lib.apo_server_stop(self._h), "apo_server_stop")
+
+
+def ruler_slice(block_index: int, block_tokens: int, capacity: int) -> int:
+    """Length of the slice analysed after block `block_index` (Section 4.4)."""
+    return int(load().apo_ruler_slice(int(block_index), int(block_tokens), int(capacity)))
+
+
+class Tracer:
+    """Trace finder for one task stream on a Context whose server is running."""
+
+    def __init__(self, ctx: Context, block_tokens: int = 500, capacity: int = 5000, min_len: int = 25,
+                 stream_id: int = 0):
+        h = ctypes.c_void_p()
+        _check(ctx._lib.apo_tracer_create(ctx._h, int(stream_id), int(block_tokens), int(capacity), int(min_len),
+                                          ctypes.byref(h)), "apo_tracer_create")
+        self._h, self._ctx = h, ctx
+
+    def push(self, tokens) -> int:
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        sub = ctypes.c_uint32(0)
+        _check(self._ctx._lib.apo_tracer_push(self._h, _np_ptr(t) if len(t) else None, len(t), ctypes.byref(sub)),
+               "apo_tracer_push")
+        return sub.value
+
+    def poll(self, cap: int = 1 << 14):
+        """(slice_begin, slice_len, rows) of the oldest finished analysis, or None."""
+        while True:
+            rows = np.zeros(max(cap, 1), dtype=ROW_DTYPE)
+            b, ln, n = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint32(0)
+            rc = self._ctx._lib.apo_tracer_poll(self._h, ctypes.byref(b), ctypes.byref(ln), _np_ptr(rows), len(rows),
+                                                ctypes.byref(n))
+            if rc == APO_EAGAIN:
+                return None
+            if rc == APO_ERANGE:
+                cap = n.value
+                continue
+            _check(rc, "apo_tracer_poll")
+            return b.value, ln.value, rows[: n.value].copy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._ctx._lib.apo_tracer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

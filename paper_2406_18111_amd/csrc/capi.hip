@@ -27,6 +27,7 @@ struct Request {
   std::chrono::steady_clock::time_point t_submit, t_done;
   int status = 0;
   bool done = false;
+  bool discard = false;  // released by the caller: drop the result when done
 };
 
 struct Slot {
@@ -80,6 +81,28 @@ struct Server {
 
 }  // namespace apo
 
+namespace apo {
+// A captured batch launch sequence and the shape it was captured for.
+struct GraphCache {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *tok = nullptr;
+  uint64_t total = 0, maxwin = 0;
+  uint32_t W = 0, min_len = 0;
+  int tile = 0, digit = 0, ktag = 0;
+  int kev_n = 0;                // timed launches recorded in the graph
+  int kround[kMaxTimed] = {0};
+  void *mem = nullptr;
+  hipStream_t stream = nullptr;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
+}  // namespace apo
+
 struct apo_ctx {
   int device = 0;
   size_t budget = 0;
@@ -87,6 +110,9 @@ struct apo_ctx {
   apo::Workspace ws;
   apo::RunInfo info;
   apo::TuneTable tune;
+  apo::GraphCache gc;
+  bool graphs = true;         // capture/replay batched launch sequences
+  uint64_t graph_replays = 0, graph_captures = 0;
   std::unique_ptr<apo::Server> server;
 };
 
@@ -133,6 +159,7 @@ extern "C" int apo_destroy(apo_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   apo_server_stop(ctx);
   (void)hipStreamSynchronize(ctx->stream);
+  ctx->gc.reset();
   ctx->ws.release();
   (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -239,16 +266,73 @@ static int check_offsets(const uint64_t *off, uint32_t W, uint64_t &total) {
   return APO_OK;
 }
 
+// One batched analysis of device tokens.  The launch sequence is sync-free;
+// with graphs enabled it is captured once per shape and replayed.  If the
+// enqueued selection rounds did not decide every candidate (adversarial
+// inputs), the batch is rerun host-driven.
 static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
                         hipStream_t s, uint64_t total) {
   std::vector<uint64_t> norm(W + 1);
+  uint64_t maxwin = 0;
   for (uint32_t w = 0; w <= W; w++) norm[w] = off[w] - off[0];
+  for (uint32_t w = 0; w < W; w++) maxwin = std::max<uint64_t>(maxwin, norm[w + 1] - norm[w]);
   int rc = ctx->ws.ensure(std::max<uint64_t>(total, 2), W, ctx->budget);
   if (rc) return map_rc(rc);
   int tl, db;
   ctx->tune.pick(total, tl, db);
   ctx->ws.eng.set_params(tl, db);
-  rc = run_pipeline(ctx->ws, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info);
+  Workspace &w = ctx->ws;
+  if (!ctx->graphs) {
+    rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::FREE);
+    if (rc == 1) rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::HOST);
+    return map_rc(rc);
+  }
+  GraphCache &G = ctx->gc;
+  const bool hit = G.exec && G.tok == d_tok && G.total == total && G.W == W && G.maxwin == maxwin &&
+                   G.min_len == min_len && G.tile == tl && G.digit == db && G.mem == w.mem && G.stream == s &&
+                   G.ktag == w.ktag;
+  if (hipMemcpyAsync(w.d_off, norm.data(), (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return APO_EDEVICE;
+  if (!hit) {
+    G.reset();
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return APO_EDEVICE;
+    rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::CAPTURE);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc || e != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return rc ? map_rc(rc) : APO_EDEVICE;
+    }
+    if (hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      G.exec = nullptr;
+      return APO_EDEVICE;
+    }
+    G.graph = g;
+    G.tok = d_tok;
+    G.total = total;
+    G.W = W;
+    G.maxwin = maxwin;
+    G.min_len = min_len;
+    G.tile = tl;
+    G.digit = db;
+    G.mem = w.mem;
+    G.stream = s;
+    G.ktag = w.ktag;
+    G.kev_n = w.kev_n;
+    for (int k = 0; k < w.kev_n; k++) G.kround[k] = w.kround[k];
+    ctx->graph_captures++;
+  } else {
+    ctx->graph_replays++;
+  }
+  w.kev_n = G.kev_n;
+  for (int k = 0; k < G.kev_n; k++) w.kround[k] = G.kround[k];
+  if (hipGraphLaunch(G.exec, s) != hipSuccess) return APO_EDEVICE;
+  ctx->info = RunInfo{};
+  rc = finish_run(w, total, 2 * total, kSelFreeRounds, ctx->info, s, false);
+  if (rc == 1) rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::HOST);
   return map_rc(rc);
 }
 
@@ -385,6 +469,20 @@ extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   const int k = std::min(nvals, 8);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
+}
+
+extern "C" int apo_set_graphs(apo_ctx *ctx, int on) {
+  if (!ctx) return APO_EINVAL;
+  ctx->graphs = on != 0;
+  if (!ctx->graphs) ctx->gc.reset();
+  return APO_OK;
+}
+
+extern "C" int apo_graph_stats(apo_ctx *ctx, uint64_t *captures, uint64_t *replays) {
+  if (!ctx || !captures || !replays) return APO_EINVAL;
+  *captures = ctx->graph_captures;
+  *replays = ctx->graph_replays;
+  return APO_OK;
 }
 
 extern "C" int apo_profile_kernel(apo_ctx *ctx, int tag) {
@@ -571,6 +669,7 @@ static void slot_loop(Server *S, Slot *sl) {
         R.tokens.shrink_to_fit();
         R.t_done = now;
         R.done = true;
+        if (R.discard) S->tickets.erase(R.ticket);
       }
     }
     S->batches++;
@@ -662,6 +761,17 @@ extern "C" int apo_fetch(apo_ctx *ctx, uint64_t ticket, apo_candidate *out, uint
   if (lat_ns)
     *lat_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(R.t_done - R.t_submit).count();
   S->tickets.erase(it);
+  return APO_OK;
+}
+
+extern "C" int apo_release(apo_ctx *ctx, uint64_t ticket) {
+  if (!ctx || !ctx->server) return APO_EINVAL;
+  Server *S = ctx->server.get();
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return APO_ENOTFOUND;
+  if (it->second->done) S->tickets.erase(it);
+  else it->second->discard = true;
   return APO_OK;
 }
 

@@ -78,3 +78,46 @@ __device__ __forceinline__ int class_of(uint32_t len) {
 }
 
 }  // namespace apo
+
+namespace apo {
+
+// Wave-aggregated increment of an LDS/global counter: when every active lane
+// of the wavefront targets the same counter (the common case for the heavily
+// repeated keys of loop-structured token streams), one lane adds the number
+// of active lanes and the others derive their slot from their rank; otherwise
+// each lane increments on its own.  Returns the counter value before this
+// lane's increment (a unique slot among all callers).
+__device__ __forceinline__ uint32_t agg_inc(uint32_t *ctr) {
+  const uint64_t active = __ballot(1);
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)active) - 1;
+  const uintptr_t mine = reinterpret_cast<uintptr_t>(ctr);
+  const uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+  const bool same = __all(lo == (uint32_t)__shfl((int)lo, leader, 64) && hi == (uint32_t)__shfl((int)hi, leader, 64));
+  if (same) {
+    const uint32_t rank = (uint32_t)__popcll(active & ((1ull << lane) - 1ull));
+    uint32_t old = 0;
+    if (lane == leader) old = atomicAdd(ctr, (uint32_t)__popcll(active));
+    old = (uint32_t)__shfl((int)old, leader, 64);
+    return old + rank;
+  }
+  return atomicAdd(ctr, 1u);
+}
+
+// Same, when only the total matters.
+__device__ __forceinline__ void agg_add(uint32_t *ctr, uint32_t v) {
+  const uint64_t active = __ballot(1);
+  const int lane = __lane_id();
+  const int leader = __ffsll((unsigned long long)active) - 1;
+  const uintptr_t mine = reinterpret_cast<uintptr_t>(ctr);
+  const uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+  const bool same = __all(lo == (uint32_t)__shfl((int)lo, leader, 64) && hi == (uint32_t)__shfl((int)hi, leader, 64));
+  if (same) {
+    // every lane adds the same v in all call sites
+    if (lane == leader) atomicAdd(ctr, v * (uint32_t)__popcll(active));
+    return;
+  }
+  atomicAdd(ctr, v);
+}
+
+}  // namespace apo

@@ -9,6 +9,14 @@ namespace apo {
 
 enum class Stop { SA, LCP, CANDS, FULL };
 
+// HOST: the host reads device counts between stages to size launches and stop
+// loops early.  FREE: everything is enqueued with host upper bounds (rounds
+// for the longest window, counts from capacities) and one sync at the end.
+// CAPTURE: FREE without timing events and without the final sync, for
+// recording into a HIP graph.
+enum class Mode { HOST, FREE, CAPTURE };
+constexpr int kSelFreeRounds = 12;
+
 enum Cnt {
   CNT_ND = 0, CNT_C, CNT_MAXL, CNT_M, CNT_NLIVE0, CNT_NLIVE1, CNT_UNDEC, CNT_A, CNT_NROWS,
   CNT_RANGE = 10,  // two 64-bit words, 8-byte aligned
@@ -87,6 +95,13 @@ struct Workspace {
 // `bits` (32/64) bits, windows given by host offsets h_off[0..W] (global,
 // ascending, h_off[0] == 0).  Results stay in the workspace.
 int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
-                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info);
+                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info, Mode mode = Mode::HOST);
+int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t *wid, const uint32_t *wbeg,
+                uint64_t m_bound, bool host, hipStream_t s);
+// sel_launched: selection rounds enqueued by a sync-free run (-1: host-driven).
+// Returns 1 when a sync-free run left candidates undecided (the caller then
+// reruns host-driven).
+int finish_run(Workspace &w, uint64_t N, uint64_t m_bound, int sel_launched, RunInfo &info, hipStream_t s,
+               bool stamps);
 
 }  // namespace apo

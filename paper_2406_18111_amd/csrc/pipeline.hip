@@ -13,8 +13,8 @@ int hip_fail(hipError_t e, const char *what, const char *file, int line) {
   return e == hipErrorOutOfMemory ? -2 : -4;
 }
 
-__global__ void k_set_range(uint64_t *r, uint32_t count) {
-  if (threadIdx.x == 0) { r[0] = 0; r[1] = count; }
+__global__ void k_set_range(uint64_t *r, const uint32_t *count) {
+  if (threadIdx.x == 0) { r[0] = 0; r[1] = *count; }
 }
 
 static uint64_t pow2_at_least(uint64_t x) {
@@ -179,47 +179,69 @@ static int read_counters(Workspace &w, hipStream_t s) {
   return 0;
 }
 
-// Multi-key sort of `count` items whose ids are 0..count-1: level k orders by
-// fields[k][id] (c - field when subs[k]) within the groups of level k-1.  The
-// final order is left in eng.val[0]; keep[slot] = 0 marks exact duplicates
-// of the previous slot at the last level (when keep != nullptr).
-static int sort_plain(Workspace &w, uint32_t count, const uint32_t *const *fields, const int *subs,
-                      const uint32_t *consts, const int *bits, int nlevels, uint8_t *keep, hipStream_t s) {
+// Multi-key sort of *count_dev items whose ids are 0..count-1 (bound: host
+// upper bound of the count): level k orders by fields[k][id] (c - field when
+// subs[k], c read from c_devs[k]) within the groups of level k-1.  The final
+// order is left in eng.val[0]; keep[slot] = 0 marks exact duplicates of the
+// previous slot at the last level (when keep != nullptr).
+static void sort_plain(Workspace &w, const uint32_t *count_dev, uint64_t bound, const uint32_t *const *fields,
+                       const int *subs, const uint32_t *const *c_devs, const int *bits, int nlevels, uint8_t *keep,
+                       hipStream_t s) {
   SortEngine &E = w.eng;
   int cur = 0;
   E.reset_counters(s);
   E.round_begin(cur, s);
-  E.iota_val(count, s);
-  E.gather_field(cur, fields[0], count, subs[0], consts[0], count, s);
+  E.iota_val(count_dev, bound, s);
+  E.gather_field(cur, fields[0], count_dev, subs[0], c_devs[0], 0, bound, s);
   uint64_t *rng = reinterpret_cast<uint64_t *>(w.dcnt + CNT_RANGE);
-  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, s, rng, count);
+  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, s, rng, count_dev);
   E.init_units(cur, rng, 1, 0, (uint32_t)bits[0], s);
-  if (keep) fill_u8(keep, count, 1, s);
+  if (keep) fill_u8_dev(keep, count_dev, bound, 1, s);
   for (int L = 0; L < nlevels; L++) {
     const int last = (L == nlevels - 1);
     const uint32_t nb = last ? 0u : (uint32_t)bits[L + 1];
-    if (count > (1u << E.tile_log())) E.msd(cur, count, bits[L], s);
-    E.lds_plain(cur, nb, last, keep ? keep : w.keep, count, s);
-    E.bulk_plain(cur, nb, last, keep ? keep : w.keep, count, s);
+    if (bound > (1u << E.tile_log())) E.msd(cur, bound, bits[L], s);
+    E.lds_plain(cur, nb, last, keep ? keep : w.keep, bound, s);
+    E.bulk_plain(cur, nb, last, keep ? keep : w.keep, bound, s);
     if (!last) {
       cur ^= 1;
       E.round_begin(cur, s);
-      E.gather_field(cur, fields[L + 1], 0, subs[L + 1], consts[L + 1], count, s);
+      E.gather_field(cur, fields[L + 1], nullptr, subs[L + 1], c_devs[L + 1], 0, bound, s);
     }
   }
-  return 0;
 }
 
-static void stamp(Workspace &w, int k, hipStream_t s) { (void)hipEventRecord(w.ev[k], s); }
+static void stamp(Workspace &w, int k, hipStream_t s, bool on) {
+  if (on) (void)hipEventRecord(w.ev[k], s);
+}
+
+// Reads the device counters of a finished analysis into `info`.
+static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
+  info.sigma = w.hcnt[CNT_ND];
+  info.cands = w.hcnt[CNT_C];
+  info.maxl = w.hcnt[CNT_MAXL];
+  info.cands_dedup = w.hcnt[CNT_M];
+  info.accepted = w.hcnt[CNT_A];
+  info.rows = w.hcnt[CNT_NROWS];
+  info.active_sum = 0;
+  for (int k = 0; k < w.nsnap; k++) {
+    info.active_sum += (k == 0) ? N : w.hrhist[4 * (k - 1)];
+    if (w.hrhist[4 * k] == 0) { info.rounds = (uint32_t)k + 1; break; }
+  }
+}
 
 int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
-                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info) {
+                 uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info, Mode mode) {
   info = RunInfo{};
   SortEngine &E = w.eng;
   SortBufs &B = E.bufs();
   int rc;
-  stamp(w, 0, s);
-  APO_HIP_TRY(hipMemcpyAsync(w.d_off, h_off, (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  const bool host = mode == Mode::HOST;
+  const bool stamps = mode != Mode::CAPTURE;
+  uint32_t *dc = w.dcnt;
+  stamp(w, 0, s, stamps);
+  if (mode != Mode::CAPTURE)  // a captured sequence expects d_off to be uploaded already
+    APO_HIP_TRY(hipMemcpyAsync(w.d_off, h_off, (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   const bool batch = W > 1;
   const uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr;
   if (batch) {
@@ -228,7 +250,10 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     wend = w.wend;
     wid = w.wid;
   }
-  fill_u32(w.dcnt, CNT_RANGE, 0, s);
+  uint64_t maxwin = 0;
+  for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
+  fill_u32(dc, CNT_RANGE, 0, s);
+  fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
   // ---- order-preserving token ranks
   const uint32_t *key0;
@@ -237,46 +262,47 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     const uint64_t hc = pow2_at_least(2 * N);
     fill_u32(w.htab, hc, kNone, s);
-    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, w.dcnt + CNT_ND, s);
-    if ((rc = read_counters(w, s))) return rc;
-    const uint32_t nd = w.hcnt[CNT_ND];
-    info.sigma = nd;
-    hash_fields(tok, w.dist_idx, w.dcnt + CNT_ND, w.dhi, w.dlo, nd, s);
+    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, s);
+    uint64_t nd_bound = N;
+    if (host) {
+      if ((rc = read_counters(w, s))) return rc;
+      nd_bound = w.hcnt[CNT_ND];
+    }
+    hash_fields(tok, w.dist_idx, dc + CNT_ND, w.dhi, w.dlo, nd_bound, s);
     const uint32_t *f[2] = {w.dhi, w.dlo};
     const int sub[2] = {0, 0};
-    const uint32_t cs[2] = {0, 0};
+    const uint32_t *cd[2] = {nullptr, nullptr};
     const int bb[2] = {32, 32};
-    sort_plain(w, nd, f, sub, cs, bb, 2, nullptr, s);
-    hash_assign(B.val[0], w.dcnt + CNT_ND, w.dist_slot, w.hrank, nd, s);
+    sort_plain(w, dc + CNT_ND, nd_bound, f, sub, cd, bb, 2, nullptr, s);
+    hash_assign(B.val[0], dc + CNT_ND, w.dist_slot, w.hrank, nd_bound, s);
     hash_lookup(tok, N, w.htab, hc - 1, w.hrank, w.tokrank, s);
     key0 = w.tokrank;
-    bits0 = (uint32_t)bit_length_u64(nd);
+    bits0 = (uint32_t)bit_length_u64(nd_bound);
   } else {
     key0 = static_cast<const uint32_t *>(d_tok);
     bits0 = 32;
   }
-  stamp(w, 1, s);
+  stamp(w, 1, s, stamps);
 
   // ---- suffix array by prefix doubling
-  // Rounds are launched `spec` at a time and the host reads their outcomes
-  // once per batch.  A round launched after the last active suffix became
-  // unique finds empty lists everywhere and changes nothing, so speculation
-  // never alters the result.  Large units only arise from large units of the
-  // previous round, so once none are left the MSD passes are skipped.
+  // Host-driven: rounds are launched `spec` at a time and the host reads their
+  // outcomes once per batch.  Otherwise every round up to the bound for the
+  // longest window is launched.  A round launched after the last active suffix
+  // became unique finds empty lists everywhere and changes nothing, so extra
+  // rounds never alter the result.  Large units only arise from large units
+  // of the previous round, so once none are left the MSD passes are skipped.
   const uint32_t rank_bits = (uint32_t)bit_length_u64(N);
+  const int r_max = ceil_log2_u64(std::max<uint64_t>(maxwin, 2)) + 1;  // rounds 0..r_max-1 suffice
   int cur = 0;
   E.reset_counters(s);
   E.round_begin(cur, s);
   E.gather_identity(key0, (uint32_t)N, s);
   E.init_units(cur, w.d_off, W, 0, bits0, s);
-  uint64_t maxwin = 0;
-  for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   bool big = maxwin > (1ull << E.tile_log());
   uint64_t act = N;
   int r = 0, synced = 0, done_round = -1;
   w.kev_n = 0;
-  const int spec = 4;
-  fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
+  const int spec = host ? 4 : r_max;
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
     if (r > 0) E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, w.rhist, r, s);
@@ -292,14 +318,19 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     E.bulk_sa(cur, R, rank_bits, act, s);
     cur ^= 1;
     r++;
+    if (!host) {
+      if (r >= r_max) {
+        E.round_end(cur ^ 1, r - 1, w.rhist, s);
+        done_round = r - 1;  // an upper bound of the last round that did work
+      }
+      continue;
+    }
     if (r - synced >= spec || r >= w.nsnap) {
       E.round_end(cur ^ 1, r - 1, w.rhist, s);
       APO_HIP_TRY(hipMemcpyAsync(w.hrhist, w.rhist, 4 * w.nsnap * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
-      for (int k = synced; k < r; k++) {
-        info.active_sum += (k == 0) ? N : w.hrhist[4 * (k - 1)];
+      for (int k = synced; k < r; k++)
         if (w.hrhist[4 * k] == 0) { done_round = k; break; }
-      }
       if (done_round < 0) {
         act = w.hrhist[4 * (r - 1)];
         big = w.hrhist[4 * (r - 1) + 1] > 0;
@@ -308,108 +339,158 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     }
   }
   r = done_round;
-  info.rounds = (uint32_t)r + 1;
   APO_HIP_TRY(hipMemcpyAsync(w.sa, B.val[0], N * 4, hipMemcpyDeviceToDevice, s));
-  stamp(w, 2, s);
-  if (stop == Stop::SA) return read_counters(w, s);
+  stamp(w, 2, s, stamps);
+  if (stop == Stop::SA) {
+    APO_HIP_TRY(hipMemcpyAsync(w.hrhist, w.rhist, 4 * w.nsnap * 4, hipMemcpyDeviceToHost, s));
+    if ((rc = read_counters(w, s))) return rc;
+    fill_info(w, N, info);
+    return 0;
+  }
 
-  // ---- LCP via Phi / PLCP
+  // ---- LCP via Phi / PLCP (lifting over rounds r-1..0; more levels than
+  // needed are harmless: no suffix pair is grouped beyond its last round)
   build_lcp(w.sa, N, wbeg, wend, w.snap, w.fin, r - 1, w.phi, w.plcp, w.lcp, s);
-  stamp(w, 3, s);
+  stamp(w, 3, s, stamps);
   if (stop == Stop::LCP) return read_counters(w, s);
 
   // ---- candidates
-  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.c_len, w.c_start, w.c_id, w.dcnt + CNT_C,
-                 w.dcnt + CNT_MAXL, s);
-  if ((rc = read_counters(w, s))) return rc;
-  const uint32_t C = w.hcnt[CNT_C], maxl = w.hcnt[CNT_MAXL];
-  info.cands = C;
-  info.maxl = maxl;
-  stamp(w, 4, s);
-  uint32_t M = 0;
-  if (C > 0) {
+  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.c_len, w.c_start, w.c_id, dc + CNT_C,
+                 dc + CNT_MAXL, s);
+  uint64_t c_bound = 2 * N;
+  uint64_t maxl_bound = std::max<uint64_t>(maxwin / 2, 1);
+  if (host) {
+    if ((rc = read_counters(w, s))) return rc;
+    c_bound = w.hcnt[CNT_C];
+    maxl_bound = std::max<uint32_t>(w.hcnt[CNT_MAXL], 1);
+  }
+  stamp(w, 4, s, stamps);
+  uint64_t m_bound = 0;
+  if (c_bound > 0) {
     const uint32_t *f[3] = {w.c_len, w.c_id, w.c_start};
     const int sub[3] = {1, 0, 0};
-    const uint32_t cs[3] = {maxl, 0, 0};
-    const int bb[3] = {bit_length_u64(maxl), (int)rank_bits, (int)rank_bits};
-    sort_plain(w, C, f, sub, cs, bb, 3, w.keep, s);
-    compact_sorted(B.val[0], w.keep, C, w.c_len, w.c_start, w.c_id, w.s_len, w.s_start, w.s_id, w.tmp_a, w.tmp_b,
-                   w.tile_tmp, w.dcnt + CNT_M, s);
-    if ((rc = read_counters(w, s))) return rc;
-    M = w.hcnt[CNT_M];
+    const uint32_t *cd[3] = {dc + CNT_MAXL, nullptr, nullptr};
+    const int bb[3] = {bit_length_u64(maxl_bound), (int)rank_bits, (int)rank_bits};
+    sort_plain(w, dc + CNT_C, c_bound, f, sub, cd, bb, 3, w.keep, s);
+    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.c_len, w.c_start, w.c_id, w.s_len, w.s_start, w.s_id,
+                   w.tmp_a, w.tmp_b, w.tile_tmp, dc + CNT_M, s);
+    m_bound = c_bound;
+    if (host) {
+      if ((rc = read_counters(w, s))) return rc;
+      m_bound = w.hcnt[CNT_M];
+    }
   }
-  info.cands_dedup = M;
-  stamp(w, 5, s);
-  if (stop == Stop::CANDS) return 0;
+  stamp(w, 5, s, stamps);
+  if (stop == Stop::CANDS) {
+    if ((rc = read_counters(w, s))) return rc;
+    fill_info(w, N, info);
+    return 0;
+  }
 
-  // ---- greedy selection (rounds launched two at a time, see sel_round)
-  if (M > 0) {
-    const int top = 31 - __builtin_clz(maxl);
+  // ---- greedy selection
+  int sel_done = -1, sel_launched = 0;
+  if (m_bound > 0) {
+    const int top = 63 - __builtin_clzll(maxl_bound);
     uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
     uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2);
     fill_u32(Ta, (uint64_t)(top + 1) * N, 0xFFFFFFFFu, s);
     fill_u32(w.selcnt, 2 * (kSelRoundCap + 2), 0, s);
-    fill_u32(nlive, 1, M, s);
-    sel_init(w.live[0], nlive, w.state, M, s);
-    int r = 0, done = -1;
-    const int ahead = 2;
-    uint64_t hint = M;
-    while (done < 0 && r < kSelRoundCap) {
-      for (int q = r; q < r + ahead && q < kSelRoundCap; q++)
+    copy_u32(nlive, dc + CNT_M, s);
+    sel_init(w.live[0], nlive, w.state, m_bound, s);
+    const int ahead = host ? 2 : kSelFreeRounds;
+    int q0 = 0;
+    uint64_t hint = m_bound;
+    while (sel_done < 0 && q0 < kSelRoundCap) {
+      const int hi = std::min(q0 + ahead, kSelRoundCap);
+      for (int q = q0; q < hi; q++)
         sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[q & 1],
                   w.live[(q + 1) & 1], nlive, undec, q, hint, s);
-      const int hi = std::min(r + ahead, kSelRoundCap);
+      q0 = hi;
+      sel_launched = hi;
+      if (!host) break;  // checked after the output stage
       APO_HIP_TRY(hipMemcpyAsync(w.hsel, w.selcnt, 2 * (kSelRoundCap + 2) * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
-      for (int q = r; q < hi; q++)
-        if (w.hsel[(kSelRoundCap + 2) + q] == 0) { done = q; break; }
-      if (done < 0) hint = w.hsel[hi];
-      r = hi;
+      for (int q = q0 - ahead; q < hi; q++)
+        if (w.hsel[(kSelRoundCap + 2) + q] == 0) { sel_done = q; break; }
+      if (sel_done < 0) hint = w.hsel[hi];
     }
-    info.sel_rounds = done >= 0 ? (uint32_t)done + 1 : (uint32_t)kSelRoundCap;
-    if (done < 0) {
-      sel_sequential(w.state, w.s_len, w.s_start, M, w.mark, N, s);
+    if (host && sel_done < 0) {
+      sel_sequential(w.state, w.s_len, w.s_start, dc + CNT_M, m_bound, w.mark, N, s);
       info.sel_sequential = 1;
     }
   }
-  stamp(w, 6, s);
+  stamp(w, 6, s, stamps);
 
   // ---- accepted occurrences and rows
-  uint32_t A = 0;
-  if (M > 0) {
-    gather_accepted(w.state, M, w.s_len, w.s_start, w.s_id, w.o_len, w.o_start, w.o_id, w.tmp_a, w.tmp_b,
-                    w.tile_tmp, w.dcnt + CNT_A, s);
-    if ((rc = read_counters(w, s))) return rc;
-    A = w.hcnt[CNT_A];
+  int orc = emit_output(w, N, W, batch, wid, wbeg, m_bound, host, s);
+  if (orc) return orc;
+  stamp(w, 7, s, stamps);
+  if (mode == Mode::CAPTURE) return 0;
+  rc = finish_run(w, N, m_bound, host ? -1 : sel_launched, info, s, stamps);
+  if (host && sel_done < 0 && m_bound > 0) {
+    info.sel_rounds = kSelRoundCap;
+    info.sel_sequential = 1;
   }
-  info.accepted = A;
+  return rc;
+}
+
+// Accepted occurrences in priority order, the per-window order of batches,
+// rows and their counts.
+int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t *wid, const uint32_t *wbeg,
+                uint64_t m_bound, bool host, hipStream_t s) {
+  SortBufs &B = w.eng.bufs();
+  uint32_t *dc = w.dcnt;
+  int rc;
+  fill_u32(dc + CNT_A, 1, 0, s);
+  fill_u32(dc + CNT_NROWS, 1, 0, s);
+  if (batch) fill_u32(w.win_rows, W + 1, 0, s);
+  if (m_bound == 0) return 0;
+  gather_accepted(w.state, dc + CNT_M, m_bound, w.s_len, w.s_start, w.s_id, w.o_len, w.o_start, w.o_id, w.tmp_a,
+                  w.tmp_b, w.tile_tmp, dc + CNT_A, s);
+  uint64_t a_bound = std::min<uint64_t>(m_bound, N);
+  if (host) {
+    if ((rc = read_counters(w, s))) return rc;
+    a_bound = w.hcnt[CNT_A];
+    if (a_bound == 0) return 0;
+  }
   const uint32_t *order = nullptr;
-  if (batch && A > 0) {
-    window_of_occ(w.o_start, w.wid, A, w.tmp_c, s);
-    iota_u32(w.tmp_d, A, s);
+  if (batch) {
+    window_of_occ(w.o_start, w.wid, dc + CNT_A, a_bound, w.tmp_c, s);
+    iota_u32(w.tmp_d, dc + CNT_A, a_bound, s);
     const uint32_t *f[2] = {w.tmp_c, w.tmp_d};
     const int sub[2] = {0, 0};
-    const uint32_t cs[2] = {0, 0};
-    const int bb[2] = {bit_length_u64(W), bit_length_u64(A)};
-    sort_plain(w, A, f, sub, cs, bb, 2, nullptr, s);
+    const uint32_t *cd[2] = {nullptr, nullptr};
+    const int bb[2] = {bit_length_u64(W), bit_length_u64(a_bound)};
+    sort_plain(w, dc + CNT_A, a_bound, f, sub, cd, bb, 2, nullptr, s);
     order = B.val[0];
   }
-  if (batch) fill_u32(w.win_rows, W + 1, 0, s);
-  uint32_t nrows = 0;
-  if (A > 0) {
-    emit_rows(order, A, w.o_len, w.o_start, w.o_id, wid, wbeg, w.tmp_a, w.rowidx, w.row_first, w.rows, w.occ,
-              batch ? w.win_rows : nullptr, w.tile_tmp, w.dcnt + CNT_NROWS, s);
-    if ((rc = read_counters(w, s))) return rc;
-    nrows = w.hcnt[CNT_NROWS];
-    row_counts(w.row_first, nrows, A, w.rows, s);
+  emit_rows(order, dc + CNT_A, a_bound, w.o_len, w.o_start, w.o_id, wid, wbeg, w.tmp_a, w.rowidx, w.row_first, w.rows,
+            w.occ, batch ? w.win_rows : nullptr, w.tile_tmp, dc + CNT_NROWS, s);
+  return 0;
+}
+
+// Final synchronisation of a run (or of a replayed graph): counters, the
+// rare selection completion for sync-free runs, stage and kernel timings.
+int finish_run(Workspace &w, uint64_t N, uint64_t m_bound, int sel_launched, RunInfo &info, hipStream_t s,
+               bool stamps) {
+  int rc;
+  APO_HIP_TRY(hipMemcpyAsync(w.hrhist, w.rhist, 4 * w.nsnap * 4, hipMemcpyDeviceToHost, s));
+  APO_HIP_TRY(hipMemcpyAsync(w.hsel, w.selcnt, 2 * (kSelRoundCap + 2) * 4, hipMemcpyDeviceToHost, s));
+  if ((rc = read_counters(w, s))) return rc;
+  fill_info(w, N, info);
+  info.sel_rounds = 0;
+  const int qmax = sel_launched < 0 ? kSelRoundCap : sel_launched;
+  for (int q = 0; q < qmax; q++)
+    if (w.hsel[(kSelRoundCap + 2) + q] == 0) { info.sel_rounds = (uint32_t)q + 1; break; }
+  // sync-free run whose launched rounds left candidates undecided
+  if (sel_launched >= 0 && m_bound > 0 && info.cands_dedup > 0 && info.sel_rounds == 0) return 1;
+  if (stamps) {
+    for (int k = 0; k < kStages; k++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) info.stage_ms[k] = ms;
+    }
   }
-  info.rows = nrows;
-  stamp(w, 7, s);
-  APO_HIP_TRY(hipStreamSynchronize(s));
-  for (int k = 0; k < kStages; k++) {
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) info.stage_ms[k] = ms;
-  }
+  // timed kernel launches (also recorded inside captured graphs)
   for (int k = 0; k < w.kev_n; k++) {
     const uint32_t elems = w.hrhist[4 * w.kround[k] + 2];
     float ms = 0;

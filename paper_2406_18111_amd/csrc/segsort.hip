@@ -140,19 +140,22 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
   }
 }
 
-// Multi-key sort: key = field[val] (or c - field[val] when `sub`), over the
-// active list, or over slots [0, all) when all > 0.
-__global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, uint32_t all,
-                               int sub, uint32_t c) {
-  const uint32_t cnt = all ? all : B.ctr->act_cnt[cur];
+// Multi-key sort: key = field[val] (or c - field[val] when `sub`, with c read
+// from c_dev when given), over the active list, or over slots [0, *all_dev)
+// when all_dev is given.
+__global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, const uint32_t *all_dev, int sub,
+                               const uint32_t *c_dev, uint32_t c) {
+  const uint32_t cnt = all_dev ? *all_dev : B.ctr->act_cnt[cur];
+  if (c_dev) c = *c_dev;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
-    const uint32_t p = all ? q : B.act[cur][q];
+    const uint32_t p = all_dev ? q : B.act[cur][q];
     const uint32_t f = field[B.val[0][p]];
     B.key[0][p] = sub ? c - f : f;
   }
 }
 
-__global__ void k_iota_val(SortBufs B, uint32_t n) {
+__global__ void k_iota_val(SortBufs B, const uint32_t *n_dev) {
+  const uint32_t n = *n_dev;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
     B.val[0][p] = p;
 }
@@ -450,7 +453,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         const uint32_t key = K[p], j = EJ[p];
         uint32_t h = (uint32_t)(mix64(((uint64_t)j << 32) | key) >> 20) & (HT - 1);
         while (true) {
-          const uint32_t prev = atomicCAS(&tab[h], 0u, (1u << 16) | (p + 1));
+          uint32_t prev = tab[h];
+          if (prev == 0u) prev = atomicCAS(&tab[h], 0u, (1u << 16) | (p + 1));
           if (prev == 0u) {
             const uint32_t d = atomicAdd(&nd, 1u);
             D[d] = ((uint64_t)j << 46) | ((uint64_t)key << 14) | h;
@@ -458,7 +462,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
           }
           const uint32_t e = (prev & 0xFFFFu) - 1;
           if (K[e] == key && EJ[e] == j) {
-            atomicAdd(&tab[h], 1u << 16);
+            agg_add(&tab[h], 1u << 16);
             break;
           }
           h = (h + 1) & (HT - 1);
@@ -521,7 +525,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         const uint32_t h = eslot[q];
         const uint32_t info = tab[h];
         const uint32_t gbase = info & 0xFFFFu, gcnt = info >> 16;
-        const uint32_t pos = atomicAdd(&cursor[h], 1u);
+        const uint32_t pos = agg_inc(&cursor[h]);
         pos_q[q] = pos;
         const uint32_t j = EJ[p];
         const Unit u = ud[j];
@@ -601,7 +605,7 @@ __global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
     const uint32_t *key = B.key[(bu.meta & kMetaAlt) ? 1 : 0];
     for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
-      atomicAdd(&h[(key[p] >> shift) & mask], 1u);
+      agg_add(&h[(key[p] >> shift) & mask], 1u);
     __syncthreads();
     uint32_t *gh = B.hist + (size_t)u * kBins;
     for (int b = threadIdx.x; b <= (int)mask; b += blockDim.x)
@@ -739,7 +743,7 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
       if (p < hi) {
         kk[q] = B.key[sb][p];
         vv[q] = B.val[sb][p];
-        oo[q] = atomicAdd(&cnt[(kk[q] >> shift) & mask], 1u);
+        oo[q] = agg_inc(&cnt[(kk[q] >> shift) & mask]);
       }
     }
     __syncthreads();
@@ -897,14 +901,14 @@ void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_w
                      slot_wend, n, h, hist, r);
 }
 
-void SortEngine::gather_field(int cur, const uint32_t *field, uint32_t all, int sub, uint32_t c,
-                              uint32_t hint, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_field, grid_for(all ? all : hint, 256, 4096), dim3(256), 0, s, b_,
-                     cur, field, all, sub, c);
+void SortEngine::gather_field(int cur, const uint32_t *field, const uint32_t *all_dev, int sub, const uint32_t *c_dev,
+                              uint32_t c, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_field, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, cur, field, all_dev, sub, c_dev,
+                     c);
 }
 
-void SortEngine::iota_val(uint32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota_val, grid_for(n, 256, 4096), dim3(256), 0, s, b_, n);
+void SortEngine::iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota_val, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, n_dev);
 }
 
 void SortEngine::msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s) {

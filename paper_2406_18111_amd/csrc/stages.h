@@ -1,4 +1,6 @@
-// Host launch wrappers of the stage kernels (stages.hip).
+// Host launch wrappers of the stage kernels (stages.hip).  Counts that are
+// produced on the device are passed as device pointers (`*_dev`) together
+// with a host upper bound that only sizes the grid.
 #pragma once
 #include "apo_internal.h"
 
@@ -8,8 +10,10 @@ constexpr int kMinLevels = 6;  // 64-ary LCP minimum levels: 64^5 > 2^26
 
 void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
-void scan_excl(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tile_tmp, uint32_t *total,
-               hipStream_t s);
+void fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint64_t bound, uint8_t v, hipStream_t s);
+void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);
+void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
+               uint32_t *total, hipStream_t s);
 
 void hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask, uint32_t *dist_idx,
                  uint32_t *dist_slot, uint32_t *nd, hipStream_t s);
@@ -31,28 +35,27 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
                     uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *c_len,
                     uint32_t *c_start, uint32_t *c_id, uint32_t *cnt, uint32_t *maxl, hipStream_t s);
 
-void compact_sorted(const uint32_t *order, const uint8_t *keep, uint64_t m, const uint32_t *c_len,
-                    const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len, uint32_t *s_start,
-                    uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
+void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
+                    const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len,
+                    uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s);
 
-void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t m, hipStream_t s);
+void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s);
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
                uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
                uint64_t live_hint, hipStream_t s);
-void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
+void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
                     uint8_t *mark, uint64_t n, hipStream_t s);
 
-void gather_accepted(const uint8_t *state, uint64_t m, const uint32_t *len, const uint32_t *start,
-                     const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,
-                     uint32_t *tmp_f, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total,
-                     hipStream_t s);
-void emit_rows(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
-               const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f,
-               uint32_t *rowidx, uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows,
-               uint32_t *tile_tmp, uint32_t *nrows, hipStream_t s);
-void row_counts(const uint32_t *row_first, uint32_t nrows, uint32_t a, void *rows, hipStream_t s);
-void window_of_occ(const uint32_t *o_start, const uint32_t *wid, uint64_t a, uint32_t *out, hipStream_t s);
-void iota_u32(uint32_t *p, uint64_t n, hipStream_t s);
+void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
+                     const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,
+                     uint32_t *tmp_f, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+void emit_rows(const uint32_t *order, const uint32_t *a_dev, uint64_t bound, const uint32_t *o_len,
+               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f,
+               uint32_t *rowidx, uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
+               uint32_t *nrows, hipStream_t s);
+void window_of_occ(const uint32_t *o_start, const uint32_t *wid, const uint32_t *a_dev, uint64_t bound, uint32_t *out,
+                   hipStream_t s);
+void iota_u32(uint32_t *p, const uint32_t *n_dev, uint64_t bound, hipStream_t s);
 
 }  // namespace apo

@@ -34,9 +34,11 @@ void fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s) {
 // per-tile sums, one-workgroup scan of the tile sums, per-tile rescan.
 constexpr int kScanNT = 256, kScanPer = 16, kScanTile = kScanNT * kScanPer;
 
-__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const uint32_t *in, uint64_t n, uint32_t *tile_sum) {
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(const uint32_t *in, const uint32_t *n_dev, uint32_t *tile_sum) {
   __shared__ uint32_t sh[kScanNT / 64];
+  const uint64_t n = *n_dev;
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  if (base >= n && blockIdx.x > 0) return;
   uint32_t loc = 0;
   for (int q = 0; q < kScanPer; q++) {
     const uint64_t i = base + (uint64_t)q * kScanNT + threadIdx.x;
@@ -47,9 +49,10 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(const uint32_t *in, uint
   if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *tile_sum, uint32_t ntiles, uint32_t *total) {
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *tile_sum, const uint32_t *n_dev, uint32_t *total) {
   __shared__ uint32_t sh[1024 / 64];
   __shared__ uint32_t carry;
+  const uint32_t ntiles = (uint32_t)(((uint64_t)*n_dev + kScanTile - 1) / kScanTile);
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (uint32_t b0 = 0; b0 < ntiles; b0 += 1024) {
@@ -65,9 +68,11 @@ __global__ __launch_bounds__(1024) void k_scan_sums(uint32_t *tile_sum, uint32_t
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(kScanNT) void k_scan_apply(const uint32_t *in, uint64_t n, const uint32_t *tile_sum,
-                                                        uint32_t *out) {
+__global__ __launch_bounds__(kScanNT) void k_scan_apply(const uint32_t *in, const uint32_t *n_dev,
+                                                        const uint32_t *tile_sum, uint32_t *out) {
   __shared__ uint32_t sh[kScanNT / 64];
+  const uint64_t n = *n_dev;
+  if ((uint64_t)blockIdx.x * kScanTile >= n) return;
   // thread owns kScanPer consecutive elements
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
   uint32_t v[kScanPer];
@@ -86,18 +91,27 @@ __global__ __launch_bounds__(kScanNT) void k_scan_apply(const uint32_t *in, uint
   }
 }
 
-void scan_excl(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tile_tmp, uint32_t *total,
-               hipStream_t s) {
-  const uint32_t tiles = (uint32_t)((n + kScanTile - 1) / kScanTile);
-  if (tiles == 0) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, total, (uint64_t)1, 0u);
-    return;
-  }
-  // k_scan_tiles reads elements strided by kScanNT within the tile; any
-  // partition of the tile gives the same tile sum.
-  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanNT), 0, s, in, n, tile_tmp);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tile_tmp, tiles, total);
-  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanNT), 0, s, in, n, tile_tmp, out);
+// n_dev: element count in device memory; bound: host upper bound (grid size).
+void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
+               uint32_t *total, hipStream_t s) {
+  const uint32_t tiles = (uint32_t)std::max<uint64_t>((bound + kScanTile - 1) / kScanTile, 1);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanNT), 0, s, in, n_dev, tile_tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tile_tmp, n_dev, total);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanNT), 0, s, in, n_dev, tile_tmp, out);
+}
+
+__global__ void k_fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint8_t v) {
+  const uint64_t n = *n_dev;
+  GRID_STRIDE(i, n) p[i] = v;
+}
+void fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint64_t bound, uint8_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u8_dev, grid_for(bound, 256, 8192), dim3(256), 0, s, p, n_dev, v);
+}
+__global__ void k_copy_u32(uint32_t *dst, const uint32_t *src) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, dst, src);
 }
 
 // ------------------------------------------------------ token ranking (u64)
@@ -142,7 +156,8 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
       const uint64_t key = lt[k];
       uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
       while (true) {
-        const uint32_t prev = atomicCAS(&ls[h], 0u, k + 1);
+        uint32_t prev = ls[h];
+        if (prev == 0u) prev = atomicCAS(&ls[h], 0u, k + 1);
         if (prev == 0u) {  // first in this tile
           global_insert(tok, (uint32_t)(t0 + k), key, tab, mask, dist_idx, dist_slot, nd);
           break;
@@ -429,9 +444,10 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
-__global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *pos, uint64_t m,
+__global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *pos, const uint32_t *m_dev,
                                 const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id,
                                 uint32_t *s_len, uint32_t *s_start, uint32_t *s_id) {
+  const uint64_t m = *m_dev;
   GRID_STRIDE(k, m) {
     if (keep[k]) {
       const uint32_t c = order[k], o = pos[k];
@@ -440,15 +456,18 @@ __global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, cons
   }
 }
 
-__global__ void k_u8_to_u32(const uint8_t *a, uint64_t n, uint32_t *b) { GRID_STRIDE(i, n) b[i] = a[i]; }
+__global__ void k_u8_to_u32(const uint8_t *a, const uint32_t *n_dev, uint32_t *b) {
+  const uint64_t n = *n_dev;
+  GRID_STRIDE(i, n) b[i] = a[i];
+}
 
-void compact_sorted(const uint32_t *order, const uint8_t *keep, uint64_t m, const uint32_t *c_len,
-                    const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len, uint32_t *s_start,
-                    uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_u8_to_u32, grid_for(m, 256, 8192), dim3(256), 0, s, keep, m, tmp_flags);
-  scan_excl(tmp_flags, tmp_pos, m, tile_tmp, total, s);
-  hipLaunchKernelGGL(k_gather_sorted, grid_for(m, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m, c_len,
+void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
+                    const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len,
+                    uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
+                    uint32_t *total, hipStream_t s) {
+  hipLaunchKernelGGL(k_u8_to_u32, grid_for(bound, 256, 8192), dim3(256), 0, s, keep, m_dev, tmp_flags);
+  scan_excl(tmp_flags, tmp_pos, m_dev, bound, tile_tmp, total, s);
+  hipLaunchKernelGGL(k_gather_sorted, grid_for(bound, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m_dev, c_len,
                      c_start, c_id, s_len, s_start, s_id);
 }
 
@@ -489,8 +508,11 @@ __global__ void k_sel_insert(SelArgs a) {
     const uint32_t l = a.len[k], s = a.start[k];
     const int j = 31 - __clz((int)l);
     uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
-    atomicMin(&Tj[s], k);
-    atomicMin(&Tj[s + l - (1u << j)], k);
+    // values only decrease: skip the atomic when a smaller priority is already
+    // there (long candidates of periodic runs share block positions)
+    uint32_t *p1 = &Tj[s], *p2 = &Tj[s + l - (1u << j)];
+    if (*p1 > k) atomicMin(p1, k);
+    if (*p2 > k) atomicMin(p2, k);
   }
 }
 
@@ -595,9 +617,9 @@ __global__ void k_iota(uint32_t *p, const uint32_t *n) {
   GRID_STRIDE(i, m) p[i] = (uint32_t)i;
 }
 
-void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t m, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, grid_for(m, 256, 8192), dim3(256), 0, s, live, nlive_dev);
-  fill_u8(state, m, 0, s);
+void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, grid_for(bound, 256, 8192), dim3(256), 0, s, live, nlive_dev);
+  fill_u8_dev(state, nlive_dev, bound, 0, s);
 }
 
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
@@ -614,8 +636,9 @@ void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_
 
 // Exact sequential completion for whatever is still undecided after the
 // round cap: one thread walks the sorted list with a mark array.
-__global__ void k_sel_paint(const uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
+__global__ void k_sel_paint(const uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev,
                             uint8_t *mark) {
+  const uint64_t m = *m_dev;
   GRID_STRIDE(k, m) {
     if (state[k] == 1) {
       const uint32_t s = start[k], l = len[k];
@@ -624,9 +647,10 @@ __global__ void k_sel_paint(const uint8_t *state, const uint32_t *len, const uin
   }
 }
 
-__global__ void k_sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m,
+__global__ void k_sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev,
                                  uint8_t *mark) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const uint64_t m = *m_dev;
   for (uint64_t k = 0; k < m; k++) {
     if (state[k] != 0) continue;
     const uint32_t s = start[k], l = len[k];
@@ -636,19 +660,23 @@ __global__ void k_sel_sequential(uint8_t *state, const uint32_t *len, const uint
   }
 }
 
-void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, uint64_t m, uint8_t *mark,
-                    uint64_t n, hipStream_t s) {
+void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
+                    uint8_t *mark, uint64_t n, hipStream_t s) {
   fill_u8(mark, n, 0, s);
-  hipLaunchKernelGGL(k_sel_paint, grid_for(m, 256, 8192), dim3(256), 0, s, state, len, start, m, mark);
-  hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m, mark);
+  hipLaunchKernelGGL(k_sel_paint, grid_for(bound, 256, 8192), dim3(256), 0, s, state, len, start, m_dev, mark);
+  hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m_dev, mark);
 }
 
 // ---------------------------------------------------------------- output
-__global__ void k_acc_flags(const uint8_t *state, uint64_t m, uint32_t *f) { GRID_STRIDE(k, m) f[k] = state[k] == 1; }
+__global__ void k_acc_flags(const uint8_t *state, const uint32_t *m_dev, uint32_t *f) {
+  const uint64_t m = *m_dev;
+  GRID_STRIDE(k, m) f[k] = state[k] == 1;
+}
 
-__global__ void k_acc_gather(const uint8_t *state, const uint32_t *pos, uint64_t m, const uint32_t *len,
+__global__ void k_acc_gather(const uint8_t *state, const uint32_t *pos, const uint32_t *m_dev, const uint32_t *len,
                              const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start,
                              uint32_t *o_id) {
+  const uint64_t m = *m_dev;
   GRID_STRIDE(k, m) {
     if (state[k] == 1) {
       const uint32_t o = pos[k];
@@ -657,19 +685,20 @@ __global__ void k_acc_gather(const uint8_t *state, const uint32_t *pos, uint64_t
   }
 }
 
-void gather_accepted(const uint8_t *state, uint64_t m, const uint32_t *len, const uint32_t *start,
-                     const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id, uint32_t *tmp_f,
-                     uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
-  hipLaunchKernelGGL(k_acc_flags, grid_for(m, 256, 8192), dim3(256), 0, s, state, m, tmp_f);
-  scan_excl(tmp_f, tmp_pos, m, tile_tmp, total, s);
-  hipLaunchKernelGGL(k_acc_gather, grid_for(m, 256, 8192), dim3(256), 0, s, state, tmp_pos, m, len, start, id,
+void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
+                     const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,
+                     uint32_t *tmp_f, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
+  hipLaunchKernelGGL(k_acc_flags, grid_for(bound, 256, 8192), dim3(256), 0, s, state, m_dev, tmp_f);
+  scan_excl(tmp_f, tmp_pos, m_dev, bound, tile_tmp, total, s);
+  hipLaunchKernelGGL(k_acc_gather, grid_for(bound, 256, 8192), dim3(256), 0, s, state, tmp_pos, m_dev, len, start, id,
                      o_len, o_start, o_id);
 }
 
 // Occurrence o (in final order: window, then priority) opens a row when its
 // window, length or substring ID differs from occurrence o-1.
-__global__ void k_row_flags(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
-                            const uint32_t *o_id, const uint32_t *wid, uint32_t *f) {
+__global__ void k_row_flags(const uint32_t *order, const uint32_t *a_dev, const uint32_t *o_len,
+                            const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, uint32_t *f) {
+  const uint64_t a = *a_dev;
   GRID_STRIDE(o, a) {
     const uint32_t c = order ? order[o] : (uint32_t)o;
     bool nr = (o == 0);
@@ -685,9 +714,10 @@ __global__ void k_row_flags(const uint32_t *order, uint64_t a, const uint32_t *o
 struct OutRow { uint32_t start, length, count; };
 struct OutOcc { uint32_t start, length, cand; };
 
-__global__ void k_emit(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
+__global__ void k_emit(const uint32_t *order, const uint32_t *a_dev, const uint32_t *o_len, const uint32_t *o_start,
                        const uint32_t *wid, const uint32_t *wbeg_of_pos, const uint32_t *f, const uint32_t *rowidx,
                        uint32_t *row_first, OutRow *rows, OutOcc *occ, uint32_t *win_rows) {
+  const uint64_t a = *a_dev;
   GRID_STRIDE(o, a) {
     const uint32_t c = order ? order[o] : (uint32_t)o;
     const uint32_t r = rowidx[o] + f[o] - 1u;  // row of this occurrence (inclusive count - 1)
@@ -703,43 +733,47 @@ __global__ void k_emit(const uint32_t *order, uint64_t a, const uint32_t *o_len,
   }
 }
 
-__global__ void k_row_counts(const uint32_t *row_first, uint32_t nrows, uint32_t a, OutRow *rows) {
+__global__ void k_row_counts(const uint32_t *row_first, const uint32_t *nrows_dev, const uint32_t *a_dev,
+                             OutRow *rows) {
+  const uint32_t nrows = *nrows_dev, a = *a_dev;
   GRID_STRIDE(r, nrows) {
     const uint32_t e = (r + 1 < nrows) ? row_first[r + 1] : a;
     rows[r].count = e - row_first[r];
   }
 }
 
-void emit_rows(const uint32_t *order, uint64_t a, const uint32_t *o_len, const uint32_t *o_start,
-               const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f, uint32_t *rowidx,
-               uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
+void emit_rows(const uint32_t *order, const uint32_t *a_dev, uint64_t bound, const uint32_t *o_len,
+               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f,
+               uint32_t *rowidx, uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
                uint32_t *nrows, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_flags, grid_for(a, 256, 8192), dim3(256), 0, s, order, a, o_len, o_start, o_id, wid, f);
-  scan_excl(f, rowidx, a, tile_tmp, nrows, s);
-  hipLaunchKernelGGL(k_emit, grid_for(a, 256, 8192), dim3(256), 0, s, order, a, o_len, o_start, wid, wbeg, f,
+  hipLaunchKernelGGL(k_row_flags, grid_for(bound, 256, 8192), dim3(256), 0, s, order, a_dev, o_len, o_start, o_id, wid,
+                     f);
+  scan_excl(f, rowidx, a_dev, bound, tile_tmp, nrows, s);
+  hipLaunchKernelGGL(k_emit, grid_for(bound, 256, 8192), dim3(256), 0, s, order, a_dev, o_len, o_start, wid, wbeg, f,
                      rowidx, row_first, (OutRow *)rows, (OutOcc *)occ, win_rows);
-}
-
-void row_counts(const uint32_t *row_first, uint32_t nrows, uint32_t a, void *rows, hipStream_t s) {
-  if (nrows)
-    hipLaunchKernelGGL(k_row_counts, grid_for(nrows, 256, 8192), dim3(256), 0, s, row_first, nrows, a,
-                       (OutRow *)rows);
+  hipLaunchKernelGGL(k_row_counts, grid_for(bound, 256, 8192), dim3(256), 0, s, row_first, nrows, a_dev,
+                     (OutRow *)rows);
 }
 
 }  // namespace apo
 
 namespace apo {
 
-__global__ void k_window_of_occ(const uint32_t *o_start, const uint32_t *wid, uint64_t a, uint32_t *out) {
+__global__ void k_window_of_occ(const uint32_t *o_start, const uint32_t *wid, const uint32_t *a_dev, uint32_t *out) {
+  const uint64_t a = *a_dev;
   GRID_STRIDE(o, a) out[o] = wid[o_start[o]];
 }
-__global__ void k_iota_n(uint32_t *p, uint64_t n) { GRID_STRIDE(i, n) p[i] = (uint32_t)i; }
-
-void window_of_occ(const uint32_t *o_start, const uint32_t *wid, uint64_t a, uint32_t *out, hipStream_t s) {
-  if (a) hipLaunchKernelGGL(k_window_of_occ, grid_for(a, 256, 8192), dim3(256), 0, s, o_start, wid, a, out);
+__global__ void k_iota_n(uint32_t *p, const uint32_t *n_dev) {
+  const uint64_t n = *n_dev;
+  GRID_STRIDE(i, n) p[i] = (uint32_t)i;
 }
-void iota_u32(uint32_t *p, uint64_t n, hipStream_t s) {
-  if (n) hipLaunchKernelGGL(k_iota_n, grid_for(n, 256, 8192), dim3(256), 0, s, p, n);
+
+void window_of_occ(const uint32_t *o_start, const uint32_t *wid, const uint32_t *a_dev, uint64_t bound, uint32_t *out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_window_of_occ, grid_for(bound, 256, 8192), dim3(256), 0, s, o_start, wid, a_dev, out);
+}
+void iota_u32(uint32_t *p, const uint32_t *n_dev, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota_n, grid_for(bound, 256, 8192), dim3(256), 0, s, p, n_dev);
 }
 
 }  // namespace apo

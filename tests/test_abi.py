@@ -51,3 +51,19 @@ def test_no_cpu_fallback_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         _lib.load()
+
+
+def test_ruler_slices():
+    """Section 4.4: slices 1,2,1,4 on a buffer of four (block of one token);
+    with a block of 250 and a buffer of 5000 the slices are 250 * 2^v(i),
+    capped."""
+    from paper_2406_18111_amd import _lib
+    assert [_lib.ruler_slice(i, 1, 4) for i in range(1, 9)] == [1, 2, 1, 4, 1, 2, 1, 4]
+    got = [_lib.ruler_slice(i, 250, 5000) for i in range(1, 33)]
+    assert got[:8] == [250, 500, 250, 1000, 250, 500, 250, 2000]
+    assert got[15] == 4000 and got[31] == 5000 and max(got) == 5000
+    assert _lib.ruler_slice(0, 250, 5000) == 0
+    # total work over K blocks: c * sum 2^v(i) = c * (K/2) * (log2 K + 2) for K a power of two (uncapped)
+    K = 1024
+    tot = sum(_lib.ruler_slice(i, 1, 1 << 30) for i in range(1, K + 1))
+    assert tot == (K // 2) * (10 + 2)

@@ -151,3 +151,107 @@ def test_server_errors(ctx):
         srv.server_stop()
         with pytest.raises(ApoError):
             srv.submit(np.arange(10, dtype=np.uint64), 2)
+
+
+def _same_shape_batches(seed):
+    """Two window layouts with the same window count, total length and longest window."""
+    rng = np.random.default_rng(seed)
+    lens_a = [3000, 700, 9000, 1, 0, 4200, 2500]
+    lens_b = [9000, 2600, 3000, 700, 4100, 1, 0]
+    assert sum(lens_a) == sum(lens_b) and max(lens_a) == max(lens_b)
+    out = []
+    for lens in (lens_a, lens_b):
+        wins = [synth.loop_stream(int(rng.integers(1 << 30)), L, int(rng.integers(10, 80)), 64, 0.05) if L > 1
+                else np.full(L, 7, np.uint64) for L in lens]
+        out.append(wins)
+    return out
+
+
+def test_graph_capture_and_replay(ctx):
+    """The batched launch sequence is captured once and replayed: results of
+    every replay equal the per-window results, with eager work between
+    replays, tokens rewritten in place, and a new layout of the same shape."""
+    import torch
+    from paper_2406_18111_amd import Context
+    wins_a, wins_b = _same_shape_batches(21)
+    with Context(0) as g:
+        g.set_graphs(True)
+        toks_a, off_a = _pack(wins_a)
+        dev = torch.from_numpy(toks_a.view(np.int64)).cuda()
+        for rep in range(3):
+            rows, oo = g.analyze_batch_dev(dev, off_a, 4)
+            rows = rows.cpu().numpy().astype(np.int64)
+            for w, win in enumerate(wins_a):
+                assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), (rep, w)
+            # eager work between replays on the same context
+            assert np.array_equal(_as3(g.analyze(wins_a[0], 4)), _rows_ref(wins_a[0], 4))
+        st = g.graph_stats()
+        assert st["captures"] == 1 and st["replays"] == 2
+        # same pointer and shape, other tokens and window boundaries
+        toks_b, off_b = _pack(wins_b)
+        dev.copy_(torch.from_numpy(toks_b.view(np.int64)))
+        rows, oo = g.analyze_batch_dev(dev, off_b, 4)
+        rows = rows.cpu().numpy().astype(np.int64)
+        for w, win in enumerate(wins_b):
+            assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), w
+        assert g.graph_stats()["replays"] == 3
+
+
+def test_sync_free_batch_without_graphs(ctx):
+    import torch
+    from paper_2406_18111_amd import Context
+    wins, m = synth.config3(num_windows=40)
+    toks, off = _pack(wins)
+    with Context(0) as g:
+        g.set_graphs(False)
+        rows, oo = g.analyze_batch_dev(torch.from_numpy(toks.view(np.int64)).cuda(), off, m)
+        rows = rows.cpu().numpy().astype(np.int64)
+        for w, win in enumerate(wins):
+            assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, m)), w
+        assert g.graph_stats()["captures"] == 0
+
+
+def test_batch_needing_many_selection_rounds(ctx):
+    """Block families need more greedy rounds than a sync-free batch enqueues;
+    the batch then completes host-driven with the same result."""
+    import torch
+    blocks = []
+    for k in range(1, 60):
+        blocks += [0] * k + [1]
+    wins = [np.array(blocks, dtype=np.uint64), synth.config0()[0]]
+    toks, off = _pack(wins)
+    rows, oo = ctx.analyze_batch_dev(torch.from_numpy(toks.view(np.int64)).cuda(), off, 1)
+    rows = rows.cpu().numpy().astype(np.int64)
+    for w, win in enumerate(wins):
+        assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 1)), w
+
+
+def test_tracer_ruler_slices(ctx):
+    """Trace finder: after every block of 250 tokens the ruler slice of the
+    last <= 5000 tokens is analysed asynchronously; each result equals the
+    single-window analysis of that slice of the stream."""
+    from paper_2406_18111_amd import Context, _lib
+    src = synth.NestedLoopSource(77, alphabet=1 << 10)
+    stream = src.take(12000)
+    with Context(0) as srv:
+        srv.server_start(slots=2)
+        tr = _lib.Tracer(srv, block_tokens=250, capacity=5000, min_len=8, stream_id=3)
+        submitted = 0
+        for k in range(0, len(stream), 700):
+            submitted += tr.push(stream[k:k + 700])
+        assert submitted == len(stream) // 250
+        results = []
+        t0 = time.time()
+        while len(results) < submitted and time.time() - t0 < 120:
+            got = tr.poll()
+            if got is None:
+                time.sleep(0.002)
+            else:
+                results.append(got)
+        assert len(results) == submitted
+        for i, (b, ln, rows) in enumerate(results, start=1):
+            assert ln == min(_lib.ruler_slice(i, 250, 5000), 250 * i)
+            assert b + ln == 250 * i
+            assert np.array_equal(_as3(rows), _as3(ctx.analyze(stream[b:b + ln], 8))), i
+        tr.close()
+        srv.server_stop()

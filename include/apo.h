@@ -253,6 +253,54 @@ int apo_tracer_poll(apo_tracer *t, uint64_t *slice_begin, uint64_t *slice_len, a
 /* Frees the tracer (results still queued are dropped). */
 int apo_tracer_destroy(apo_tracer *t);
 
+/* ---- trace replayer (Section 4.3; Algorithm 1's TraceReplayer) ---- */
+
+typedef struct apo_replayer apo_replayer;
+
+/* Issued task range [begin, end) (task indices since creation); trace is the
+ * id of the replayed candidate trace, or -1 for tasks issued untraced. */
+typedef struct {
+  uint64_t begin, end;
+  int64_t trace;
+} apo_replay_event;
+
+/* Host-side replayer.  Candidates are scored length * min(count, count_cap) *
+ * decay^(tasks since last seen) * (1 + replay_bonus if replayed before)
+ * (Section 4.3 names these factors, not their constants).  APO_EINVAL for
+ * count_cap == 0, decay outside (0, 1], replay_bonus < 0 or out == NULL. */
+int apo_replayer_create(uint32_t count_cap, double decay, double replay_bonus, apo_replayer **out);
+
+/* Adds the rows of a FindRepeats result over tokens[0..n) as candidate
+ * traces (the row's substring; a trace already known keeps the larger
+ * count).  APO_EINVAL if a row lies outside tokens. */
+int apo_replayer_ingest(apo_replayer *r, const uint64_t *tokens, uint64_t n, const apo_candidate *rows,
+                        uint32_t nrows);
+
+/* Issues n tasks with the given tokens, in order: active pointers advance
+ * in the candidate trie, a completed candidate (best score, ties to the
+ * lower id) is replayed with the pending tasks before it issued untraced,
+ * and pending tasks no pointer covers are issued untraced. */
+int apo_replayer_step(apo_replayer *r, const uint64_t *tokens, uint64_t n);
+
+/* Issues every pending task untraced. */
+int apo_replayer_flush(apo_replayer *r);
+
+/* Moves the events issued so far to out; *n gets their number.  APO_ERANGE
+ * (events kept) if out_cap is too small. */
+int apo_replayer_events(apo_replayer *r, apo_replay_event *out, uint32_t out_cap, uint32_t *n);
+
+/* Tasks seen, tasks issued inside replayed traces, replays, known traces. */
+int apo_replayer_stats(apo_replayer *r, uint64_t *tasks, uint64_t *traced, uint64_t *replays, uint64_t *traces);
+
+int apo_replayer_destroy(apo_replayer *r);
+
+/* Section 6.2's maximum trace length: each row longer than max_len becomes
+ * consecutive pieces of max_len tokens (the last one shorter), each with the
+ * row's count; pieces shorter than min_len are dropped.  *out_n gets the
+ * number of pieces; APO_ERANGE if more than out_cap. */
+int apo_split_rows(const apo_candidate *rows, uint32_t n, uint32_t max_len, uint32_t min_len, apo_candidate *out,
+                   uint32_t out_cap, uint32_t *out_n);
+
 #ifdef __cplusplus
 }
 #endif

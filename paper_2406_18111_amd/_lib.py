@@ -20,6 +20,7 @@ APO_MAX_N = 1 << 26
 
 ROW_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("count", "<u4")])
 OCC_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("cand", "<u4")])
+EVENT_DTYPE = np.dtype([("begin", "<u8"), ("end", "<u8"), ("trace", "<i8")])
 
 STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
 COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
@@ -60,6 +61,14 @@ SIGNATURES = {
     "apo_tracer_push": (_I, [_P, _P, _U32, _P]),
     "apo_tracer_poll": (_I, [_P, _P, _P, _P, _U32, _P]),
     "apo_tracer_destroy": (_I, [_P]),
+    "apo_replayer_create": (_I, [_U32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_P)]),
+    "apo_replayer_ingest": (_I, [_P, _P, _U64, _P, _U32]),
+    "apo_replayer_step": (_I, [_P, _P, _U64]),
+    "apo_replayer_flush": (_I, [_P]),
+    "apo_replayer_events": (_I, [_P, _P, _U32, _P]),
+    "apo_replayer_stats": (_I, [_P, _P, _P, _P, _P]),
+    "apo_replayer_destroy": (_I, [_P]),
+    "apo_split_rows": (_I, [_P, _U32, _U32, _U32, _P, _U32, _P]),
 }
 
 _lib = None
@@ -365,6 +374,75 @@ class Tracer:
     def close(self):
         if getattr(self, "_h", None):
             self._ctx._lib.apo_tracer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def split_rows(rows: np.ndarray, max_len: int, min_len: int = 1) -> np.ndarray:
+    """Rows cut into pieces of at most max_len tokens (Section 6.2)."""
+    lib = load()
+    rows = np.ascontiguousarray(rows, dtype=ROW_DTYPE)
+    cap = max(1, len(rows))
+    while True:
+        out = np.zeros(cap, dtype=ROW_DTYPE)
+        n = ctypes.c_uint32(0)
+        rc = lib.apo_split_rows(_np_ptr(rows) if len(rows) else None, len(rows), int(max_len), int(min_len),
+                                _np_ptr(out), cap, ctypes.byref(n))
+        if rc == APO_ERANGE:
+            cap = n.value
+            continue
+        _check(rc, "apo_split_rows")
+        return out[: n.value].copy()
+
+
+class Replayer:
+    """Trace replayer over a task stream (Section 4.3), host-side."""
+
+    def __init__(self, count_cap: int = 8, decay: float = 0.999, replay_bonus: float = 0.1):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.apo_replayer_create(int(count_cap), float(decay), float(replay_bonus), ctypes.byref(h)),
+               "apo_replayer_create")
+        self._h = h
+
+    def ingest(self, tokens, rows):
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        r = np.ascontiguousarray(rows, dtype=ROW_DTYPE)
+        _check(self._lib.apo_replayer_ingest(self._h, _np_ptr(t) if len(t) else None, len(t),
+                                             _np_ptr(r) if len(r) else None, len(r)), "apo_replayer_ingest")
+
+    def step(self, tokens):
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        _check(self._lib.apo_replayer_step(self._h, _np_ptr(t) if len(t) else None, len(t)), "apo_replayer_step")
+
+    def flush(self):
+        _check(self._lib.apo_replayer_flush(self._h), "apo_replayer_flush")
+
+    def events(self) -> np.ndarray:
+        cap = 256
+        while True:
+            out = np.zeros(cap, dtype=EVENT_DTYPE)
+            n = ctypes.c_uint32(0)
+            rc = self._lib.apo_replayer_events(self._h, _np_ptr(out), cap, ctypes.byref(n))
+            if rc == APO_ERANGE:
+                cap = n.value
+                continue
+            _check(rc, "apo_replayer_events")
+            return out[: n.value].copy()
+
+    def stats(self) -> dict:
+        v = [ctypes.c_uint64(0) for _ in range(4)]
+        _check(self._lib.apo_replayer_stats(self._h, *[ctypes.byref(x) for x in v]), "apo_replayer_stats")
+        return dict(zip(("tasks", "traced", "replays", "traces"), [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.apo_replayer_destroy(self._h)
             self._h = None
 
     def __del__(self):

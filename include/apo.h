@@ -245,10 +245,12 @@ int apo_tracer_create(apo_ctx *ctx, uint32_t stream_id, uint32_t block_tokens, u
 int apo_tracer_push(apo_tracer *t, const uint64_t *tokens, uint32_t n, uint32_t *submitted);
 
 /* Oldest finished analysis in submission order: slice start (in stream
- * positions) and length, and its rows (start relative to the slice).
- * APO_EAGAIN if it is not ready or none is pending. */
+ * positions) and length, and its rows (start relative to the slice).  If
+ * slice_tokens is not NULL it receives the slice's tokens (room for
+ * `capacity` tokens).  APO_EAGAIN if it is not ready or none is pending;
+ * APO_ERANGE (result kept, *out_n = rows) if out_cap is too small. */
 int apo_tracer_poll(apo_tracer *t, uint64_t *slice_begin, uint64_t *slice_len, apo_candidate *out,
-                    uint32_t out_cap, uint32_t *out_n);
+                    uint32_t out_cap, uint32_t *out_n, uint64_t *slice_tokens);
 
 /* Frees the tracer (results still queued are dropped). */
 int apo_tracer_destroy(apo_tracer *t);
@@ -300,6 +302,65 @@ int apo_replayer_destroy(apo_replayer *r);
  * number of pieces; APO_ERANGE if more than out_cap. */
 int apo_split_rows(const apo_candidate *rows, uint32_t n, uint32_t max_len, uint32_t min_len, apo_candidate *out,
                    uint32_t out_cap, uint32_t *out_n);
+
+/* ---- Algorithm 1 end to end, with deterministic ingestion (Section 5.1) ---- */
+
+typedef struct apo_agree apo_agree;
+
+/* Agreement among `nodes` (1..64) replicas of one task stream.  timeout_ms
+ * bounds each vote's wait for the other nodes (0 = wait indefinitely). */
+int apo_agree_create(uint32_t nodes, uint32_t timeout_ms, apo_agree **out);
+
+/* Collective for analysis j: every node calls it once with whether it had
+ * to wait for that analysis; all get *any_waited = OR over the nodes.
+ * Blocks until all nodes voted; APO_EAGAIN (vote withdrawn) on timeout,
+ * APO_EINVAL for a bad node or a second vote. */
+int apo_agree_vote(apo_agree *a, uint32_t node, uint64_t j, int waited, int *any_waited);
+
+int apo_agree_destroy(apo_agree *a);
+
+typedef struct {
+  uint32_t block_tokens;   /* trace finder block (ruler unit), e.g. 250 or 500 */
+  uint32_t capacity;       /* history buffer, e.g. 5000 */
+  uint32_t min_len;        /* minimum trace length, e.g. 25 */
+  uint32_t max_trace_len;  /* recorded traces are split into pieces of at most this, e.g. 200 */
+  uint64_t lag0;           /* tasks between an analysis' submission and its ingestion, initially */
+  uint32_t count_cap;      /* replayer score parameters (apo_replayer_create) */
+  double decay, replay_bonus;
+} apo_auto_params;
+
+/* One ingested analysis: tasks seen at submission and at ingestion, the
+ * analysed slice, pieces ingested, whether this node waited and whether any
+ * node did (which grew the lag). */
+typedef struct {
+  uint64_t submitted_at, ingested_at, slice_begin, slice_len;
+  uint32_t pieces, waited, any_waited;
+} apo_auto_ingest;
+
+typedef struct apo_auto apo_auto;
+
+/* Algorithm 1 over one task stream on ctx's server (apo_server_start must
+ * have been called): trace finder + trace replayer.  Analysis j is ingested
+ * before the task at which submitted_at + lag tasks have been seen (waiting
+ * for it if needed); when any node waited the lag becomes
+ * max(2 * lag, block_tokens).  agree (nullable) is shared by the replicas;
+ * node is this replica's index. */
+int apo_auto_create(apo_ctx *ctx, uint32_t stream_id, const apo_auto_params *p, apo_agree *agree, uint32_t node,
+                    apo_auto **out);
+
+/* ExecuteTask for n tasks with the given tokens (task hashes). */
+int apo_auto_execute(apo_auto *a, const uint64_t *tokens, uint64_t n);
+
+/* The replayer inside (events, stats, flush); owned by the apo_auto. */
+int apo_auto_replayer(apo_auto *a, apo_replayer **out);
+
+/* Ingestion log so far; APO_ERANGE (with *n set) if out_cap is too small. */
+int apo_auto_ingests(apo_auto *a, apo_auto_ingest *out, uint32_t out_cap, uint32_t *n);
+
+/* Current lag and number of analyses this node waited for. */
+int apo_auto_lag(apo_auto *a, uint64_t *lag, uint64_t *waits);
+
+int apo_auto_destroy(apo_auto *a);
 
 #ifdef __cplusplus
 }

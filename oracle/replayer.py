@@ -2,10 +2,11 @@
 Algorithm 1) and of the max-trace-length split (Section 6.2) -- TEST
 INFRASTRUCTURE ONLY, like the rest of ``oracle``.
 
-No trie: a pending match is just the task index where it began, and it stays
-alive while the tokens issued since then are a prefix of some candidate
-(checked by comparing tuples).  A match is complete when those tokens equal a
-candidate.  The decisions follow the order of the algorithm:
+No trie: a pending match is the task index where it began plus the list of
+candidates whose first tokens equal the tokens issued since then (filtered
+token by token).  A match completes a candidate when it has matched all of
+the candidate's tokens, and it dies when no candidate is left.  The decisions
+follow the order of the algorithm:
 
 1. add the task to the pending list P and start a match at it;
 2. keep the matches whose tokens are still a prefix of a candidate;
@@ -48,7 +49,8 @@ class ReplayerRef:
         self.replayed: List[bool] = []
         self.tokens: List[int] = []            # every task's token
         self.issued = 0                        # tasks before this index are issued
-        self.matches: List[int] = []           # start task of each live match
+        # live matches: [start task, ids of the candidates that begin with tokens[start:now]]
+        self.matches: List[list] = []
         self.events: List[Tuple[int, int, int]] = []
 
     def ingest(self, tokens, rows):
@@ -57,15 +59,18 @@ class ReplayerRef:
             if key in self.index:
                 c = self.index[key]
                 self.count[c] = max(self.count[c], float(count))
-            else:
-                self.index[key] = len(self.cands)
-                self.cands.append(key)
-                self.count.append(float(count))
-                self.last.append(len(self.tokens))
-                self.replayed.append(False)
-
-    def _is_prefix(self, seq: tuple) -> bool:
-        return any(c[:len(seq)] == seq for c in self.cands)
+                continue
+            c = len(self.cands)
+            self.index[key] = c
+            self.cands.append(key)
+            self.count.append(float(count))
+            self.last.append(len(self.tokens))
+            self.replayed.append(False)
+            # live matches continue into the new candidate where it agrees with them
+            now = len(self.tokens)
+            for m in self.matches:
+                if len(key) > now - m[0] and key[:now - m[0]] == tuple(self.tokens[m[0]:now]):
+                    m[1].append(c)
 
     def _emit(self, b: int, e: int, trace: int):
         if e <= b:
@@ -81,17 +86,23 @@ class ReplayerRef:
 
     def step(self, tokens):
         for tok in tokens:
-            self.tokens.append(int(tok))
+            tok = int(tok)
+            self.tokens.append(tok)
             now = len(self.tokens)             # tasks seen, including this one
-            self.matches.append(now - 1)
-            self.matches = [b for b in self.matches if self._is_prefix(tuple(self.tokens[b:now]))]
-            done = []
-            for b in self.matches:
-                c = self.index.get(tuple(self.tokens[b:now]))
-                if c is not None:
-                    self.count[c] = self.count[c] * self.decay ** (now - self.last[c]) + 1.0
-                    self.last[c] = now
-                    done.append(c)
+            self.matches.append([now - 1, list(range(len(self.cands)))])
+            done, alive = [], []
+            for b, ids in self.matches:
+                pos = now - 1 - b              # index of this token inside the candidates
+                ids = [c for c in ids if len(self.cands[c]) > pos and self.cands[c][pos] == tok]
+                for c in ids:
+                    if len(self.cands[c]) == pos + 1:
+                        self.count[c] = self.count[c] * self.decay ** (now - self.last[c]) + 1.0
+                        self.last[c] = now
+                        done.append(c)
+                ids = [c for c in ids if len(self.cands[c]) > pos + 1]
+                if ids:
+                    alive.append([b, ids])
+            self.matches = alive
             if done:
                 best = done[0]
                 for c in done[1:]:
@@ -104,7 +115,7 @@ class ReplayerRef:
                 self.replayed[best] = True
                 self.matches = []
                 continue
-            keep = min(self.matches) if self.matches else now
+            keep = min(m[0] for m in self.matches) if self.matches else now
             if keep > self.issued:
                 self._emit(self.issued, keep, -1)
                 self.issued = keep

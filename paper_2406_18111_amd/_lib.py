@@ -21,6 +21,15 @@ APO_MAX_N = 1 << 26
 ROW_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("count", "<u4")])
 OCC_DTYPE = np.dtype([("start", "<u4"), ("length", "<u4"), ("cand", "<u4")])
 EVENT_DTYPE = np.dtype([("begin", "<u8"), ("end", "<u8"), ("trace", "<i8")])
+INGEST_DTYPE = np.dtype([("submitted_at", "<u8"), ("ingested_at", "<u8"), ("slice_begin", "<u8"),
+                         ("slice_len", "<u8"), ("pieces", "<u4"), ("waited", "<u4"), ("any_waited", "<u4"),
+                         ("_pad", "<u4")])
+
+
+class AutoParams(ctypes.Structure):
+    _fields_ = [("block_tokens", ctypes.c_uint32), ("capacity", ctypes.c_uint32), ("min_len", ctypes.c_uint32),
+                ("max_trace_len", ctypes.c_uint32), ("lag0", ctypes.c_uint64), ("count_cap", ctypes.c_uint32),
+                ("decay", ctypes.c_double), ("replay_bonus", ctypes.c_double)]
 
 STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
 COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
@@ -59,7 +68,7 @@ SIGNATURES = {
     "apo_ruler_slice": (_U64, [_U64, _U32, _U64]),
     "apo_tracer_create": (_I, [_P, _U32, _U32, _U32, _U32, ctypes.POINTER(_P)]),
     "apo_tracer_push": (_I, [_P, _P, _U32, _P]),
-    "apo_tracer_poll": (_I, [_P, _P, _P, _P, _U32, _P]),
+    "apo_tracer_poll": (_I, [_P, _P, _P, _P, _U32, _P, _P]),
     "apo_tracer_destroy": (_I, [_P]),
     "apo_replayer_create": (_I, [_U32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_P)]),
     "apo_replayer_ingest": (_I, [_P, _P, _U64, _P, _U32]),
@@ -69,6 +78,15 @@ SIGNATURES = {
     "apo_replayer_stats": (_I, [_P, _P, _P, _P, _P]),
     "apo_replayer_destroy": (_I, [_P]),
     "apo_split_rows": (_I, [_P, _U32, _U32, _U32, _P, _U32, _P]),
+    "apo_agree_create": (_I, [_U32, _U32, ctypes.POINTER(_P)]),
+    "apo_agree_vote": (_I, [_P, _U32, _U64, _I, _P]),
+    "apo_agree_destroy": (_I, [_P]),
+    "apo_auto_create": (_I, [_P, _U32, _P, _P, _U32, ctypes.POINTER(_P)]),
+    "apo_auto_execute": (_I, [_P, _P, _U64]),
+    "apo_auto_replayer": (_I, [_P, ctypes.POINTER(_P)]),
+    "apo_auto_ingests": (_I, [_P, _P, _U32, _P]),
+    "apo_auto_lag": (_I, [_P, _P, _P]),
+    "apo_auto_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -362,7 +380,7 @@ class Tracer:
             rows = np.zeros(max(cap, 1), dtype=ROW_DTYPE)
             b, ln, n = ctypes.c_uint64(0), ctypes.c_uint64(0), ctypes.c_uint32(0)
             rc = self._ctx._lib.apo_tracer_poll(self._h, ctypes.byref(b), ctypes.byref(ln), _np_ptr(rows), len(rows),
-                                                ctypes.byref(n))
+                                                ctypes.byref(n), None)
             if rc == APO_EAGAIN:
                 return None
             if rc == APO_ERANGE:
@@ -403,8 +421,12 @@ def split_rows(rows: np.ndarray, max_len: int, min_len: int = 1) -> np.ndarray:
 class Replayer:
     """Trace replayer over a task stream (Section 4.3), host-side."""
 
-    def __init__(self, count_cap: int = 8, decay: float = 0.999, replay_bonus: float = 0.1):
+    def __init__(self, count_cap: int = 8, decay: float = 0.999, replay_bonus: float = 0.1, _borrow=None):
         self._lib = load()
+        self._owned = _borrow is None
+        if _borrow is not None:
+            self._h = _borrow
+            return
         h = ctypes.c_void_p()
         _check(self._lib.apo_replayer_create(int(count_cap), float(decay), float(replay_bonus), ctypes.byref(h)),
                "apo_replayer_create")
@@ -442,7 +464,87 @@ class Replayer:
 
     def close(self):
         if getattr(self, "_h", None):
-            self._lib.apo_replayer_destroy(self._h)
+            if self._owned:
+                self._lib.apo_replayer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Agreement:
+    """Ingestion agreement among replicas of one task stream (Section 5.1)."""
+
+    def __init__(self, nodes: int, timeout_ms: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        _check(self._lib.apo_agree_create(int(nodes), int(timeout_ms), ctypes.byref(h)), "apo_agree_create")
+        self._h = h
+
+    def vote(self, node: int, j: int, waited: bool) -> bool:
+        out = ctypes.c_int(0)
+        _check(self._lib.apo_agree_vote(self._h, int(node), int(j), int(bool(waited)), ctypes.byref(out)),
+               "apo_agree_vote")
+        return bool(out.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.apo_agree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Auto:
+    """Algorithm 1 over one task stream: trace finder on ctx's server + replayer."""
+
+    def __init__(self, ctx: Context, stream_id: int = 0, block_tokens: int = 250, capacity: int = 5000,
+                 min_len: int = 25, max_trace_len: int = 200, lag0: int = 0, count_cap: int = 8,
+                 decay: float = 0.999, replay_bonus: float = 0.1, agreement: Optional[Agreement] = None,
+                 node: int = 0):
+        self._lib = ctx._lib
+        self.params = AutoParams(block_tokens, capacity, min_len, max_trace_len, lag0, count_cap, decay, replay_bonus)
+        h = ctypes.c_void_p()
+        _check(self._lib.apo_auto_create(ctx._h, int(stream_id), ctypes.byref(self.params),
+                                         agreement._h if agreement is not None else None, int(node), ctypes.byref(h)),
+               "apo_auto_create")
+        self._h, self._ctx = h, ctx
+        r = ctypes.c_void_p()
+        _check(self._lib.apo_auto_replayer(self._h, ctypes.byref(r)), "apo_auto_replayer")
+        self.replayer = Replayer(_borrow=r)
+
+    def execute(self, tokens):
+        t = np.ascontiguousarray(np.asarray(tokens, dtype=np.uint64))
+        _check(self._lib.apo_auto_execute(self._h, _np_ptr(t) if len(t) else None, len(t)), "apo_auto_execute")
+
+    def ingests(self) -> np.ndarray:
+        cap = 64
+        while True:
+            out = np.zeros(cap, dtype=INGEST_DTYPE)
+            n = ctypes.c_uint32(0)
+            rc = self._lib.apo_auto_ingests(self._h, _np_ptr(out), cap, ctypes.byref(n))
+            if rc == APO_ERANGE:
+                cap = n.value
+                continue
+            _check(rc, "apo_auto_ingests")
+            return out[: n.value].copy()
+
+    def lag(self):
+        lag, waits = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(self._lib.apo_auto_lag(self._h, ctypes.byref(lag), ctypes.byref(waits)), "apo_auto_lag")
+        return lag.value, waits.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.replayer._h = None
+            self._lib.apo_auto_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -89,9 +89,7 @@ struct GraphCache {
   const void *tok = nullptr;
   uint64_t total = 0, maxwin = 0;
   uint32_t W = 0, min_len = 0;
-  int tile = 0, digit = 0, ktag = 0;
-  int kev_n = 0;                // timed launches recorded in the graph
-  int kround[kMaxTimed] = {0};
+  int tile = 0, digit = 0;
   void *mem = nullptr;
   hipStream_t stream = nullptr;
   void reset() {
@@ -282,33 +280,42 @@ static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
   ctx->tune.pick(total, tl, db);
   ctx->ws.eng.set_params(tl, db);
   Workspace &w = ctx->ws;
-  if (!ctx->graphs) {
+  // Timed kernel launches are bracketed by events on the stream, which is
+  // only reliable outside captured graphs: profiling runs the same sync-free
+  // sequence without capture.
+  if (!ctx->graphs || w.ktag != 0) {
     rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::FREE);
     if (rc == 1) rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::HOST);
     return map_rc(rc);
   }
   GraphCache &G = ctx->gc;
   const bool hit = G.exec && G.tok == d_tok && G.total == total && G.W == W && G.maxwin == maxwin &&
-                   G.min_len == min_len && G.tile == tl && G.digit == db && G.mem == w.mem && G.stream == s &&
-                   G.ktag == w.ktag;
+                   G.min_len == min_len && G.tile == tl && G.digit == db && G.mem == w.mem && G.stream == s;
   if (hipMemcpyAsync(w.d_off, norm.data(), (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return APO_EDEVICE;
   if (!hit) {
     G.reset();
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return APO_EDEVICE;
-    rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::CAPTURE);
+    bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
-    if (rc || e != hipSuccess || !g) {
+    if (ok) {
+      rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::CAPTURE);
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      ok = rc == 0 && e == hipSuccess && g != nullptr;
+      if (ok && hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        G.exec = nullptr;
+        ok = false;
+      }
+    }
+    if (!ok) {
+      // capture unavailable: run the same sync-free sequence directly from now on
       if (g) (void)hipGraphDestroy(g);
       (void)hipGetLastError();
-      return rc ? map_rc(rc) : APO_EDEVICE;
-    }
-    if (hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      G.exec = nullptr;
-      return APO_EDEVICE;
+      fprintf(stderr, "[apo] graph capture failed; batches run without graphs\n");
+      ctx->graphs = false;
+      rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::FREE);
+      if (rc == 1) rc = run_pipeline(w, d_tok, 64, total, norm.data(), W, min_len, Stop::FULL, s, ctx->info, Mode::HOST);
+      return map_rc(rc);
     }
     G.graph = g;
     G.tok = d_tok;
@@ -320,15 +327,11 @@ static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
     G.digit = db;
     G.mem = w.mem;
     G.stream = s;
-    G.ktag = w.ktag;
-    G.kev_n = w.kev_n;
-    for (int k = 0; k < w.kev_n; k++) G.kround[k] = w.kround[k];
     ctx->graph_captures++;
   } else {
     ctx->graph_replays++;
   }
-  w.kev_n = G.kev_n;
-  for (int k = 0; k < G.kev_n; k++) w.kround[k] = G.kround[k];
+  w.kev_n = 0;
   if (hipGraphLaunch(G.exec, s) != hipSuccess) return APO_EDEVICE;
   ctx->info = RunInfo{};
   rc = finish_run(w, total, 2 * total, kSelFreeRounds, ctx->info, s, false);

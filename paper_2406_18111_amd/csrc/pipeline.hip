@@ -488,16 +488,20 @@ int finish_run(Workspace &w, uint64_t N, uint64_t m_bound, int sel_launched, Run
     for (int k = 0; k < kStages; k++) {
       float ms = 0;
       if (hipEventElapsedTime(&ms, w.ev[k], w.ev[k + 1]) == hipSuccess) info.stage_ms[k] = ms;
+      else (void)hipGetLastError();  // a failed query must not linger as the thread's last error
     }
   }
-  // timed kernel launches (also recorded inside captured graphs)
+  // timed kernel launches (never inside captured graphs)
   for (int k = 0; k < w.kev_n; k++) {
     const uint32_t elems = w.hrhist[4 * w.kround[k] + 2];
     float ms = 0;
-    if (elems && hipEventElapsedTime(&ms, w.kev[2 * k], w.kev[2 * k + 1]) == hipSuccess) {
+    if (!elems) continue;
+    if (hipEventElapsedTime(&ms, w.kev[2 * k], w.kev[2 * k + 1]) == hipSuccess) {
       info.k_launches++;
       info.k_elems += elems;
       info.k_ms += ms;
+    } else {
+      (void)hipGetLastError();
     }
   }
   return 0;

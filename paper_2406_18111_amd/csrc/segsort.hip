@@ -349,6 +349,119 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
   }
 }
 
+// ---------------------------------------------- wavefront sort (tiny units)
+// Units of at most 64 entries (classes 1..6) are sorted inside one wavefront:
+// a 64-lane row holds 64/2^c units of class c, bitonic stages are cross-lane
+// exchanges, group heads come from a wave-wide max-scan, and appends are
+// aggregated per wavefront with ballots.  No LDS, no barriers.
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+constexpr int kWaveMaxCi = 6;  // classes 1..6 (0-based 0..5)
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut R, int last_level, uint8_t *keep) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int nxt = cur ^ 1;
+  uint32_t cnt[kWaveMaxCi], items[kWaveMaxCi];
+  uint32_t total = 0;
+  for (int ci = 0; ci < kWaveMaxCi; ci++) {
+    cnt[ci] = B.ctr->cls_cnt[cur][ci];
+    const uint32_t per = 64u >> (ci + 1);
+    items[ci] = (cnt[ci] + per - 1) / per;
+    total += items[ci];
+  }
+  const uint64_t lanes_lt = (1ull << lane) - 1ull;
+  for (uint32_t item = wave; item < total; item += nwaves) {
+    uint32_t it = item;
+    int ci = 0;
+    while (it >= items[ci]) { it -= items[ci]; ci++; }
+    const int c = ci + 1;
+    const uint32_t sub = 1u << c, per = 64u >> c;
+    const uint32_t first = it * per;
+    const uint32_t nb = min(per, cnt[ci] - first);
+    const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
+    Unit u{0, 0};
+    if (j < nb) u = B.cls[cur][B.cls_off[ci] + first + j];
+    const uint32_t len = u.len & ~kBufBit;
+    const bool valid = j < nb && idx < len;
+    uint64_t v = ~0ull;
+    if (valid) {
+      const int b = (u.len & kBufBit) ? 1 : 0;
+      const uint32_t p = u.start + idx;
+      v = ((uint64_t)B.key[b][p] << 32) | B.val[b][p];
+    }
+    if (lane == 0) {
+      uint32_t tot = 0;
+      for (uint32_t q = 0; q < nb; q++) tot += B.cls[cur][B.cls_off[ci] + first + q].len & ~kBufBit;
+      atomicAdd(&B.ctr->lds_elems, tot);
+    }
+    for (uint32_t k = 2; k <= sub; k <<= 1) {
+      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+        const uint64_t o = shfl_xor64(v, (int)jj);
+        const bool asc = (k == sub) || (((uint32_t)lane & k) == 0);
+        const bool lower = ((uint32_t)lane & jj) == 0;
+        v = (lower == asc) ? (v < o ? v : o) : (v > o ? v : o);
+      }
+    }
+    const uint32_t key = (uint32_t)(v >> 32);
+    const uint32_t prevkey = (uint32_t)__shfl_up((int)key, 1, 64);
+    const uint32_t nextkey = (uint32_t)__shfl_down((int)key, 1, 64);
+    const bool bnd = valid && (idx == 0 || key != prevkey);
+    const bool last = valid && (idx + 1 == len || nextkey != key);
+    const uint32_t hs = wave_incl_max(bnd ? (uint32_t)lane : 0u);  // head lane of this lane's group
+    const bool single = bnd && last;
+    const uint32_t p = u.start + idx;
+    const uint32_t gpos = u.start + (hs - (j << c));
+    if (valid) {
+      const uint32_t val = (uint32_t)v;
+      B.val[0][p] = val;
+      if (MODE == MODE_SA) {
+        R.rank[val] = gpos + 1;
+        R.snap[val] = gpos + 1;
+        if (single) R.fin[val] = (uint8_t)R.round;
+      }
+      if (last_level) keep[p] = bnd ? 1 : 0;
+    }
+    if (!last_level) {
+      const uint64_t am = __ballot(valid && !single);
+      uint32_t abase = 0;
+      if (lane == 0 && am) abase = atomicAdd(&B.ctr->act_cnt[nxt], (uint32_t)__popcll(am));
+      abase = (uint32_t)__shfl((int)abase, 0, 64);
+      if (valid && !single) {
+        const uint32_t w = abase + (uint32_t)__popcll(am & lanes_lt);
+        if (w < B.cap) B.act[nxt][w] = p;
+        else atomicOr(&B.ctr->err, 4u);
+      }
+      // new units: groups of size >= 2, emitted by their last lane, per class
+      const bool emit = last && !bnd;
+      const uint32_t size = (uint32_t)lane - hs + 1;
+      const int mycc = emit ? class_of(size) : -1;
+      uint64_t em = __ballot(emit);
+      while (em) {
+        const int leader = __ffsll((unsigned long long)em) - 1;
+        const int cc = __shfl(mycc, leader, 64);
+        const uint64_t m = __ballot(emit && mycc == cc);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&B.ctr->cls_cnt[nxt][cc], (uint32_t)__popcll(m));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if (emit && mycc == cc) {
+          const uint32_t k = base + (uint32_t)__popcll(m & lanes_lt);
+          const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
+          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{gpos, size};
+          else atomicOr(&B.ctr->err, 8u);
+        }
+        em &= ~m;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------- LDS grouping (large units)
 // For units of 65..2^TLG entries: count the entries of every distinct
 // (unit, key) pair in an LDS hash table, sort only the distinct pairs, turn
@@ -927,25 +1040,15 @@ static void launch_lds(const SortBufs &b, int cur, RankOut R, uint32_t next_bits
   const uint64_t tile = 1ull << b.tile_log;
   const unsigned g = (unsigned)std::min<uint64_t>(2048, std::max<uint64_t>(64, 2 * work_hint / tile + 16));
   const int tl = (int)b.tile_log;
-  // classes below kGroupMinCi: bitonic sub-block sort; kGroupMinCi..min(tl,12)-1:
-  // hash grouping; class 13 (tile 2^13 only): bitonic
+  // classes below kGroupMinCi: wavefront sort; kGroupMinCi..min(tl,12)-1:
+  // hash grouping; class 13 (tile 2^13 only): LDS bitonic
   const int grp_hi = std::min(tl, 12);
-  switch (tl) {
-    case 11:
-      hipLaunchKernelGGL((k_lds_sort<MODE, 11>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep, 0, kGroupMinCi);
-      break;
-    case 13:
-      hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep, 0, kGroupMinCi);
-      hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep, 12, 13);
-      break;
-    default:
-      hipLaunchKernelGGL((k_lds_sort<MODE, 12>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
-                         keep, 0, kGroupMinCi);
-      break;
-  }
+  // units of <= 64 entries: one wavefront each row
+  const unsigned gw = (unsigned)std::min<uint64_t>(4096, std::max<uint64_t>(64, work_hint / 256 + 1));
+  hipLaunchKernelGGL(k_wave_sort<MODE>, dim3(gw), dim3(256), 0, s, b, cur, R, last_level, keep);
+  if (tl == 13)
+    hipLaunchKernelGGL((k_lds_sort<MODE, 13>), dim3(g), dim3(kLdsThreads), 0, s, b, cur, R, next_bits, last_level,
+                       keep, 12, 13);
   if (grp_hi > kGroupMinCi) {
     if (tl == 11)
       hipLaunchKernelGGL((k_lds_group<MODE, 11>), dim3(g), dim3(kGroupThreads), 0, s, b, cur, R, last_level, keep);

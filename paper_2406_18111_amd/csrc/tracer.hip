@@ -18,7 +18,10 @@ struct apo_tracer {
   uint64_t total = 0;             // tokens pushed so far
   uint64_t blocks = 0;            // completed blocks
   uint32_t in_block = 0;
-  struct Pending { uint64_t ticket, begin, len; };
+  struct Pending {
+    uint64_t ticket, begin, len;
+    std::vector<uint64_t> tokens;  // the slice as submitted
+  };
   std::deque<Pending> pending;
   std::mutex mu;
 };
@@ -75,7 +78,7 @@ extern "C" int apo_tracer_push(apo_tracer *t, const uint64_t *tokens, uint32_t n
       if (submitted) *submitted = sub;
       return rc;
     }
-    t->pending.push_back({ticket, begin, len});
+    t->pending.push_back({ticket, begin, len, slice});
     sub++;
   }
   if (submitted) *submitted = sub;
@@ -83,19 +86,20 @@ extern "C" int apo_tracer_push(apo_tracer *t, const uint64_t *tokens, uint32_t n
 }
 
 // Oldest finished analysis (in submission order): the slice it covered in
-// stream coordinates and its rows.  APO_EAGAIN if the oldest is not ready or
-// none is pending.  On APO_ERANGE *out_n holds the row count and the result
-// stays queued.
+// stream coordinates, optionally its tokens, and its rows.  APO_EAGAIN if the
+// oldest is not ready or none is pending.  On APO_ERANGE *out_n holds the row
+// count and the result stays queued.
 extern "C" int apo_tracer_poll(apo_tracer *t, uint64_t *slice_begin, uint64_t *slice_len, apo_candidate *out,
-                               uint32_t out_cap, uint32_t *out_n) {
+                               uint32_t out_cap, uint32_t *out_n, uint64_t *slice_tokens) {
   if (!t || !slice_begin || !slice_len || !out_n || (!out && out_cap)) return APO_EINVAL;
   std::lock_guard<std::mutex> lk(t->mu);
   if (t->pending.empty()) return APO_EAGAIN;
-  const auto p = t->pending.front();
+  const auto &p = t->pending.front();
   const int rc = apo_fetch(t->ctx, p.ticket, out, out_cap, out_n, nullptr);
   if (rc != APO_OK) return rc;
   *slice_begin = p.begin;
   *slice_len = p.len;
+  if (slice_tokens) std::copy(p.tokens.begin(), p.tokens.end(), slice_tokens);
   t->pending.pop_front();
   return APO_OK;
 }

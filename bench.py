@@ -133,7 +133,9 @@ def roofline(kprof, steps):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "LDS sort + LDS grouping kernels of the doubling rounds (k_lds_sort<0>, k_lds_group<0>)",
+            "kernel": "per doubling round, the LDS sort family in SA mode: k_wave_sort<0> (units <= 64) + "
+                      "k_lds_group<0> (65..4096) [+ k_lds_sort<0,13> with 8192-entry tiles], one event pair "
+                      "around the family",
             "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
             "launches_per_step": kprof["launches"] / steps}
 

@@ -157,6 +157,18 @@ int apo_candidates_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, uint3
                        uint32_t min_len, uint32_t *d_len, uint32_t *d_start, uint32_t *d_id,
                        uint32_t cap, uint32_t *h_count, void *hip_stream);
 
+/* Equal-length greedy per substring (Algorithm 2's selection among the
+ * occurrences of one substring, Section 4.2): for m candidates on the device
+ * in the order apo_candidates_dev returns them (a substring's occurrences
+ * are contiguous, by increasing start), d_next[k] = index of the first
+ * occurrence of the same substring starting at or after start[k] + len[k]
+ * (0xFFFFFFFF if none), and d_count[k] = number of occurrences on the chain
+ * k, next[k], next[next[k]], ...; at a substring's first occurrence that is
+ * its non-overlapping occurrence count in isolation.  d_tmp: 3m words of
+ * scratch.  All buffers are the caller's; synchronous on hip_stream. */
+int apo_interval_counts_dev(apo_ctx *ctx, const uint32_t *d_len, const uint32_t *d_start, const uint32_t *d_id,
+                            uint32_t m, uint32_t *d_next, uint32_t *d_count, uint32_t *d_tmp, void *hip_stream);
+
 /* Per-stage device times of the last analysis (ms): token ranks, suffix
  * array, LCP, candidates, candidate sort, selection, output.  Returns the
  * number of stages written (<= nstages). */

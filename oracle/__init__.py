@@ -147,3 +147,26 @@ def find_repeats(tokens, min_len: int, with_stats: bool = False):
     if with_stats:
         res["stats"] = dict(zip(STAT_NAMES, (int(x) for x in st)))
     return res
+
+
+def interval_counts(length, start, ident):
+    """Equal-length greedy per substring over a sorted candidate list
+    (Algorithm 2's selection restricted to the occurrences of one substring,
+    Section 4.2).  Candidates with equal (length, ID) form one substring,
+    listed by increasing start.  Returns (next, count): next[k] = index of the
+    first later occurrence of the same substring starting at or after
+    start[k] + length[k] (-1 if none); count[k] = number of occurrences on the
+    chain k, next[k], ... .  Plain loops."""
+    m = len(length)
+    nxt = np.full(m, -1, dtype=np.int64)
+    cnt = np.zeros(m, dtype=np.int64)
+    for k in range(m):
+        j = k + 1
+        while j < m and length[j] == length[k] and ident[j] == ident[k]:
+            if start[j] >= start[k] + length[k]:
+                nxt[k] = j
+                break
+            j += 1
+    for k in range(m - 1, -1, -1):
+        cnt[k] = 1 + (cnt[nxt[k]] if nxt[k] >= 0 else 0)
+    return nxt, cnt

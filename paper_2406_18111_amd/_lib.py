@@ -51,6 +51,7 @@ SIGNATURES = {
     "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_candidates_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
+    "apo_interval_counts_dev": (_I, [_P, _P, _P, _P, _U32, _P, _P, _P, _P]),
     "apo_last_stage_ms": (_I, [_P, _P, _I]),
     "apo_last_counters": (_I, [_P, _P, _I]),
     "apo_profile_kernel": (_I, [_P, _I]),
@@ -275,6 +276,20 @@ class Context:
                "apo_candidates_dev")
         m = cnt.value
         return {"len": ln[:m], "start": st[:m], "id": ids[:m]}
+
+    def interval_counts_dev(self, cands, stream=None):
+        """Per-substring equal-length greedy over sorted candidates (dict of
+        device tensors as candidates_dev returns): next index and chain count."""
+        import torch
+        ln, st, ids = (cands[k].contiguous() for k in ("len", "start", "id"))
+        m = ln.numel()
+        nxt = torch.empty(max(m, 1), dtype=torch.int32, device=ln.device)
+        cnt = torch.empty(max(m, 1), dtype=torch.int32, device=ln.device)
+        tmp = torch.empty(max(3 * m, 1), dtype=torch.int32, device=ln.device)
+        _check(self._lib.apo_interval_counts_dev(self._h, _dev_ptr(ln), _dev_ptr(st), _dev_ptr(ids), m,
+                                                 _dev_ptr(nxt), _dev_ptr(cnt), _dev_ptr(tmp), _stream_ptr(stream)),
+               "apo_interval_counts_dev")
+        return nxt[:m], cnt[:m]
 
     # ------------------------------------------------------ diagnostics
     def stage_ms(self):

@@ -2,6 +2,7 @@
 // buffers, and the continuous-batching server.
 #include "apo.h"
 #include "pipeline.h"
+#include "stages.h"
 #include <algorithm>
 #include <atomic>
 #include <cstdio>
@@ -455,6 +456,19 @@ extern "C" int apo_candidates_dev(apo_ctx *ctx, const void *d_tokens, int token_
         hipMemcpyAsync(d_id, ctx->ws.s_id, (size_t)m * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
       return APO_EDEVICE;
   }
+  return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_interval_counts_dev(apo_ctx *ctx, const uint32_t *d_len, const uint32_t *d_start,
+                                       const uint32_t *d_id, uint32_t m, uint32_t *d_next, uint32_t *d_count,
+                                       uint32_t *d_tmp, void *stream) {
+  if (!ctx || (m && (!d_len || !d_start || !d_id || !d_next || !d_count || !d_tmp)) || m > 2u * APO_MAX_N)
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  if (m == 0) return APO_OK;
+  hipStream_t s = pick_stream(ctx, stream);
+  apo::interval_counts(d_len, d_start, d_id, m, d_next, d_count, d_tmp, s);
+  if (hipGetLastError() != hipSuccess) return APO_EDEVICE;
   return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
 }
 

@@ -56,7 +56,8 @@ struct Workspace {
   size_t bytes = 0;
 
   uint64_t *tok64 = nullptr;
-  uint32_t *tokrank = nullptr, *htab = nullptr, *hrank = nullptr, *dist_idx = nullptr, *dist_slot = nullptr;
+  uint32_t *tokrank = nullptr, *hrank = nullptr, *dist_idx = nullptr, *dist_slot = nullptr;
+  uint64_t *htab = nullptr;  // distinct token values (hcap + 1 slots)
   uint32_t *dhi = nullptr, *dlo = nullptr;
   uint64_t *d_off = nullptr;
   uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;

@@ -44,7 +44,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   plan(N, W, ns, nt, nl, hc);
   const uint64_t C2 = 2 * N;
   size_t b = 0;
-  b += N * 8 + N * 4 * 8 + hc * 8 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
+  b += N * 8 + N * 4 * 8 + (hc + 1) * 12 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
   b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
   b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
@@ -79,7 +79,8 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   plan(wantN, wantW, nsnap, nT, nlev, hcap);
   const uint64_t N_ = wantN, C2 = 2 * wantN;
   Layout L;
-  size_t o_tok64 = L.take(N_ * 8), o_tokrank = L.take(N_ * 4), o_htab = L.take(hcap * 4), o_hrank = L.take(hcap * 4);
+  size_t o_tok64 = L.take(N_ * 8), o_tokrank = L.take(N_ * 4), o_htab = L.take((hcap + 1) * 8),
+         o_hrank = L.take((hcap + 1) * 4);
   size_t o_di = L.take(N_ * 4), o_ds = L.take(N_ * 4), o_dhi = L.take(N_ * 4), o_dlo = L.take(N_ * 4);
   size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
   size_t o_wr = L.take((wantW + 1) * 4);
@@ -107,7 +108,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   char *m = static_cast<char *>(mem);
   tok64 = (uint64_t *)(m + o_tok64);
   tokrank = (uint32_t *)(m + o_tokrank);
-  htab = (uint32_t *)(m + o_htab);
+  htab = (uint64_t *)(m + o_htab);
   hrank = (uint32_t *)(m + o_hrank);
   dist_idx = (uint32_t *)(m + o_di);
   dist_slot = (uint32_t *)(m + o_ds);
@@ -261,7 +262,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     const uint64_t hc = pow2_at_least(2 * N);
-    fill_u32(w.htab, hc, kNone, s);
+    hash_clear(w.htab, hc - 1, s);
     hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, s);
     uint64_t nd_bound = N;
     if (host) {
@@ -404,7 +405,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       const int hi = std::min(q0 + ahead, kSelRoundCap);
       for (int q = q0; q < hi; q++)
         sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[q & 1],
-                  w.live[(q + 1) & 1], nlive, undec, q, hint, s);
+                  w.live[(q + 1) & 1], nlive, undec, q, hint, dc + CNT_MAXL, s);
       q0 = hi;
       sel_launched = hi;
       if (!host) break;  // checked after the output stage

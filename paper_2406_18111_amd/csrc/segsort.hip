@@ -361,104 +361,163 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
 }
 
 constexpr int kWaveMaxCi = 6;  // classes 1..6 (0-based 0..5)
+constexpr int kWaveItems = 8;  // items per wavefront per block batch
+constexpr int kWaveCtrs = kWaveMaxCi + 2;  // new units per class, active entries, sorted entries
 
+// Units of <= 64 entries, several per wavefront (2^(6-c) units of class c
+// side by side), sorted by a bitonic network over lane shuffles.  A block
+// takes a batch of 4 x kWaveItems items; the slots its new active entries
+// and units need are reserved with one atomic per counter per batch (the
+// per-item counts are wave ballots), so the hot list counters see few
+// atomics.  The batch loop is uniform across the block.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut R, int last_level, uint8_t *keep) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nxt = cur ^ 1;
-  uint32_t cnt[kWaveMaxCi], items[kWaveMaxCi];
-  uint32_t total = 0;
+  __shared__ uint32_t wtot[4][kWaveCtrs];
+  __shared__ uint32_t wbase[4][kWaveCtrs];
+  uint32_t cnt[kWaveMaxCi], first_item[kWaveMaxCi + 1];
+  first_item[0] = 0;
+#pragma unroll
   for (int ci = 0; ci < kWaveMaxCi; ci++) {
     cnt[ci] = B.ctr->cls_cnt[cur][ci];
     const uint32_t per = 64u >> (ci + 1);
-    items[ci] = (cnt[ci] + per - 1) / per;
-    total += items[ci];
+    first_item[ci + 1] = first_item[ci] + (cnt[ci] + per - 1) / per;
   }
+  const uint32_t total = first_item[kWaveMaxCi];
   const uint64_t lanes_lt = (1ull << lane) - 1ull;
-  for (uint32_t item = wave; item < total; item += nwaves) {
-    uint32_t it = item;
-    int ci = 0;
-    while (it >= items[ci]) { it -= items[ci]; ci++; }
-    const int c = ci + 1;
-    const uint32_t sub = 1u << c, per = 64u >> c;
-    const uint32_t first = it * per;
-    const uint32_t nb = min(per, cnt[ci] - first);
-    const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
-    Unit u{0, 0};
-    if (j < nb) u = B.cls[cur][B.cls_off[ci] + first + j];
-    const uint32_t len = u.len & ~kBufBit;
-    const bool valid = j < nb && idx < len;
-    uint64_t v = ~0ull;
-    if (valid) {
-      const int b = (u.len & kBufBit) ? 1 : 0;
-      const uint32_t p = u.start + idx;
-      v = ((uint64_t)B.key[b][p] << 32) | B.val[b][p];
-    }
-    if (lane == 0) {
-      uint32_t tot = 0;
-      for (uint32_t q = 0; q < nb; q++) tot += B.cls[cur][B.cls_off[ci] + first + q].len & ~kBufBit;
-      atomicAdd(&B.ctr->lds_elems, tot);
-    }
-    for (uint32_t k = 2; k <= sub; k <<= 1) {
-      for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-        const uint64_t o = shfl_xor64(v, (int)jj);
-        const bool asc = (k == sub) || (((uint32_t)lane & k) == 0);
-        const bool lower = ((uint32_t)lane & jj) == 0;
-        v = (lower == asc) ? (v < o ? v : o) : (v > o ? v : o);
+  constexpr uint32_t kBatch = 4 * kWaveItems;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * kBatch; b0 < total; b0 += (uint64_t)gridDim.x * kBatch) {
+    // per item and lane: slot of an entry that stays active, and a new unit
+    uint32_t act_p[kWaveItems], unit_pos[kWaveItems], unit_code[kWaveItems];
+    uint32_t tot[kWaveCtrs];
+#pragma unroll
+    for (int q = 0; q < kWaveCtrs; q++) tot[q] = 0;
+#pragma unroll
+    for (int k = 0; k < kWaveItems; k++) {
+      act_p[k] = kNone;
+      unit_code[k] = 0;
+      unit_pos[k] = 0;
+      const uint64_t item = b0 + (uint64_t)wid * kWaveItems + k;
+      if (item >= total) continue;  // wave-uniform
+      int ci = 0;
+#pragma unroll
+      for (int q = 1; q < kWaveMaxCi; q++) ci += item >= first_item[q] ? 1 : 0;
+      uint32_t cnt_ci = 0, off_ci = 0;
+#pragma unroll
+      for (int q = 0; q < kWaveMaxCi; q++)
+        if (q == ci) { cnt_ci = cnt[q]; off_ci = first_item[q]; }
+      const int c = ci + 1;
+      const uint32_t sub = 1u << c, per = 64u >> c;
+      const uint32_t first = (uint32_t)(item - off_ci) * per;
+      const uint32_t nb = min(per, cnt_ci - first);
+      const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
+      Unit u{0, 0};
+      if (j < nb) u = B.cls[cur][B.cls_off[ci] + first + j];
+      const uint32_t len = u.len & ~kBufBit;
+      const bool valid = j < nb && idx < len;
+      uint64_t v = ~0ull;
+      if (valid) {
+        const int bb = (u.len & kBufBit) ? 1 : 0;
+        const uint32_t p = u.start + idx;
+        v = ((uint64_t)B.key[bb][p] << 32) | B.val[bb][p];
       }
-    }
-    const uint32_t key = (uint32_t)(v >> 32);
-    const uint32_t prevkey = (uint32_t)__shfl_up((int)key, 1, 64);
-    const uint32_t nextkey = (uint32_t)__shfl_down((int)key, 1, 64);
-    const bool bnd = valid && (idx == 0 || key != prevkey);
-    const bool last = valid && (idx + 1 == len || nextkey != key);
-    const uint32_t hs = wave_incl_max(bnd ? (uint32_t)lane : 0u);  // head lane of this lane's group
-    const bool single = bnd && last;
-    const uint32_t p = u.start + idx;
-    const uint32_t gpos = u.start + (hs - (j << c));
-    if (valid) {
-      const uint32_t val = (uint32_t)v;
-      B.val[0][p] = val;
-      if (MODE == MODE_SA) {
-        R.rank[val] = gpos + 1;
-        R.snap[val] = gpos + 1;
-        if (single) R.fin[val] = (uint8_t)R.round;
-      }
-      if (last_level) keep[p] = bnd ? 1 : 0;
-    }
-    if (!last_level) {
-      const uint64_t am = __ballot(valid && !single);
-      uint32_t abase = 0;
-      if (lane == 0 && am) abase = atomicAdd(&B.ctr->act_cnt[nxt], (uint32_t)__popcll(am));
-      abase = (uint32_t)__shfl((int)abase, 0, 64);
-      if (valid && !single) {
-        const uint32_t w = abase + (uint32_t)__popcll(am & lanes_lt);
-        if (w < B.cap) B.act[nxt][w] = p;
-        else atomicOr(&B.ctr->err, 4u);
-      }
-      // new units: groups of size >= 2, emitted by their last lane, per class
-      const bool emit = last && !bnd;
-      const uint32_t size = (uint32_t)lane - hs + 1;
-      const int mycc = emit ? class_of(size) : -1;
-      uint64_t em = __ballot(emit);
-      while (em) {
-        const int leader = __ffsll((unsigned long long)em) - 1;
-        const int cc = __shfl(mycc, leader, 64);
-        const uint64_t m = __ballot(emit && mycc == cc);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&B.ctr->cls_cnt[nxt][cc], (uint32_t)__popcll(m));
-        base = (uint32_t)__shfl((int)base, leader, 64);
-        if (emit && mycc == cc) {
-          const uint32_t k = base + (uint32_t)__popcll(m & lanes_lt);
-          const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
-          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{gpos, size};
-          else atomicOr(&B.ctr->err, 8u);
+      for (uint32_t kk = 2; kk <= sub; kk <<= 1) {
+        for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+          const uint64_t o = shfl_xor64(v, (int)jj);
+          const bool asc = (kk == sub) || (((uint32_t)lane & kk) == 0);
+          const bool lower = ((uint32_t)lane & jj) == 0;
+          v = (lower == asc) ? (v < o ? v : o) : (v > o ? v : o);
         }
-        em &= ~m;
+      }
+      const uint32_t key = (uint32_t)(v >> 32);
+      const uint32_t prevkey = (uint32_t)__shfl_up((int)key, 1, 64);
+      const uint32_t nextkey = (uint32_t)__shfl_down((int)key, 1, 64);
+      const bool bnd = valid && (idx == 0 || key != prevkey);
+      const bool last = valid && (idx + 1 == len || nextkey != key);
+      const uint32_t hs = wave_incl_max(bnd ? (uint32_t)lane : 0u);  // head lane of this lane's group
+      const bool single = bnd && last;
+      const uint32_t p = u.start + idx;
+      const uint32_t gpos = u.start + (hs - (j << c));
+      if (valid) {
+        const uint32_t val = (uint32_t)v;
+        B.val[0][p] = val;
+        if (MODE == MODE_SA) {
+          R.rank[val] = gpos + 1;
+          R.snap[val] = gpos + 1;
+          if (single) R.fin[val] = (uint8_t)R.round;
+        }
+        if (last_level) keep[p] = bnd ? 1 : 0;
+      }
+      tot[kWaveMaxCi + 1] += (uint32_t)__popcll(__ballot(valid));
+      if (!last_level) {
+        const bool stay = valid && !single;
+        tot[kWaveMaxCi] += (uint32_t)__popcll(__ballot(stay));
+        if (stay) act_p[k] = p;
+        // new units: groups of size >= 2, emitted by their last lane
+        const bool emit = last && !bnd;
+        const uint32_t size = (uint32_t)lane - hs + 1;
+        const int mycc = emit ? class_of(size) : -1;
+#pragma unroll
+        for (int cc = 0; cc < kWaveMaxCi; cc++) tot[cc] += (uint32_t)__popcll(__ballot(mycc == cc));
+        if (emit) {
+          unit_pos[k] = gpos;
+          unit_code[k] = (size << 8) | (uint32_t)(mycc + 1);
+        }
       }
     }
+    // reserve list slots: one atomic per counter per block batch
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kWaveCtrs; q++) wtot[wid][q] = tot[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < kWaveCtrs) {
+      const int q = threadIdx.x;
+      uint32_t sum = 0;
+      for (int w = 0; w < 4; w++) sum += wtot[w][q];
+      uint32_t base = 0;
+      if (sum) {
+        if (q < kWaveMaxCi) base = atomicAdd(&B.ctr->cls_cnt[nxt][q], sum);
+        else if (q == kWaveMaxCi) base = atomicAdd(&B.ctr->act_cnt[nxt], sum);
+        else atomicAdd(&B.ctr->lds_elems, sum);
+      }
+      for (int w = 0; w < 4; w++) {
+        wbase[w][q] = base;
+        base += wtot[w][q];
+      }
+    }
+    __syncthreads();
+    if (!last_level) {
+      uint32_t abase = wbase[wid][kWaveMaxCi];
+      uint32_t cbase[kWaveMaxCi];
+#pragma unroll
+      for (int cc = 0; cc < kWaveMaxCi; cc++) cbase[cc] = wbase[wid][cc];
+#pragma unroll
+      for (int k = 0; k < kWaveItems; k++) {
+        const bool stay = act_p[k] != kNone;
+        const uint64_t am = __ballot(stay);
+        if (stay) {
+          const uint32_t w = abase + (uint32_t)__popcll(am & lanes_lt);
+          if (w < B.cap) B.act[nxt][w] = act_p[k];
+          else atomicOr(&B.ctr->err, 4u);
+        }
+        abase += (uint32_t)__popcll(am);
+        const int mycc = (int)(unit_code[k] & 0xFF) - 1;
+#pragma unroll
+        for (int cc = 0; cc < kWaveMaxCi; cc++) {
+          const uint64_t m = __ballot(mycc == cc);
+          if (mycc == cc) {
+            const uint32_t kk = cbase[cc] + (uint32_t)__popcll(m & lanes_lt);
+            const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
+            if (kk < capc) B.cls[nxt][B.cls_off[cc] + kk] = Unit{unit_pos[k], unit_code[k] >> 8};
+            else atomicOr(&B.ctr->err, 8u);
+          }
+          cbase[cc] += (uint32_t)__popcll(m);
+        }
+      }
+    }
+    __syncthreads();  // wtot/wbase are reused by the next batch
   }
 }
 

@@ -12,16 +12,20 @@ void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
 void fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint64_t bound, uint8_t v, hipStream_t s);
 void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s);
+void copy_n_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t s);
 void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
                uint32_t *total, hipStream_t s);
 
-void hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask, uint32_t *dist_idx,
+// Table of hc = mask + 1 slots plus one (the token value equal to the empty
+// mark has slot mask + 1); hash_clear empties it.
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s);
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
                  uint32_t *dist_slot, uint32_t *nd, hipStream_t s);
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s);
 void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot,
                  uint32_t *slot_rank, uint64_t hint, hipStream_t s);
-void hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *tab, uint64_t mask,
+void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t mask,
                  const uint32_t *slot_rank, uint32_t *out, hipStream_t s);
 
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
@@ -43,7 +47,7 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *
 void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s);
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
                uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
-               uint64_t live_hint, hipStream_t s);
+               uint64_t live_hint, const uint32_t *maxl, hipStream_t s);
 void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
                     uint8_t *mark, uint64_t n, hipStream_t s);
 
@@ -56,6 +60,10 @@ void emit_rows(const uint32_t *order, const uint32_t *a_dev, uint64_t bound, con
                uint32_t *nrows, hipStream_t s);
 void window_of_occ(const uint32_t *o_start, const uint32_t *wid, const uint32_t *a_dev, uint64_t bound, uint32_t *out,
                    hipStream_t s);
+// Per-substring equal-length greedy over sorted candidates: next occurrence
+// kept after each one and the chain length from it; tmp holds 3m words.
+void interval_counts(const uint32_t *len, const uint32_t *start, const uint32_t *id, uint32_t m, uint32_t *next,
+                     uint32_t *count, uint32_t *tmp, hipStream_t s);
 void iota_u32(uint32_t *p, const uint32_t *n_dev, uint64_t bound, hipStream_t s);
 
 }  // namespace apo

@@ -110,47 +110,62 @@ void fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint64_t bound, uint8_t v, h
 __global__ void k_copy_u32(uint32_t *dst, const uint32_t *src) {
   if (threadIdx.x == 0) *dst = *src;
 }
+__global__ void k_copy_n_u32(uint32_t *dst, const uint32_t *src, uint64_t n) { GRID_STRIDE(i, n) dst[i] = src[i]; }
+
+void copy_n_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t s) {
+  if (n) hipLaunchKernelGGL(k_copy_n_u32, grid_for(n, 256, 8192), dim3(256), 0, s, dst, src, n);
+}
+
 void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, dst, src);
 }
 
 // ------------------------------------------------------ token ranking (u64)
-// Open-addressing table of first-occurrence indices.  Each workgroup first
-// removes duplicates within its tile of tokens with a table in LDS, so only
-// one thread per distinct value and tile touches the global table (loop
-// streams repeat a few hundred hashes thousands of times).  The thread whose
-// CAS claims an empty global slot records a new distinct value.
+// Open-addressing table of the distinct 64-bit token values themselves
+// (kEmpty marks a free slot; the token value equal to kEmpty has the extra
+// slot mask+1 of its own).  Each workgroup first removes duplicates within
+// its tile of tokens with a table in LDS, so only one thread per distinct
+// value and tile probes the global table (loop streams repeat a few hundred
+// hashes thousands of times); a probe compares the stored key, with no
+// dependent read of the token array.  The threads whose CAS claims a slot
+// collect their new distinct values in LDS, and the tile reserves their list
+// entries with one atomic.
 constexpr int kHashTile = 2048, kHashLds = 4096;
+constexpr uint64_t kEmpty = ~0ull;
 
-__device__ __forceinline__ void global_insert(const uint64_t *tok, uint32_t i, uint64_t key, uint32_t *tab,
-                                              uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
-                                              uint32_t *nd) {
+__device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t mask,
+                                              uint64_t *slot) {
+  if (key == kEmpty) {
+    *slot = mask + 1;
+    return atomicCAS(&tab[mask + 1], 0ull, 1ull) == 0ull;
+  }
   uint64_t h = mix64(key) & mask;
   while (true) {
-    uint32_t cur = tab[h];
-    if (cur == kNone) {
-      const uint32_t prev = atomicCAS(&tab[h], kNone, i);
-      if (prev == kNone) {
-        const uint32_t d = atomicAdd(nd, 1u);
-        dist_idx[d] = i;
-        dist_slot[d] = (uint32_t)h;
-        return;
+    unsigned long long cur = tab[h];
+    if (cur == kEmpty) {
+      cur = atomicCAS(&tab[h], (unsigned long long)kEmpty, (unsigned long long)key);
+      if (cur == kEmpty) {
+        *slot = h;
+        return true;
       }
-      cur = prev;
     }
-    if (tok[cur] == key) return;
+    if (cur == key) return false;
     h = (h + 1) & mask;
   }
 }
 
-__global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask,
-                                                     uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd) {
+__global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, unsigned long long *tab,
+                                                     uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
+                                                     uint32_t *nd) {
   __shared__ uint64_t lt[kHashTile];   // the tile's tokens
   __shared__ uint32_t ls[kHashLds];    // local table: tile index + 1 (0 = empty)
+  __shared__ uint32_t new_i[kHashTile], new_h[kHashTile];
+  __shared__ uint32_t nnew, nbase;
   for (uint64_t t0 = (uint64_t)blockIdx.x * kHashTile; t0 < n; t0 += (uint64_t)gridDim.x * kHashTile) {
     const uint32_t m = (uint32_t)min((uint64_t)kHashTile, n - t0);
     for (uint32_t k = threadIdx.x; k < kHashLds; k += blockDim.x) ls[k] = 0;
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) lt[k] = tok[t0 + k];
+    if (threadIdx.x == 0) nnew = 0;
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
       const uint64_t key = lt[k];
@@ -159,12 +174,24 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
         uint32_t prev = ls[h];
         if (prev == 0u) prev = atomicCAS(&ls[h], 0u, k + 1);
         if (prev == 0u) {  // first in this tile
-          global_insert(tok, (uint32_t)(t0 + k), key, tab, mask, dist_idx, dist_slot, nd);
+          uint64_t slot;
+          if (global_insert(key, tab, mask, &slot)) {
+            const uint32_t q = atomicAdd(&nnew, 1u);
+            new_i[q] = (uint32_t)(t0 + k);
+            new_h[q] = (uint32_t)slot;
+          }
           break;
         }
         if (lt[prev - 1] == key) break;
         h = (h + 1) & (kHashLds - 1);
       }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) nbase = nnew ? atomicAdd(nd, nnew) : 0u;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < nnew; k += blockDim.x) {
+      dist_idx[nbase + k] = new_i[k];
+      dist_slot[nbase + k] = new_h[k];
     }
     __syncthreads();
   }
@@ -186,24 +213,33 @@ __global__ void k_hash_assign(const uint32_t *sorted_d, const uint32_t *nd, cons
   GRID_STRIDE(q, m) slot_rank[dist_slot[sorted_d[q]]] = (uint32_t)q + 1u;
 }
 
-__global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *tab, uint64_t mask,
+__global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const unsigned long long *tab, uint64_t mask,
                               const uint32_t *slot_rank, uint32_t *out) {
   GRID_STRIDE(i, n) {
     const uint64_t key = tok[i];
-    uint64_t h = mix64(key) & mask;
-    while (true) {
-      const uint32_t cur = tab[h];
-      if (cur != kNone && tok[cur] == key) { out[i] = slot_rank[h]; break; }
-      h = (h + 1) & mask;
+    uint64_t h = mask + 1;
+    if (key != kEmpty) {
+      h = mix64(key) & mask;
+      while (tab[h] != key) h = (h + 1) & mask;  // every token was inserted
     }
+    out[i] = slot_rank[h];
   }
 }
 
-void hash_insert(const uint64_t *tok, uint64_t n, uint32_t *tab, uint64_t mask, uint32_t *dist_idx,
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) { GRID_STRIDE(i, n) p[i] = v; }
+
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s) {
+  auto *t = reinterpret_cast<unsigned long long *>(tab);
+  hipLaunchKernelGGL(k_fill_u64, grid_for(mask + 1, 256, 8192), dim3(256), 0, s, t, mask + 1,
+                     (unsigned long long)kEmpty);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + mask + 1, (uint64_t)1, 0ull);
+}
+
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
                  uint32_t *dist_slot, uint32_t *nd, hipStream_t s) {
   const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
   hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
-                     0, s, tok, n, tab, mask, dist_idx, dist_slot, nd);
+                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -214,9 +250,10 @@ void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *d
   hipLaunchKernelGGL(k_hash_assign, grid_for(hint, 256, 8192), dim3(256), 0, s, sorted_d, nd, dist_slot,
                      slot_rank);
 }
-void hash_lookup(const uint64_t *tok, uint64_t n, const uint32_t *tab, uint64_t mask, const uint32_t *slot_rank,
+void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t mask, const uint32_t *slot_rank,
                  uint32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_hash_lookup, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n, tab, mask, slot_rank, out);
+  hipLaunchKernelGGL(k_hash_lookup, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n,
+                     reinterpret_cast<const unsigned long long *>(tab), mask, slot_rank, out);
 }
 
 // -------------------------------------------------------------- windows
@@ -496,6 +533,7 @@ struct SelArgs {
   uint32_t *nlive;          // nlive[r]: live count of round r
   uint32_t *undec;          // undec[r]: undecided after round r
   int r;
+  const uint32_t *maxl;     // longest candidate: levels above log2 of it stay empty
 };
 
 __device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.undec[a.r - 1] > 0; }
@@ -518,7 +556,7 @@ __global__ void k_sel_insert(SelArgs a) {
 
 // Level j -> j-1 for the large levels; clears level j of the other table.
 __global__ void k_sel_push(SelArgs a, int j) {
-  if (!sel_active(a)) return;
+  if (!sel_active(a) || (1u << j) > *a.maxl) return;  // level j empty in both tables
   const uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
   uint32_t *Td = a.Tc + (uint64_t)(j - 1) * a.n;
   uint32_t *Oj = a.To + (uint64_t)j * a.n;
@@ -624,8 +662,8 @@ void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_
 
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
                uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
-               uint64_t live_hint, hipStream_t s) {
-  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r};
+               uint64_t live_hint, const uint32_t *maxl, hipStream_t s) {
+  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r, maxl};
   hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
   for (int j = top; j > kSelSmall; j--)
     hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, a, j);
@@ -665,6 +703,65 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
   fill_u8(mark, n, 0, s);
   hipLaunchKernelGGL(k_sel_paint, grid_for(bound, 256, 8192), dim3(256), 0, s, state, len, start, m_dev, mark);
   hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m_dev, mark);
+}
+
+// ------------------------------------------------- per-interval greedy counts
+// Candidates sorted by (length desc, ID asc, start asc): a group of equal
+// (length, ID) is one substring, its occurrences in increasing start order.
+// next[k] = first member k' of k's group with start[k'] >= start[k] + len[k]
+// (the next occurrence the equal-length greedy of Algorithm 2 would keep
+// after k, ignoring other substrings), found by binary search in priority
+// order; count[k] = length of the chain k, next[k], next[next[k]], ...  by
+// pointer jumping.  count at a group's first member is the substring's
+// isolated non-overlapping occurrence count.
+
+__global__ void k_group_next(const uint32_t *len, const uint32_t *start, const uint32_t *id, uint32_t m,
+                             uint32_t *next, uint32_t *cnt, uint32_t *ptr) {
+  GRID_STRIDE(k, m) {
+    const uint32_t l = len[k], g = id[k];
+    const uint64_t e = (uint64_t)start[k] + l;
+    // first index in (k, m) whose key is not below (l, g, e) in priority order
+    uint32_t lo = (uint32_t)k + 1, hi = m;
+    while (lo < hi) {
+      const uint32_t mid = lo + (hi - lo) / 2;
+      const uint32_t lm = len[mid];
+      const bool below = lm > l || (lm == l && (id[mid] < g || (id[mid] == g && (uint64_t)start[mid] < e)));
+      if (below) lo = mid + 1;
+      else hi = mid;
+    }
+    const uint32_t nx = (lo < m && len[lo] == l && id[lo] == g) ? lo : kNone;
+    next[k] = nx;
+    ptr[k] = nx;
+    cnt[k] = 1;
+  }
+}
+
+__global__ void k_chain_jump(uint32_t m, const uint32_t *cnt, const uint32_t *ptr, uint32_t *cnt2, uint32_t *ptr2) {
+  GRID_STRIDE(k, m) {
+    const uint32_t p = ptr[k];
+    if (p == kNone) {
+      cnt2[k] = cnt[k];
+      ptr2[k] = kNone;
+    } else {
+      cnt2[k] = cnt[k] + cnt[p];
+      ptr2[k] = ptr[p];
+    }
+  }
+}
+
+void interval_counts(const uint32_t *len, const uint32_t *start, const uint32_t *id, uint32_t m, uint32_t *next,
+                     uint32_t *count, uint32_t *tmp, hipStream_t s) {
+  if (m == 0) return;
+  uint32_t *c[2] = {count, tmp}, *p[2] = {tmp + m, tmp + 2 * (uint64_t)m};
+  hipLaunchKernelGGL(k_group_next, grid_for(m, 256, 8192), dim3(256), 0, s, len, start, id, m, next, c[0], p[0]);
+  // a chain is at most m long: ceil(log2 m) doublings reach every end
+  int cur = 0;
+  for (uint64_t span = 1; span < m; span <<= 1) {
+    hipLaunchKernelGGL(k_chain_jump, grid_for(m, 256, 8192), dim3(256), 0, s, m, c[cur], p[cur], c[cur ^ 1],
+                       p[cur ^ 1]);
+    cur ^= 1;
+  }
+  if (cur) copy_n_u32(count, c[1], m, s);
 }
 
 // ---------------------------------------------------------------- output

@@ -234,3 +234,39 @@ def test_tune_table_roundtrip(ctx, tmp_path):
     assert open(path).read().split("\n")[1].split() == ["14", str(tl), str(db)]
     ctx.tune_load(path)
     _check_full(ctx, t, m)
+
+
+@pytest.mark.parametrize("name,tokens", CASES, ids=[c[0] for c in CASES])
+def test_interval_counts(ctx, name, tokens):
+    """Per-substring equal-length greedy (next occurrence kept, chain counts)
+    on the sorted candidate list, against the oracle on its own list."""
+    print("case", name, flush=True)
+    ref = _dedup(oracle.sorted_candidates(tokens, 2))
+    rnxt, rcnt = oracle.interval_counts(ref["len"], ref["start"], ref["id"])
+    got = ctx.candidates_dev(_dev(tokens), 2)
+    nxt, cnt = ctx.interval_counts_dev(got)
+    g = nxt.cpu().numpy().astype(np.int64)  # int32 view: "none" reads as -1
+    assert np.array_equal(np.where(g < 0, -1, g), rnxt)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.int64), rcnt)
+
+
+def test_interval_counts_synthetic_lists(ctx):
+    """Seeded candidate lists built directly (groups of equal length and ID,
+    starts ascending; many members per group, long chains)."""
+    import torch
+    rng = np.random.default_rng(23)
+    for trial in range(6):
+        L, S, I = [], [], []
+        lens = sorted(rng.integers(1, 40, int(rng.integers(1, 50))).tolist(), reverse=True)
+        for g, l in enumerate(lens):
+            st = np.unique(rng.integers(0, 20000, int(rng.integers(1, 3000))))
+            L += [l] * len(st)
+            S += st.tolist()
+            I += [g] * len(st)
+        rnxt, rcnt = oracle.interval_counts(L, S, I)
+        d = {k: torch.tensor(np.array(v, dtype=np.int64).astype(np.int32)).cuda()
+             for k, v in (("len", L), ("start", S), ("id", I))}
+        nxt, cnt = ctx.interval_counts_dev(d)
+        g = nxt.cpu().numpy().astype(np.int64)
+        assert np.array_equal(np.where(g < 0, -1, g), rnxt), trial
+        assert np.array_equal(cnt.cpu().numpy().astype(np.int64), rcnt), trial

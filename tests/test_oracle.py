@@ -19,6 +19,7 @@ import pytest
 
 import oracle
 import oracle.naive as nv
+from paper_2406_18111_amd import synth
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")))
 
@@ -347,3 +348,65 @@ def test_planted_mistake_sort_order_is_caught(monkeypatch):
         if all(st + l <= a or a + b <= st for (a, b) in acc):
             acc.append((st, l))
     assert [list(x) for x in acc] != case["runs"][0]["occurrences"]
+
+
+# ---- per-substring equal-length greedy (interval counts) -----------------------
+
+def test_interval_counts_hand_example():
+    # one substring of length 4 at starts 0, 2, 4, 6 (e.g. "abab" in "ababababab"):
+    # 0 -> 4 -> none; 2 -> 6 -> none
+    nxt, cnt = oracle.interval_counts([4, 4, 4, 4], [0, 2, 4, 6], [7, 7, 7, 7])
+    assert nxt.tolist() == [2, 3, -1, -1] and cnt.tolist() == [2, 2, 1, 1]
+    # a second substring never continues the first one's chain
+    nxt, cnt = oracle.interval_counts([4, 4, 3, 3], [0, 9, 0, 3], [7, 7, 1, 1])
+    assert nxt.tolist() == [1, -1, 3, -1] and cnt.tolist() == [2, 1, 2, 1]
+
+
+def _max_disjoint(starts, l):
+    best = 0
+    n = len(starts)
+    for mask in range(1 << n):
+        sel = sorted(starts[i] for i in range(n) if mask >> i & 1)
+        if all(b >= a + l for a, b in zip(sel, sel[1:])):
+            best = max(best, len(sel))
+    return best
+
+
+def test_interval_counts_head_is_maximum_disjoint_set():
+    """Earliest-start greedy over equal-length intervals is optimal (interval
+    scheduling), so the count at a substring's first occurrence equals the
+    largest set of pairwise disjoint occurrences, found by brute force."""
+    rng = np.random.default_rng(17)
+    for _ in range(300):
+        groups = []
+        for g in range(int(rng.integers(1, 4))):
+            l = int(rng.integers(1, 6))
+            starts = sorted(set(rng.integers(0, 30, int(rng.integers(1, 11))).tolist()))
+            groups.append((l, g, starts))
+        groups.sort(key=lambda x: (-x[0], x[1]))
+        L = [l for l, g, st in groups for _ in st]
+        S = [s for l, g, st in groups for s in st]
+        I = [g for l, g, st in groups for _ in st]
+        nxt, cnt = oracle.interval_counts(L, S, I)
+        k = 0
+        for l, g, st in groups:
+            assert cnt[k] == _max_disjoint(st, l)
+            k += len(st)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_interval_counts_on_real_candidates(seed):
+    """On FindRepeats' own candidate lists: chains stay inside a substring and
+    every link is the first non-overlapping later occurrence."""
+    t = synth.loop_stream(seed, 3000, 17 + seed, 16, 0.03)
+    c = oracle.sorted_candidates(t, 4)
+    nxt, cnt = oracle.interval_counts(c["len"], c["start"], c["id"])
+    for k in range(len(nxt)):
+        j = nxt[k]
+        if j >= 0:
+            assert c["len"][j] == c["len"][k] and c["id"][j] == c["id"][k]
+            assert c["start"][j] >= c["start"][k] + c["len"][k]
+            assert all(c["start"][i] < c["start"][k] + c["len"][k] for i in range(k + 1, j))
+            assert cnt[k] == cnt[j] + 1
+        else:
+            assert cnt[k] == 1

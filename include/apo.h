@@ -179,6 +179,14 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
  * sum over rounds of active suffixes, distinct tokens. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
 
+/* Per-round sizes of the last analysis (diagnostic): sa_active[r] = suffixes
+ * entering doubling round r (r < *n_sa); sel_live[q] / sel_undecided[q] =
+ * candidates live at the start of selection round q and still undecided
+ * after it (q < *n_sel).  APO_ERANGE if cap is below either count (the
+ * first cap entries are written). */
+int apo_last_rounds(apo_ctx *ctx, uint32_t *sa_active, uint32_t *n_sa, uint32_t *sel_live, uint32_t *sel_undecided,
+                    uint32_t *n_sel, uint32_t cap);
+
 /* Live timing of one kernel family with HIP events around each of its
  * launches (on the stream the kernel runs on): tag 1 = the LDS sort-and-regroup
  * kernel of the suffix-array doubling rounds; 0 = off.  Costs one event pair

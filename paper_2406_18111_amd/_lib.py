@@ -53,6 +53,7 @@ SIGNATURES = {
     "apo_candidates_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _P, _P, _U32, _P, _P]),
     "apo_interval_counts_dev": (_I, [_P, _P, _P, _P, _U32, _P, _P, _P, _P]),
     "apo_last_stage_ms": (_I, [_P, _P, _I]),
+    "apo_last_rounds": (_I, [_P, _P, _P, _P, _P, _P, _U32]),
     "apo_last_counters": (_I, [_P, _P, _I]),
     "apo_profile_kernel": (_I, [_P, _I]),
     "apo_last_kernel_profile": (_I, [_P, _P, _P, _P]),
@@ -301,6 +302,18 @@ class Context:
         a = (ctypes.c_uint64 * len(COUNTERS))()
         k = self._lib.apo_last_counters(self._h, a, len(COUNTERS))
         return dict(zip(COUNTERS[:k], list(a)[:k]))
+
+    def rounds(self):
+        """Per-round sizes of the last analysis: suffixes entering each doubling
+        round; live and undecided candidates of each selection round."""
+        cap = 128
+        a, l, u = (ctypes.c_uint32 * cap)(), (ctypes.c_uint32 * cap)(), (ctypes.c_uint32 * cap)()
+        ns, nq = ctypes.c_uint32(0), ctypes.c_uint32(0)
+        rc = self._lib.apo_last_rounds(self._h, a, ctypes.byref(ns), l, u, ctypes.byref(nq), cap)
+        if rc not in (APO_OK, APO_ERANGE):
+            _check(rc, "apo_last_rounds")
+        ns, nq = min(ns.value, cap), min(nq.value, cap)
+        return {"sa_active": list(a)[:ns], "sel_live": list(l)[:nq], "sel_undecided": list(u)[:nq]}
 
     def profile_kernel(self, tag: int):
         """Time one kernel family with HIP events (1: LDS sort of the doubling rounds; 0: off)."""

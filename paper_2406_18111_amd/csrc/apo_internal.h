@@ -10,7 +10,7 @@ namespace apo {
 // ---------------------------------------------------------------- tuning
 // The LDS sort tile (2^tile_log 64-bit entries) and the MSD digit width are
 // chosen per run (defaults below, or the autotuner's table).
-constexpr int kMinTileLog = 11, kMaxTileLog = 13, kDefaultTileLog = 12;
+constexpr int kMinTileLog = 11, kMaxTileLog = 13, kDefaultTileLog = 11;
 constexpr int kClasses = kMaxTileLog;       // size class c holds units of length (2^(c-1), 2^c]
 constexpr int kLdsThreads = 256;
 constexpr int kMinDigitBits = 8, kMaxDigitBits = 12, kDefaultDigitBits = 11;

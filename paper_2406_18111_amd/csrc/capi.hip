@@ -516,6 +516,26 @@ extern "C" int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double 
   return APO_OK;
 }
 
+extern "C" int apo_last_rounds(apo_ctx *ctx, uint32_t *sa_active, uint32_t *n_sa, uint32_t *sel_live,
+                               uint32_t *sel_undecided, uint32_t *n_sel, uint32_t cap) {
+  if (!ctx || !n_sa || !n_sel || (cap && (!sa_active || !sel_live || !sel_undecided))) return APO_EINVAL;
+  const Workspace &w = ctx->ws;
+  const RunInfo &I = ctx->info;
+  *n_sa = I.rounds;
+  *n_sel = I.sel_rounds;
+  if (!w.hrhist || !w.hsel) {
+    *n_sa = *n_sel = 0;
+    return APO_OK;
+  }
+  for (uint32_t r = 0; r < I.rounds && r < cap; r++)
+    sa_active[r] = r == 0 ? (uint32_t)ctx->info.n : w.hrhist[4 * (r - 1)];
+  for (uint32_t q = 0; q < I.sel_rounds && q < cap && q < (uint32_t)kSelRoundCap; q++) {
+    sel_live[q] = w.hsel[q];
+    sel_undecided[q] = w.hsel[(kSelRoundCap + 2) + q];
+  }
+  return (I.rounds > cap || I.sel_rounds > cap) ? APO_ERANGE : APO_OK;
+}
+
 // ================================================================== autotuner
 // Times every (LDS tile, digit width) pair on the caller's window and keeps the
 // fastest for the window's size bucket.  Results never depend on the choice.

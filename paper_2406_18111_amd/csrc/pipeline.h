@@ -27,6 +27,7 @@ constexpr int kStages = 7;
 constexpr int kSelRoundCap = 64;
 
 struct RunInfo {
+  uint64_t n = 0;             // tokens analysed (all windows)
   uint32_t rounds = 0;        // doubling rounds incl. the token sort
   uint64_t active_sum = 0;    // sum over rounds of processed suffixes
   uint32_t sigma = 0;         // distinct tokens (64-bit input)
@@ -71,6 +72,7 @@ struct Workspace {
   uint32_t *tmp_a = nullptr, *tmp_b = nullptr, *tmp_c = nullptr, *tmp_d = nullptr, *tile_tmp = nullptr;
   uint32_t *T = nullptr, *live[2] = {nullptr, nullptr};
   uint8_t *state = nullptr, *mark = nullptr;
+  uint32_t *ctree = nullptr;       // canonical-block tree of sparse selection rounds (2 * capN)
   uint32_t *o_len = nullptr, *o_start = nullptr, *o_id = nullptr;
   void *rows = nullptr, *occ = nullptr;
   uint32_t *row_first = nullptr, *rowidx = nullptr;

@@ -45,7 +45,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   const uint64_t C2 = 2 * N;
   size_t b = 0;
   b += N * 8 + N * 4 * 8 + (hc + 1) * 12 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
-  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8;
+  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8;
   b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
 }
@@ -96,7 +96,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
   size_t o_tile = L.take((C2 / 4096 + 4) * 4);
   size_t o_T = L.take(2 * (size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
-  size_t o_state = L.take(C2), o_mark = L.take(N_);
+  size_t o_state = L.take(C2), o_mark = L.take(N_), o_ctree = L.take(2 * N_ * 4);
   size_t o_ol = L.take(N_ * 4), o_os = L.take(N_ * 4), o_oi = L.take(N_ * 4);
   size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
   size_t o_cnt = L.take(CNT_COUNT * 4);
@@ -144,6 +144,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   live[1] = (uint32_t *)(m + o_live1);
   state = (uint8_t *)(m + o_state);
   mark = (uint8_t *)(m + o_mark);
+  ctree = (uint32_t *)(m + o_ctree);
   o_len = (uint32_t *)(m + o_ol);
   o_start = (uint32_t *)(m + o_os);
   o_id = (uint32_t *)(m + o_oi);
@@ -218,6 +219,7 @@ static void stamp(Workspace &w, int k, hipStream_t s, bool on) {
 
 // Reads the device counters of a finished analysis into `info`.
 static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
+  info.n = N;
   info.sigma = w.hcnt[CNT_ND];
   info.cands = w.hcnt[CNT_C];
   info.maxl = w.hcnt[CNT_MAXL];
@@ -396,6 +398,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2);
     fill_u32(Ta, (uint64_t)(top + 1) * N, 0xFFFFFFFFu, s);
     fill_u32(w.selcnt, 2 * (kSelRoundCap + 2), 0, s);
+    const uint64_t npad = pow2_at_least(N);
+    fill_u32(w.ctree, 2 * npad, 0xFFFFFFFFu, s);
+    fill_u8(w.mark, N, 0, s);
     copy_u32(nlive, dc + CNT_M, s);
     sel_init(w.live[0], nlive, w.state, m_bound, s);
     const int ahead = host ? 2 : kSelFreeRounds;
@@ -405,7 +410,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       const int hi = std::min(q0 + ahead, kSelRoundCap);
       for (int q = q0; q < hi; q++)
         sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[q & 1],
-                  w.live[(q + 1) & 1], nlive, undec, q, hint, dc + CNT_MAXL, s);
+                  w.live[(q + 1) & 1], nlive, undec, q, hint, dc + CNT_MAXL, w.ctree, npad, w.mark, s);
       q0 = hi;
       sel_launched = hi;
       if (!host) break;  // checked after the output stage

@@ -534,12 +534,24 @@ struct SelArgs {
   uint32_t *undec;          // undec[r]: undecided after round r
   int r;
   const uint32_t *maxl;     // longest candidate: levels above log2 of it stay empty
+  uint32_t *ctree;          // canonical-block tree for sparse rounds (all kInf between rounds)
+  uint64_t npad;            // power of two >= n: level j of ctree has npad >> j nodes
+  uint8_t *mark;            // positions covered by accepted candidates (sparse rounds)
 };
 
+// Dense rounds while many candidates are undecided; once at most
+// n / kSparseDiv remain, rounds work on the undecided candidates alone.
+constexpr uint32_t kSparseDiv = 32;
+
 __device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.undec[a.r - 1] > 0; }
+__device__ __forceinline__ bool sel_dense_at(const SelArgs &a, int r) {
+  return r == 0 || (uint64_t)a.undec[r - 1] * kSparseDiv > a.n;
+}
+__device__ __forceinline__ bool sel_run_dense(const SelArgs &a) { return sel_active(a) && sel_dense_at(a, a.r); }
+__device__ __forceinline__ bool sel_run_sparse(const SelArgs &a) { return sel_active(a) && !sel_dense_at(a, a.r); }
 
 __global__ void k_sel_insert(SelArgs a) {
-  if (!sel_active(a)) return;
+  if (!sel_run_dense(a)) return;
   const uint32_t m = a.nlive[a.r];
   GRID_STRIDE(q, m) {
     const uint32_t k = a.live[q];
@@ -556,7 +568,7 @@ __global__ void k_sel_insert(SelArgs a) {
 
 // Level j -> j-1 for the large levels; clears level j of the other table.
 __global__ void k_sel_push(SelArgs a, int j) {
-  if (!sel_active(a) || (1u << j) > *a.maxl) return;  // level j empty in both tables
+  if (!sel_run_dense(a) || (1u << j) > *a.maxl) return;  // level j empty in both tables
   const uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
   uint32_t *Td = a.Tc + (uint64_t)(j - 1) * a.n;
   uint32_t *Oj = a.To + (uint64_t)j * a.n;
@@ -573,7 +585,7 @@ __global__ void k_sel_push(SelArgs a, int j) {
 // Levels min(top, kSelSmall)..0 for one tile of positions, halos included;
 // writes level 0 and clears levels 0..J of the other table on the tile.
 __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
-  if (!sel_active(a)) return;
+  if (!sel_run_dense(a)) return;
   constexpr int HMAX = 1 << kSelSmall;
   __shared__ uint32_t buf[2][kPushTile + HMAX];
   const int J = min(a.top, kSelSmall);
@@ -611,7 +623,7 @@ __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
 }
 
 __global__ void k_sel_decide(SelArgs a) {
-  if (!sel_active(a)) return;
+  if (!sel_run_dense(a)) return;
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t und;
@@ -650,6 +662,109 @@ __global__ void k_sel_decide(SelArgs a) {
   if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
 }
 
+// ---- sparse rounds
+// Accepted candidates are final and pairwise disjoint, so they are painted
+// into `mark`; the undecided ones write their priority into the canonical
+// power-of-two blocks of their interval (at most two per level, like a
+// segment tree), and a point's minimum is the minimum over its enclosing
+// blocks.  A round touches only the undecided candidates' blocks.
+__device__ __forceinline__ uint32_t *ctree_level(const SelArgs &a, int j) {
+  return a.ctree + (j == 0 ? 0 : 2 * a.npad - (a.npad >> (j - 1)));
+}
+
+template <bool CLEAR>
+__device__ __forceinline__ void ctree_cover(const SelArgs &a, uint32_t s, uint32_t l, uint32_t k) {
+  uint64_t lo = s, hi = (uint64_t)s + l;
+  for (int j = 0; lo < hi; j++) {
+    uint32_t *Tj = ctree_level(a, j);
+    if (lo & 1) {
+      if (CLEAR) Tj[lo] = kInf;
+      else if (Tj[lo] > k) atomicMin(&Tj[lo], k);
+      lo++;
+    }
+    if (hi & 1) {
+      hi--;
+      if (CLEAR) Tj[hi] = kInf;
+      else if (Tj[hi] > k) atomicMin(&Tj[hi], k);
+    }
+    lo >>= 1;
+    hi >>= 1;
+  }
+}
+
+__device__ __forceinline__ uint32_t ctree_point(const SelArgs &a, uint32_t x, int levels) {
+  uint32_t v = kInf;
+  for (int j = 0; j < levels; j++) v = min(v, ctree_level(a, j)[x >> j]);
+  return v;
+}
+
+__device__ __forceinline__ void paint(uint8_t *mark, uint32_t s, uint32_t l) {
+  for (uint32_t x = s; x < s + l; x++) mark[x] = 1;
+}
+
+// First sparse round: paint the candidates accepted by the dense rounds.
+__global__ void k_sel_sparse_paint(SelArgs a) {
+  if (!sel_run_sparse(a) || !sel_dense_at(a, a.r - 1)) return;
+  const uint32_t m = a.nlive[a.r];
+  GRID_STRIDE(q, m) {
+    const uint32_t k = a.live[q];
+    if (a.state[k] == 1) paint(a.mark, a.start[k], a.len[k]);
+  }
+}
+
+template <bool CLEAR>
+__global__ void k_sel_sparse_cover(SelArgs a) {
+  if (!sel_run_sparse(a)) return;
+  const uint32_t m = a.nlive[a.r];
+  GRID_STRIDE(q, m) {
+    const uint32_t k = a.live[q];
+    // the clear pass walks every listed candidate: blocks never written are kInf already
+    if (CLEAR || a.state[k] == 0) ctree_cover<CLEAR>(a, a.start[k], a.len[k], k);
+  }
+}
+
+__global__ void k_sel_sparse_decide(SelArgs a) {
+  if (!sel_run_sparse(a)) return;
+  __shared__ uint32_t sh[4];
+  __shared__ uint32_t base;
+  __shared__ uint32_t und;
+  if (threadIdx.x == 0) und = 0;
+  __syncthreads();
+  const uint32_t m = a.nlive[a.r];
+  const uint32_t ml = *a.maxl;
+  const int levels = ml ? 32 - __clz((int)ml) : 1;  // blocks of size <= maxl
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
+    const uint64_t q = q0 + threadIdx.x;
+    bool keep = false;
+    uint32_t k = 0;
+    if (q < m) {
+      k = a.live[q];
+      if (a.state[k] == 0) {
+        const uint32_t l = a.len[k], s = a.start[k], e = s + l - 1;
+        uint8_t st = 0;
+        // an accepted candidate touching an endpoint has higher priority
+        if (a.mark[s] || a.mark[e]) {
+          st = 2;
+        } else if (ctree_point(a, s, levels) >= k && ctree_point(a, e, levels) >= k) {
+          st = 1;
+          paint(a.mark, s, l);
+        }
+        if (st != 0) a.state[k] = st;
+        else atomicAdd(&und, 1u);
+        keep = st == 0;
+      }
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
+    __syncthreads();
+    if (keep) a.live_next[base + off] = k;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
+}
+
 __global__ void k_iota(uint32_t *p, const uint32_t *n) {
   const uint32_t m = *n;
   GRID_STRIDE(i, m) p[i] = (uint32_t)i;
@@ -662,14 +777,24 @@ void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_
 
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
                uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
-               uint64_t live_hint, const uint32_t *maxl, hipStream_t s) {
-  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r, maxl};
+               uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
+               hipStream_t s) {
+  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r, maxl, ctree, npad, mark};
+  // dense round (each kernel returns at once when the round is sparse or not needed)
   hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
   for (int j = top; j > kSelSmall; j--)
     hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, a, j);
   const uint64_t ntiles = (n + kPushTile - 1) / kPushTile;
   hipLaunchKernelGGL(k_sel_push_tile, dim3((unsigned)std::min<uint64_t>(ntiles, 4096)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_sel_decide, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
+  // sparse round (returns at once unless few candidates are undecided)
+  if (r > 0) {
+    const dim3 g = grid_for(live_hint, 256, 4096);
+    hipLaunchKernelGGL(k_sel_sparse_paint, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_sparse_cover<false>, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_sparse_decide, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_sparse_cover<true>, g, dim3(256), 0, s, a);
+  }
 }
 
 // Exact sequential completion for whatever is still undecided after the

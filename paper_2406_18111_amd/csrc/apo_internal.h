@@ -13,6 +13,9 @@ namespace apo {
 constexpr int kMinTileLog = 11, kMaxTileLog = 13, kDefaultTileLog = 11;
 constexpr int kClasses = kMaxTileLog;       // size class c holds units of length (2^(c-1), 2^c]
 constexpr int kLdsThreads = 256;
+// Doubling rounds from this one on keep a rank snapshot for the LCP stage;
+// shorter prefixes are compared token by token there.
+constexpr int kSnapFrom = 4;
 constexpr int kMinDigitBits = 8, kMaxDigitBits = 12, kDefaultDigitBits = 11;
 constexpr int kBins = 1 << kMaxDigitBits;   // histogram stride per large unit
 constexpr int kMaxMsdLevels = 4;            // 32-bit keys / 8-bit digits
@@ -75,6 +78,7 @@ struct RankOut {
   uint32_t *snap;       // snapshot of this round: snap[pos]
   uint8_t *fin;         // round in which the suffix became a singleton
   uint32_t round;
+  uint8_t *aflag;       // aflag[slot] = 1 if the slot's suffix is still grouped (replaces the active list)
 };
 
 inline int ceil_log2_u64(uint64_t x) {

@@ -73,6 +73,7 @@ struct Workspace {
   uint32_t *T = nullptr, *live[2] = {nullptr, nullptr};
   uint8_t *state = nullptr, *mark = nullptr;
   uint32_t *ctree = nullptr;       // canonical-block tree of sparse selection rounds (2 * capN)
+  uint8_t *aflag = nullptr;        // doubling rounds: slot still grouped
   uint32_t *o_len = nullptr, *o_start = nullptr, *o_id = nullptr;
   void *rows = nullptr, *occ = nullptr;
   uint32_t *row_first = nullptr, *rowidx = nullptr;

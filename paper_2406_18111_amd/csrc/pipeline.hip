@@ -45,7 +45,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   const uint64_t C2 = 2 * N;
   size_t b = 0;
   b += N * 8 + N * 4 * 8 + (hc + 1) * 12 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
-  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8;
+  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8 + N;
   b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
 }
@@ -96,7 +96,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
   size_t o_tile = L.take((C2 / 4096 + 4) * 4);
   size_t o_T = L.take(2 * (size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
-  size_t o_state = L.take(C2), o_mark = L.take(N_), o_ctree = L.take(2 * N_ * 4);
+  size_t o_state = L.take(C2), o_mark = L.take(N_), o_ctree = L.take(2 * N_ * 4), o_aflag = L.take(N_);
   size_t o_ol = L.take(N_ * 4), o_os = L.take(N_ * 4), o_oi = L.take(N_ * 4);
   size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
   size_t o_cnt = L.take(CNT_COUNT * 4);
@@ -145,6 +145,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   state = (uint8_t *)(m + o_state);
   mark = (uint8_t *)(m + o_mark);
   ctree = (uint32_t *)(m + o_ctree);
+  aflag = (uint8_t *)(m + o_aflag);
   o_len = (uint32_t *)(m + o_ol);
   o_start = (uint32_t *)(m + o_os);
   o_id = (uint32_t *)(m + o_oi);
@@ -308,8 +309,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   const int spec = host ? 4 : r_max;
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
-    if (r > 0) E.gather_sa(cur, w.rank, wend, (uint32_t)N, 1u << (r - 1), (uint32_t)act, w.rhist, r, s);
-    RankOut R{w.rank, w.snap + (size_t)r * N, w.fin, (uint32_t)r};
+    if (r > 0) E.gather_sa(cur, w.rank, w.aflag, wend, (uint32_t)N, 1u << (r - 1), w.rhist, r, s);
+    RankOut R{w.rank, r >= kSnapFrom ? w.snap + (size_t)r * N : nullptr, w.fin, (uint32_t)r, w.aflag};
     if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rank_bits, s);
     const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
     if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
@@ -353,7 +354,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 
   // ---- LCP via Phi / PLCP (lifting over rounds r-1..0; more levels than
   // needed are harmless: no suffix pair is grouped beyond its last round)
-  build_lcp(w.sa, N, wbeg, wend, w.snap, w.fin, r - 1, w.phi, w.plcp, w.lcp, s);
+  build_lcp(w.sa, N, wbeg, wend, w.snap, w.fin, key0, r - 1, w.phi, w.plcp, w.lcp, s);
   stamp(w, 3, s, stamps);
   if (stop == Stop::LCP) return read_counters(w, s);
 
@@ -396,7 +397,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int top = 63 - __builtin_clzll(maxl_bound);
     uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
     uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2);
-    fill_u32(Ta, (uint64_t)(top + 1) * N, 0xFFFFFFFFu, s);
+    sel_table_init(Ta, N, dc + CNT_MAXL, top, s);
     fill_u32(w.selcnt, 2 * (kSelRoundCap + 2), 0, s);
     const uint64_t npad = pow2_at_least(N);
     fill_u32(w.ctree, 2 * npad, 0xFFFFFFFFu, s);

@@ -21,8 +21,8 @@ class SortEngine {
   void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
                   hipStream_t s);
   void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
-  void gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n, uint32_t h,
-                 uint32_t act_hint, uint32_t *hist, int r, hipStream_t s);
+  void gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend, uint32_t n,
+                 uint32_t h, uint32_t *hist, int r, hipStream_t s);
   void gather_field(int cur, const uint32_t *field, const uint32_t *all_dev, int sub, const uint32_t *c_dev,
                     uint32_t c, uint64_t bound, hipStream_t s);
   void iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s);

@@ -115,8 +115,13 @@ __global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n) {
 // 0 when that lies past the end of the suffix's window.
 // Block 0 also closes the previous round (records its outcome in hist[r-1])
 // and clears the counters of this round (what k_round_end / k_round_begin do).
-__global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uint32_t *slot_wend,
-                            uint32_t n, uint32_t h, uint32_t *hist, int r) {
+// Opens round r (records round r-1's outcome, resets the list counters) and
+// gathers the sort key of every still-grouped slot: the rank of the suffix
+// 2^(r-1) positions later (0 past the window end).  A dense pass over the
+// slots (the grouped-slot flags are sequential) instead of an active list;
+// blocks are renumbered so each XCD sweeps one contiguous share of the slots.
+__global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uint8_t *aflag,
+                            const uint32_t *slot_wend, uint32_t n, uint32_t h, uint32_t *hist, int r) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     SortCounters *c = B.ctr;
     const int nxt = cur ^ 1;
@@ -130,19 +135,16 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
     c->act_cnt[nxt] = 0;
     c->lds_elems = 0;
   }
-  const uint32_t cnt = B.ctr->act_cnt[cur];
-  const uint32_t *act = B.act[cur];
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
-    const uint32_t p = act[q];
+  const uint32_t g = gridDim.x, b = blockIdx.x;
+  const uint64_t lb = (g & 7u) ? b : (uint64_t)(b & 7u) * (g >> 3) + (b >> 3);
+  for (uint64_t p = lb * blockDim.x + threadIdx.x; p < n; p += (uint64_t)g * blockDim.x) {
+    if (!aflag[p]) continue;
     const uint32_t x = B.val[0][p] + h;
     const uint32_t we = slot_wend ? slot_wend[p] : n;
     B.key[0][p] = x < we ? rank[x] : 0u;
   }
 }
 
-// Multi-key sort: key = field[val] (or c - field[val] when `sub`, with c read
-// from c_dev when given), over the active list, or over slots [0, *all_dev)
-// when all_dev is given.
 __global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, const uint32_t *all_dev, int sub,
                                const uint32_t *c_dev, uint32_t c) {
   const uint32_t cnt = all_dev ? *all_dev : B.ctr->act_cnt[cur];
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       B.val[0][p] = v;
       if (MODE == MODE_SA) {
         R.rank[v] = gpos + 1;
-        R.snap[v] = gpos + 1;
+        if (R.snap) R.snap[v] = gpos + 1;
         if (single) R.fin[v] = (uint8_t)R.round;
       }
       if (last_level) {
@@ -329,7 +331,9 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
         const uint32_t hs = hd[s];
         const bool bnd = hs == (uint32_t)s;
         const bool last = (idx + 1 == len) || ((uint32_t)(d[s + 1] >> 32) != (uint32_t)(d[s] >> 32));
-        if (!(bnd && last)) {
+        if (R.aflag) {
+          R.aflag[u.start + idx] = (bnd && last) ? 0 : 1;
+        } else if (!(bnd && last)) {
           if (w < B.cap) B.act[nxt][w] = u.start + idx;
           else atomicOr(&B.ctr->err, 4u);
           w++;
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
         B.val[0][p] = val;
         if (MODE == MODE_SA) {
           R.rank[val] = gpos + 1;
-          R.snap[val] = gpos + 1;
+          if (R.snap) R.snap[val] = gpos + 1;
           if (single) R.fin[val] = (uint8_t)R.round;
         }
         if (last_level) keep[p] = bnd ? 1 : 0;
@@ -453,7 +457,11 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
       if (!last_level) {
         const bool stay = valid && !single;
         tot[kWaveMaxCi] += (uint32_t)__popcll(__ballot(stay));
-        if (stay) act_p[k] = p;
+        if (R.aflag) {
+          if (valid) R.aflag[p] = stay ? 1 : 0;
+        } else if (stay) {
+          act_p[k] = p;
+        }
         // new units: groups of size >= 2, emitted by their last lane
         const bool emit = last && !bnd;
         const uint32_t size = (uint32_t)lane - hs + 1;
@@ -707,8 +715,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         B.val[0][slot] = v;
         if (MODE == MODE_SA) {
           R.rank[v] = head + 1;
-          R.snap[v] = head + 1;
+          if (R.snap) R.snap[v] = head + 1;
           if (gcnt == 1) R.fin[v] = (uint8_t)R.round;
+          if (R.aflag) R.aflag[slot] = gcnt >= 2 ? 1 : 0;
         }
         if (last_level) {
           keep[slot] = (pos == gbase) ? 1 : 0;
@@ -738,9 +747,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         const uint32_t j = EJ[p];
         const Unit u = ud[j];
         const uint32_t slot = u.start + (pos_q[q] - uoff[j]);
-        if (w < B.cap) B.act[nxt][w] = slot;
-        else atomicOr(&B.ctr->err, 4u);
-        w++;
+        if (!R.aflag) {
+          if (w < B.cap) B.act[nxt][w] = slot;
+          else atomicOr(&B.ctr->err, 4u);
+          w++;
+        }
         if (pos_q[q] == gbase) {
           const int cc = class_of(gcnt);
           const uint32_t k = cls_base[cc] + atomicAdd(&cls_loc[cc], 1u);
@@ -967,7 +978,8 @@ __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, ui
         if (alt) B.val[0][p] = v;
         if (MODE == MODE_SA) {
           R.rank[v] = bu.start + 1;
-          R.snap[v] = bu.start + 1;
+          if (R.snap) R.snap[v] = bu.start + 1;
+          if (R.aflag) R.aflag[p] = 1;
         }
         if (last_level) keep[p] = (p == bu.start) ? 1 : 0;
       }
@@ -976,7 +988,7 @@ __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, ui
       const uint32_t cnt = hi - lo;
       if (threadIdx.x == 0) base = atomicAdd(&B.ctr->act_cnt[nxt], cnt);
       __syncthreads();
-      for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+      for (uint32_t e = threadIdx.x; e < cnt && !R.aflag; e += NT) {
         const uint32_t w = base + e;
         if (w < B.cap) B.act[nxt][w] = lo + e;
         else atomicOr(&B.ctr->err, 256u);
@@ -1067,10 +1079,9 @@ void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s)
   hipLaunchKernelGGL(k_gather_identity, grid_for(n, 256, 4096), dim3(256), 0, s, b_, src, n);
 }
 
-void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint32_t *slot_wend, uint32_t n,
-                           uint32_t h, uint32_t act_hint, uint32_t *hist, int r, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_sa, grid_for(act_hint, 256, 4096), dim3(256), 0, s, b_, cur, rank,
-                     slot_wend, n, h, hist, r);
+void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend,
+                           uint32_t n, uint32_t h, uint32_t *hist, int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sa, dim3(4096), dim3(256), 0, s, b_, cur, rank, aflag, slot_wend, n, h, hist, r);
 }
 
 void SortEngine::gather_field(int cur, const uint32_t *field, const uint32_t *all_dev, int sub, const uint32_t *c_dev,

@@ -31,9 +31,9 @@ void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t 
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 
-void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-               const uint32_t *snap, const uint8_t *fin, int top, uint32_t *phi, uint32_t *plcp,
-               uint32_t *lcp, hipStream_t s);
+void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
+               const uint8_t *fin, const uint32_t *key0, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp,
+               hipStream_t s);
 
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend,
                     uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *c_len,
@@ -44,6 +44,8 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *
                     uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s);
 
+// Empties the levels of a selection sparse table that a run can use.
+void sel_table_init(uint32_t *T, uint64_t n, const uint32_t *maxl, int top, hipStream_t s);
 void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s);
 // One selection round: dense (sparse table over all positions) while many
 // candidates are undecided, sparse (canonical blocks of the undecided ones,

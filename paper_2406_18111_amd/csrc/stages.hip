@@ -8,15 +8,27 @@
 
 namespace apo {
 
+// Grids are multiples of 8 blocks (caps are multiples of 8 too).
 static inline dim3 grid_for(uint64_t n, int threads, int cap_blocks) {
   uint64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
+  b = (b + 7) & ~7ull;
   if (b > (uint64_t)cap_blocks) b = cap_blocks;
   return dim3((unsigned)b);
 }
 
+// Workgroups of one launch go to the 8 XCDs in turn (block b to XCD b % 8),
+// and each XCD has its own L2.  Renumbering the blocks so that every XCD
+// works on one contiguous eighth of the index range keeps a window's random
+// accesses (its ranks, tokens, LCPs) inside one L2.
+__device__ __forceinline__ uint64_t xcd_block() {
+  const uint32_t b = blockIdx.x, g = gridDim.x;
+  if (g & 7u) return b;
+  return (uint64_t)(b & 7u) * (g >> 3) + (b >> 3);
+}
+
 #define GRID_STRIDE(i, n) \
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
+  for (uint64_t i = xcd_block() * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
 
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) { GRID_STRIDE(i, n) p[i] = v; }
@@ -286,27 +298,48 @@ __global__ void k_phi(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, uint
 // lcp(x, y) >= acc known; extend by binary lifting over the per-round rank
 // snapshots: 2^j-prefixes at x+acc and y+acc are equal iff both suffixes were
 // still in a shared group after round j and carried the same rank then.
+// Snapshots exist for rounds >= kSnapFrom only; the last < 2^kSnapFrom
+// tokens are compared directly (key0: order-preserving token keys).
 __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t acc, uint32_t we, int top,
-                                             const uint32_t *snap, uint64_t n, const uint8_t *fin) {
-  for (int j = top; j >= 0; j--) {
+                                             const uint32_t *snap, uint64_t n, const uint8_t *fin,
+                                             const uint32_t *key0) {
+  for (int j = top; j >= kSnapFrom; j--) {
     const uint32_t a = x + acc, b = y + acc;
     if (a >= we || b >= we) break;
     if (fin[a] > j && fin[b] > j && snap[(uint64_t)j * n + a] == snap[(uint64_t)j * n + b]) acc += 1u << j;
   }
-  return acc;
+  // the remaining < 2^kSnapFrom tokens: issue all loads at once, then find
+  // the first mismatch (or the window end)
+  constexpr int kTail = 1 << kSnapFrom;
+  const uint32_t a = x + acc, b = y + acc;
+  const uint32_t room = (a < we && b < we) ? we - max(a, b) : 0u;
+  uint32_t ka[kTail], kb[kTail];
+#pragma unroll
+  for (int k = 0; k < kTail; k++) {
+    const bool in = (uint32_t)k < room;
+    ka[k] = in ? key0[a + k] : 0u;
+    kb[k] = in ? key0[b + k] : 1u;
+  }
+  uint32_t t = kTail;
+#pragma unroll
+  for (int k = kTail - 1; k >= 0; k--)
+    if (ka[k] != kb[k]) t = (uint32_t)k;
+  return acc + t;
 }
 
-constexpr int kKasaiChunk = 16;
 constexpr int kKasaiCap = 64;
 
-// Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of consecutive
-// positions; each chunk (and each window start) is seeded exactly by lifting,
-// and an extension longer than kKasaiCap tokens switches to lifting.
+// Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of `chunk`
+// consecutive positions; each chunk (and each window start) is seeded exactly
+// by lifting, and an extension longer than kKasaiCap tokens switches to
+// lifting.  Consecutive positions mostly have consecutive Phi values on
+// repetitive input, so the chunk's token reads stay local.
 __global__ void k_plcp(const uint32_t *phi, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-                       const uint32_t *snap, const uint8_t *fin, int top, uint32_t *plcp) {
-  const uint64_t nchunks = (n + kKasaiChunk - 1) / kKasaiChunk;
+                       const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t chunk,
+                       uint32_t *plcp) {
+  const uint64_t nchunks = (n + chunk - 1) / chunk;
   GRID_STRIDE(t, nchunks) {
-    const uint64_t j0 = t * kKasaiChunk, j1 = min(j0 + kKasaiChunk, n);
+    const uint64_t j0 = t * chunk, j1 = min(j0 + chunk, n);
     uint32_t h = 0;
     bool fresh = true;
     for (uint64_t j = j0; j < j1; j++) {
@@ -316,14 +349,14 @@ __global__ void k_plcp(const uint32_t *phi, uint64_t n, const uint32_t *wbeg, co
       if (y == kNone) { plcp[j] = 0; h = 0; fresh = true; continue; }
       const uint32_t we = wend ? wend[j] : (uint32_t)n;
       if (fresh) {
-        h = lcp_lift((uint32_t)j, y, 0u, we, top, snap, n, fin);
+        h = lcp_lift((uint32_t)j, y, 0u, we, top, snap, n, fin, key0);
         fresh = false;
       } else {
         h = h > 0 ? h - 1 : 0;
         int steps = 0;
-        while ((uint32_t)j + h < we && y + h < we && snap[(uint32_t)j + h] == snap[y + h]) {
+        while ((uint32_t)j + h < we && y + h < we && key0[(uint32_t)j + h] == key0[y + h]) {
           h++;
-          if (++steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin); break; }
+          if (++steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin, key0); break; }
         }
       }
       plcp[j] = h;
@@ -339,10 +372,15 @@ __global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, cons
 }
 
 void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
-               const uint8_t *fin, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp, hipStream_t s) {
+               const uint8_t *fin, const uint32_t *key0, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp,
+               hipStream_t s) {
   hipLaunchKernelGGL(k_phi, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wbeg, phi);
-  const uint64_t nch = (n + kKasaiChunk - 1) / kKasaiChunk;
-  hipLaunchKernelGGL(k_plcp, grid_for(nch, 256, 8192), dim3(256), 0, s, phi, n, wbeg, wend, snap, fin, top, plcp);
+  // short chunks: each thread's walk is a chain of dependent loads, so many
+  // threads are needed to cover latency (longer chunks measured slower)
+  const uint32_t chunk = 16;
+  const uint64_t nch = (n + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_plcp, grid_for(nch, 256, 8192), dim3(256), 0, s, phi, n, wbeg, wend, snap, fin, key0, top,
+                     chunk, plcp);
   hipLaunchKernelGGL(k_lcp, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
 }
 
@@ -363,23 +401,32 @@ struct MinLevels {
   int nlev;
 };
 
-// Largest j < i with lcp[j] < l, or -1.  Scans the block of i at level 0,
-// climbs 64-ary minimum levels until an entry below l appears, then descends
-// to its rightmost qualifying leaf.
-// `win` holds lcp[wlo, wlo + wn) in LDS (level-0 reads inside it come from LDS).
-__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l, const uint32_t *win, uint64_t wlo,
-                             uint64_t wn) {
-  uint64_t pos = i;  // exclusive bound at the current level
-  int lev = 0;
+constexpr int kWinBack = 64;                 // window entries before the block's first pair
+constexpr int kWin = 256 + kWinBack;         // LDS window of LCP values per block
+constexpr int kWinLevels = 9;                // 2^8 < kWin <= 2^9
+
+// Largest j < i with lcp[j] < l, or -1.  Inside the block's LDS window the
+// search is binary lifting over a sparse table of window minima
+// (st[k][x] = min lcp[wlo + x .. wlo + x + 2^k)); below the window (which
+// starts on a multiple of 64) it climbs the 64-ary minimum levels until an
+// entry below l appears, then descends to its rightmost qualifying leaf.
+__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l, const uint32_t (*st)[kWin], uint64_t wlo) {
+  int x = (int)(i - wlo);  // [x, i - wlo) holds only values >= l
+#pragma unroll
+  for (int k = kWinLevels - 1; k >= 0; k--)
+    if (x >= (1 << k) && st[k][x - (1 << k)] >= l) x -= 1 << k;
+  if (x > 0) return (int64_t)(wlo + x - 1);
+  if (wlo == 0) return -1;
+  uint64_t pos = wlo >> 6;  // exclusive bound at level 1
+  int lev = 1;
   int64_t found = -1;
+  if (M.nlev < 2) return -1;
   while (pos > 0) {
     // the top level has no parent: scan it down to entry 0
     const uint64_t bs = (lev + 1 >= M.nlev) ? 0 : ((pos - 1) >> 6) << 6;
     const uint32_t *L = M.lv[lev];
     for (uint64_t e = pos; e > bs; e--) {
-      const uint64_t x = e - 1;
-      const uint32_t v = (lev == 0 && x >= wlo && x - wlo < wn) ? win[x - wlo] : L[x];
-      if (v < l) { found = (int64_t)x; break; }
+      if (L[e - 1] < l) { found = (int64_t)(e - 1); break; }
     }
     if (found >= 0) break;
     if (lev + 1 >= M.nlev) return -1;
@@ -413,16 +460,21 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t bmax;
-  __shared__ uint32_t win[256 + 64];
+  __shared__ uint32_t st[kWinLevels][kWin];
   if (threadIdx.x == 0) bmax = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+  for (uint64_t i0 = xcd_block() * blockDim.x; i0 < n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
-    // pairs [i0, i0+256) scan at most 64 entries to their left at level 0
-    const uint64_t wlo = i0 >= 64 ? i0 - 64 : 0;
-    const uint64_t wn = min((uint64_t)(256 + 64), n - wlo);
-    for (uint64_t x = threadIdx.x; x < wn; x += blockDim.x) win[x] = lcp[wlo + x];
+    // LDS window lcp[wlo, wlo + wn) with a sparse table of minima over it
+    const uint64_t wlo = i0 >= kWinBack ? i0 - kWinBack : 0;
+    const int wn = (int)min((uint64_t)kWin, n - wlo);
+    for (int x = threadIdx.x; x < kWin; x += blockDim.x) st[0][x] = x < wn ? lcp[wlo + x] : 0u;
     __syncthreads();
+    for (int k = 1; k < kWinLevels; k++) {
+      for (int x = threadIdx.x; x < kWin; x += blockDim.x)
+        st[k][x] = x + (1 << (k - 1)) < kWin ? min(st[k - 1][x], st[k - 1][x + (1 << (k - 1))]) : st[k - 1][x];
+      __syncthreads();
+    }
     uint32_t l = 0, a = 0, b = 0, id = 0;
     bool emit = false;
     if (i + 1 < n) {
@@ -440,7 +492,7 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
         }
         if (l >= min_len) {
           emit = true;
-          id = (uint32_t)(psv_query(M, i, l, win, wlo, wn) + 1);
+          id = (uint32_t)(psv_query(M, i, l, st, wlo) + 1);
         }
       }
     }
@@ -588,9 +640,10 @@ __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
   if (!sel_run_dense(a)) return;
   constexpr int HMAX = 1 << kSelSmall;
   __shared__ uint32_t buf[2][kPushTile + HMAX];
-  const int J = min(a.top, kSelSmall);
+  const uint32_t ml = *a.maxl;
+  const int J = min(min(a.top, kSelSmall), ml ? 31 - __clz((int)ml) : 0);  // levels above log2(maxl) are empty
   const uint64_t ntiles = (a.n + kPushTile - 1) / kPushTile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (uint64_t t = xcd_block(); t < ntiles; t += gridDim.x) {
     const int64_t x0 = (int64_t)t * kPushTile;
     const int64_t x1 = min((int64_t)a.n, x0 + kPushTile);
     // level J over [x0 - 2^J + 1, x1)
@@ -768,6 +821,20 @@ __global__ void k_sel_sparse_decide(SelArgs a) {
 __global__ void k_iota(uint32_t *p, const uint32_t *n) {
   const uint32_t m = *n;
   GRID_STRIDE(i, m) p[i] = (uint32_t)i;
+}
+
+// Fills levels 0..min(top, log2 maxl) of a sparse table (the only ones a
+// run touches).
+__global__ void k_fill_levels(uint32_t *p, uint64_t n, const uint32_t *maxl, int top, uint32_t v) {
+  const uint32_t ml = *maxl;
+  const int lv = ml ? 32 - __clz((int)ml) : 1;
+  const uint64_t lim = (uint64_t)min(lv, top + 1) * n;
+  GRID_STRIDE(i, lim) p[i] = v;
+}
+
+void sel_table_init(uint32_t *T, uint64_t n, const uint32_t *maxl, int top, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_levels, grid_for((uint64_t)(top + 1) * n, 256, 8192), dim3(256), 0, s, T, n, maxl, top,
+                     kInf);
 }
 
 void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s) {

@@ -101,7 +101,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_rows = L.take(N_ * 12), o_occ = L.take(N_ * 12), o_rf = L.take(N_ * 4), o_ri = L.take(N_ * 4);
   size_t o_cnt = L.take(CNT_COUNT * 4);
   size_t o_rh = L.take(4 * 64 * 4);
-  size_t o_sc = L.take(2 * (kSelRoundCap + 2) * 4);
+  size_t o_sc = L.take(3 * (kSelRoundCap + 2) * 4);
   hipError_t e = hipMalloc(&mem, L.total);
   if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
   bytes = L.total;
@@ -396,22 +396,22 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   if (m_bound > 0) {
     const int top = 63 - __builtin_clzll(maxl_bound);
     uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
-    uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2);
+    uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2), *nwork = w.selcnt + 2 * (kSelRoundCap + 2);
     sel_table_init(Ta, N, dc + CNT_MAXL, top, s);
-    fill_u32(w.selcnt, 2 * (kSelRoundCap + 2), 0, s);
+    fill_u32(w.selcnt, 3 * (kSelRoundCap + 2), 0, s);
     const uint64_t npad = pow2_at_least(N);
     fill_u32(w.ctree, 2 * npad, 0xFFFFFFFFu, s);
     fill_u8(w.mark, N, 0, s);
     copy_u32(nlive, dc + CNT_M, s);
-    sel_init(w.live[0], nlive, w.state, m_bound, s);
+    sel_init(w.live[1], nlive, w.state, m_bound, s);
     const int ahead = host ? 2 : kSelFreeRounds;
     int q0 = 0;
     uint64_t hint = m_bound;
     while (sel_done < 0 && q0 < kSelRoundCap) {
       const int hi = std::min(q0 + ahead, kSelRoundCap);
       for (int q = q0; q < hi; q++)
-        sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[q & 1],
-                  w.live[(q + 1) & 1], nlive, undec, q, hint, dc + CNT_MAXL, w.ctree, npad, w.mark, s);
+        sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[0],
+                  w.live[1], nlive, nwork, undec, q, hint, dc + CNT_MAXL, w.ctree, npad, w.mark, s);
       q0 = hi;
       sel_launched = hi;
       if (!host) break;  // checked after the output stage

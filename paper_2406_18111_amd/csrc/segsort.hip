@@ -118,8 +118,7 @@ __global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n) {
 // Opens round r (records round r-1's outcome, resets the list counters) and
 // gathers the sort key of every still-grouped slot: the rank of the suffix
 // 2^(r-1) positions later (0 past the window end).  A dense pass over the
-// slots (the grouped-slot flags are sequential) instead of an active list;
-// blocks are renumbered so each XCD sweeps one contiguous share of the slots.
+// slots (the grouped-slot flags are sequential) instead of an active list.
 __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uint8_t *aflag,
                             const uint32_t *slot_wend, uint32_t n, uint32_t h, uint32_t *hist, int r) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -135,9 +134,7 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
     c->act_cnt[nxt] = 0;
     c->lds_elems = 0;
   }
-  const uint32_t g = gridDim.x, b = blockIdx.x;
-  const uint64_t lb = (g & 7u) ? b : (uint64_t)(b & 7u) * (g >> 3) + (b >> 3);
-  for (uint64_t p = lb * blockDim.x + threadIdx.x; p < n; p += (uint64_t)g * blockDim.x) {
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
     if (!aflag[p]) continue;
     const uint32_t x = B.val[0][p] + h;
     const uint32_t we = slot_wend ? slot_wend[p] : n;

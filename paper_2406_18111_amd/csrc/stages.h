@@ -46,15 +46,16 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *
 
 // Empties the levels of a selection sparse table that a run can use.
 void sel_table_init(uint32_t *T, uint64_t n, const uint32_t *maxl, int top, hipStream_t s);
-void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s);
-// One selection round: dense (sparse table over all positions) while many
-// candidates are undecided, sparse (canonical blocks of the undecided ones,
-// accepted ones painted into mark) afterwards; chosen on the device.  ctree
-// holds 2 * npad words, all 0xFFFFFFFF between rounds; mark must be clear
-// before round 0.
+void sel_init(uint32_t *work, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s);
+// One selection round: filter by painted positions (r >= 1), then dense
+// (sparse table over all positions) or sparse (canonical blocks of the
+// working list) evaluation, chosen on the device.  Round 0 works on `work`
+// filled by sel_init; undecided candidates go to `pend`, which the next
+// round filters back into `work`.  ctree holds 2 * npad words, all
+// 0xFFFFFFFF between rounds; mark must be clear before round 0.
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
-               uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
-               uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
+               uint8_t *state, uint32_t *pend, uint32_t *work, uint32_t *nlive, uint32_t *nwork, uint32_t *undec,
+               int r, uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
                hipStream_t s);
 void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
                     uint8_t *mark, uint64_t n, hipStream_t s);

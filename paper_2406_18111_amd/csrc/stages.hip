@@ -8,27 +8,15 @@
 
 namespace apo {
 
-// Grids are multiples of 8 blocks (caps are multiples of 8 too).
 static inline dim3 grid_for(uint64_t n, int threads, int cap_blocks) {
   uint64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
-  b = (b + 7) & ~7ull;
   if (b > (uint64_t)cap_blocks) b = cap_blocks;
   return dim3((unsigned)b);
 }
 
-// Workgroups of one launch go to the 8 XCDs in turn (block b to XCD b % 8),
-// and each XCD has its own L2.  Renumbering the blocks so that every XCD
-// works on one contiguous eighth of the index range keeps a window's random
-// accesses (its ranks, tokens, LCPs) inside one L2.
-__device__ __forceinline__ uint64_t xcd_block() {
-  const uint32_t b = blockIdx.x, g = gridDim.x;
-  if (g & 7u) return b;
-  return (uint64_t)(b & 7u) * (g >> 3) + (b >> 3);
-}
-
 #define GRID_STRIDE(i, n) \
-  for (uint64_t i = xcd_block() * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (uint64_t)gridDim.x * blockDim.x)
 
 // ------------------------------------------------------------------ fills
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) { GRID_STRIDE(i, n) p[i] = v; }
@@ -463,7 +451,7 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
   __shared__ uint32_t st[kWinLevels][kWin];
   if (threadIdx.x == 0) bmax = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i0 = xcd_block() * blockDim.x; i0 < n; i0 += stride) {
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
     // LDS window lcp[wlo, wlo + wn) with a sparse table of minima over it
     const uint64_t wlo = i0 >= kWinBack ? i0 - kWinBack : 0;
@@ -561,52 +549,113 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *
 }
 
 // ------------------------------------------------------------- selection
-// Round-based exact evaluation of the greedy: a candidate is accepted once no
-// live (undecided or accepted) candidate of higher priority covers its first
-// or last position, and rejected once an accepted one does.  Coverage minima
-// come from a sparse table: every live interval writes its priority into the
-// two power-of-two blocks that tile it, then minima are pushed down level by
-// level to single positions (levels above kSelSmall one pass each, the rest
-// inside one tiled LDS kernel).  Two tables alternate between rounds; each
-// round clears the other one as it goes.  Round r runs only if round r-1 left
-// undecided candidates, so rounds can be launched ahead of the host.
+// Round-based exact evaluation of the greedy.  Accepted candidates are final
+// and pairwise disjoint; each one paints its interval into `mark` when it is
+// accepted.  Round r >= 1 first rejects every undecided candidate with a
+// painted endpoint (an accepted candidate overlapping it always has higher
+// priority) and keeps the rest as the round's working list.  Then a working
+// candidate is accepted when no working candidate of higher priority covers
+// its first or last position (sufficient because higher priority means not
+// shorter).  Coverage minima of the working list come from one of two
+// structures, chosen on the device from the list's size:
+//  * dense: a sparse table over all positions -- every working interval
+//    writes its priority into the two power-of-two blocks that tile it, then
+//    minima are pushed down level by level (levels above kSelSmall one pass
+//    each, the rest inside one tiled LDS kernel); two tables alternate and
+//    each round clears the other one as it goes;
+//  * sparse (at most n / kSparseDiv working candidates): canonical
+//    power-of-two blocks of each interval (at most two per level, as in a
+//    segment tree); a point's minimum is the minimum over its enclosing
+//    blocks, and the round resets the blocks it wrote.
+// Round r runs only if round r-1 left candidates undecided, so rounds can be
+// launched ahead of the host.
 constexpr int kSelSmall = 8;
 constexpr int kPushTile = 1024;
 constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr uint32_t kSparseDiv = 32;
 
 struct SelArgs {
   const uint32_t *len, *start;
-  uint32_t *Tc, *To;        // this round's table and the other one; level j at + j*n
+  uint32_t *Tc, *To;        // dense: this round's table and the other one; level j at + j*n
   uint64_t n;
   int top;
-  uint8_t *state;
-  const uint32_t *live;
-  uint32_t *live_next;
-  uint32_t *nlive;          // nlive[r]: live count of round r
+  uint8_t *state;           // 0 undecided, 1 accepted, 2 rejected
+  uint32_t *pend;           // undecided candidates entering round r (r >= 1)
+  uint32_t *work;           // round r's working list (round 0: every candidate)
+  uint32_t *nlive;          // nlive[r]: entries of pend at round r (nlive[0]: all candidates)
+  uint32_t *nwork;          // nwork[r]: entries of work at round r (r >= 1)
   uint32_t *undec;          // undec[r]: undecided after round r
   int r;
-  const uint32_t *maxl;     // longest candidate: levels above log2 of it stay empty
-  uint32_t *ctree;          // canonical-block tree for sparse rounds (all kInf between rounds)
+  const uint32_t *maxl;     // longest candidate: table levels above log2 of it stay empty
+  uint32_t *ctree;          // sparse: canonical-block tree (all kInf between rounds)
   uint64_t npad;            // power of two >= n: level j of ctree has npad >> j nodes
-  uint8_t *mark;            // positions covered by accepted candidates (sparse rounds)
+  uint8_t *mark;            // positions covered by accepted candidates
 };
 
-// Dense rounds while many candidates are undecided; once at most
-// n / kSparseDiv remain, rounds work on the undecided candidates alone.
-constexpr uint32_t kSparseDiv = 32;
-
 __device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.undec[a.r - 1] > 0; }
-__device__ __forceinline__ bool sel_dense_at(const SelArgs &a, int r) {
-  return r == 0 || (uint64_t)a.undec[r - 1] * kSparseDiv > a.n;
+__device__ __forceinline__ uint32_t sel_nwork(const SelArgs &a) { return a.r == 0 ? a.nlive[0] : a.nwork[a.r]; }
+__device__ __forceinline__ bool sel_dense(const SelArgs &a) {
+  return a.r == 0 || (uint64_t)a.nwork[a.r] * kSparseDiv > a.n;
 }
-__device__ __forceinline__ bool sel_run_dense(const SelArgs &a) { return sel_active(a) && sel_dense_at(a, a.r); }
-__device__ __forceinline__ bool sel_run_sparse(const SelArgs &a) { return sel_active(a) && !sel_dense_at(a, a.r); }
+__device__ __forceinline__ bool sel_run_dense(const SelArgs &a) { return sel_active(a) && sel_dense(a); }
+__device__ __forceinline__ bool sel_run_sparse(const SelArgs &a) { return sel_active(a) && !sel_dense(a); }
+
+// Paints [s, s + l) for every lane with `on` set; called by the whole
+// wavefront.  Short intervals are painted by their own lane; long ones (up to
+// half a window on runs) by all 64 lanes together with 16-byte stores.
+constexpr uint32_t kPaintShort = 64;
+
+__device__ __forceinline__ void paint_wave(uint8_t *mark, bool on, uint32_t s, uint32_t l) {
+  const int lane = threadIdx.x & 63;
+  const bool lng = on && l > kPaintShort;
+  if (on && !lng)
+    for (uint32_t x = s; x < s + l; x++) mark[x] = 1;
+  uint64_t lm = __ballot(lng);
+  while (lm) {
+    const int src = __ffsll((unsigned long long)lm) - 1;
+    lm &= lm - 1;
+    const uint32_t S = (uint32_t)__shfl((int)s, src, 64), E = S + (uint32_t)__shfl((int)l, src, 64);
+    const uint32_t A = min((S + 15u) & ~15u, E), B = max(A, E & ~15u);  // [A, B) 16-byte aligned
+    if (S + (uint32_t)lane < A) mark[S + lane] = 1;
+    if (B + (uint32_t)lane < E) mark[B + lane] = 1;
+    uint4 *body = reinterpret_cast<uint4 *>(mark + A);
+    const uint4 ones = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+    for (uint32_t q = lane; q < (B - A) / 16; q += 64) body[q] = ones;
+  }
+}
+
+// Round r >= 1: reject undecided candidates with a painted endpoint; the
+// others form the working list.
+__global__ void k_sel_filter(SelArgs a) {
+  if (!sel_active(a)) return;
+  __shared__ uint32_t sh[4];
+  __shared__ uint32_t base;
+  const uint32_t m = a.nlive[a.r];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
+    const uint64_t q = q0 + threadIdx.x;
+    bool keep = false;
+    uint32_t k = 0;
+    if (q < m) {
+      k = a.pend[q];
+      const uint32_t s = a.start[k], e = s + a.len[k] - 1;
+      if (a.mark[s] || a.mark[e]) a.state[k] = 2;
+      else keep = true;
+    }
+    uint32_t tot;
+    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nwork[a.r], tot) : 0u;
+    __syncthreads();
+    if (keep) a.work[base + off] = k;
+    __syncthreads();
+  }
+}
 
 __global__ void k_sel_insert(SelArgs a) {
   if (!sel_run_dense(a)) return;
-  const uint32_t m = a.nlive[a.r];
+  const uint32_t m = sel_nwork(a);
   GRID_STRIDE(q, m) {
-    const uint32_t k = a.live[q];
+    const uint32_t k = a.work[q];
     const uint32_t l = a.len[k], s = a.start[k];
     const int j = 31 - __clz((int)l);
     uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
@@ -643,7 +692,7 @@ __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
   const uint32_t ml = *a.maxl;
   const int J = min(min(a.top, kSelSmall), ml ? 31 - __clz((int)ml) : 0);  // levels above log2(maxl) are empty
   const uint64_t ntiles = (a.n + kPushTile - 1) / kPushTile;
-  for (uint64_t t = xcd_block(); t < ntiles; t += gridDim.x) {
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t x0 = (int64_t)t * kPushTile;
     const int64_t x1 = min((int64_t)a.n, x0 + kPushTile);
     // level J over [x0 - 2^J + 1, x1)
@@ -675,54 +724,58 @@ __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
   }
 }
 
+__device__ __forceinline__ uint32_t *ctree_level(const SelArgs &a, int j) {
+  return a.ctree + (j == 0 ? 0 : 2 * a.npad - (a.npad >> (j - 1)));
+}
+
+__device__ __forceinline__ uint32_t ctree_point(const SelArgs &a, uint32_t x, int levels) {
+  uint32_t v = kInf;
+  for (int j = 0; j < levels; j++) v = min(v, ctree_level(a, j)[x >> j]);
+  return v;
+}
+
+// Accept the working candidates with no higher-priority working candidate on
+// an endpoint (and paint them); the others stay undecided for round r + 1.
+template <bool DENSE>
 __global__ void k_sel_decide(SelArgs a) {
-  if (!sel_run_dense(a)) return;
+  if (DENSE ? !sel_run_dense(a) : !sel_run_sparse(a)) return;
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t und;
   if (threadIdx.x == 0) und = 0;
   __syncthreads();
-  const uint32_t m = a.nlive[a.r];
-  const uint32_t *T0 = a.Tc;
+  const uint32_t m = sel_nwork(a);
+  const uint32_t ml = *a.maxl;
+  const int levels = ml ? 32 - __clz((int)ml) : 1;  // sparse: blocks of size <= maxl
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
     const uint64_t q = q0 + threadIdx.x;
-    bool keep_live = false;
-    uint32_t k = 0;
+    bool keep = false, acc = false;
+    uint32_t k = 0, l = 0, s = 0;
     if (q < m) {
-      k = a.live[q];
-      uint8_t st = a.state[k];
-      if (st == 0) {
-        const uint32_t l = a.len[k], s = a.start[k];
-        const uint32_t t1 = T0[s], t2 = T0[s + l - 1];
-        if (t1 >= k && t2 >= k) {
-          st = 1;
-        } else if ((t1 < k && a.state[t1] == 1) || (t2 < k && a.state[t2] == 1)) {
-          st = 2;
-        }
-        if (st != 0) a.state[k] = st;
-        else atomicAdd(&und, 1u);
+      k = a.work[q];
+      l = a.len[k];
+      s = a.start[k];
+      const uint32_t e = s + l - 1;
+      const uint32_t t1 = DENSE ? a.Tc[s] : ctree_point(a, s, levels);
+      const uint32_t t2 = DENSE ? a.Tc[e] : ctree_point(a, e, levels);
+      if (t1 >= k && t2 >= k) {
+        a.state[k] = 1;
+        acc = true;
+      } else {
+        keep = true;
+        atomicAdd(&und, 1u);
       }
-      keep_live = st != 2;
     }
+    paint_wave(a.mark, acc, s, l);
     uint32_t tot;
-    const uint32_t off = block_excl_sum<256>(keep_live ? 1u : 0u, sh, &tot);
+    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
     __syncthreads();
-    if (keep_live) a.live_next[base + off] = k;
+    if (keep) a.pend[base + off] = k;
     __syncthreads();
   }
   if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
-}
-
-// ---- sparse rounds
-// Accepted candidates are final and pairwise disjoint, so they are painted
-// into `mark`; the undecided ones write their priority into the canonical
-// power-of-two blocks of their interval (at most two per level, like a
-// segment tree), and a point's minimum is the minimum over its enclosing
-// blocks.  A round touches only the undecided candidates' blocks.
-__device__ __forceinline__ uint32_t *ctree_level(const SelArgs &a, int j) {
-  return a.ctree + (j == 0 ? 0 : 2 * a.npad - (a.npad >> (j - 1)));
 }
 
 template <bool CLEAR>
@@ -745,77 +798,14 @@ __device__ __forceinline__ void ctree_cover(const SelArgs &a, uint32_t s, uint32
   }
 }
 
-__device__ __forceinline__ uint32_t ctree_point(const SelArgs &a, uint32_t x, int levels) {
-  uint32_t v = kInf;
-  for (int j = 0; j < levels; j++) v = min(v, ctree_level(a, j)[x >> j]);
-  return v;
-}
-
-__device__ __forceinline__ void paint(uint8_t *mark, uint32_t s, uint32_t l) {
-  for (uint32_t x = s; x < s + l; x++) mark[x] = 1;
-}
-
-// First sparse round: paint the candidates accepted by the dense rounds.
-__global__ void k_sel_sparse_paint(SelArgs a) {
-  if (!sel_run_sparse(a) || !sel_dense_at(a, a.r - 1)) return;
-  const uint32_t m = a.nlive[a.r];
-  GRID_STRIDE(q, m) {
-    const uint32_t k = a.live[q];
-    if (a.state[k] == 1) paint(a.mark, a.start[k], a.len[k]);
-  }
-}
-
 template <bool CLEAR>
 __global__ void k_sel_sparse_cover(SelArgs a) {
   if (!sel_run_sparse(a)) return;
-  const uint32_t m = a.nlive[a.r];
+  const uint32_t m = sel_nwork(a);
   GRID_STRIDE(q, m) {
-    const uint32_t k = a.live[q];
-    // the clear pass walks every listed candidate: blocks never written are kInf already
-    if (CLEAR || a.state[k] == 0) ctree_cover<CLEAR>(a, a.start[k], a.len[k], k);
+    const uint32_t k = a.work[q];
+    ctree_cover<CLEAR>(a, a.start[k], a.len[k], k);
   }
-}
-
-__global__ void k_sel_sparse_decide(SelArgs a) {
-  if (!sel_run_sparse(a)) return;
-  __shared__ uint32_t sh[4];
-  __shared__ uint32_t base;
-  __shared__ uint32_t und;
-  if (threadIdx.x == 0) und = 0;
-  __syncthreads();
-  const uint32_t m = a.nlive[a.r];
-  const uint32_t ml = *a.maxl;
-  const int levels = ml ? 32 - __clz((int)ml) : 1;  // blocks of size <= maxl
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
-    const uint64_t q = q0 + threadIdx.x;
-    bool keep = false;
-    uint32_t k = 0;
-    if (q < m) {
-      k = a.live[q];
-      if (a.state[k] == 0) {
-        const uint32_t l = a.len[k], s = a.start[k], e = s + l - 1;
-        uint8_t st = 0;
-        // an accepted candidate touching an endpoint has higher priority
-        if (a.mark[s] || a.mark[e]) {
-          st = 2;
-        } else if (ctree_point(a, s, levels) >= k && ctree_point(a, e, levels) >= k) {
-          st = 1;
-          paint(a.mark, s, l);
-        }
-        if (st != 0) a.state[k] = st;
-        else atomicAdd(&und, 1u);
-        keep = st == 0;
-      }
-    }
-    uint32_t tot;
-    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
-    __syncthreads();
-    if (keep) a.live_next[base + off] = k;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
 }
 
 __global__ void k_iota(uint32_t *p, const uint32_t *n) {
@@ -837,29 +827,29 @@ void sel_table_init(uint32_t *T, uint64_t n, const uint32_t *maxl, int top, hipS
                      kInf);
 }
 
-void sel_init(uint32_t *live, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s) {
-  hipLaunchKernelGGL(k_iota, grid_for(bound, 256, 8192), dim3(256), 0, s, live, nlive_dev);
+void sel_init(uint32_t *work, const uint32_t *nlive_dev, uint8_t *state, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, grid_for(bound, 256, 8192), dim3(256), 0, s, work, nlive_dev);
   fill_u8_dev(state, nlive_dev, bound, 0, s);
 }
 
 void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_t *To, int top, uint64_t n,
-               uint8_t *state, const uint32_t *live, uint32_t *live_next, uint32_t *nlive, uint32_t *undec, int r,
-               uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
+               uint8_t *state, uint32_t *pend, uint32_t *work, uint32_t *nlive, uint32_t *nwork, uint32_t *undec,
+               int r, uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
                hipStream_t s) {
-  SelArgs a{len, start, Tc, To, n, top, state, live, live_next, nlive, undec, r, maxl, ctree, npad, mark};
+  SelArgs a{len, start, Tc, To, n, top, state, pend, work, nlive, nwork, undec, r, maxl, ctree, npad, mark};
+  const dim3 g = grid_for(live_hint, 256, 8192);
+  if (r > 0) hipLaunchKernelGGL(k_sel_filter, g, dim3(256), 0, s, a);
   // dense round (each kernel returns at once when the round is sparse or not needed)
-  hipLaunchKernelGGL(k_sel_insert, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_sel_insert, g, dim3(256), 0, s, a);
   for (int j = top; j > kSelSmall; j--)
     hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, a, j);
   const uint64_t ntiles = (n + kPushTile - 1) / kPushTile;
   hipLaunchKernelGGL(k_sel_push_tile, dim3((unsigned)std::min<uint64_t>(ntiles, 4096)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_sel_decide, grid_for(live_hint, 256, 8192), dim3(256), 0, s, a);
-  // sparse round (returns at once unless few candidates are undecided)
+  hipLaunchKernelGGL(k_sel_decide<true>, g, dim3(256), 0, s, a);
+  // sparse round (returns at once unless the working list is short)
   if (r > 0) {
-    const dim3 g = grid_for(live_hint, 256, 4096);
-    hipLaunchKernelGGL(k_sel_sparse_paint, g, dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sel_sparse_cover<false>, g, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_sel_sparse_decide, g, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sel_decide<false>, g, dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sel_sparse_cover<true>, g, dim3(256), 0, s, a);
   }
 }

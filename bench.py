@@ -49,7 +49,21 @@ def parse():
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps of the main workload (for profilers)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 3 times (a plain copy kernel of known size, "
+                         "to scale hardware byte counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": n, "bytes_written": n, "dispatches": 3}), flush=True)
 
 
 def single_workload(name):
@@ -125,14 +139,38 @@ def timed_steps(ctx, step, steps):
     return el, kprof, {k: v / steps for k, v in stage_tot.items()}, out
 
 
-def roofline(kprof, steps):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "findrepeats_batched_lds_family_traffic.md")
+FAMILY_SOURCE = os.path.join(ROOT, "paper_2406_18111_amd", "csrc", "segsort.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the timed kernel family from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when it does not exist,
+    covers another workload, or the kernels' source changed since."""
+    import hashlib
+    try:
+        rec = None
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("TRAFFIC_RECORD "):
+                rec = json.loads(line[len("TRAFFIC_RECORD "):])
+        src = hashlib.sha256(open(FAMILY_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if not rec or rec.get("workload") != workload or rec.get("kernel_source_sha256") != src:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
+def roofline(kprof, steps, workload=None):
     if not kprof["launches"]:
         return None
     avg_ms = kprof["ms"] / kprof["launches"]
     bytes_per_launch = kprof["elems"] * LDS_SA_BYTES_PER_ENTRY / kprof["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(workload) if workload else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "per doubling round, the LDS sort family in SA mode: k_wave_sort<0> (units <= 64) + "
                       "k_lds_group<0> (65..4096) [+ k_lds_sort<0,13> with 8192-entry tiles], one event pair "
                       "around the family",
@@ -239,6 +277,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     ctx = Context(0)
     ctx.set_graphs(not args.no_graphs)
     steps = args.profile_steps or args.steps
@@ -265,7 +306,7 @@ def main():
                                               "alphabet 2^12, 5% substitutions; one packed sync-free launch "
                                               "sequence per step"},
                     "counters": ctx.counters(), "rows": int(res[1][-1])})
-        rf = roofline(kprof, steps)
+        rf = roofline(kprof, steps, "config3")
         if rf:
             out["roofline"] = rf
         if not args.profile_steps and not args.no_graphs:

@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--no-graphs", action="store_true")
+    ap.add_argument("--lanes", type=int, default=3, help="concurrent window groups per batch (1..4)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps of the main workload (for profilers)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -282,6 +283,7 @@ def main():
         return
     ctx = Context(0)
     ctx.set_graphs(not args.no_graphs)
+    ctx.set_lanes(args.lanes)
     steps = args.profile_steps or args.steps
     warm = 1 if args.profile_steps else args.warmup
     out = {"metric": "tokens analyzed/sec (SA+LCP+repeat mining)", "unit": "tokens/s", "n_gpus": 1,
@@ -302,19 +304,34 @@ def main():
         ctx.profile_kernel(0)
         out.update({"value": total / sec, "ms_per_step": sec * 1e3, "dtype": "u64",
                     "config": {"workload": "config3", "windows": len(wins), "tokens": total, "min_len": m,
-                               "description": "4096 windows, lengths log-uniform 256..65536, loop bodies 10..500, "
-                                              "alphabet 2^12, 5% substitutions; one packed sync-free launch "
-                                              "sequence per step"},
+                               "description": ("4096 windows, lengths log-uniform 256..65536, loop bodies 10..500, "
+                                               "alphabet 2^12, 5 percent substitutions; per step the windows are "
+                                               "split into {} groups of about equal tokens, each one packed "
+                                               "sync-free launch sequence on its own stream").format(args.lanes),
+                               "lanes": args.lanes},
                     "counters": ctx.counters(), "rows": int(res[1][-1])})
         rf = roofline(kprof, steps, "config3")
         if rf:
             out["roofline"] = rf
+        if not args.profile_steps and not args.no_extras and args.lanes > 1:
+            # the same kernel family timed with one stream only (no other lane
+            # sharing the GPU while an event pair is open)
+            ctx.set_lanes(1)
+            ctx.profile_kernel(LDS_SA_TAG)
+            ctx.analyze_batch_dev(dev, off, m)
+            _, kp1, _, _ = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), 3)
+            ctx.profile_kernel(0)
+            ctx.set_lanes(args.lanes)
+            out["roofline_one_lane"] = roofline(kp1, 3, "config3")
         if not args.profile_steps and not args.no_graphs:
-            # the same step captured once as a HIP graph and replayed
+            # one stream: the step captured once as a HIP graph and replayed
+            ctx.set_lanes(1)
             ctx.analyze_batch_dev(dev, off, m)
             gsec, _, _, gres = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), steps)
-            out["graph_replay"] = {"tokens_per_s": total / gsec, "ms": gsec * 1e3, "graph": ctx.graph_stats(),
-                                   "same_rows": bool(np.array_equal(gres[1], res[1]) and torch.equal(gres[0], res[0]))}
+            ctx.set_lanes(args.lanes)
+            out["graph_replay_one_lane"] = {
+                "tokens_per_s": total / gsec, "ms": gsec * 1e3, "graph": ctx.graph_stats(),
+                "same_rows": bool(np.array_equal(gres[1], res[1]) and torch.equal(gres[0], res[0]))}
         if not args.profile_steps and not args.no_extras:
             tw, nrows = per_window_leg(ctx, dev, off, m)
             out["per_window"] = {"tokens_per_s": total / tw, "ms": tw * 1e3, "rows": nrows,

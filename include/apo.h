@@ -125,6 +125,13 @@ int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t
                           uint32_t num_windows, uint32_t min_len, apo_candidate *d_out,
                           uint64_t out_cap, uint64_t *h_out_offsets, void *hip_stream);
 
+/* Batches are split into `lanes` (1..4, default 3) groups of consecutive
+ * windows with about equal token counts, analysed concurrently on separate
+ * streams and workspaces (lane 0 uses the caller's stream); results are
+ * identical for every value.  With more than one lane, batch calls do not
+ * use graph capture.  APO_EINVAL outside 1..4. */
+int apo_set_lanes(apo_ctx *ctx, int lanes);
+
 /* Batched analyses enqueue their whole launch sequence without host
  * synchronisation (round counts bounded by the longest window) and, when
  * enabled (default), record it as a HIP graph that is replayed for later

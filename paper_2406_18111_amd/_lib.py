@@ -47,6 +47,7 @@ SIGNATURES = {
     "apo_analyze_batch": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P]),
     "apo_analyze_batch_dev": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P, _P]),
     "apo_set_graphs": (_I, [_P, _I]),
+    "apo_set_lanes": (_I, [_P, _I]),
     "apo_graph_stats": (_I, [_P, _P, _P]),
     "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
@@ -234,6 +235,10 @@ class Context:
                                              _dev_ptr(rows), cap, _np_ptr(oo), _stream_ptr(stream))
         _check(rc, "apo_analyze_batch_dev")
         return rows[: int(oo[-1])], oo
+
+    def set_lanes(self, lanes: int):
+        """Concurrent window groups per batch (1..4)."""
+        _check(self._lib.apo_set_lanes(self._h, int(lanes)), "apo_set_lanes")
 
     def set_graphs(self, on: bool):
         _check(self._lib.apo_set_graphs(self._h, int(bool(on))), "apo_set_graphs")

@@ -113,6 +113,18 @@ struct apo_ctx {
   bool graphs = true;         // capture/replay batched launch sequences
   uint64_t graph_replays = 0, graph_captures = 0;
   std::unique_ptr<apo::Server> server;
+  // Batches are split into `lanes` groups of windows, each analysed on its
+  // own stream and workspace concurrently (lane 0: ws and the caller's stream).
+  int lanes = 3;
+  std::vector<std::unique_ptr<apo::Workspace>> lane_ws;
+  std::vector<hipStream_t> lane_stream;
+  hipEvent_t lane_ready = nullptr;
+  // where the last batch's rows are: workspace, windows, rows (in window order)
+  struct LaneOut {
+    apo::Workspace *ws;
+    uint32_t W, rows;
+  };
+  std::vector<LaneOut> louts;
 };
 
 using namespace apo;
@@ -160,6 +172,12 @@ extern "C" int apo_destroy(apo_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   ctx->gc.reset();
   ctx->ws.release();
+  for (auto &l : ctx->lane_ws) l->release();
+  for (auto st : ctx->lane_stream) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  if (ctx->lane_ready) (void)hipEventDestroy(ctx->lane_ready);
   (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return APO_OK;
@@ -265,11 +283,127 @@ static int check_offsets(const uint64_t *off, uint32_t W, uint64_t &total) {
   return APO_OK;
 }
 
-// One batched analysis of device tokens.  The launch sequence is sync-free;
+// Sums what the per-lane runs counted (maxima for round counts).
+static void merge_info(RunInfo &a, const RunInfo &b) {
+  a.n += b.n;
+  a.rounds = std::max(a.rounds, b.rounds);
+  a.active_sum += b.active_sum;
+  a.sigma += b.sigma;
+  a.cands += b.cands;
+  a.cands_dedup += b.cands_dedup;
+  a.maxl = std::max(a.maxl, b.maxl);
+  a.sel_rounds = std::max(a.sel_rounds, b.sel_rounds);
+  a.sel_sequential |= b.sel_sequential;
+  a.accepted += b.accepted;
+  a.rows += b.rows;
+  for (int k = 0; k < kStages; k++) a.stage_ms[k] = std::max(a.stage_ms[k], b.stage_ms[k]);
+  a.k_launches += b.k_launches;
+  a.k_elems += b.k_elems;
+  a.k_ms += b.k_ms;
+}
+
+// Batch split into L groups of consecutive windows with about equal tokens,
+// each enqueued sync-free on its own stream and workspace; the streams run
+// concurrently, so one lane's latency-bound kernels overlap the others'.
+// Results stay per lane (ctx->louts), in window order.
+static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
+                       hipStream_t s, uint64_t total, int L) {
+  while ((int)ctx->lane_ws.size() < L - 1) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return APO_EDEVICE;
+    ctx->lane_stream.push_back(st);
+    ctx->lane_ws.emplace_back(new Workspace());
+  }
+  if (!ctx->lane_ready && hipEventCreateWithFlags(&ctx->lane_ready, hipEventDisableTiming) != hipSuccess)
+    return APO_EDEVICE;
+  // group g holds windows w0[g] .. w0[g+1]
+  std::vector<uint32_t> w0(L + 1, W);
+  w0[0] = 0;
+  for (int g = 1; g < L; g++) {
+    const uint64_t target = off[0] + total * (uint64_t)g / (uint64_t)L;
+    const uint32_t w = (uint32_t)(std::lower_bound(off, off + W + 1, target) - off);
+    w0[g] = std::max(std::min(w, W), w0[g - 1]);
+  }
+  // the tokens were written on the caller's stream
+  if (hipEventRecord(ctx->lane_ready, s) != hipSuccess) return APO_EDEVICE;
+  struct Lane {
+    Workspace *ws;
+    hipStream_t st;
+    std::vector<uint64_t> norm;  // window offsets relative to the lane's first token
+    uint64_t tok0, total;        // first token (relative to off[0]) and token count
+    uint32_t W;
+    RunInfo info;
+  };
+  std::vector<Lane> lanes;
+  for (int g = 0; g < L; g++) {
+    if (w0[g + 1] == w0[g]) continue;
+    Lane ln;
+    ln.ws = g == 0 ? &ctx->ws : ctx->lane_ws[g - 1].get();
+    ln.st = g == 0 ? s : ctx->lane_stream[g - 1];
+    ln.W = w0[g + 1] - w0[g];
+    ln.tok0 = off[w0[g]] - off[0];
+    ln.total = off[w0[g + 1]] - off[w0[g]];
+    ln.norm.resize(ln.W + 1);
+    for (uint32_t w = 0; w <= ln.W; w++) ln.norm[w] = off[w0[g] + w] - off[w0[g]];
+    const int rc = ln.ws->ensure(std::max<uint64_t>(ln.total, 2), ln.W, ctx->budget);
+    if (rc) return map_rc(rc);
+    int tl, db;
+    ctx->tune.pick(ln.total, tl, db);
+    ln.ws->eng.set_params(tl, db);
+    ln.ws->ktag = ctx->ws.ktag;
+    if (ln.st != s && hipStreamWaitEvent(ln.st, ctx->lane_ready, 0) != hipSuccess) return APO_EDEVICE;
+    lanes.push_back(std::move(ln));
+  }
+  // enqueue every lane before waiting for any, from one host thread per lane
+  // so that no lane's launches wait behind another lane's enqueueing
+  std::vector<int> erc(lanes.size(), 0);
+  {
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < lanes.size(); i++)
+      th.emplace_back([&, i] {
+        Lane &ln = lanes[i];
+        if (hipSetDevice(ctx->device) != hipSuccess) { erc[i] = -4; return; }
+        erc[i] = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL,
+                              ln.st, ln.info, Mode::ENQUEUE);
+      });
+    Lane &l0 = lanes[0];
+    erc[0] = run_pipeline(*l0.ws, d_tok + l0.tok0, 64, l0.total, l0.norm.data(), l0.W, min_len, Stop::FULL, l0.st,
+                          l0.info, Mode::ENQUEUE);
+    for (auto &t : th) t.join();
+  }
+  for (int rc : erc)
+    if (rc) return map_rc(rc);
+  ctx->info = RunInfo{};
+  ctx->louts.clear();
+  for (Lane &ln : lanes) {
+    int rc = finish_run(*ln.ws, ln.total, 2 * ln.total, kSelFreeRounds, ln.info, ln.st, true);
+    if (rc == 1)
+      rc = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL, ln.st,
+                        ln.info, Mode::HOST);
+    if (rc) return map_rc(rc);
+    merge_info(ctx->info, ln.info);
+    ctx->louts.push_back({ln.ws, ln.W, ln.info.rows});
+  }
+  return APO_OK;
+}
+
+// One batched analysis of device tokens.  The launch sequence is sync-free;// One batched analysis of device tokens.  The launch sequence is sync-free;
 // with graphs enabled it is captured once per shape and replayed.  If the
 // enqueued selection rounds did not decide every candidate (adversarial
 // inputs), the batch is rerun host-driven.
+static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
+                        hipStream_t s, uint64_t total);
+
 static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
+                        hipStream_t s, uint64_t total) {
+  const int L = std::min<int>(ctx->lanes, (int)(W / 2));
+  if (L >= 2) return batch_lanes(ctx, d_tok, off, W, min_len, s, total, L);
+  const int rc = batch_single(ctx, d_tok, off, W, min_len, s, total);
+  ctx->louts.assign(1, {&ctx->ws, W, ctx->info.rows});
+  return rc;
+}
+
+static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
                         hipStream_t s, uint64_t total) {
   std::vector<uint64_t> norm(W + 1);
   uint64_t maxwin = 0;
@@ -341,16 +475,36 @@ static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
 }
 
 static int batch_offsets(apo_ctx *ctx, uint32_t W, uint64_t *out_offsets, uint64_t out_cap) {
-  std::vector<uint32_t> cnt(W, 0);
-  const uint32_t rows = ctx->info.rows;
-  if (W > 1 && rows) {
-    if (hipMemcpy(cnt.data(), ctx->ws.win_rows, W * 4, hipMemcpyDeviceToHost) != hipSuccess) return APO_EDEVICE;
-  } else if (W == 1) {
-    cnt[0] = rows;
+  std::vector<uint32_t> cnt;
+  cnt.reserve(W);
+  for (const auto &lo : ctx->louts) {
+    std::vector<uint32_t> c(lo.W, 0);
+    if (lo.W > 1 && lo.rows) {
+      if (hipMemcpy(c.data(), lo.ws->win_rows, lo.W * 4, hipMemcpyDeviceToHost) != hipSuccess) return APO_EDEVICE;
+    } else if (lo.W == 1) {
+      c[0] = lo.rows;
+    }
+    cnt.insert(cnt.end(), c.begin(), c.end());
   }
+  if (cnt.size() != W) return APO_EDEVICE;
   out_offsets[0] = 0;
   for (uint32_t w = 0; w < W; w++) out_offsets[w + 1] = out_offsets[w] + cnt[w];
-  return rows > out_cap ? APO_ERANGE : APO_OK;
+  return ctx->info.rows > out_cap ? APO_ERANGE : APO_OK;
+}
+
+// Copies the rows of every lane, in window order, to `out` (device or host).
+static int batch_rows(apo_ctx *ctx, apo_candidate *out, bool to_host, hipStream_t s) {
+  uint64_t at = 0;
+  for (const auto &lo : ctx->louts) {
+    if (lo.rows) {
+      const size_t bytes = (size_t)lo.rows * sizeof(apo_candidate);
+      const hipError_t e = to_host ? hipMemcpy(out + at, lo.ws->rows, bytes, hipMemcpyDeviceToHost)
+                                   : hipMemcpyAsync(out + at, lo.ws->rows, bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return APO_EDEVICE;
+    }
+    at += lo.rows;
+  }
+  return APO_OK;
 }
 
 extern "C" int apo_analyze_batch(apo_ctx *ctx, const uint64_t *tokens, const uint64_t *offsets, uint32_t W,
@@ -375,11 +529,7 @@ extern "C" int apo_analyze_batch(apo_ctx *ctx, const uint64_t *tokens, const uin
   if (rc) return rc;
   rc = batch_offsets(ctx, W, out_offsets, out_cap);
   if (rc) return rc;
-  if (ctx->info.rows &&
-      hipMemcpy(out, ctx->ws.rows, (size_t)ctx->info.rows * sizeof(apo_candidate), hipMemcpyDeviceToHost) !=
-          hipSuccess)
-    return APO_EDEVICE;
-  return APO_OK;
+  return batch_rows(ctx, out, true, ctx->stream);
 }
 
 extern "C" int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t *h_offsets, uint32_t W,
@@ -401,9 +551,8 @@ extern "C" int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, con
   if (rc) return rc;
   rc = batch_offsets(ctx, W, h_out_offsets, out_cap);
   if (rc) return rc;
-  if (ctx->info.rows &&
-      hipMemcpyAsync(d_out, ctx->ws.rows, (size_t)ctx->info.rows * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return APO_EDEVICE;
+  rc = batch_rows(ctx, d_out, false, s);
+  if (rc) return rc;
   return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
 }
 
@@ -486,6 +635,12 @@ extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   const int k = std::min(nvals, 8);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
+}
+
+extern "C" int apo_set_lanes(apo_ctx *ctx, int lanes) {
+  if (!ctx || lanes < 1 || lanes > 4) return APO_EINVAL;
+  ctx->lanes = lanes;
+  return APO_OK;
 }
 
 extern "C" int apo_set_graphs(apo_ctx *ctx, int on) {

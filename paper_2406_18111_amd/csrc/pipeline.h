@@ -13,8 +13,9 @@ enum class Stop { SA, LCP, CANDS, FULL };
 // loops early.  FREE: everything is enqueued with host upper bounds (rounds
 // for the longest window, counts from capacities) and one sync at the end.
 // CAPTURE: FREE without timing events and without the final sync, for
-// recording into a HIP graph.
-enum class Mode { HOST, FREE, CAPTURE };
+// recording into a HIP graph.  ENQUEUE: FREE without the final sync (the
+// caller runs finish_run later, so several streams can be filled first).
+enum class Mode { HOST, FREE, CAPTURE, ENQUEUE };
 constexpr int kSelFreeRounds = 12;
 
 enum Cnt {

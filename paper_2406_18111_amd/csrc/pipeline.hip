@@ -432,7 +432,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   int orc = emit_output(w, N, W, batch, wid, wbeg, m_bound, host, s);
   if (orc) return orc;
   stamp(w, 7, s, stamps);
-  if (mode == Mode::CAPTURE) return 0;
+  if (mode == Mode::CAPTURE || mode == Mode::ENQUEUE) return 0;
   rc = finish_run(w, N, m_bound, host ? -1 : sel_launched, info, s, stamps);
   if (host && sel_done < 0 && m_bound > 0) {
     info.sel_rounds = kSelRoundCap;

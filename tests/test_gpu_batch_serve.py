@@ -176,6 +176,7 @@ def test_graph_capture_and_replay(ctx):
     wins_a, wins_b = _same_shape_batches(21)
     with Context(0) as g:
         g.set_graphs(True)
+        g.set_lanes(1)  # graphs record single-stream batches
         toks_a, off_a = _pack(wins_a)
         dev = torch.from_numpy(toks_a.view(np.int64)).cuda()
         for rep in range(3):
@@ -195,6 +196,29 @@ def test_graph_capture_and_replay(ctx):
         for w, win in enumerate(wins_b):
             assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), w
         assert g.graph_stats()["replays"] == 3
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 3, 4])
+def test_lanes_give_identical_results(lanes):
+    """Concurrent window groups on separate streams: every lane count gives
+    the rows of the single-stream batch and of the oracle."""
+    import torch
+    from paper_2406_18111_amd import Context
+    wins = _mixed_windows(17, 23) + [np.zeros(0, np.uint64)] * 3
+    toks, off = _pack(wins)
+    dev = torch.from_numpy(toks.view(np.int64)).cuda()
+    with Context(0) as g:
+        g.set_lanes(lanes)
+        for m in (2, 8):
+            rows, oo = g.analyze_batch_dev(dev, off, m)
+            rows = rows.cpu().numpy().astype(np.int64)
+            hrows, hoo = g.analyze_batch(toks, off, m)
+            assert np.array_equal(oo, hoo)
+            assert np.array_equal(rows, _as3(hrows))
+            for w, win in enumerate(wins):
+                assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, m)), (lanes, m, w)
+    with pytest.raises(Exception):
+        Context(0).set_lanes(5)
 
 
 def test_sync_free_batch_without_graphs(ctx):

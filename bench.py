@@ -144,7 +144,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "findrepeats_batched_lds_family_tr
 FAMILY_SOURCE = os.path.join(ROOT, "paper_2406_18111_amd", "csrc", "segsort.hip")
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, lanes=1):
     """HBM bytes per launch of the timed kernel family from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when it does not exist,
     covers another workload, or the kernels' source changed since."""
@@ -157,18 +157,19 @@ def measured_traffic(workload):
         src = hashlib.sha256(open(FAMILY_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
-    if not rec or rec.get("workload") != workload or rec.get("kernel_source_sha256") != src:
+    if (not rec or rec.get("workload") != workload or rec.get("lanes", 1) != lanes
+            or rec.get("kernel_source_sha256") != src):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
 
-def roofline(kprof, steps, workload=None):
+def roofline(kprof, steps, workload=None, lanes=1):
     if not kprof["launches"]:
         return None
     avg_ms = kprof["ms"] / kprof["launches"]
     bytes_per_launch = kprof["elems"] * LDS_SA_BYTES_PER_ENTRY / kprof["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(workload) if workload else None
+    traffic = measured_traffic(workload, lanes) if workload else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -310,7 +311,7 @@ def main():
                                                "sync-free launch sequence on its own stream").format(args.lanes),
                                "lanes": args.lanes},
                     "counters": ctx.counters(), "rows": int(res[1][-1])})
-        rf = roofline(kprof, steps, "config3")
+        rf = roofline(kprof, steps, "config3", args.lanes)
         if rf:
             out["roofline"] = rf
         if not args.profile_steps and not args.no_extras and args.lanes > 1:
@@ -322,7 +323,7 @@ def main():
             _, kp1, _, _ = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), 3)
             ctx.profile_kernel(0)
             ctx.set_lanes(args.lanes)
-            out["roofline_one_lane"] = roofline(kp1, 3, "config3")
+            out["roofline_one_lane"] = roofline(kp1, 3, "config3", 1)
         if not args.profile_steps and not args.no_graphs:
             # one stream: the step captured once as a HIP graph and replayed
             ctx.set_lanes(1)

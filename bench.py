@@ -144,6 +144,18 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "findrepeats_batched_lds_family_tr
 FAMILY_SOURCE = os.path.join(ROOT, "paper_2406_18111_amd", "csrc", "segsort.hip")
 
 
+def code_hash(path):
+    """SHA-256 of a source file's code with comments and blank space removed
+    (comment edits do not invalidate stored counter readings)."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+    return hashlib.sha256(text.encode()).hexdigest()
+
+
 def measured_traffic(workload, lanes=1):
     """HBM bytes per launch of the timed kernel family from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when it does not exist,
@@ -154,7 +166,7 @@ def measured_traffic(workload, lanes=1):
         for line in open(TRAFFIC_FILE):
             if line.startswith("TRAFFIC_RECORD "):
                 rec = json.loads(line[len("TRAFFIC_RECORD "):])
-        src = hashlib.sha256(open(FAMILY_SOURCE, "rb").read()).hexdigest()
+        src = code_hash(FAMILY_SOURCE)
     except OSError:
         return None
     if (not rec or rec.get("workload") != workload or rec.get("lanes", 1) != lanes

@@ -67,7 +67,7 @@ struct SortBufs {
   uint32_t digit_bits;  // MSD digit width
   uint32_t *hist;       // big_cap * kBins
   uint32_t *cursor;     // big_cap * kBins
-  uint32_t *act[2];
+  uint32_t *act[2];     // plain mode: slots still grouped after a level (SA rounds use RankOut::aflag)
   SortCounters *ctr;
   uint64_t cap;
 };

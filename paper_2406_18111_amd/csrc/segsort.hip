@@ -947,9 +947,9 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
 
 // --------------------------------------------------- bulk (one-group) units
 // Pieces whose key bits are used up are one group each.  Processed chunk by
-// chunk: SA-mode ranks/snapshots, copy-back from the alternate buffer, the
-// next level's active slots, and (by the unit's first chunk) the unit itself
-// as a large unit of the next level.
+// chunk: SA-mode ranks/snapshots and grouped-slot flags, copy-back from the
+// alternate buffer, the next level's active slots (plain mode), and (by the
+// unit's first chunk) the unit itself as a large unit of the next level.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, uint32_t next_bits,
                                               int last_level, uint8_t *keep) {

@@ -24,6 +24,8 @@ constexpr int kChunk = 8192;                // elements per workgroup in MSD / b
 constexpr int kMaxRounds = 32;              // doubling rounds (n <= 2^26 needs <= 28)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kBufBit = 0x80000000u;   // unit data lives in the alternate buffer
+constexpr uint32_t kHeadBit = 0x40000000u;  // SA rounds: every entry's rank is already unit.start + 1
+constexpr uint32_t kLenMask = 0x3FFFFFFFu;  // unit length without the flags
 
 // Unit descriptor for the LDS sort: a contiguous slot range sorted by key.
 struct Unit {

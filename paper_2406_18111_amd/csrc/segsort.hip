@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
     __syncthreads();
     if (tid == 0) {
       uint32_t tot = 0;
-      for (uint32_t j = 0; j < nb; j++) tot += ud[j].len & ~kBufBit;
+      for (uint32_t j = 0; j < nb; j++) tot += ud[j].len & kLenMask;
       atomicAdd(&B.ctr->lds_elems, tot);
     }
 
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       uint64_t v = ~0ull;
       if (j < nb) {
         const Unit u = ud[j];
-        const uint32_t len = u.len & ~kBufBit;
+        const uint32_t len = u.len & kLenMask;
         if (idx < len) {
           const int b = (u.len & kBufBit) ? 1 : 0;
           const uint32_t p = u.start + idx;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       const uint32_t j = (uint32_t)s >> c, idx = (uint32_t)s & (sub - 1);
       if (j >= nb) continue;
       const Unit u = ud[j];
-      const uint32_t len = u.len & ~kBufBit;
+      const uint32_t len = u.len & kLenMask;
       if (idx >= len) continue;
       const uint32_t hs = hd[s];
       const bool bnd = hs == (uint32_t)s;
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       const uint32_t p = u.start + idx;
       B.val[0][p] = v;
       if (MODE == MODE_SA) {
-        R.rank[v] = gpos + 1;
+        if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[v] = gpos + 1;  // else unchanged
         if (R.snap) R.snap[v] = gpos + 1;
         if (single) R.fin[v] = (uint8_t)R.round;
       }
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
         const uint32_t j = (uint32_t)s >> c, idx = (uint32_t)s & (sub - 1);
         if (j >= nb) continue;
         const Unit u = ud[j];
-        const uint32_t len = u.len & ~kBufBit;
+        const uint32_t len = u.len & kLenMask;
         if (idx >= len) continue;
         const uint32_t hs = hd[s];
         const bool bnd = hs == (uint32_t)s;
@@ -340,7 +340,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
           const int cc = class_of(size);
           const uint32_t k = cls_base[cc] + atomicAdd(&cls_loc[cc], 1u);
           const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
-          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (hs - (j << c)), size};
+          if (k < capc)
+            B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (hs - (j << c)), size | (MODE == MODE_SA ? kHeadBit : 0u)};
           else atomicOr(&B.ctr->err, 8u);
         }
       }
@@ -415,7 +416,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
       const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
       Unit u{0, 0};
       if (j < nb) u = B.cls[cur][B.cls_off[ci] + first + j];
-      const uint32_t len = u.len & ~kBufBit;
+      const uint32_t len = u.len & kLenMask;
       const bool valid = j < nb && idx < len;
       uint64_t v = ~0ull;
       if (valid) {
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
         const uint32_t val = (uint32_t)v;
         B.val[0][p] = val;
         if (MODE == MODE_SA) {
-          R.rank[val] = gpos + 1;
+          if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[val] = gpos + 1;  // else unchanged
           if (R.snap) R.snap[val] = gpos + 1;
           if (single) R.fin[val] = (uint8_t)R.round;
         }
@@ -515,7 +516,8 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
           if (mycc == cc) {
             const uint32_t kk = cbase[cc] + (uint32_t)__popcll(m & lanes_lt);
             const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
-            if (kk < capc) B.cls[nxt][B.cls_off[cc] + kk] = Unit{unit_pos[k], unit_code[k] >> 8};
+            if (kk < capc)
+              B.cls[nxt][B.cls_off[cc] + kk] = Unit{unit_pos[k], (unit_code[k] >> 8) | (MODE == MODE_SA ? kHeadBit : 0u)};
             else atomicOr(&B.ctr->err, 8u);
           }
           cbase[cc] += (uint32_t)__popcll(m);
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
       uint32_t len = 0;
       if (tid < (int)nb) {
         ud[tid] = src[tid];
-        len = src[tid].len & ~kBufBit;
+        len = src[tid].len & kLenMask;
       }
       uint32_t tot;
       const uint32_t ex = block_excl_sum<NT>(len, sh, &tot);
@@ -711,7 +713,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         const uint32_t v = V[p];
         B.val[0][slot] = v;
         if (MODE == MODE_SA) {
-          R.rank[v] = head + 1;
+          if (!((u.len & kHeadBit) && head == u.start)) R.rank[v] = head + 1;  // else unchanged
           if (R.snap) R.snap[v] = head + 1;
           if (gcnt == 1) R.fin[v] = (uint8_t)R.round;
           if (R.aflag) R.aflag[slot] = gcnt >= 2 ? 1 : 0;
@@ -753,7 +755,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
           const int cc = class_of(gcnt);
           const uint32_t k = cls_base[cc] + atomicAdd(&cls_loc[cc], 1u);
           const uint32_t capc = B.cls_off[cc + 1] - B.cls_off[cc];
-          if (k < capc) B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (gbase - uoff[j]), gcnt};
+          if (k < capc)
+            B.cls[nxt][B.cls_off[cc] + k] = Unit{u.start + (gbase - uoff[j]), gcnt | (MODE == MODE_SA ? kHeadBit : 0u)};
           else atomicOr(&B.ctr->err, 8u);
         }
       }

@@ -215,6 +215,13 @@ int apo_last_kernel_profile(apo_ctx *ctx, uint64_t *launches, double *total_ms, 
 int apo_tune(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t min_len, int reps,
              int *best_tile_log, int *best_digit_bits, double *best_ms);
 
+/* Tunes on a whole batch of device windows (offsets as in
+ * apo_analyze_batch_dev), timing each pair as the batch call runs it
+ * (lanes included), and keeps the fastest for the size of one lane's share.
+ * Same outputs as apo_tune.  APO_EINVAL for fewer than 2 tokens. */
+int apo_tune_batch(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t *h_offsets, uint32_t num_windows,
+                   uint32_t min_len, int reps, int *best_tile_log, int *best_digit_bits, double *best_ms);
+
 /* Fix the pair for all sizes (tile_log 11..13, digit_bits 8..12); negative
  * values return to the tuned table. */
 int apo_set_params(apo_ctx *ctx, int tile_log, int digit_bits);

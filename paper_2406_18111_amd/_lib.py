@@ -60,6 +60,7 @@ SIGNATURES = {
     "apo_last_kernel_profile": (_I, [_P, _P, _P, _P]),
     "apo_tune": (_I, [_P, _P, _I, _U32, _U32, _I, _P, _P, _P]),
     "apo_set_params": (_I, [_P, _I, _I]),
+    "apo_tune_batch": (_I, [_P, _P, _P, _U32, _U32, _I, _P, _P, _P]),
     "apo_tune_save": (_I, [_P, ctypes.c_char_p]),
     "apo_tune_load": (_I, [_P, ctypes.c_char_p]),
     "apo_server_start": (_I, [_P, _U32, _U32]),
@@ -337,6 +338,15 @@ class Context:
         t, d, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
         _check(self._lib.apo_tune(self._h, _dev_ptr(tokens), bits, tokens.numel(), int(min_len), int(reps),
                                   ctypes.byref(t), ctypes.byref(d), ctypes.byref(ms)), "apo_tune")
+        return t.value, d.value, ms.value
+
+    def tune_batch(self, tokens, offsets, min_len: int, reps: int = 1):
+        """Autotune on a batch of device windows; returns (tile_log, digit_bits, ms)."""
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        t, d, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0)
+        _check(self._lib.apo_tune_batch(self._h, _dev_ptr(tokens), _np_ptr(off), len(off) - 1, int(min_len),
+                                        int(reps), ctypes.byref(t), ctypes.byref(d), ctypes.byref(ms)),
+               "apo_tune_batch")
         return t.value, d.value, ms.value
 
     def set_params(self, tile_log: int, digit_bits: int):

@@ -694,6 +694,53 @@ extern "C" int apo_last_rounds(apo_ctx *ctx, uint32_t *sa_active, uint32_t *n_sa
 // ================================================================== autotuner
 // Times every (LDS tile, digit width) pair on the caller's window and keeps the
 // fastest for the window's size bucket.  Results never depend on the choice.
+// Batch tuning: times every pair on the caller's whole batch (as
+// apo_analyze_batch_dev runs it, lanes included) and keeps the fastest for the
+// size bucket of one lane's share.  Results never depend on the choice.
+static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
+                        hipStream_t s, uint64_t total);
+
+extern "C" int apo_tune_batch(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t *h_offsets, uint32_t W,
+                              uint32_t min_len, int reps, int *best_tile_log, int *best_digit_bits, double *best_ms) {
+  if (!ctx || !d_tokens || min_len == 0) return APO_EINVAL;
+  uint64_t total = 0;
+  int rc = check_offsets(h_offsets, W, total);
+  if (rc) return rc;
+  if (total < 2) return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  reps = std::max(1, std::min(reps, 50));
+  const int keep_t = ctx->tune.fixed_tile, keep_d = ctx->tune.fixed_digit;
+  double best = 1e30;
+  int bt = kDefaultTileLog, bd = kDefaultDigitBits;
+  for (int tl = kMinTileLog; tl <= kMaxTileLog && rc == APO_OK; tl++) {
+    for (int db : {8, 10, 11, 12}) {
+      ctx->tune.fixed_tile = tl;
+      ctx->tune.fixed_digit = db;
+      std::vector<double> t;
+      for (int k = 0; k <= reps; k++) {
+        const auto t0 = std::chrono::steady_clock::now();
+        rc = batch_common(ctx, d_tokens + h_offsets[0], h_offsets, W, min_len, ctx->stream, total);
+        if (rc) break;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (k > 0) t.push_back(ms);
+      }
+      if (rc) break;
+      std::sort(t.begin(), t.end());
+      const double med = t[t.size() / 2];
+      if (med < best) { best = med; bt = tl; bd = db; }
+    }
+  }
+  ctx->tune.fixed_tile = keep_t;
+  ctx->tune.fixed_digit = keep_d;
+  if (rc) return rc;
+  const int L = std::max(1, std::min<int>(ctx->lanes, (int)(W / 2)));
+  ctx->tune.best[ceil_log2_u64(std::max<uint64_t>(total / L, 2))] = {bt, bd};
+  if (best_tile_log) *best_tile_log = bt;
+  if (best_digit_bits) *best_digit_bits = bd;
+  if (best_ms) *best_ms = best;
+  return APO_OK;
+}
+
 extern "C" int apo_tune(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n, uint32_t min_len, int reps,
                         int *best_tile_log, int *best_digit_bits, double *best_ms) {
   if (!ctx || !d_tokens || n < 2 || n > APO_MAX_N || min_len == 0 || (token_bits != 32 && token_bits != 64))

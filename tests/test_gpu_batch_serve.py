@@ -221,6 +221,23 @@ def test_lanes_give_identical_results(lanes):
         Context(0).set_lanes(5)
 
 
+def test_batch_tuning_keeps_results():
+    """The batch autotuner times all 12 (tile, digit) pairs on the batch; the
+    chosen pair is used afterwards and results stay those of the oracle."""
+    import torch
+    from paper_2406_18111_amd import Context
+    wins, m = synth.config3(num_windows=30)
+    toks, off = _pack(wins)
+    dev = torch.from_numpy(toks.view(np.int64)).cuda()
+    with Context(0) as g:
+        tl, db, ms = g.tune_batch(dev, off, m, reps=1)
+        assert 11 <= tl <= 13 and db in (8, 10, 11, 12) and ms > 0
+        rows, oo = g.analyze_batch_dev(dev, off, m)
+        rows = rows.cpu().numpy().astype(np.int64)
+        for w, win in enumerate(wins):
+            assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, m)), w
+
+
 def test_sync_free_batch_without_graphs(ctx):
     import torch
     from paper_2406_18111_amd import Context

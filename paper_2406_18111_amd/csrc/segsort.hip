@@ -134,6 +134,7 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
     c->act_cnt[nxt] = 0;
     c->lds_elems = 0;
   }
+  if (B.ctr->act_cnt[cur] == 0) return;  // nothing grouped: a round launched past the last one
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
     if (!aflag[p]) continue;
     const uint32_t x = B.val[0][p] + h;

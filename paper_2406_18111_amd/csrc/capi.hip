@@ -303,8 +303,9 @@ static void merge_info(RunInfo &a, const RunInfo &b) {
 }
 
 // Batch split into L groups of consecutive windows with about equal tokens,
-// each enqueued sync-free on its own stream and workspace; the streams run
-// concurrently, so one lane's latency-bound kernels overlap the others'.
+// each run host-driven (exact launch sizes, loops stopped when done) on its
+// own stream, workspace and host thread; the streams run concurrently, so one
+// lane's host syncs and latency-bound kernels overlap the others' work.
 // Results stay per lane (ctx->louts), in window order.
 static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
                        hipStream_t s, uint64_t total, int L) {
@@ -354,8 +355,8 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
     if (ln.st != s && hipStreamWaitEvent(ln.st, ctx->lane_ready, 0) != hipSuccess) return APO_EDEVICE;
     lanes.push_back(std::move(ln));
   }
-  // enqueue every lane before waiting for any, from one host thread per lane
-  // so that no lane's launches wait behind another lane's enqueueing
+  // one host thread per lane, so that no lane's launches wait behind another
+  // lane's syncs
   std::vector<int> erc(lanes.size(), 0);
   {
     std::vector<std::thread> th;
@@ -364,11 +365,11 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
         Lane &ln = lanes[i];
         if (hipSetDevice(ctx->device) != hipSuccess) { erc[i] = -4; return; }
         erc[i] = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL,
-                              ln.st, ln.info, Mode::ENQUEUE);
+                              ln.st, ln.info, Mode::HOST);
       });
     Lane &l0 = lanes[0];
     erc[0] = run_pipeline(*l0.ws, d_tok + l0.tok0, 64, l0.total, l0.norm.data(), l0.W, min_len, Stop::FULL, l0.st,
-                          l0.info, Mode::ENQUEUE);
+                          l0.info, Mode::HOST);
     for (auto &t : th) t.join();
   }
   for (int rc : erc)
@@ -376,18 +377,13 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
   ctx->info = RunInfo{};
   ctx->louts.clear();
   for (Lane &ln : lanes) {
-    int rc = finish_run(*ln.ws, ln.total, 2 * ln.total, kSelFreeRounds, ln.info, ln.st, true);
-    if (rc == 1)
-      rc = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL, ln.st,
-                        ln.info, Mode::HOST);
-    if (rc) return map_rc(rc);
     merge_info(ctx->info, ln.info);
     ctx->louts.push_back({ln.ws, ln.W, ln.info.rows});
   }
   return APO_OK;
 }
 
-// One batched analysis of device tokens.  The launch sequence is sync-free;// One batched analysis of device tokens.  The launch sequence is sync-free;
+// One batched analysis of device tokens.  The launch sequence is sync-free;
 // with graphs enabled it is captured once per shape and replayed.  If the
 // enqueued selection rounds did not decide every candidate (adversarial
 // inputs), the batch is rerun host-driven.

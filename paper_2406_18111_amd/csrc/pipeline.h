@@ -13,9 +13,8 @@ enum class Stop { SA, LCP, CANDS, FULL };
 // loops early.  FREE: everything is enqueued with host upper bounds (rounds
 // for the longest window, counts from capacities) and one sync at the end.
 // CAPTURE: FREE without timing events and without the final sync, for
-// recording into a HIP graph.  ENQUEUE: FREE without the final sync (the
-// caller runs finish_run later, so several streams can be filled first).
-enum class Mode { HOST, FREE, CAPTURE, ENQUEUE };
+// recording into a HIP graph.
+enum class Mode { HOST, FREE, CAPTURE };
 constexpr int kSelFreeRounds = 12;
 
 enum Cnt {
@@ -65,9 +64,9 @@ struct Workspace {
   uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;
   uint32_t *rank = nullptr, *snap = nullptr, *sa = nullptr;
   uint8_t *fin = nullptr;
-  uint32_t *phi = nullptr, *plcp = nullptr, *lcp = nullptr;
+  uint32_t *plcp = nullptr, *lcp = nullptr;
   uint32_t *lvl[8] = {nullptr};
-  uint32_t *c_len = nullptr, *c_start = nullptr, *c_id = nullptr;
+  uint32_t *crec = nullptr;  // candidates: records (length, start, ID), three words each
   uint8_t *keep = nullptr;
   uint32_t *s_len = nullptr, *s_start = nullptr, *s_id = nullptr;
   uint32_t *tmp_a = nullptr, *tmp_b = nullptr, *tmp_c = nullptr, *tmp_d = nullptr, *tile_tmp = nullptr;

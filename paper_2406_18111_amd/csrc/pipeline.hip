@@ -33,7 +33,7 @@ static void plan(uint64_t N, uint32_t W, int &nsnap, int &nT, int &nlev, uint64_
   nsnap = ceil_log2_u64(N) + 2;
   nT = ceil_log2_u64(N) + 1;
   nlev = 1;
-  for (uint64_t sz = N; sz > 1 && nlev < 6; sz = (sz + 63) / 64) nlev++;
+  for (uint64_t sz = N; sz > (uint64_t)kMinFan && nlev < kMinLevels; sz = (sz + kMinFan - 1) / kMinFan) nlev++;
   hcap = pow2_at_least(2 * N);
   (void)W;
 }
@@ -85,13 +85,13 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
   size_t o_wr = L.take((wantW + 1) * 4);
   size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_fin = L.take(N_), o_sa = L.take(N_ * 4);
-  size_t o_phi = L.take(N_ * 4), o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
+  size_t o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
   size_t o_lvl[8] = {0};
   {
     uint64_t sz = N_;
-    for (int k = 1; k < nlev; k++) { sz = (sz + 63) / 64; o_lvl[k] = L.take(sz * 4 + 4); }
+    for (int k = 1; k < nlev; k++) { sz = (sz + kMinFan - 1) / kMinFan; o_lvl[k] = L.take(sz * 4 + 4 * kMinFan); }
   }
-  size_t o_cl = L.take(C2 * 4), o_cs = L.take(C2 * 4), o_ci = L.take(C2 * 4), o_keep = L.take(C2);
+  size_t o_crec = L.take(C2 * 4 * kCandWords), o_keep = L.take(C2);
   size_t o_sl = L.take(C2 * 4), o_ss = L.take(C2 * 4), o_si = L.take(C2 * 4);
   size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
   size_t o_tile = L.take((C2 / 4096 + 4) * 4);
@@ -123,13 +123,10 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   snap = (uint32_t *)(m + o_snap);
   fin = (uint8_t *)(m + o_fin);
   sa = (uint32_t *)(m + o_sa);
-  phi = (uint32_t *)(m + o_phi);
   plcp = (uint32_t *)(m + o_plcp);
   lcp = (uint32_t *)(m + o_lcp);
   for (int k = 1; k < nlev; k++) lvl[k] = (uint32_t *)(m + o_lvl[k]);
-  c_len = (uint32_t *)(m + o_cl);
-  c_start = (uint32_t *)(m + o_cs);
-  c_id = (uint32_t *)(m + o_ci);
+  crec = (uint32_t *)(m + o_crec);
   keep = (uint8_t *)(m + o_keep);
   s_len = (uint32_t *)(m + o_sl);
   s_start = (uint32_t *)(m + o_ss);
@@ -183,19 +180,19 @@ static int read_counters(Workspace &w, hipStream_t s) {
 }
 
 // Multi-key sort of *count_dev items whose ids are 0..count-1 (bound: host
-// upper bound of the count): level k orders by fields[k][id] (c - field when
+// upper bound of the count): level k orders by fields[k][id * strides[k]] (c - field when
 // subs[k], c read from c_devs[k]) within the groups of level k-1.  The final
 // order is left in eng.val[0]; keep[slot] = 0 marks exact duplicates of the
 // previous slot at the last level (when keep != nullptr).
 static void sort_plain(Workspace &w, const uint32_t *count_dev, uint64_t bound, const uint32_t *const *fields,
-                       const int *subs, const uint32_t *const *c_devs, const int *bits, int nlevels, uint8_t *keep,
-                       hipStream_t s) {
+                       const int *strides, const int *subs, const uint32_t *const *c_devs, const int *bits,
+                       int nlevels, uint8_t *keep, hipStream_t s) {
   SortEngine &E = w.eng;
   int cur = 0;
   E.reset_counters(s);
   E.round_begin(cur, s);
   E.iota_val(count_dev, bound, s);
-  E.gather_field(cur, fields[0], count_dev, subs[0], c_devs[0], 0, bound, s);
+  E.gather_field(cur, fields[0], strides[0], count_dev, subs[0], c_devs[0], 0, bound, s);
   uint64_t *rng = reinterpret_cast<uint64_t *>(w.dcnt + CNT_RANGE);
   hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, s, rng, count_dev);
   E.init_units(cur, rng, 1, 0, (uint32_t)bits[0], s);
@@ -209,7 +206,7 @@ static void sort_plain(Workspace &w, const uint32_t *count_dev, uint64_t bound, 
     if (!last) {
       cur ^= 1;
       E.round_begin(cur, s);
-      E.gather_field(cur, fields[L + 1], nullptr, subs[L + 1], c_devs[L + 1], 0, bound, s);
+      E.gather_field(cur, fields[L + 1], strides[L + 1], nullptr, subs[L + 1], c_devs[L + 1], 0, bound, s);
     }
   }
 }
@@ -277,7 +274,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int sub[2] = {0, 0};
     const uint32_t *cd[2] = {nullptr, nullptr};
     const int bb[2] = {32, 32};
-    sort_plain(w, dc + CNT_ND, nd_bound, f, sub, cd, bb, 2, nullptr, s);
+    const int str[2] = {1, 1};
+    sort_plain(w, dc + CNT_ND, nd_bound, f, str, sub, cd, bb, 2, nullptr, s);
     hash_assign(B.val[0], dc + CNT_ND, w.dist_slot, w.hrank, nd_bound, s);
     hash_lookup(tok, N, w.htab, hc - 1, w.hrank, w.tokrank, s);
     key0 = w.tokrank;
@@ -354,13 +352,13 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 
   // ---- LCP via Phi / PLCP (lifting over rounds r-1..0; more levels than
   // needed are harmless: no suffix pair is grouped beyond its last round)
-  build_lcp(w.sa, N, wbeg, wend, w.snap, w.fin, key0, r - 1, w.phi, w.plcp, w.lcp, s);
+  build_lcp(w.sa, w.rank, N, wbeg, wend, w.snap, w.fin, key0, r - 1, w.plcp, w.lcp, s);
   stamp(w, 3, s, stamps);
   if (stop == Stop::LCP) return read_counters(w, s);
 
   // ---- candidates
-  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.c_len, w.c_start, w.c_id, dc + CNT_C,
-                 dc + CNT_MAXL, s);
+  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.crec,
+                 dc + CNT_C, dc + CNT_MAXL, s);
   uint64_t c_bound = 2 * N;
   uint64_t maxl_bound = std::max<uint64_t>(maxwin / 2, 1);
   if (host) {
@@ -371,12 +369,14 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   stamp(w, 4, s, stamps);
   uint64_t m_bound = 0;
   if (c_bound > 0) {
-    const uint32_t *f[3] = {w.c_len, w.c_id, w.c_start};
+    const uint32_t *f[3] = {w.crec, w.crec + 2, w.crec + 1};  // length, ID, start
+    const int str[3] = {kCandWords, kCandWords, kCandWords};
     const int sub[3] = {1, 0, 0};
     const uint32_t *cd[3] = {dc + CNT_MAXL, nullptr, nullptr};
     const int bb[3] = {bit_length_u64(maxl_bound), (int)rank_bits, (int)rank_bits};
-    sort_plain(w, dc + CNT_C, c_bound, f, sub, cd, bb, 3, w.keep, s);
-    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.c_len, w.c_start, w.c_id, w.s_len, w.s_start, w.s_id,
+    sort_plain(w, dc + CNT_C, c_bound, f, str, sub, cd, bb, 3, w.keep, s);
+    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.crec, w.s_len,
+                   w.s_start, w.s_id,
                    w.tmp_a, w.tmp_b, w.tile_tmp, dc + CNT_M, s);
     m_bound = c_bound;
     if (host) {
@@ -432,7 +432,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   int orc = emit_output(w, N, W, batch, wid, wbeg, m_bound, host, s);
   if (orc) return orc;
   stamp(w, 7, s, stamps);
-  if (mode == Mode::CAPTURE || mode == Mode::ENQUEUE) return 0;
+  if (mode == Mode::CAPTURE) return 0;
   rc = finish_run(w, N, m_bound, host ? -1 : sel_launched, info, s, stamps);
   if (host && sel_done < 0 && m_bound > 0) {
     info.sel_rounds = kSelRoundCap;
@@ -468,7 +468,8 @@ int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t
     const int sub[2] = {0, 0};
     const uint32_t *cd[2] = {nullptr, nullptr};
     const int bb[2] = {bit_length_u64(W), bit_length_u64(a_bound)};
-    sort_plain(w, dc + CNT_A, a_bound, f, sub, cd, bb, 2, nullptr, s);
+    const int str[2] = {1, 1};
+    sort_plain(w, dc + CNT_A, a_bound, f, str, sub, cd, bb, 2, nullptr, s);
     order = B.val[0];
   }
   emit_rows(order, dc + CNT_A, a_bound, w.o_len, w.o_start, w.o_id, wid, wbeg, w.tmp_a, w.rowidx, w.row_first, w.rows,

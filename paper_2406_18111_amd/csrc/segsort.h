@@ -23,8 +23,8 @@ class SortEngine {
   void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
   void gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend, uint32_t n,
                  uint32_t h, uint32_t *hist, int r, hipStream_t s);
-  void gather_field(int cur, const uint32_t *field, const uint32_t *all_dev, int sub, const uint32_t *c_dev,
-                    uint32_t c, uint64_t bound, hipStream_t s);
+  void gather_field(int cur, const uint32_t *field, int stride, const uint32_t *all_dev, int sub,
+                    const uint32_t *c_dev, uint32_t c, uint64_t bound, hipStream_t s);
   void iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s);
   void msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s);
   void lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s);

@@ -143,13 +143,13 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
   }
 }
 
-__global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, const uint32_t *all_dev, int sub,
-                               const uint32_t *c_dev, uint32_t c) {
+__global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, int stride, const uint32_t *all_dev,
+                               int sub, const uint32_t *c_dev, uint32_t c) {
   const uint32_t cnt = all_dev ? *all_dev : B.ctr->act_cnt[cur];
   if (c_dev) c = *c_dev;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
     const uint32_t p = all_dev ? q : B.act[cur][q];
-    const uint32_t f = field[B.val[0][p]];
+    const uint32_t f = field[(uint64_t)B.val[0][p] * stride];
     B.key[0][p] = sub ? c - f : f;
   }
 }
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       B.val[0][p] = v;
       if (MODE == MODE_SA) {
         if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[v] = gpos + 1;  // else unchanged
-        if (R.snap) R.snap[v] = gpos + 1;
+        if (R.snap && !single) R.snap[v] = gpos + 1;  // a singleton's snapshot is never read
         if (single) R.fin[v] = (uint8_t)R.round;
       }
       if (last_level) {
@@ -374,7 +374,7 @@ constexpr int kWaveCtrs = kWaveMaxCi + 2;  // new units per class, active entrie
 // per-item counts are wave ballots), so the hot list counters see few
 // atomics.  The batch loop is uniform across the block.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut R, int last_level, uint8_t *keep) {
+__global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankOut R, int last_level, uint8_t *keep) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nxt = cur ^ 1;
   __shared__ uint32_t wtot[4][kWaveCtrs];
@@ -396,11 +396,17 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
     uint32_t tot[kWaveCtrs];
 #pragma unroll
     for (int q = 0; q < kWaveCtrs; q++) tot[q] = 0;
+    // the batch's global loads first (unit descriptors, then entries), so
+    // that their latencies overlap instead of adding up item by item
+    int ck[kWaveItems];
+    uint32_t nbk[kWaveItems];
+    Unit uk[kWaveItems];
+    uint64_t vk[kWaveItems];
 #pragma unroll
     for (int k = 0; k < kWaveItems; k++) {
-      act_p[k] = kNone;
-      unit_code[k] = 0;
-      unit_pos[k] = 0;
+      ck[k] = 0;
+      nbk[k] = 0;
+      uk[k] = Unit{0, 0};
       const uint64_t item = b0 + (uint64_t)wid * kWaveItems + k;
       if (item >= total) continue;  // wave-uniform
       int ci = 0;
@@ -410,21 +416,41 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
 #pragma unroll
       for (int q = 0; q < kWaveMaxCi; q++)
         if (q == ci) { cnt_ci = cnt[q]; off_ci = first_item[q]; }
-      const int c = ci + 1;
-      const uint32_t sub = 1u << c, per = 64u >> c;
+      const uint32_t per = 64u >> (ci + 1);
       const uint32_t first = (uint32_t)(item - off_ci) * per;
       const uint32_t nb = min(per, cnt_ci - first);
-      const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
-      Unit u{0, 0};
-      if (j < nb) u = B.cls[cur][B.cls_off[ci] + first + j];
-      const uint32_t len = u.len & kLenMask;
-      const bool valid = j < nb && idx < len;
-      uint64_t v = ~0ull;
-      if (valid) {
+      const uint32_t j = (uint32_t)lane >> (ci + 1);
+      ck[k] = ci;
+      nbk[k] = nb;
+      if (j < nb) uk[k] = B.cls[cur][B.cls_off[ci] + first + j];
+    }
+#pragma unroll
+    for (int k = 0; k < kWaveItems; k++) {
+      vk[k] = ~0ull;
+      const int c = ck[k] + 1;
+      const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & ((1u << c) - 1);
+      const Unit u = uk[k];
+      if (j < nbk[k] && idx < (u.len & kLenMask)) {
         const int bb = (u.len & kBufBit) ? 1 : 0;
         const uint32_t p = u.start + idx;
-        v = ((uint64_t)B.key[bb][p] << 32) | B.val[bb][p];
+        vk[k] = ((uint64_t)B.key[bb][p] << 32) | B.val[bb][p];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < kWaveItems; k++) {
+      act_p[k] = kNone;
+      unit_code[k] = 0;
+      unit_pos[k] = 0;
+      const uint64_t item = b0 + (uint64_t)wid * kWaveItems + k;
+      if (item >= total) continue;  // wave-uniform
+      const int c = ck[k] + 1;
+      const uint32_t sub = 1u << c;
+      const uint32_t nb = nbk[k];
+      const uint32_t j = (uint32_t)lane >> c, idx = (uint32_t)lane & (sub - 1);
+      const Unit u = uk[k];
+      const uint32_t len = u.len & kLenMask;
+      const bool valid = j < nb && idx < len;
+      uint64_t v = vk[k];
       for (uint32_t kk = 2; kk <= sub; kk <<= 1) {
         for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
           const uint64_t o = shfl_xor64(v, (int)jj);
@@ -447,7 +473,7 @@ __global__ __launch_bounds__(256) void k_wave_sort(SortBufs B, int cur, RankOut 
         B.val[0][p] = val;
         if (MODE == MODE_SA) {
           if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[val] = gpos + 1;  // else unchanged
-          if (R.snap) R.snap[val] = gpos + 1;
+          if (R.snap && !single) R.snap[val] = gpos + 1;
           if (single) R.fin[val] = (uint8_t)R.round;
         }
         if (last_level) keep[p] = bnd ? 1 : 0;
@@ -540,7 +566,7 @@ constexpr int kGroupMinCi = 6;  // 0-based class 6 = lengths 65..128
 constexpr int kGroupThreads = 512;
 
 template <int MODE, int TLG>
-__global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur, RankOut R, int last_level,
+__global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(SortBufs B, int cur, RankOut R, int last_level,
                                                             uint8_t *keep) {
   constexpr int NT = kGroupThreads;
   constexpr int T = 1 << TLG;
@@ -609,19 +635,37 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
     }
     __syncthreads();
     const uint32_t total = uoff[nb];
-    // load entries
-    for (uint32_t p = tid; p < total; p += NT) {
-      uint32_t lo = 0, hi = nb;  // unit j: uoff[j] <= p < uoff[j+1]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (uoff[mid] <= p) lo = mid; else hi = mid;
+    // load entries: all of a thread's global loads are issued before the
+    // first is waited for
+    {
+      uint32_t kq[PER], vq[PER], jq[PER];
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        const uint32_t p = tid + q * NT;
+        jq[q] = 0;
+        if (p < total) {
+          uint32_t lo = 0, hi = nb;  // unit j: uoff[j] <= p < uoff[j+1]
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uoff[mid] <= p) lo = mid; else hi = mid;
+          }
+          const Unit u = ud[lo];
+          const int b = (u.len & kBufBit) ? 1 : 0;
+          const uint32_t g = u.start + (p - uoff[lo]);
+          kq[q] = B.key[b][g];
+          vq[q] = B.val[b][g];
+          jq[q] = lo;
+        }
       }
-      const Unit u = ud[lo];
-      const int b = (u.len & kBufBit) ? 1 : 0;
-      const uint32_t g = u.start + (p - uoff[lo]);
-      K[p] = B.key[b][g];
-      V[p] = B.val[b][g];
-      EJ[p] = (uint16_t)lo;
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        const uint32_t p = tid + q * NT;
+        if (p < total) {
+          K[p] = kq[q];
+          V[p] = vq[q];
+          EJ[p] = (uint16_t)jq[q];
+        }
+      }
     }
     __syncthreads();
     // insert into the hash table
@@ -715,7 +759,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_lds_group(SortBufs B, int cur
         B.val[0][slot] = v;
         if (MODE == MODE_SA) {
           if (!((u.len & kHeadBit) && head == u.start)) R.rank[v] = head + 1;  // else unchanged
-          if (R.snap) R.snap[v] = head + 1;
+          if (R.snap && gcnt >= 2) R.snap[v] = head + 1;
           if (gcnt == 1) R.fin[v] = (uint8_t)R.round;
           if (R.aflag) R.aflag[slot] = gcnt >= 2 ? 1 : 0;
         }
@@ -1085,10 +1129,10 @@ void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, 
   hipLaunchKernelGGL(k_gather_sa, dim3(4096), dim3(256), 0, s, b_, cur, rank, aflag, slot_wend, n, h, hist, r);
 }
 
-void SortEngine::gather_field(int cur, const uint32_t *field, const uint32_t *all_dev, int sub, const uint32_t *c_dev,
-                              uint32_t c, uint64_t bound, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_field, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, cur, field, all_dev, sub, c_dev,
-                     c);
+void SortEngine::gather_field(int cur, const uint32_t *field, int stride, const uint32_t *all_dev, int sub,
+                              const uint32_t *c_dev, uint32_t c, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_field, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, cur, field, stride, all_dev, sub,
+                     c_dev, c);
 }
 
 void SortEngine::iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s) {

@@ -6,7 +6,8 @@
 
 namespace apo {
 
-constexpr int kMinLevels = 6;  // 64-ary LCP minimum levels: 64^5 > 2^26
+constexpr int kMinFan = 16;    // LCP minimum hierarchy: each level holds minima of kMinFan entries below
+constexpr int kMinLevels = 8;  // levels 0..7: a top level of at most 16 entries for up to 2^32 positions
 
 void fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 void fill_u8(uint8_t *p, uint64_t n, uint8_t v, hipStream_t s);
@@ -31,16 +32,19 @@ void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t 
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 
-void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
-               const uint8_t *fin, const uint32_t *key0, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp,
-               hipStream_t s);
+// LCP of adjacent suffixes.  rank: final ranks of the suffix sort (1 + slot).
+void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
+               const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp,
+               uint32_t *lcp, hipStream_t s);
 
+// Candidates are written as records of kCandWords words: length, start, ID.
+constexpr int kCandWords = 3;
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend,
-                    uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *c_len,
-                    uint32_t *c_start, uint32_t *c_id, uint32_t *cnt, uint32_t *maxl, hipStream_t s);
+                    uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt,
+                    uint32_t *maxl, hipStream_t s);
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
-                    const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len,
+                    const uint32_t *crec, uint32_t *s_len,
                     uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s);
 

@@ -276,13 +276,6 @@ void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *w
 }
 
 // ------------------------------------------------------------------- LCP
-__global__ void k_phi(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, uint32_t *phi) {
-  GRID_STRIDE(i, n) {
-    const uint32_t b = wbeg ? wbeg[i] : 0u;
-    phi[sa[i]] = (i > b) ? sa[i - 1] : kNone;
-  }
-}
-
 // lcp(x, y) >= acc known; extend by binary lifting over the per-round rank
 // snapshots: 2^j-prefixes at x+acc and y+acc are equal iff both suffixes were
 // still in a shared group after round j and carried the same rank then.
@@ -316,39 +309,111 @@ __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t ac
 }
 
 constexpr int kKasaiCap = 64;
+constexpr int kSeedGroup = 8;
+constexpr int kPlcpChunk = 8;                        // positions per thread
+constexpr int kPlcpSpan = 256 * kPlcpChunk;          // positions per workgroup pass
+constexpr int kPlcpMargin = 256;                     // staged tokens past the span
+__host__ __device__ constexpr int pad16(int p) { return p + (p >> 4); }  // one bank skew per chunk
 
-// Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of `chunk`
+// lcp(x, y) from scratch.  The levels at which both suffixes were still
+// grouped (below both fin values) are probed kSeedGroup at a time with
+// independent loads: equal 2^j-prefixes imply equal 2^i-prefixes for i < j, so
+// the highest equal level j* gives lcp in [2^j*, 2^(j*+1)), and lifting goes
+// on below it.
+__device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, uint32_t we, int top, const uint32_t *snap,
+                                             uint64_t n, const uint8_t *fin, const uint32_t *key0) {
+  const int J = min(top, (int)min(fin[x], fin[y]) - 1);
+  int best = kSnapFrom - 1;
+  for (int lo = kSnapFrom; lo <= J; lo += kSeedGroup) {
+#pragma unroll
+    for (int k = 0; k < kSeedGroup; k++) {
+      const int j = lo + k;
+      if (j <= J && snap[(uint64_t)j * n + x] == snap[(uint64_t)j * n + y]) best = j;
+    }
+    if (best < lo + kSeedGroup - 1) break;  // a level of this group differed (or J ended it)
+  }
+  if (best < kSnapFrom) return lcp_lift(x, y, 0u, we, kSnapFrom - 1, snap, n, fin, key0);  // tail only
+  return lcp_lift(x, y, 1u << best, we, best - 1, snap, n, fin, key0);
+}
+
+// Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of kPlcpChunk
 // consecutive positions; each chunk (and each window start) is seeded exactly
 // by lifting, and an extension longer than kKasaiCap tokens switches to
-// lifting.  Consecutive positions mostly have consecutive Phi values on
-// repetitive input, so the chunk's token reads stay local.
-__global__ void k_plcp(const uint32_t *phi, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-                       const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t chunk,
-                       uint32_t *plcp) {
-  const uint64_t nchunks = (n + chunk - 1) / chunk;
-  GRID_STRIDE(t, nchunks) {
-    const uint64_t j0 = t * chunk, j1 = min(j0 + chunk, n);
-    uint32_t h = 0;
-    bool fresh = true;
-    for (uint64_t j = j0; j < j1; j++) {
-      const uint32_t y = phi[j];
-      const uint32_t b = wbeg ? wbeg[j] : 0u;
-      if (j == b) fresh = true;
-      if (y == kNone) { plcp[j] = 0; h = 0; fresh = true; continue; }
-      const uint32_t we = wend ? wend[j] : (uint32_t)n;
-      if (fresh) {
-        h = lcp_lift((uint32_t)j, y, 0u, we, top, snap, n, fin, key0);
-        fresh = false;
-      } else {
-        h = h > 0 ? h - 1 : 0;
-        int steps = 0;
-        while ((uint32_t)j + h < we && y + h < we && key0[(uint32_t)j + h] == key0[y + h]) {
-          h++;
-          if (++steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin, key0); break; }
-        }
-      }
-      plcp[j] = h;
+// lifting.  Phi[j] = SA[ISA[j] - 1] comes from the final ranks (rank =
+// 1 + slot once every suffix is alone in its group).  A workgroup stages its
+// span's Phi values and tokens in LDS with coalesced loads, so each thread's
+// sequential walk reads LDS, and writes the span's PLCP back coalesced; only
+// the Phi side of the comparisons reads tokens from global memory.
+__global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t *rank, uint64_t n,
+                                              const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
+                                              const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp) {
+  __shared__ uint32_t ps[pad16(kPlcpSpan)];
+  __shared__ uint32_t ks[pad16(kPlcpSpan + kPlcpMargin)];
+  const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
+  for (uint64_t sp = blockIdx.x; sp < nspan; sp += gridDim.x) {
+    const uint64_t j0 = sp * kPlcpSpan;
+    const int len = (int)min((uint64_t)kPlcpSpan, n - j0);
+    const int klen = (int)min((uint64_t)(kPlcpSpan + kPlcpMargin), n - j0);
+    for (int p = threadIdx.x; p < len; p += blockDim.x) {
+      const uint32_t i = rank[j0 + p] - 1u;  // slot of suffix j0 + p
+      const uint32_t b = wbeg ? wbeg[j0 + p] : 0u;
+      ps[pad16(p)] = i > b ? sa[i - 1] : kNone;
     }
+    for (int p = threadIdx.x; p < klen; p += blockDim.x) ks[pad16(p)] = key0[j0 + p];
+    __syncthreads();
+    const int c0 = threadIdx.x * kPlcpChunk;
+    if (c0 < len) {
+      const int c1 = min(c0 + kPlcpChunk, len);
+      uint64_t j = j0 + c0;
+      uint32_t wb = wbeg ? wbeg[j] : 0u, we = wend ? wend[j] : (uint32_t)n;
+      uint32_t h = 0;
+      bool fresh = true;
+      for (int c = c0; c < c1; c++, j++) {
+        if (j == we) {  // the next window starts here (only with window bounds: otherwise we == n > j)
+          wb = (uint32_t)j;
+          we = wend[j];
+        }
+        if (j == wb) fresh = true;
+        const uint32_t y = ps[pad16(c)];
+        if (y == kNone) {
+          h = 0;
+          fresh = true;
+        } else if (fresh) {
+          h = lcp_seed((uint32_t)j, y, we, top, snap, n, fin, key0);
+          fresh = false;
+        } else {
+          // extend from h - 1, kExt tokens per step with independent loads
+          constexpr int kExt = 4;
+          h = h > 0 ? h - 1 : 0;
+          int steps = 0;
+          for (;;) {
+            const uint32_t a = (uint32_t)j + h, b = y + h;
+            if (a >= we || b >= we) break;
+            const uint32_t room = we - max(a, b);
+            const uint32_t q = a - (uint32_t)j0;
+            uint32_t ka[kExt], kb[kExt];
+#pragma unroll
+            for (int k = 0; k < kExt; k++) {
+              const bool in = (uint32_t)k < room;
+              kb[k] = in ? key0[b + k] : 0u;
+              ka[k] = in ? (q + k < (uint32_t)klen ? ks[pad16((int)(q + k))] : key0[a + k]) : 1u;
+            }
+            uint32_t m = kExt;
+#pragma unroll
+            for (int k = kExt - 1; k >= 0; k--)
+              if (ka[k] != kb[k]) m = (uint32_t)k;
+            h += m;
+            if (m < (uint32_t)kExt) break;
+            steps += kExt;
+            if (steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin, key0); break; }
+          }
+        }
+        ps[pad16(c)] = h;  // this thread's own slot, already read
+      }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < len; p += blockDim.x) plcp[j0 + p] = ps[pad16(p)];
+    __syncthreads();
   }
 }
 
@@ -359,25 +424,21 @@ __global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, cons
   }
 }
 
-void build_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
-               const uint8_t *fin, const uint32_t *key0, int top, uint32_t *phi, uint32_t *plcp, uint32_t *lcp,
-               hipStream_t s) {
-  hipLaunchKernelGGL(k_phi, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wbeg, phi);
-  // short chunks: each thread's walk is a chain of dependent loads, so many
-  // threads are needed to cover latency (longer chunks measured slower)
-  const uint32_t chunk = 16;
-  const uint64_t nch = (n + chunk - 1) / chunk;
-  hipLaunchKernelGGL(k_plcp, grid_for(nch, 256, 8192), dim3(256), 0, s, phi, n, wbeg, wend, snap, fin, key0, top,
-                     chunk, plcp);
+void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
+               const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp,
+               uint32_t *lcp, hipStream_t s) {
+  const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
+  hipLaunchKernelGGL(k_plcp, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(nspan, 1), 8192)), dim3(256), 0, s,
+                     sa, rank, n, wbeg, wend, snap, fin, key0, top, plcp);
   hipLaunchKernelGGL(k_lcp, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
 }
 
 // ------------------------------------------------------------ candidates
-// Block minima of LCP (64-ary levels) for previous-smaller-value queries.
+// Block minima of LCP (kMinFan-ary levels) for previous-smaller-value queries.
 __global__ void k_blockmin(const uint32_t *src, uint64_t nsrc, uint32_t *dst, uint64_t ndst) {
   GRID_STRIDE(k, ndst) {
     uint32_t m = 0xFFFFFFFFu;
-    const uint64_t b = k * 64, e = min(b + 64, nsrc);
+    const uint64_t b = k * kMinFan, e = min(b + kMinFan, nsrc);
     for (uint64_t i = b; i < e; i++) m = min(m, src[i]);
     dst[k] = m;
   }
@@ -389,49 +450,45 @@ struct MinLevels {
   int nlev;
 };
 
-constexpr int kWinBack = 64;                 // window entries before the block's first pair
-constexpr int kWin = 256 + kWinBack;         // LDS window of LCP values per block
-constexpr int kWinLevels = 9;                // 2^8 < kWin <= 2^9
-
-// Largest j < i with lcp[j] < l, or -1.  Inside the block's LDS window the
-// search is binary lifting over a sparse table of window minima
-// (st[k][x] = min lcp[wlo + x .. wlo + x + 2^k)); below the window (which
-// starts on a multiple of 64) it climbs the 64-ary minimum levels until an
-// entry below l appears, then descends to its rightmost qualifying leaf.
-__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l, const uint32_t (*st)[kWin], uint64_t wlo) {
-  int x = (int)(i - wlo);  // [x, i - wlo) holds only values >= l
+// Largest e in [lo, hi) with L[e] < l, or -1; lo is a multiple of kMinFan
+// and the aligned block [lo, lo + kMinFan) lies inside L's allocation.  The
+// block is read with four independent 16-byte loads.
+__device__ __forceinline__ int64_t last_below(const uint32_t *L, uint64_t lo, uint64_t hi, uint32_t l) {
+  static_assert(kMinFan == 16, "one block is four uint4 loads");
+  const uint4 *q = reinterpret_cast<const uint4 *>(L + lo);
+  const uint4 a = q[0], b = q[1], c = q[2], d = q[3];
+  const uint32_t v[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+  int f = -1;
 #pragma unroll
-  for (int k = kWinLevels - 1; k >= 0; k--)
-    if (x >= (1 << k) && st[k][x - (1 << k)] >= l) x -= 1 << k;
-  if (x > 0) return (int64_t)(wlo + x - 1);
-  if (wlo == 0) return -1;
-  uint64_t pos = wlo >> 6;  // exclusive bound at level 1
-  int lev = 1;
-  int64_t found = -1;
-  if (M.nlev < 2) return -1;
-  while (pos > 0) {
-    // the top level has no parent: scan it down to entry 0
-    const uint64_t bs = (lev + 1 >= M.nlev) ? 0 : ((pos - 1) >> 6) << 6;
-    const uint32_t *L = M.lv[lev];
-    for (uint64_t e = pos; e > bs; e--) {
-      if (L[e - 1] < l) { found = (int64_t)(e - 1); break; }
-    }
+  for (int k = 0; k < 16; k++)
+    if (lo + k < hi && v[k] < l) f = k;
+  return f >= 0 ? (int64_t)(lo + f) : -1;
+}
+
+// Largest j < i with lcp[j] < l, or -1: scans the aligned block of kMinFan
+// entries left of the bound at each level, climbing while nothing below l is
+// found, then descends to the rightmost qualifying leaf.  Each step is one
+// block read; near answers (the common case) take one or two.
+__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
+  uint64_t pos = i;  // exclusive bound at level `lev`: its entries below pos cover [0, i)
+  int lev = 0;
+  int64_t found;
+  for (;;) {
+    if (pos == 0) return -1;
+    const uint64_t lo = (pos - 1) / kMinFan * kMinFan;
+    found = last_below(M.lv[lev], lo, pos, l);
     if (found >= 0) break;
-    if (lev + 1 >= M.nlev) return -1;
-    pos = bs >> 6;
-    lev++;
+    if (lev + 1 < M.nlev) {
+      pos = lo / kMinFan;
+      lev++;
+    } else {
+      pos = lo;  // top level: go on down the same level
+    }
   }
-  if (found < 0) return -1;
   while (lev > 0) {
     lev--;
-    const uint32_t *L = M.lv[lev];
-    const uint64_t b = (uint64_t)found * 64;
-    const uint64_t e = min(b + 64, M.sz[lev]);
-    int64_t f = -1;
-    for (uint64_t q = e; q > b; q--) {
-      if (L[q - 1] < l) { f = (int64_t)(q - 1); break; }
-    }
-    found = f;  // always found: the parent minimum is < l
+    const uint64_t lo = (uint64_t)found * kMinFan;
+    found = last_below(M.lv[lev], lo, min(lo + kMinFan, M.sz[lev]), l);  // found: the parent minimum is < l
     if (found < 0) return -1;
   }
   return found;
@@ -440,95 +497,99 @@ __device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l, const u
 // Loop body of the paper's candidate pass for every adjacent pair i (both
 // suffixes in one window): disjoint branch -> (p, s1), (p, s2); overlap branch
 // -> l = floor((p+d)/2) - remainder mod d, at base and base+l.  Candidates
-// with l >= min_len are appended with their substring ID.
+// with l >= min_len are appended with their substring ID.  A workgroup takes
+// kCandItems consecutive pairs per thread per pass, so output space is
+// reserved with one global atomic per 256 * kCandItems pairs, and the output
+// keeps suffix-array order within a pass.
+constexpr int kCandItems = 8;
+
 __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
-                                                    uint32_t *c_len, uint32_t *c_start, uint32_t *c_id,
-                                                    uint32_t *cnt, uint32_t *maxl) {
+                                                    uint32_t *crec, uint32_t *cnt, uint32_t *maxl) {
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t bmax;
-  __shared__ uint32_t st[kWinLevels][kWin];
   if (threadIdx.x == 0) bmax = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
-    const uint64_t i = i0 + threadIdx.x;
-    // LDS window lcp[wlo, wlo + wn) with a sparse table of minima over it
-    const uint64_t wlo = i0 >= kWinBack ? i0 - kWinBack : 0;
-    const int wn = (int)min((uint64_t)kWin, n - wlo);
-    for (int x = threadIdx.x; x < kWin; x += blockDim.x) st[0][x] = x < wn ? lcp[wlo + x] : 0u;
-    __syncthreads();
-    for (int k = 1; k < kWinLevels; k++) {
-      for (int x = threadIdx.x; x < kWin; x += blockDim.x)
-        st[k][x] = x + (1 << (k - 1)) < kWin ? min(st[k - 1][x], st[k - 1][x + (1 << (k - 1))]) : st[k - 1][x];
-      __syncthreads();
-    }
-    uint32_t l = 0, a = 0, b = 0, id = 0;
-    bool emit = false;
-    if (i + 1 < n) {
+  uint32_t mymax = 0;
+  const uint64_t span = (uint64_t)blockDim.x * kCandItems;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * span; i0 < n; i0 += (uint64_t)gridDim.x * span) {
+    uint32_t L[kCandItems], A[kCandItems], B[kCandItems], I[kCandItems];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kCandItems; k++) {
+      const uint64_t i = i0 + (uint64_t)threadIdx.x * kCandItems + k;  // a thread's pairs are consecutive
+      L[k] = 0;
+      A[k] = B[k] = I[k] = 0;
+      if (i + 1 >= n) continue;
       const uint32_t we = wend ? wend[i] : (uint32_t)n;
-      if (i + 1 < we) {
-        const uint32_t s1 = sa[i], s2 = sa[i + 1], p = lcp[i];
-        const uint32_t lo = min(s1, s2), hi = max(s1, s2);
-        if (lo + p <= hi) {
-          l = p; a = s1; b = s2;
-        } else {
-          const uint32_t d = hi - lo;
-          l = (p + d) / 2;
-          l -= l % d;
-          a = lo; b = lo + l;
-        }
-        if (l >= min_len) {
-          emit = true;
-          id = (uint32_t)(psv_query(M, i, l, st, wlo) + 1);
-        }
+      if (i + 1 >= we) continue;
+      const uint32_t s1 = sa[i], s2 = sa[i + 1], p = lcp[i];
+      const uint32_t lo = min(s1, s2), hi = max(s1, s2);
+      uint32_t l, a, b;
+      if (lo + p <= hi) {
+        l = p; a = s1; b = s2;
+      } else {
+        const uint32_t d = hi - lo;
+        l = (p + d) / 2;
+        l -= l % d;
+        a = lo; b = lo + l;
+      }
+      if (l >= min_len) {  // min_len >= 1, so L[k] != 0 marks an emitted pair
+        L[k] = l; A[k] = a; B[k] = b;
+        I[k] = (uint32_t)(psv_query(M, i, l) + 1);
+        mine += 2;
+        mymax = max(mymax, l);
       }
     }
     uint32_t tot;
-    const uint32_t off = block_excl_sum<256>(emit ? 2u : 0u, sh, &tot);
+    const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(cnt, tot) : 0u;
-    if (emit) atomicMax(&bmax, l);
     __syncthreads();
-    if (emit) {
-      const uint32_t w = base + off;
-      c_len[w] = l; c_start[w] = a; c_id[w] = id;
-      c_len[w + 1] = l; c_start[w + 1] = b; c_id[w + 1] = id;
+    uint32_t *r = crec + kCandWords * (uint64_t)(base + off);
+#pragma unroll
+    for (int k = 0; k < kCandItems; k++) {
+      if (!L[k]) continue;
+      r[0] = L[k]; r[1] = A[k]; r[2] = I[k];
+      r[3] = L[k]; r[4] = B[k]; r[5] = I[k];
+      r += 2 * kCandWords;
     }
     __syncthreads();
   }
+  const uint32_t wm = wave_incl_max(mymax);
+  if ((threadIdx.x & 63) == 63 && wm) atomicMax(&bmax, wm);
+  __syncthreads();
   if (threadIdx.x == 0 && bmax) atomicMax(maxl, bmax);
 }
 
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend, uint32_t min_len,
-                    uint32_t *const *levels, int nlev, uint32_t *c_len, uint32_t *c_start, uint32_t *c_id,
-                    uint32_t *cnt, uint32_t *maxl, hipStream_t s) {
+                    uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt, uint32_t *maxl,
+                    hipStream_t s) {
   MinLevels M{};
   uint64_t sz = n;
   M.lv[0] = lcp;
   M.sz[0] = n;
   M.nlev = 1;
-  for (int k = 1; k < nlev && k < kMinLevels; k++) {
-    const uint64_t nd = (sz + 63) / 64;
+  for (int k = 1; k < nlev && k < kMinLevels && sz > (uint64_t)kMinFan; k++) {
+    const uint64_t nd = (sz + kMinFan - 1) / kMinFan;
     hipLaunchKernelGGL(k_blockmin, grid_for(nd, 256, 8192), dim3(256), 0, s, M.lv[k - 1], sz, levels[k], nd);
     M.lv[k] = levels[k];
     M.sz[k] = nd;
     M.nlev = k + 1;
     sz = nd;
-    if (nd <= 1) break;
   }
-  hipLaunchKernelGGL(k_candidates, grid_for(n, 256, 8192), dim3(256), 0, s, sa, lcp, n, wend, min_len, M, c_len,
-                     c_start, c_id, cnt, maxl);
+  hipLaunchKernelGGL(k_candidates, grid_for((n + kCandItems - 1) / kCandItems, 256, 8192), dim3(256), 0, s, sa, lcp,
+                     n, wend, min_len, M, crec, cnt, maxl);
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
 __global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *pos, const uint32_t *m_dev,
-                                const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id,
-                                uint32_t *s_len, uint32_t *s_start, uint32_t *s_id) {
+                                const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id) {
   const uint64_t m = *m_dev;
   GRID_STRIDE(k, m) {
     if (keep[k]) {
-      const uint32_t c = order[k], o = pos[k];
-      s_len[o] = c_len[c]; s_start[o] = c_start[c]; s_id[o] = c_id[c];
+      const uint32_t o = pos[k];
+      const uint32_t *r = crec + kCandWords * (uint64_t)order[k];
+      s_len[o] = r[0]; s_start[o] = r[1]; s_id[o] = r[2];
     }
   }
 }
@@ -539,13 +600,12 @@ __global__ void k_u8_to_u32(const uint8_t *a, const uint32_t *n_dev, uint32_t *b
 }
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
-                    const uint32_t *c_len, const uint32_t *c_start, const uint32_t *c_id, uint32_t *s_len,
-                    uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
-                    uint32_t *total, hipStream_t s) {
+                    const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags,
+                    uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
   hipLaunchKernelGGL(k_u8_to_u32, grid_for(bound, 256, 8192), dim3(256), 0, s, keep, m_dev, tmp_flags);
   scan_excl(tmp_flags, tmp_pos, m_dev, bound, tile_tmp, total, s);
-  hipLaunchKernelGGL(k_gather_sorted, grid_for(bound, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m_dev, c_len,
-                     c_start, c_id, s_len, s_start, s_id);
+  hipLaunchKernelGGL(k_gather_sorted, grid_for(bound, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m_dev, crec,
+                     s_len, s_start, s_id);
 }
 
 // ------------------------------------------------------------- selection
@@ -624,6 +684,10 @@ __device__ __forceinline__ void paint_wave(uint8_t *mark, bool on, uint32_t s, u
   }
 }
 
+// Lists built by a pass (working list, next round's undecided list) reserve
+// their space once per workgroup pass of 256 * kSelItems entries.
+constexpr int kSelItems = 4;
+
 // Round r >= 1: reject undecided candidates with a painted endpoint; the
 // others form the working list.
 __global__ void k_sel_filter(SelArgs a) {
@@ -631,22 +695,34 @@ __global__ void k_sel_filter(SelArgs a) {
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   const uint32_t m = a.nlive[a.r];
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
-    const uint64_t q = q0 + threadIdx.x;
-    bool keep = false;
-    uint32_t k = 0;
-    if (q < m) {
-      k = a.pend[q];
-      const uint32_t s = a.start[k], e = s + a.len[k] - 1;
-      if (a.mark[s] || a.mark[e]) a.state[k] = 2;
-      else keep = true;
+  const uint64_t span = (uint64_t)blockDim.x * kSelItems;
+  for (uint64_t q0 = (uint64_t)blockIdx.x * span; q0 < m; q0 += (uint64_t)gridDim.x * span) {
+    uint32_t K[kSelItems];
+    uint32_t mine = 0, kept = 0;
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++) {
+      const uint64_t q = q0 + threadIdx.x + (uint64_t)t * blockDim.x;
+      K[t] = 0;
+      if (q < m) {
+        const uint32_t k = a.pend[q];
+        const uint32_t s = a.start[k], e = s + a.len[k] - 1;
+        if (a.mark[s] || a.mark[e]) {
+          a.state[k] = 2;
+        } else {
+          K[t] = k;
+          kept |= 1u << t;
+          mine++;
+        }
+      }
     }
     uint32_t tot;
-    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
+    const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nwork[a.r], tot) : 0u;
     __syncthreads();
-    if (keep) a.work[base + off] = k;
+    uint32_t w = base + off;
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++)
+      if (kept & (1u << t)) a.work[w++] = K[t];
     __syncthreads();
   }
 }
@@ -747,32 +823,44 @@ __global__ void k_sel_decide(SelArgs a) {
   const uint32_t m = sel_nwork(a);
   const uint32_t ml = *a.maxl;
   const int levels = ml ? 32 - __clz((int)ml) : 1;  // sparse: blocks of size <= maxl
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x; q0 < m; q0 += stride) {
-    const uint64_t q = q0 + threadIdx.x;
-    bool keep = false, acc = false;
-    uint32_t k = 0, l = 0, s = 0;
-    if (q < m) {
-      k = a.work[q];
-      l = a.len[k];
-      s = a.start[k];
-      const uint32_t e = s + l - 1;
-      const uint32_t t1 = DENSE ? a.Tc[s] : ctree_point(a, s, levels);
-      const uint32_t t2 = DENSE ? a.Tc[e] : ctree_point(a, e, levels);
-      if (t1 >= k && t2 >= k) {
-        a.state[k] = 1;
-        acc = true;
-      } else {
-        keep = true;
-        atomicAdd(&und, 1u);
+  const uint64_t span = (uint64_t)blockDim.x * kSelItems;
+  for (uint64_t q0 = (uint64_t)blockIdx.x * span; q0 < m; q0 += (uint64_t)gridDim.x * span) {
+    uint32_t K[kSelItems];
+    uint32_t mine = 0, kept = 0;
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++) {
+      const uint64_t q = q0 + threadIdx.x + (uint64_t)t * blockDim.x;
+      bool acc = false;
+      uint32_t k = 0, l = 0, s = 0;
+      if (q < m) {
+        k = a.work[q];
+        l = a.len[k];
+        s = a.start[k];
+        const uint32_t e = s + l - 1;
+        const uint32_t t1 = DENSE ? a.Tc[s] : ctree_point(a, s, levels);
+        const uint32_t t2 = DENSE ? a.Tc[e] : ctree_point(a, e, levels);
+        if (t1 >= k && t2 >= k) {
+          a.state[k] = 1;
+          acc = true;
+        } else {
+          kept |= 1u << t;
+          mine++;
+        }
       }
+      K[t] = k;
+      paint_wave(a.mark, acc, s, l);
     }
-    paint_wave(a.mark, acc, s, l);
     uint32_t tot;
-    const uint32_t off = block_excl_sum<256>(keep ? 1u : 0u, sh, &tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
+    const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
+    if (threadIdx.x == 0) {
+      base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
+      und += tot;
+    }
     __syncthreads();
-    if (keep) a.pend[base + off] = k;
+    uint32_t w = base + off;
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++)
+      if (kept & (1u << t)) a.pend[w++] = K[t];
     __syncthreads();
   }
   if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
@@ -837,7 +925,7 @@ void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_
                int r, uint64_t live_hint, const uint32_t *maxl, uint32_t *ctree, uint64_t npad, uint8_t *mark,
                hipStream_t s) {
   SelArgs a{len, start, Tc, To, n, top, state, pend, work, nlive, nwork, undec, r, maxl, ctree, npad, mark};
-  const dim3 g = grid_for(live_hint, 256, 8192);
+  const dim3 g = grid_for((live_hint + kSelItems - 1) / kSelItems, 256, 8192);
   if (r > 0) hipLaunchKernelGGL(k_sel_filter, g, dim3(256), 0, s, a);
   // dense round (each kernel returns at once when the round is sparse or not needed)
   hipLaunchKernelGGL(k_sel_insert, g, dim3(256), 0, s, a);

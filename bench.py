@@ -313,9 +313,10 @@ def main():
             # untimed: the project's autotuner picks the LDS tile and MSD digit width on this batch
             tl, db, tms = ctx.tune_batch(dev, off, m, reps=1)
             tuned = {"tile_log": tl, "digit_bits": db, "tuning_ms_at_best": tms}
-        # timed region: the sync-free launch sequence with the dominant kernel
-        # family bracketed by events on its stream (kernel timing is not taken
-        # inside captured graphs)
+        # timed region: one batch call per step (lanes run host-driven, one
+        # lane runs the sync-free sequence) with the dominant kernel family
+        # bracketed by events on its stream (kernel timing is not taken inside
+        # captured graphs)
         ctx.profile_kernel(LDS_SA_TAG)
         for _ in range(warm):
             ctx.analyze_batch_dev(dev, off, m)
@@ -325,8 +326,8 @@ def main():
                     "config": {"workload": "config3", "windows": len(wins), "tokens": total, "min_len": m,
                                "description": ("4096 windows, lengths log-uniform 256..65536, loop bodies 10..500, "
                                                "alphabet 2^12, 5 percent substitutions; per step the windows are "
-                                               "split into {} groups of about equal tokens, each one packed "
-                                               "sync-free launch sequence on its own stream").format(args.lanes),
+                                               "split into {} groups of about equal tokens, each analysed "
+                                               "on its own stream").format(args.lanes),
                                "lanes": args.lanes},
                     "counters": ctx.counters(), "rows": int(res[1][-1]), "tuned": tuned})
         rf = roofline(kprof, steps, "config3", args.lanes)

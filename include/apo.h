@@ -127,12 +127,13 @@ int apo_analyze_batch_dev(apo_ctx *ctx, const uint64_t *d_tokens, const uint64_t
 
 /* Batches are split into `lanes` (1..4, default 3) groups of consecutive
  * windows with about equal token counts, analysed concurrently on separate
- * streams and workspaces (lane 0 uses the caller's stream); results are
- * identical for every value.  With more than one lane, batch calls do not
- * use graph capture.  APO_EINVAL outside 1..4. */
+ * streams, workspaces and host threads (lane 0 uses the caller's stream),
+ * each lane host-driven (launches sized from device counts read between
+ * stages); results are identical for every value.  With more than one lane,
+ * batch calls do not use graph capture.  APO_EINVAL outside 1..4. */
 int apo_set_lanes(apo_ctx *ctx, int lanes);
 
-/* Batched analyses enqueue their whole launch sequence without host
+/* Batches on one lane enqueue their whole launch sequence without host
  * synchronisation (round counts bounded by the longest window) and, when
  * enabled (default), record it as a HIP graph that is replayed for later
  * batches of the same shape (same token pointer, total length, window count,

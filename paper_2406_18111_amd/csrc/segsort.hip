@@ -22,6 +22,12 @@ namespace apo {
 
 enum { MODE_SA = 0, MODE_PLAIN = 1 };
 
+// Buffer b of the key/value pairs.  A per-lane index into the kernel
+// argument's pointer array would be a dependent global load; selecting
+// between the two pointers (scalar kernel-argument loads) avoids it.
+__device__ __forceinline__ uint32_t *key_buf(const SortBufs &B, int b) { return b ? B.key[1] : B.key[0]; }
+__device__ __forceinline__ uint32_t *val_buf(const SortBufs &B, int b) { return b ? B.val[1] : B.val[0]; }
+
 // ------------------------------------------------------------------ resets
 __global__ void k_round_begin(SortCounters *c, int cur) {
   const int nxt = cur ^ 1;
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
         if (idx < len) {
           const int b = (u.len & kBufBit) ? 1 : 0;
           const uint32_t p = u.start + idx;
-          v = ((uint64_t)B.key[b][p] << 32) | B.val[b][p];
+          v = ((uint64_t)key_buf(B, b)[p] << 32) | val_buf(B, b)[p];
         }
       }
       d[s] = v;
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankO
       if (j < nbk[k] && idx < (u.len & kLenMask)) {
         const int bb = (u.len & kBufBit) ? 1 : 0;
         const uint32_t p = u.start + idx;
-        vk[k] = ((uint64_t)B.key[bb][p] << 32) | B.val[bb][p];
+        vk[k] = ((uint64_t)key_buf(B, bb)[p] << 32) | val_buf(B, bb)[p];
       }
     }
 #pragma unroll
@@ -652,8 +658,8 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
           const Unit u = ud[lo];
           const int b = (u.len & kBufBit) ? 1 : 0;
           const uint32_t g = u.start + (p - uoff[lo]);
-          kq[q] = B.key[b][g];
-          vq[q] = B.val[b][g];
+          kq[q] = key_buf(B, b)[g];
+          vq[q] = val_buf(B, b)[g];
           jq[q] = lo;
         }
       }
@@ -831,7 +837,7 @@ __global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level
     digit_params(bu.meta & 0xFFu, B.digit_bits, shift, mask);
     const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
-    const uint32_t *key = B.key[(bu.meta & kMetaAlt) ? 1 : 0];
+    const uint32_t *key = key_buf(B, (bu.meta & kMetaAlt) ? 1 : 0);
     for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
       agg_add(&h[(key[p] >> shift) & mask], 1u);
     __syncthreads();
@@ -969,8 +975,8 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
     for (int q = 0; q < PER; q++) {
       const uint32_t p = lo + threadIdx.x + q * NT;
       if (p < hi) {
-        kk[q] = B.key[sb][p];
-        vv[q] = B.val[sb][p];
+        kk[q] = key_buf(B, sb)[p];
+        vv[q] = val_buf(B, sb)[p];
         oo[q] = agg_inc(&cnt[(kk[q] >> shift) & mask]);
       }
     }
@@ -985,8 +991,8 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
       const uint32_t p = lo + threadIdx.x + q * NT;
       if (p < hi) {
         const uint32_t dst = cnt[(kk[q] >> shift) & mask] + oo[q];
-        B.key[db][dst] = kk[q];
-        B.val[db][dst] = vv[q];
+        key_buf(B, db)[dst] = kk[q];
+        val_buf(B, db)[dst] = vv[q];
       }
     }
     __syncthreads();
@@ -1019,7 +1025,7 @@ __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, ui
     for (int q = 0; q < PER; q++) {
       const uint32_t p = lo + threadIdx.x + q * NT;
       if (p < hi) {
-        const uint32_t v = B.val[alt ? 1 : 0][p];
+        const uint32_t v = val_buf(B, alt ? 1 : 0)[p];
         if (alt) B.val[0][p] = v;
         if (MODE == MODE_SA) {
           R.rank[v] = bu.start + 1;

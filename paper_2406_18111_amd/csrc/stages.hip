@@ -469,16 +469,16 @@ __device__ __forceinline__ int64_t last_below(const uint32_t *L, uint64_t lo, ui
 // entries left of the bound at each level, climbing while nothing below l is
 // found, then descends to the rightmost qualifying leaf.  Each step is one
 // block read; near answers (the common case) take one or two.
-__device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
+__device__ int64_t psv_query(const uint32_t *const *lv, const uint64_t *sz, int nlev, uint64_t i, uint32_t l) {
   uint64_t pos = i;  // exclusive bound at level `lev`: its entries below pos cover [0, i)
   int lev = 0;
   int64_t found;
   for (;;) {
     if (pos == 0) return -1;
     const uint64_t lo = (pos - 1) / kMinFan * kMinFan;
-    found = last_below(M.lv[lev], lo, pos, l);
+    found = last_below(lv[lev], lo, pos, l);
     if (found >= 0) break;
-    if (lev + 1 < M.nlev) {
+    if (lev + 1 < nlev) {
       pos = lo / kMinFan;
       lev++;
     } else {
@@ -488,7 +488,7 @@ __device__ int64_t psv_query(const MinLevels &M, uint64_t i, uint32_t l) {
   while (lev > 0) {
     lev--;
     const uint64_t lo = (uint64_t)found * kMinFan;
-    found = last_below(M.lv[lev], lo, min(lo + kMinFan, M.sz[lev]), l);  // found: the parent minimum is < l
+    found = last_below(lv[lev], lo, min(lo + kMinFan, sz[lev]), l);  // found: the parent minimum is < l
     if (found < 0) return -1;
   }
   return found;
@@ -509,21 +509,38 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
   __shared__ uint32_t bmax;
+  // level pointers in LDS: per-lane indexing of the kernel argument would
+  // cost a dependent global load per level step
+  __shared__ const uint32_t *slv[kMinLevels];
+  __shared__ uint64_t ssz[kMinLevels];
   if (threadIdx.x == 0) bmax = 0;
+  if (threadIdx.x < kMinLevels) {
+    slv[threadIdx.x] = M.lv[threadIdx.x];
+    ssz[threadIdx.x] = M.sz[threadIdx.x];
+  }
+  __syncthreads();
   uint32_t mymax = 0;
   const uint64_t span = (uint64_t)blockDim.x * kCandItems;
   for (uint64_t i0 = (uint64_t)blockIdx.x * span; i0 < n; i0 += (uint64_t)gridDim.x * span) {
+    const uint64_t ib = i0 + (uint64_t)threadIdx.x * kCandItems;  // a thread's pairs are consecutive
+    // every input of the thread's pairs is loaded before any is used
+    uint32_t S[kCandItems + 1], P[kCandItems], WE[kCandItems];
+#pragma unroll
+    for (int k = 0; k <= kCandItems; k++) S[k] = ib + k < n ? sa[ib + k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kCandItems; k++) {
+      P[k] = ib + k < n ? lcp[ib + k] : 0u;
+      WE[k] = (wend && ib + k < n) ? wend[ib + k] : (uint32_t)n;
+    }
     uint32_t L[kCandItems], A[kCandItems], B[kCandItems], I[kCandItems];
     uint32_t mine = 0;
 #pragma unroll
     for (int k = 0; k < kCandItems; k++) {
-      const uint64_t i = i0 + (uint64_t)threadIdx.x * kCandItems + k;  // a thread's pairs are consecutive
+      const uint64_t i = ib + k;
       L[k] = 0;
       A[k] = B[k] = I[k] = 0;
-      if (i + 1 >= n) continue;
-      const uint32_t we = wend ? wend[i] : (uint32_t)n;
-      if (i + 1 >= we) continue;
-      const uint32_t s1 = sa[i], s2 = sa[i + 1], p = lcp[i];
+      if (i + 1 >= n || i + 1 >= WE[k]) continue;
+      const uint32_t s1 = S[k], s2 = S[k + 1], p = P[k];
       const uint32_t lo = min(s1, s2), hi = max(s1, s2);
       uint32_t l, a, b;
       if (lo + p <= hi) {
@@ -536,7 +553,7 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
       }
       if (l >= min_len) {  // min_len >= 1, so L[k] != 0 marks an emitted pair
         L[k] = l; A[k] = a; B[k] = b;
-        I[k] = (uint32_t)(psv_query(M, i, l) + 1);
+        I[k] = (uint32_t)(psv_query(slv, ssz, M.nlev, i, l) + 1);
         mine += 2;
         mymax = max(mymax, l);
       }

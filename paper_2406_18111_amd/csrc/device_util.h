@@ -5,6 +5,10 @@
 
 namespace apo {
 
+// LDS index with one skew word per 16: threads that each walk 16
+// consecutive words then hit different banks.
+__host__ __device__ constexpr int pad16(int p) { return p + (p >> 4); }
+
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -105,6 +109,23 @@ __device__ __forceinline__ uint32_t agg_inc(uint32_t *ctr) {
 }
 
 // Same, when only the total matters.
+// atomicAdd(ctr, v) for every active lane, one atomic per distinct address
+// among the wavefront's active lanes (v must agree among lanes that share an
+// address).  For counters that a few addresses share per wavefront.
+__device__ __forceinline__ void agg_add_any(uint32_t *ctr, uint32_t v) {
+  uint64_t todo = __ballot(1);
+  const int lane = __lane_id();
+  const uint64_t mine = reinterpret_cast<uintptr_t>(ctr);
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint64_t la = ((uint64_t)(uint32_t)__shfl((int)(mine >> 32), leader, 64) << 32) |
+                        (uint32_t)__shfl((int)(uint32_t)mine, leader, 64);
+    const uint64_t grp = __ballot(mine == la) & todo;
+    if (lane == leader) atomicAdd(ctr, v * (uint32_t)__popcll(grp));
+    todo &= ~grp;
+  }
+}
+
 __device__ __forceinline__ void agg_add(uint32_t *ctr, uint32_t v) {
   const uint64_t active = __ballot(1);
   const int lane = __lane_id();

@@ -375,9 +375,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const uint32_t *cd[3] = {dc + CNT_MAXL, nullptr, nullptr};
     const int bb[3] = {bit_length_u64(maxl_bound), (int)rank_bits, (int)rank_bits};
     sort_plain(w, dc + CNT_C, c_bound, f, str, sub, cd, bb, 3, w.keep, s);
-    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.crec, w.s_len,
-                   w.s_start, w.s_id,
-                   w.tmp_a, w.tmp_b, w.tile_tmp, dc + CNT_M, s);
+    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.crec, w.s_len, w.s_start, w.s_id, w.tile_tmp,
+                   dc + CNT_M, s);
     m_bound = c_bound;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;
@@ -452,8 +451,8 @@ int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t
   fill_u32(dc + CNT_NROWS, 1, 0, s);
   if (batch) fill_u32(w.win_rows, W + 1, 0, s);
   if (m_bound == 0) return 0;
-  gather_accepted(w.state, dc + CNT_M, m_bound, w.s_len, w.s_start, w.s_id, w.o_len, w.o_start, w.o_id, w.tmp_a,
-                  w.tmp_b, w.tile_tmp, dc + CNT_A, s);
+  gather_accepted(w.state, dc + CNT_M, m_bound, w.s_len, w.s_start, w.s_id, w.o_len, w.o_start, w.o_id, w.tile_tmp,
+                  dc + CNT_A, s);
   uint64_t a_bound = std::min<uint64_t>(m_bound, N);
   if (host) {
     if ((rc = read_counters(w, s))) return rc;
@@ -472,7 +471,7 @@ int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t
     sort_plain(w, dc + CNT_A, a_bound, f, str, sub, cd, bb, 2, nullptr, s);
     order = B.val[0];
   }
-  emit_rows(order, dc + CNT_A, a_bound, w.o_len, w.o_start, w.o_id, wid, wbeg, w.tmp_a, w.rowidx, w.row_first, w.rows,
+  emit_rows(order, dc + CNT_A, a_bound, w.o_len, w.o_start, w.o_id, wid, wbeg ? w.d_off : nullptr, w.tmp_a, w.rowidx, w.row_first, w.rows,
             w.occ, batch ? w.win_rows : nullptr, w.tile_tmp, dc + CNT_NROWS, s);
   return 0;
 }

@@ -141,11 +141,30 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
     c->lds_elems = 0;
   }
   if (B.ctr->act_cnt[cur] == 0) return;  // nothing grouped: a round launched past the last one
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
-    if (!aflag[p]) continue;
-    const uint32_t x = B.val[0][p] + h;
+  // four consecutive slots per thread: flags, suffixes and window ends are
+  // single 4- and 16-byte loads and the four partner-rank reads are issued
+  // together.  Keys of slots no longer grouped are never read (only units
+  // are sorted), so all four keys go out as one 16-byte store.
+  const uint32_t *val = B.val[0];
+  uint32_t *key = B.key[0];
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t n4 = n / 4;
+  for (uint64_t q = gid; q < n4; q += stride) {
+    const uint32_t fl = reinterpret_cast<const uint32_t *>(aflag)[q];
+    if (!fl) continue;
+    const uint4 v = reinterpret_cast<const uint4 *>(val)[q];
+    const uint4 we = slot_wend ? reinterpret_cast<const uint4 *>(slot_wend)[q] : make_uint4(n, n, n, n);
+    const uint32_t x[4] = {v.x + h, v.y + h, v.z + h, v.w + h}, e[4] = {we.x, we.y, we.z, we.w};
+    uint32_t k[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) k[u] = (((fl >> (8 * u)) & 0xFFu) && x[u] < e[u]) ? rank[x[u]] : 0u;
+    reinterpret_cast<uint4 *>(key)[q] = make_uint4(k[0], k[1], k[2], k[3]);
+  }
+  const uint64_t p = 4 * n4 + gid;  // the last n mod 4 slots
+  if (p < n && aflag[p]) {
+    const uint32_t x = val[p] + h;
     const uint32_t we = slot_wend ? slot_wend[p] : n;
-    B.key[0][p] = x < we ? rank[x] : 0u;
+    key[p] = x < we ? rank[x] : 0u;
   }
 }
 
@@ -153,10 +172,24 @@ __global__ void k_gather_field(SortBufs B, int cur, const uint32_t *field, int s
                                int sub, const uint32_t *c_dev, uint32_t c) {
   const uint32_t cnt = all_dev ? *all_dev : B.ctr->act_cnt[cur];
   if (c_dev) c = *c_dev;
-  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) {
-    const uint32_t p = all_dev ? q : B.act[cur][q];
-    const uint32_t f = field[(uint64_t)B.val[0][p] * stride];
-    B.key[0][p] = sub ? c - f : f;
+  // four entries per thread, each step's loads issued together
+  const uint32_t *act = B.act[cur], *val = B.val[0];
+  uint32_t *key = B.key[0];
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < cnt; b0 += step) {
+    uint32_t p[4], v[4], f[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t q = b0 + (uint64_t)u * blockDim.x + threadIdx.x;  // coalesced for each u
+      p[u] = q < cnt ? (all_dev ? (uint32_t)q : act[q]) : ~0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) v[u] = p[u] != ~0u ? val[p[u]] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; u++) f[u] = p[u] != ~0u ? field[(uint64_t)v[u] * stride] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (p[u] != ~0u) key[p[u]] = sub ? c - f[u] : f[u];
   }
 }
 
@@ -1137,8 +1170,8 @@ void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, 
 
 void SortEngine::gather_field(int cur, const uint32_t *field, int stride, const uint32_t *all_dev, int sub,
                               const uint32_t *c_dev, uint32_t c, uint64_t bound, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_field, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, cur, field, stride, all_dev, sub,
-                     c_dev, c);
+  hipLaunchKernelGGL(k_gather_field, grid_for((bound + 3) / 4, 256, 4096), dim3(256), 0, s, b_, cur, field, stride,
+                     all_dev, sub, c_dev, c);
 }
 
 void SortEngine::iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s) {

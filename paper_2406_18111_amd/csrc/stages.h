@@ -44,8 +44,7 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
                     uint32_t *maxl, hipStream_t s);
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
-                    const uint32_t *crec, uint32_t *s_len,
-                    uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags, uint32_t *tmp_pos, uint32_t *tile_tmp,
+                    const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s);
 
 // Empties the levels of a selection sparse table that a run can use.
@@ -66,9 +65,9 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
 
 void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
                      const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,
-                     uint32_t *tmp_f, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+                     uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
 void emit_rows(const uint32_t *order, const uint32_t *a_dev, uint64_t bound, const uint32_t *o_len,
-               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f,
+               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint64_t *woff, uint32_t *f,
                uint32_t *rowidx, uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
                uint32_t *nrows, hipStream_t s);
 void window_of_occ(const uint32_t *o_start, const uint32_t *wid, const uint32_t *a_dev, uint64_t bound, uint32_t *out,

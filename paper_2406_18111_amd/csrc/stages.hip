@@ -100,6 +100,91 @@ void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_
   hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanNT), 0, s, in, n_dev, tile_tmp, out);
 }
 
+// ---------------------------------------------------- byte-flag compaction
+// Stream compaction over a byte array with a predicate: per-tile counts, a
+// scan of the tile counts, then each thread takes kScanPer consecutive flags
+// (one 16-byte load) and scans its count across the workgroup; the output
+// positions go through LDS so that the gather act.get(k) / act.put(o, rec)
+// runs with consecutive threads on consecutive entries.  No flag or position
+// array is written to global memory.
+struct FlagNonZero {
+  __device__ bool operator()(uint8_t x) const { return x != 0; }
+};
+struct FlagIsOne {
+  __device__ bool operator()(uint8_t x) const { return x == 1; }
+};
+
+template <class P>
+__device__ __forceinline__ uint32_t flag_mask16(const uint8_t *f, uint64_t base, uint64_t n, P pred) {
+  static_assert(kScanPer == 16, "one 16-byte load per thread");
+  uint32_t mask = 0;
+  if (base + 16 <= n) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(f + base);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int b = 0; b < 16; b++)
+      if (pred((uint8_t)(w[b >> 2] >> (8 * (b & 3))))) mask |= 1u << b;
+  } else {
+    for (int b = 0; b < 16; b++)
+      if (base + b < n && pred(f[base + b])) mask |= 1u << b;
+  }
+  return mask;
+}
+
+template <class P>
+__global__ __launch_bounds__(kScanNT) void k_flag_tiles(const uint8_t *f, P pred, const uint32_t *n_dev,
+                                                        uint32_t *tile_sum) {
+  __shared__ uint32_t sh[kScanNT / 64];
+  const uint64_t n = *n_dev;
+  if ((uint64_t)blockIdx.x * kScanTile >= n && blockIdx.x > 0) return;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+  const uint32_t loc = base < n ? (uint32_t)__popc(flag_mask16(f, base, n, pred)) : 0u;
+  uint32_t tot;
+  (void)block_excl_sum<kScanNT>(loc, sh, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+template <class P, class A>
+__global__ __launch_bounds__(kScanNT) void k_flag_compact(const uint8_t *f, P pred, const uint32_t *n_dev,
+                                                          const uint32_t *tile_sum, A act) {
+  __shared__ uint32_t sh[kScanNT / 64];
+  __shared__ uint32_t opos[pad16(kScanTile)];  // output position of each flagged entry of the tile, else ~0
+  const uint64_t n = *n_dev;
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kScanTile;
+  if (tile0 >= n) return;
+  const int first = threadIdx.x * kScanPer;
+  const uint64_t base = tile0 + first;
+  const uint32_t mask = base < n ? flag_mask16(f, base, n, pred) : 0u;
+  uint32_t tot;
+  uint32_t o = block_excl_sum<kScanNT>((uint32_t)__popc(mask), sh, &tot) + tile_sum[blockIdx.x];
+#pragma unroll
+  for (int b = 0; b < kScanPer; b++) opos[pad16(first + b)] = ((mask >> b) & 1u) ? o++ : ~0u;
+  __syncthreads();
+  // gather with consecutive threads on consecutive entries, every load of
+  // the thread's entries issued before any store
+  typename A::Rec rec[kScanPer];
+  uint32_t dst[kScanPer];
+#pragma unroll
+  for (int q = 0; q < kScanPer; q++) {
+    const int e = q * kScanNT + threadIdx.x;
+    dst[q] = tile0 + e < n ? opos[pad16(e)] : ~0u;
+    if (dst[q] != ~0u) rec[q] = act.get(tile0 + e);
+  }
+#pragma unroll
+  for (int q = 0; q < kScanPer; q++)
+    if (dst[q] != ~0u) act.put(dst[q], rec[q]);
+}
+
+// *total receives the number of flagged entries.
+template <class P, class A>
+static void flag_compact(const uint8_t *f, P pred, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
+                         uint32_t *total, A act, hipStream_t s) {
+  const uint32_t tiles = (uint32_t)std::max<uint64_t>((bound + kScanTile - 1) / kScanTile, 1);
+  hipLaunchKernelGGL((k_flag_tiles<P>), dim3(tiles), dim3(kScanNT), 0, s, f, pred, n_dev, tile_tmp);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, tile_tmp, n_dev, total);
+  hipLaunchKernelGGL((k_flag_compact<P, A>), dim3(tiles), dim3(kScanNT), 0, s, f, pred, n_dev, tile_tmp, act);
+}
+
 __global__ void k_fill_u8_dev(uint8_t *p, const uint32_t *n_dev, uint8_t v) {
   const uint64_t n = *n_dev;
   GRID_STRIDE(i, n) p[i] = v;
@@ -213,16 +298,39 @@ __global__ void k_hash_assign(const uint32_t *sorted_d, const uint32_t *nd, cons
   GRID_STRIDE(q, m) slot_rank[dist_slot[sorted_d[q]]] = (uint32_t)q + 1u;
 }
 
+// Four tokens per thread: the first probes and the rank reads of the four
+// are issued together (further probes are rare at load <= 1/2).
 __global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const unsigned long long *tab, uint64_t mask,
                               const uint32_t *slot_rank, uint32_t *out) {
-  GRID_STRIDE(i, n) {
-    const uint64_t key = tok[i];
-    uint64_t h = mask + 1;
-    if (key != kEmpty) {
-      h = mix64(key) & mask;
-      while (tab[h] != key) h = (h + 1) & mask;  // every token was inserted
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
+    uint64_t key[4], h[4], t[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      key[u] = i < n ? tok[i] : kEmpty;
     }
-    out[i] = slot_rank[h];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      h[u] = key[u] != kEmpty ? mix64(key[u]) & mask : mask + 1;  // the empty key has its own slot
+      t[u] = key[u] != kEmpty ? tab[h[u]] : kEmpty;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if (key[u] == kEmpty) continue;
+      while (t[u] != key[u]) {  // every token was inserted
+        h[u] = (h[u] + 1) & mask;
+        t[u] = tab[h[u]];
+      }
+    }
+    uint32_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) r[u] = slot_rank[h[u]];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      if (i < n) out[i] = r[u];
+    }
   }
 }
 
@@ -252,7 +360,7 @@ void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *d
 }
 void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t mask, const uint32_t *slot_rank,
                  uint32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_hash_lookup, grid_for(n, 256, 8192), dim3(256), 0, s, tok, n,
+  hipLaunchKernelGGL(k_hash_lookup, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, tok, n,
                      reinterpret_cast<const unsigned long long *>(tab), mask, slot_rank, out);
 }
 
@@ -313,7 +421,6 @@ constexpr int kSeedGroup = 8;
 constexpr int kPlcpChunk = 8;                        // positions per thread
 constexpr int kPlcpSpan = 256 * kPlcpChunk;          // positions per workgroup pass
 constexpr int kPlcpMargin = 256;                     // staged tokens past the span
-__host__ __device__ constexpr int pad16(int p) { return p + (p >> 4); }  // one bank skew per chunk
 
 // lcp(x, y) from scratch.  The levels at which both suffixes were still
 // grouped (below both fin values) are probed kSeedGroup at a time with
@@ -417,10 +524,27 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
   }
 }
 
+// Four pairs per thread (strided by the block size, so each load is
+// coalesced); the four PLCP reads are issued together.
 __global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, const uint32_t *plcp, uint32_t *lcp) {
-  GRID_STRIDE(i, n) {
-    const uint32_t we = wend ? wend[i] : (uint32_t)n;
-    lcp[i] = (i + 1 < we) ? plcp[sa[i + 1]] : 0u;
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
+    uint32_t nx[4], v[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;  // coalesced for each u
+      const uint32_t we = (wend && i < n) ? wend[i] : (uint32_t)n;
+      ok[u] = i + 1 < we;
+      nx[u] = ok[u] ? sa[i + 1] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) v[u] = ok[u] ? plcp[nx[u]] : 0u;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      if (i < n) lcp[i] = v[u];
+    }
   }
 }
 
@@ -430,7 +554,7 @@ void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint3
   const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
   hipLaunchKernelGGL(k_plcp, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(nspan, 1), 8192)), dim3(256), 0, s,
                      sa, rank, n, wbeg, wend, snap, fin, key0, top, plcp);
-  hipLaunchKernelGGL(k_lcp, grid_for(n, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
+  hipLaunchKernelGGL(k_lcp, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
 }
 
 // ------------------------------------------------------------ candidates
@@ -599,30 +723,21 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
-__global__ void k_gather_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *pos, const uint32_t *m_dev,
-                                const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id) {
-  const uint64_t m = *m_dev;
-  GRID_STRIDE(k, m) {
-    if (keep[k]) {
-      const uint32_t o = pos[k];
-      const uint32_t *r = crec + kCandWords * (uint64_t)order[k];
-      s_len[o] = r[0]; s_start[o] = r[1]; s_id[o] = r[2];
-    }
+struct GatherSorted {
+  using Rec = uint3;
+  const uint32_t *order, *crec;
+  uint32_t *s_len, *s_start, *s_id;
+  __device__ Rec get(uint64_t k) const {
+    const uint32_t *r = crec + kCandWords * (uint64_t)order[k];
+    return make_uint3(r[0], r[1], r[2]);
   }
-}
-
-__global__ void k_u8_to_u32(const uint8_t *a, const uint32_t *n_dev, uint32_t *b) {
-  const uint64_t n = *n_dev;
-  GRID_STRIDE(i, n) b[i] = a[i];
-}
+  __device__ void put(uint32_t o, Rec r) const { s_len[o] = r.x; s_start[o] = r.y; s_id[o] = r.z; }
+};
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
-                    const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tmp_flags,
-                    uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
-  hipLaunchKernelGGL(k_u8_to_u32, grid_for(bound, 256, 8192), dim3(256), 0, s, keep, m_dev, tmp_flags);
-  scan_excl(tmp_flags, tmp_pos, m_dev, bound, tile_tmp, total, s);
-  hipLaunchKernelGGL(k_gather_sorted, grid_for(bound, 256, 8192), dim3(256), 0, s, order, keep, tmp_pos, m_dev, crec,
-                     s_len, s_start, s_id);
+                    const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,
+                    uint32_t *total, hipStream_t s) {
+  flag_compact(keep, FlagNonZero{}, m_dev, bound, tile_tmp, total, GatherSorted{order, crec, s_len, s_start, s_id}, s);
 }
 
 // ------------------------------------------------------------- selection
@@ -747,16 +862,37 @@ __global__ void k_sel_filter(SelArgs a) {
 __global__ void k_sel_insert(SelArgs a) {
   if (!sel_run_dense(a)) return;
   const uint32_t m = sel_nwork(a);
-  GRID_STRIDE(q, m) {
-    const uint32_t k = a.work[q];
-    const uint32_t l = a.len[k], s = a.start[k];
-    const int j = 31 - __clz((int)l);
-    uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
-    // values only decrease: skip the atomic when a smaller priority is already
-    // there (long candidates of periodic runs share block positions)
-    uint32_t *p1 = &Tj[s], *p2 = &Tj[s + l - (1u << j)];
-    if (*p1 > k) atomicMin(p1, k);
-    if (*p2 > k) atomicMin(p2, k);
+  // four working candidates per thread, each step's loads issued together
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < m; b0 += step) {
+    uint32_t k[4], l[4], st[4], t1[4], t2[4];
+    uint32_t *p1[4], *p2[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t q = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      k[u] = q < m ? a.work[q] : kInf;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      l[u] = k[u] != kInf ? a.len[k[u]] : 1u;
+      st[u] = k[u] != kInf ? a.start[k[u]] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int j = 31 - __clz((int)l[u]);
+      uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
+      p1[u] = &Tj[st[u]];
+      p2[u] = &Tj[st[u] + l[u] - (1u << j)];
+      // values only decrease: skip the atomic when a smaller priority is
+      // already there (long candidates of periodic runs share block positions)
+      t1[u] = k[u] != kInf ? *p1[u] : 0u;
+      t2[u] = k[u] != kInf ? *p2[u] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if (t1[u] > k[u]) atomicMin(p1[u], k[u]);
+      if (t2[u] > k[u]) atomicMin(p2[u], k[u]);
+    }
   }
 }
 
@@ -1052,30 +1188,19 @@ void interval_counts(const uint32_t *len, const uint32_t *start, const uint32_t 
 }
 
 // ---------------------------------------------------------------- output
-__global__ void k_acc_flags(const uint8_t *state, const uint32_t *m_dev, uint32_t *f) {
-  const uint64_t m = *m_dev;
-  GRID_STRIDE(k, m) f[k] = state[k] == 1;
-}
-
-__global__ void k_acc_gather(const uint8_t *state, const uint32_t *pos, const uint32_t *m_dev, const uint32_t *len,
-                             const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start,
-                             uint32_t *o_id) {
-  const uint64_t m = *m_dev;
-  GRID_STRIDE(k, m) {
-    if (state[k] == 1) {
-      const uint32_t o = pos[k];
-      o_len[o] = len[k]; o_start[o] = start[k]; o_id[o] = id[k];
-    }
-  }
-}
+struct GatherAccepted {
+  using Rec = uint3;
+  const uint32_t *len, *start, *id;
+  uint32_t *o_len, *o_start, *o_id;
+  __device__ Rec get(uint64_t k) const { return make_uint3(len[k], start[k], id[k]); }
+  __device__ void put(uint32_t o, Rec r) const { o_len[o] = r.x; o_start[o] = r.y; o_id[o] = r.z; }
+};
 
 void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
                      const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,
-                     uint32_t *tmp_f, uint32_t *tmp_pos, uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
-  hipLaunchKernelGGL(k_acc_flags, grid_for(bound, 256, 8192), dim3(256), 0, s, state, m_dev, tmp_f);
-  scan_excl(tmp_f, tmp_pos, m_dev, bound, tile_tmp, total, s);
-  hipLaunchKernelGGL(k_acc_gather, grid_for(bound, 256, 8192), dim3(256), 0, s, state, tmp_pos, m_dev, len, start, id,
-                     o_len, o_start, o_id);
+                     uint32_t *tile_tmp, uint32_t *total, hipStream_t s) {
+  flag_compact(state, FlagIsOne{}, m_dev, bound, tile_tmp, total, GatherAccepted{len, start, id, o_len, o_start, o_id},
+               s);
 }
 
 // Occurrence o (in final order: window, then priority) opens a row when its
@@ -1098,20 +1223,27 @@ __global__ void k_row_flags(const uint32_t *order, const uint32_t *a_dev, const 
 struct OutRow { uint32_t start, length, count; };
 struct OutOcc { uint32_t start, length, cand; };
 
+// woff: window offsets (window w starts at position woff[w]; null for one
+// window).  Rows come in window order, so a wavefront's new rows fall into one
+// or two windows and their per-window counts are added once per window.
 __global__ void k_emit(const uint32_t *order, const uint32_t *a_dev, const uint32_t *o_len, const uint32_t *o_start,
-                       const uint32_t *wid, const uint32_t *wbeg_of_pos, const uint32_t *f, const uint32_t *rowidx,
+                       const uint32_t *wid, const uint64_t *woff, const uint32_t *f, const uint32_t *rowidx,
                        uint32_t *row_first, OutRow *rows, OutOcc *occ, uint32_t *win_rows) {
   const uint64_t a = *a_dev;
-  GRID_STRIDE(o, a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t o0 = (uint64_t)blockIdx.x * blockDim.x; o0 < a; o0 += stride) {  // wavefront-uniform trip count
+    const uint64_t o = o0 + threadIdx.x;
+    if (o >= a) continue;
     const uint32_t c = order ? order[o] : (uint32_t)o;
     const uint32_t r = rowidx[o] + f[o] - 1u;  // row of this occurrence (inclusive count - 1)
     const uint32_t st = o_start[c];
-    const uint32_t rel = st - (wbeg_of_pos ? wbeg_of_pos[st] : 0u);
+    const uint32_t w = wid ? wid[st] : 0u;
+    const uint32_t rel = st - (woff ? (uint32_t)woff[w] : 0u);
     if (f[o]) {
       row_first[r] = (uint32_t)o;
       rows[r].start = rel;
       rows[r].length = o_len[c];
-      if (win_rows) atomicAdd(&win_rows[wid ? wid[st] : 0u], 1u);
+      if (win_rows) agg_add_any(&win_rows[w], 1u);
     }
     if (occ) { occ[o].start = rel; occ[o].length = o_len[c]; occ[o].cand = r; }
   }
@@ -1127,13 +1259,13 @@ __global__ void k_row_counts(const uint32_t *row_first, const uint32_t *nrows_de
 }
 
 void emit_rows(const uint32_t *order, const uint32_t *a_dev, uint64_t bound, const uint32_t *o_len,
-               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint32_t *wbeg, uint32_t *f,
+               const uint32_t *o_start, const uint32_t *o_id, const uint32_t *wid, const uint64_t *woff, uint32_t *f,
                uint32_t *rowidx, uint32_t *row_first, void *rows, void *occ, uint32_t *win_rows, uint32_t *tile_tmp,
                uint32_t *nrows, hipStream_t s) {
   hipLaunchKernelGGL(k_row_flags, grid_for(bound, 256, 8192), dim3(256), 0, s, order, a_dev, o_len, o_start, o_id, wid,
                      f);
   scan_excl(f, rowidx, a_dev, bound, tile_tmp, nrows, s);
-  hipLaunchKernelGGL(k_emit, grid_for(bound, 256, 8192), dim3(256), 0, s, order, a_dev, o_len, o_start, wid, wbeg, f,
+  hipLaunchKernelGGL(k_emit, grid_for(bound, 256, 8192), dim3(256), 0, s, order, a_dev, o_len, o_start, wid, woff, f,
                      rowidx, row_first, (OutRow *)rows, (OutOcc *)occ, win_rows);
   hipLaunchKernelGGL(k_row_counts, grid_for(bound, 256, 8192), dim3(256), 0, s, row_first, nrows, a_dev,
                      (OutRow *)rows);

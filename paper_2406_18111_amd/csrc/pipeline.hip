@@ -219,7 +219,7 @@ static void stamp(Workspace &w, int k, hipStream_t s, bool on) {
 static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
   info.n = N;
   info.sigma = w.hcnt[CNT_ND];
-  info.cands = w.hcnt[CNT_C];
+  info.cands = w.hcnt[CNT_C] + w.hcnt[CNT_CSKIP];
   info.maxl = w.hcnt[CNT_MAXL];
   info.cands_dedup = w.hcnt[CNT_M];
   info.accepted = w.hcnt[CNT_A];
@@ -357,8 +357,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   if (stop == Stop::LCP) return read_counters(w, s);
 
   // ---- candidates
-  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.crec,
-                 dc + CNT_C, dc + CNT_MAXL, s);
+  gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.crec, dc + CNT_C, dc + CNT_CSKIP, dc + CNT_MAXL,
+                 s);
   uint64_t c_bound = 2 * N;
   uint64_t maxl_bound = std::max<uint64_t>(maxwin / 2, 1);
   if (host) {

@@ -38,10 +38,13 @@ void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint3
                uint32_t *lcp, hipStream_t s);
 
 // Candidates are written as records of kCandWords words: length, start, ID.
+// *cnt counts the records written; a candidate that exactly repeats one of
+// the previous pair (both pairs in the disjoint branch with equal LCP: same
+// length, same start SA[i], same ID) is not written and counts in *skipped.
 constexpr int kCandWords = 3;
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend,
                     uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt,
-                    uint32_t *maxl, hipStream_t s);
+                    uint32_t *skipped, uint32_t *maxl, hipStream_t s);
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
                     const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,

@@ -621,54 +621,68 @@ __device__ int64_t psv_query(const uint32_t *const *lv, const uint64_t *sz, int 
 // Loop body of the paper's candidate pass for every adjacent pair i (both
 // suffixes in one window): disjoint branch -> (p, s1), (p, s2); overlap branch
 // -> l = floor((p+d)/2) - remainder mod d, at base and base+l.  Candidates
-// with l >= min_len are appended with their substring ID.  A workgroup takes
-// kCandItems consecutive pairs per thread per pass, so output space is
-// reserved with one global atomic per 256 * kCandItems pairs, and the output
-// keeps suffix-array order within a pass.
+// with l >= min_len are appended with their substring ID.  When pairs i-1 and
+// i are both in the disjoint branch with LCP[i-1] == LCP[i], pair i's first
+// candidate (LCP[i], SA[i]) equals pair i-1's second one, ID included (no
+// LCP value between them is below the length), so it is counted but not
+// written: on loop streams this removes nearly all exact duplicates before
+// the sort.  A workgroup takes kCandItems consecutive pairs per thread per
+// pass, so output space is reserved with one global atomic per 256 *
+// kCandItems pairs, and the output keeps suffix-array order within a pass.
 constexpr int kCandItems = 8;
 
 __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
-                                                    uint32_t *crec, uint32_t *cnt, uint32_t *maxl) {
+                                                    uint32_t *crec, uint32_t *cnt, uint32_t *skipped,
+                                                    uint32_t *maxl) {
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
-  __shared__ uint32_t bmax;
+  __shared__ uint32_t bmax, bskip;
   // level pointers in LDS: per-lane indexing of the kernel argument would
   // cost a dependent global load per level step
   __shared__ const uint32_t *slv[kMinLevels];
   __shared__ uint64_t ssz[kMinLevels];
-  if (threadIdx.x == 0) bmax = 0;
+  if (threadIdx.x == 0) bmax = bskip = 0;
   if (threadIdx.x < kMinLevels) {
     slv[threadIdx.x] = M.lv[threadIdx.x];
     ssz[threadIdx.x] = M.sz[threadIdx.x];
   }
   __syncthreads();
-  uint32_t mymax = 0;
+  uint32_t mymax = 0, myskip = 0;
   const uint64_t span = (uint64_t)blockDim.x * kCandItems;
   for (uint64_t i0 = (uint64_t)blockIdx.x * span; i0 < n; i0 += (uint64_t)gridDim.x * span) {
     const uint64_t ib = i0 + (uint64_t)threadIdx.x * kCandItems;  // a thread's pairs are consecutive
-    // every input of the thread's pairs is loaded before any is used
-    uint32_t S[kCandItems + 1], P[kCandItems], WE[kCandItems];
+    // every input of the thread's pairs (and of the pair before them) is
+    // loaded before any is used; index 0 is pair ib - 1
+    uint32_t S[kCandItems + 2], P[kCandItems + 1], WE[kCandItems + 1];
 #pragma unroll
-    for (int k = 0; k <= kCandItems; k++) S[k] = ib + k < n ? sa[ib + k] : 0u;
-#pragma unroll
-    for (int k = 0; k < kCandItems; k++) {
-      P[k] = ib + k < n ? lcp[ib + k] : 0u;
-      WE[k] = (wend && ib + k < n) ? wend[ib + k] : (uint32_t)n;
+    for (int k = 0; k < kCandItems + 2; k++) {
+      const uint64_t i = ib + k - 1;
+      S[k] = (ib + k >= 1 && i < n) ? sa[i] : 0u;
     }
-    uint32_t L[kCandItems], A[kCandItems], B[kCandItems], I[kCandItems];
-    uint32_t mine = 0;
 #pragma unroll
-    for (int k = 0; k < kCandItems; k++) {
-      const uint64_t i = ib + k;
+    for (int k = 0; k < kCandItems + 1; k++) {
+      const uint64_t i = ib + k - 1;
+      const bool in = ib + k >= 1 && i < n;
+      P[k] = in ? lcp[i] : 0u;
+      WE[k] = (wend && in) ? wend[i] : (uint32_t)n;
+    }
+    uint32_t L[kCandItems + 1], A[kCandItems + 1], B[kCandItems + 1];
+    bool D[kCandItems + 1];  // pair in the disjoint branch with l >= min_len
+#pragma unroll
+    for (int k = 0; k < kCandItems + 1; k++) {
+      const uint64_t i = ib + k - 1;
       L[k] = 0;
-      A[k] = B[k] = I[k] = 0;
-      if (i + 1 >= n || i + 1 >= WE[k]) continue;
+      A[k] = B[k] = 0;
+      D[k] = false;
+      if (ib + k < 1 || i + 1 >= n || i + 1 >= WE[k]) continue;
       const uint32_t s1 = S[k], s2 = S[k + 1], p = P[k];
       const uint32_t lo = min(s1, s2), hi = max(s1, s2);
       uint32_t l, a, b;
+      bool disj = false;
       if (lo + p <= hi) {
         l = p; a = s1; b = s2;
+        disj = true;
       } else {
         const uint32_t d = hi - lo;
         l = (p + d) / 2;
@@ -677,10 +691,20 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
       }
       if (l >= min_len) {  // min_len >= 1, so L[k] != 0 marks an emitted pair
         L[k] = l; A[k] = a; B[k] = b;
-        I[k] = (uint32_t)(psv_query(slv, ssz, M.nlev, i, l) + 1);
-        mine += 2;
-        mymax = max(mymax, l);
+        D[k] = disj;
       }
+    }
+    uint32_t I[kCandItems + 1];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 1; k < kCandItems + 1; k++) {
+      I[k] = 0;
+      if (!L[k]) continue;
+      I[k] = (uint32_t)(psv_query(slv, ssz, M.nlev, ib + k - 1, L[k]) + 1);
+      const bool rep = D[k] && D[k - 1] && L[k - 1] == L[k];
+      mine += rep ? 1u : 2u;
+      myskip += rep ? 1u : 0u;
+      mymax = max(mymax, L[k]);
     }
     uint32_t tot;
     const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
@@ -688,23 +712,30 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
     __syncthreads();
     uint32_t *r = crec + kCandWords * (uint64_t)(base + off);
 #pragma unroll
-    for (int k = 0; k < kCandItems; k++) {
+    for (int k = 1; k < kCandItems + 1; k++) {
       if (!L[k]) continue;
-      r[0] = L[k]; r[1] = A[k]; r[2] = I[k];
-      r[3] = L[k]; r[4] = B[k]; r[5] = I[k];
-      r += 2 * kCandWords;
+      if (!(D[k] && D[k - 1] && L[k - 1] == L[k])) {
+        r[0] = L[k]; r[1] = A[k]; r[2] = I[k];
+        r += kCandWords;
+      }
+      r[0] = L[k]; r[1] = B[k]; r[2] = I[k];
+      r += kCandWords;
     }
     __syncthreads();
   }
-  const uint32_t wm = wave_incl_max(mymax);
-  if ((threadIdx.x & 63) == 63 && wm) atomicMax(&bmax, wm);
+  const uint32_t wm = wave_incl_max(mymax), ws = wave_incl_sum(myskip);
+  if ((threadIdx.x & 63) == 63) {
+    if (wm) atomicMax(&bmax, wm);
+    if (ws) atomicAdd(&bskip, ws);
+  }
   __syncthreads();
   if (threadIdx.x == 0 && bmax) atomicMax(maxl, bmax);
+  if (threadIdx.x == 0 && bskip) atomicAdd(skipped, bskip);
 }
 
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend, uint32_t min_len,
-                    uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt, uint32_t *maxl,
-                    hipStream_t s) {
+                    uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt, uint32_t *skipped,
+                    uint32_t *maxl, hipStream_t s) {
   MinLevels M{};
   uint64_t sz = n;
   M.lv[0] = lcp;
@@ -719,7 +750,7 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
     sz = nd;
   }
   hipLaunchKernelGGL(k_candidates, grid_for((n + kCandItems - 1) / kCandItems, 256, 8192), dim3(256), 0, s, sa, lcp,
-                     n, wend, min_len, M, crec, cnt, maxl);
+                     n, wend, min_len, M, crec, cnt, skipped, maxl);
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
@@ -829,22 +860,33 @@ __global__ void k_sel_filter(SelArgs a) {
   const uint32_t m = a.nlive[a.r];
   const uint64_t span = (uint64_t)blockDim.x * kSelItems;
   for (uint64_t q0 = (uint64_t)blockIdx.x * span; q0 < m; q0 += (uint64_t)gridDim.x * span) {
-    uint32_t K[kSelItems];
-    uint32_t mine = 0, kept = 0;
+    // loads of all items first (entries, then intervals, then marks)
+    uint32_t K[kSelItems], S[kSelItems], E[kSelItems];
+    uint8_t M1[kSelItems], M2[kSelItems];
 #pragma unroll
     for (int t = 0; t < kSelItems; t++) {
       const uint64_t q = q0 + threadIdx.x + (uint64_t)t * blockDim.x;
-      K[t] = 0;
-      if (q < m) {
-        const uint32_t k = a.pend[q];
-        const uint32_t s = a.start[k], e = s + a.len[k] - 1;
-        if (a.mark[s] || a.mark[e]) {
-          a.state[k] = 2;
-        } else {
-          K[t] = k;
-          kept |= 1u << t;
-          mine++;
-        }
+      K[t] = q < m ? a.pend[q] : kInf;
+    }
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++) {
+      S[t] = K[t] != kInf ? a.start[K[t]] : 0u;
+      E[t] = K[t] != kInf ? S[t] + a.len[K[t]] - 1 : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++) {
+      M1[t] = K[t] != kInf ? a.mark[S[t]] : 0;
+      M2[t] = K[t] != kInf ? a.mark[E[t]] : 0;
+    }
+    uint32_t mine = 0, kept = 0;
+#pragma unroll
+    for (int t = 0; t < kSelItems; t++) {
+      if (K[t] == kInf) continue;
+      if (M1[t] || M2[t]) {
+        a.state[K[t]] = 2;
+      } else {
+        kept |= 1u << t;
+        mine++;
       }
     }
     uint32_t tot;

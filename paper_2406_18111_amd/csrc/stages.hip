@@ -901,17 +901,28 @@ __global__ void k_sel_filter(SelArgs a) {
   }
 }
 
-__global__ void k_sel_insert(SelArgs a) {
+// Round-0 style insert: each working candidate min-writes its priority into
+// the two blocks of level floor(log2 l) that tile it.  Four candidates per
+// thread (consecutive in the working list across the workgroup), all loads
+// issued before any atomic.  Values only decrease, so a write is skipped
+// when the table already holds a smaller priority, or when the previous
+// candidate of the working list targets the same word with a priority not
+// above this one (long periodic runs send whole stretches of the list to
+// one word: the right blocks of a run's candidates all end at its end).
+__global__ __launch_bounds__(256) void k_sel_insert(SelArgs a) {
   if (!sel_run_dense(a)) return;
+  constexpr int NT = 256, NW = NT / 64;
+  __shared__ unsigned long long lastA[4][NW][2];  // per item and wavefront: lane 63's two targets
+  __shared__ uint32_t lastK[4][NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t m = sel_nwork(a);
-  // four working candidates per thread, each step's loads issued together
-  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
-  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < m; b0 += step) {
+  const uint64_t step = (uint64_t)gridDim.x * NT * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * NT * 4; b0 < m; b0 += step) {  // workgroup-uniform
     uint32_t k[4], l[4], st[4], t1[4], t2[4];
-    uint32_t *p1[4], *p2[4];
+    uint64_t a1[4], a2[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      const uint64_t q = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      const uint64_t q = b0 + (uint64_t)u * NT + threadIdx.x;
       k[u] = q < m ? a.work[q] : kInf;
     }
 #pragma unroll
@@ -922,19 +933,45 @@ __global__ void k_sel_insert(SelArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const int j = 31 - __clz((int)l[u]);
-      uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
-      p1[u] = &Tj[st[u]];
-      p2[u] = &Tj[st[u] + l[u] - (1u << j)];
-      // values only decrease: skip the atomic when a smaller priority is
-      // already there (long candidates of periodic runs share block positions)
-      t1[u] = k[u] != kInf ? *p1[u] : 0u;
-      t2[u] = k[u] != kInf ? *p2[u] : 0u;
+      a1[u] = (uint64_t)j * a.n + st[u];  // word index in the table
+      a2[u] = (uint64_t)j * a.n + st[u] + l[u] - (1u << j);
+      t1[u] = k[u] != kInf ? a.Tc[a1[u]] : 0u;
+      t2[u] = k[u] != kInf ? a.Tc[a2[u]] : 0u;
     }
+    if (lane == 63) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        lastA[u][w][0] = a1[u];
+        lastA[u][w][1] = a2[u];
+        lastK[u][w] = k[u];
+      }
+    }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      if (t1[u] > k[u]) atomicMin(p1[u], k[u]);
-      if (t2[u] > k[u]) atomicMin(p2[u], k[u]);
+      // the previous candidate of the list: lane - 1, else the previous
+      // wavefront's lane 63, else the previous item's last wavefront
+      uint64_t p1 = ((uint64_t)(uint32_t)__shfl_up((int)(uint32_t)(a1[u] >> 32), 1, 64) << 32) |
+                    (uint32_t)__shfl_up((int)(uint32_t)a1[u], 1, 64);
+      uint64_t p2 = ((uint64_t)(uint32_t)__shfl_up((int)(uint32_t)(a2[u] >> 32), 1, 64) << 32) |
+                    (uint32_t)__shfl_up((int)(uint32_t)a2[u], 1, 64);
+      uint32_t pk = (uint32_t)__shfl_up((int)k[u], 1, 64);
+      if (lane == 0) {
+        const int pu = w > 0 ? u : u - 1, pw = w > 0 ? w - 1 : NW - 1;
+        if (pu >= 0) {
+          p1 = lastA[pu][pw][0];
+          p2 = lastA[pu][pw][1];
+          pk = lastK[pu][pw];
+        } else {
+          pk = kInf;
+        }
+      }
+      const bool c1 = pk != kInf && p1 == a1[u] && pk <= k[u];
+      const bool c2 = pk != kInf && p2 == a2[u] && pk <= k[u];
+      if (!c1 && t1[u] > k[u]) atomicMin(&a.Tc[a1[u]], k[u]);
+      if (!c2 && t2[u] > k[u]) atomicMin(&a.Tc[a2[u]], k[u]);
     }
+    __syncthreads();
   }
 }
 

@@ -21,6 +21,7 @@ enum Cnt {
   CNT_ND = 0, CNT_C, CNT_MAXL, CNT_M, CNT_NLIVE0, CNT_NLIVE1, CNT_UNDEC, CNT_A, CNT_NROWS,
   CNT_CSKIP,       // candidates not written because they repeat the previous pair's (counted in the total)
   CNT_RANGE = 10,  // two 64-bit words, 8-byte aligned
+  CNT_AUX = 14,    // scratch count of a stage (tile counts, histogram size, runs)
   CNT_COUNT = 32
 };
 

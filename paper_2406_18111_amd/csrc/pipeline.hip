@@ -45,7 +45,7 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
   const uint64_t C2 = 2 * N;
   size_t b = 0;
   b += N * 8 + N * 4 * 8 + (hc + 1) * 12 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
-  b += C2 * (4 * 8 + 2) + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8 + N;
+  b += C2 * (4 * 8 + 2) + 8192 + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8 + N;
   b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
   return b;
 }
@@ -93,7 +93,8 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   }
   size_t o_crec = L.take(C2 * 4 * kCandWords), o_keep = L.take(C2);
   size_t o_sl = L.take(C2 * 4), o_ss = L.take(C2 * 4), o_si = L.take(C2 * 4);
-  size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take(C2 * 4);
+  // tmp_d also holds the candidate sort's digit histograms: 1024 words per 4096 candidates, at least 1024
+  size_t o_ta = L.take(C2 * 4), o_tb = L.take(C2 * 4), o_tc = L.take(C2 * 4), o_td = L.take((C2 + 2048) * 4);
   size_t o_tile = L.take((C2 / 4096 + 4) * 4);
   size_t o_T = L.take(2 * (size_t)nT * N_ * 4), o_live0 = L.take(C2 * 4), o_live1 = L.take(C2 * 4);
   size_t o_state = L.take(C2), o_mark = L.take(N_), o_ctree = L.take(2 * N_ * 4), o_aflag = L.take(N_);
@@ -358,7 +359,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 
   // ---- candidates
   gen_candidates(w.sa, w.lcp, N, wend, min_len, w.lvl, w.nlev, w.crec, dc + CNT_C, dc + CNT_CSKIP, dc + CNT_MAXL,
-                 s);
+                 w.tmp_d, dc + CNT_AUX, w.tile_tmp, s);
   uint64_t c_bound = 2 * N;
   uint64_t maxl_bound = std::max<uint64_t>(maxwin / 2, 1);
   if (host) {
@@ -369,14 +370,28 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   stamp(w, 4, s, stamps);
   uint64_t m_bound = 0;
   if (c_bound > 0) {
-    const uint32_t *f[3] = {w.crec, w.crec + 2, w.crec + 1};  // length, ID, start
-    const int str[3] = {kCandWords, kCandWords, kCandWords};
-    const int sub[3] = {1, 0, 0};
-    const uint32_t *cd[3] = {dc + CNT_MAXL, nullptr, nullptr};
-    const int bb[3] = {bit_length_u64(maxl_bound), (int)rank_bits, (int)rank_bits};
-    sort_plain(w, dc + CNT_C, c_bound, f, str, sub, cd, bb, 3, w.keep, s);
-    compact_sorted(B.val[0], w.keep, dc + CNT_C, c_bound, w.crec, w.s_len, w.s_start, w.s_id, w.tile_tmp,
-                   dc + CNT_M, s);
+    // Priority order (length desc, ID asc, start asc).  The records are in
+    // suffix-array order, where the ID of a fixed length never decreases, so
+    // a stable sort by length leaves (length, ID) ordered; runs of equal
+    // (length, ID) are then sorted by start as units of the sort engine,
+    // whose last level also marks exact duplicates.
+    uint32_t *xs[3] = {w.tmp_a, w.tmp_b, w.tmp_c};  // length key, start, ID
+    uint32_t *ys[3] = {w.s_len, w.s_start, w.s_id};
+    lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, bit_length_u64(maxl_bound), xs, ys, w.tmp_d,
+                        dc + CNT_AUX, w.tile_tmp, s);
+    E.reset_counters(s);
+    E.round_begin(0, s);
+    E.iota_val(dc + CNT_C, c_bound, s);
+    E.gather_field(0, w.tmp_b, 1, dc + CNT_C, 0, nullptr, 0, c_bound, s);  // key = start
+    run_flags(w.tmp_a, w.tmp_c, dc + CNT_C, c_bound, w.keep, s);
+    flag_positions(w.keep, dc + CNT_C, c_bound, w.tmp_d, dc + CNT_AUX, w.tile_tmp, s);
+    E.init_runs(0, w.tmp_d, dc + CNT_AUX, dc + CNT_C, c_bound, rank_bits, s);
+    fill_u8_dev(w.keep, dc + CNT_C, c_bound, 1, s);
+    if (c_bound > (1ull << E.tile_log())) E.msd(0, c_bound, (int)rank_bits, s);
+    E.lds_plain(0, 0, 1, w.keep, c_bound, s);
+    E.bulk_plain(0, 0, 1, w.keep, c_bound, s);
+    compact_sorted_runs(B.val[0], w.keep, dc + CNT_C, c_bound, w.tmp_a, w.tmp_b, w.tmp_c, dc + CNT_MAXL, w.s_len,
+                        w.s_start, w.s_id, w.tile_tmp, dc + CNT_M, s);
     m_bound = c_bound;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;

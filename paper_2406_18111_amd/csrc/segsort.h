@@ -20,6 +20,10 @@ class SortEngine {
   void round_end(int cur, int r, uint32_t *hist, hipStream_t s);
   void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
                   hipStream_t s);
+  // units from runs: run r is [run_start[r], run_start[r+1]) (the last ends at
+  // *total_dev); bound: host upper bound of the run count
+  void init_runs(int cur, const uint32_t *run_start, const uint32_t *nruns_dev, const uint32_t *total_dev,
+                 uint64_t bound, uint32_t key_bits, hipStream_t s);
   void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
   void gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend, uint32_t n,
                  uint32_t h, uint32_t *hist, int r, hipStream_t s);

@@ -107,6 +107,68 @@ __global__ void k_init_units(SortBufs B, int cur, const uint64_t *off, uint32_t 
   }
 }
 
+// Routes runs [rs[r], rs[r+1]) (the last one ends at *total_dev) of length
+// >= 2 to the class lists or the level-0 big list of list `cur`; *nruns_dev
+// runs.  A thread takes kRunItems consecutive runs, and class-list slots are
+// reserved once per workgroup pass and class (most runs are singletons).
+constexpr int kRunItems = 8;
+
+__global__ __launch_bounds__(256) void k_init_runs(SortBufs B, int cur, const uint32_t *rs,
+                                                   const uint32_t *nruns_dev, const uint32_t *total_dev,
+                                                   uint32_t key_bits) {
+  __shared__ uint32_t cnt[kClasses], cbase[kClasses];
+  const uint32_t R = *nruns_dev, total = *total_dev;
+  const int lane = threadIdx.x & 63;
+  const uint64_t span = (uint64_t)blockDim.x * kRunItems;
+  for (uint64_t r0 = (uint64_t)blockIdx.x * span; r0 < R; r0 += (uint64_t)gridDim.x * span) {
+    if (threadIdx.x < kClasses) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t rb = r0 + (uint64_t)threadIdx.x * kRunItems;
+    uint32_t bound[kRunItems + 1];
+#pragma unroll
+    for (int k = 0; k <= kRunItems; k++) bound[k] = rb + k < R ? rs[rb + k] : total;
+    uint32_t loc[kRunItems];
+    int ci[kRunItems];
+#pragma unroll
+    for (int k = 0; k < kRunItems; k++) {
+      const uint32_t len = rb + k < R ? bound[k + 1] - bound[k] : 0u;
+      ci[k] = -1;
+      loc[k] = 0;
+      if (len >= 2 && len <= (1u << B.tile_log)) ci[k] = class_of(len);
+      else if (len > (1u << B.tile_log))
+        append_big(B.big[cur][0], &B.ctr->big_pk[cur][0], B.big_cap, bound[k], len, key_bits, &B.ctr->err);
+      // slot within the workgroup's share of the class: one LDS add per
+      // class present in the wavefront
+      uint64_t todo = __ballot(ci[k] >= 0);
+      while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int lc = __shfl(ci[k], leader, 64);
+        const uint64_t grp = __ballot(ci[k] == lc) & todo;
+        uint32_t b = 0;
+        if (lane == leader) b = atomicAdd(&cnt[lc], (uint32_t)__popcll(grp));
+        b = (uint32_t)__shfl((int)b, leader, 64);
+        if ((grp >> lane) & 1ull) loc[k] = b + (uint32_t)__popcll(grp & ((1ull << lane) - 1ull));
+        todo &= ~grp;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kClasses) {
+      const uint32_t c = cnt[threadIdx.x];
+      cbase[threadIdx.x] = c ? atomicAdd(&B.ctr->cls_cnt[cur][threadIdx.x], c) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRunItems; k++) {
+      if (ci[k] < 0) continue;
+      const uint32_t slot = cbase[ci[k]] + loc[k];
+      const uint32_t capc = B.cls_off[ci[k] + 1] - B.cls_off[ci[k]];
+      if (slot < capc) B.cls[cur][B.cls_off[ci[k]] + slot] = Unit{bound[k], bound[k + 1] - bound[k]};
+      else atomicOr(&B.ctr->err, 1u);
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ gathers
 // Round 0 of suffix sorting: slot p holds suffix p, keyed by its first token
 // (its dense rank or, for 32-bit input, the token itself).
@@ -1157,6 +1219,12 @@ void SortEngine::init_units(int cur, const uint64_t *d_off, uint32_t nranges, ui
                             uint32_t key_bits, hipStream_t s) {
   hipLaunchKernelGGL(k_init_units, grid_for(nranges, 256, 1 << 16), dim3(256), 0, s, b_, cur, d_off,
                      nranges, base, key_bits);
+}
+
+void SortEngine::init_runs(int cur, const uint32_t *run_start, const uint32_t *nruns_dev, const uint32_t *total_dev,
+                           uint64_t bound, uint32_t key_bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_runs, grid_for((bound + kRunItems - 1) / kRunItems, 256, 8192), dim3(256), 0, s, b_, cur,
+                     run_start, nruns_dev, total_dev, key_bits);
 }
 
 void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s) {

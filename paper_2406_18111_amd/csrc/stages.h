@@ -44,7 +44,29 @@ void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint3
 constexpr int kCandWords = 3;
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend,
                     uint32_t min_len, uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt,
-                    uint32_t *skipped, uint32_t *maxl, hipStream_t s);
+                    uint32_t *skipped, uint32_t *maxl, uint32_t *tile_val, uint32_t *ntiles_dev,
+                    uint32_t *tile_tmp, hipStream_t s);
+
+// Stable sort of the candidate records by length, longest first (records in
+// suffix-array order come out ordered by (length desc, ID asc)): LSD passes
+// over key = *maxl - length, carrying start and ID.  The result lands in
+// xs = {key, start, ID} arrays; ys is the alternate set; hist holds 256 u32
+// per 4096 records (at least 256); hist_n is one device word of scratch.
+void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
+                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *hist, uint32_t *hist_n,
+                         uint32_t *tile_tmp, hipStream_t s);
+// flag[i] = 1 where (key, p2) differs from position i - 1.
+void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint64_t bound, uint8_t *flag,
+               hipStream_t s);
+// Positions of the set flags, in order; *count receives their number.
+void flag_positions(const uint8_t *flag, const uint32_t *n_dev, uint64_t bound, uint32_t *out, uint32_t *count,
+                    uint32_t *tile_tmp, hipStream_t s);
+// Compaction of the sorted candidates: slot k (keep[k] set) takes position
+// order[k] of the length-sorted arrays; length = *maxl - lkey.
+void compact_sorted_runs(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
+                         const uint32_t *lkey, const uint32_t *start, const uint32_t *id, const uint32_t *maxl,
+                         uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp, uint32_t *total,
+                         hipStream_t s);
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
                     const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,

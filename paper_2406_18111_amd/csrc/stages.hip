@@ -627,16 +627,18 @@ __device__ int64_t psv_query(const uint32_t *const *lv, const uint64_t *sz, int 
 // LCP value between them is below the length), so it is counted but not
 // written: on loop streams this removes nearly all exact duplicates before
 // the sort.  A workgroup takes kCandItems consecutive pairs per thread per
-// pass, so output space is reserved with one global atomic per 256 *
-// kCandItems pairs, and the output keeps suffix-array order within a pass.
+// pass (a tile of 256 * kCandItems pairs).  Two passes keep the output in
+// suffix-array order: the first counts each tile's records (and the longest
+// length and the skipped repeats), a scan turns the counts into tile offsets,
+// and the second computes the IDs and writes every record at its place.
 constexpr int kCandItems = 8;
 
+template <bool WRITE>
 __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
-                                                    uint32_t *crec, uint32_t *cnt, uint32_t *skipped,
+                                                    uint32_t *tile_val, uint32_t *crec, uint32_t *skipped,
                                                     uint32_t *maxl) {
   __shared__ uint32_t sh[4];
-  __shared__ uint32_t base;
   __shared__ uint32_t bmax, bskip;
   // level pointers in LDS: per-lane indexing of the kernel argument would
   // cost a dependent global load per level step
@@ -651,21 +653,41 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
   uint32_t mymax = 0, myskip = 0;
   const uint64_t span = (uint64_t)blockDim.x * kCandItems;
   for (uint64_t i0 = (uint64_t)blockIdx.x * span; i0 < n; i0 += (uint64_t)gridDim.x * span) {
+    const uint64_t tile = i0 / span;
     const uint64_t ib = i0 + (uint64_t)threadIdx.x * kCandItems;  // a thread's pairs are consecutive
     // every input of the thread's pairs (and of the pair before them) is
     // loaded before any is used; index 0 is pair ib - 1
     uint32_t S[kCandItems + 2], P[kCandItems + 1], WE[kCandItems + 1];
+    static_assert(kCandItems == 8, "two 16-byte loads per array");
+    if (ib + kCandItems + 1 <= n) {  // ib is a multiple of 8: aligned 16-byte loads
+      const uint4 s0 = reinterpret_cast<const uint4 *>(sa + ib)[0], s1 = reinterpret_cast<const uint4 *>(sa + ib)[1];
+      const uint4 p0 = reinterpret_cast<const uint4 *>(lcp + ib)[0], p1 = reinterpret_cast<const uint4 *>(lcp + ib)[1];
+      S[0] = ib ? sa[ib - 1] : 0u;
+      S[1] = s0.x; S[2] = s0.y; S[3] = s0.z; S[4] = s0.w; S[5] = s1.x; S[6] = s1.y; S[7] = s1.z; S[8] = s1.w;
+      S[9] = sa[ib + kCandItems];
+      P[0] = ib ? lcp[ib - 1] : 0u;
+      P[1] = p0.x; P[2] = p0.y; P[3] = p0.z; P[4] = p0.w; P[5] = p1.x; P[6] = p1.y; P[7] = p1.z; P[8] = p1.w;
+      if (wend) {
+        const uint4 e0 = reinterpret_cast<const uint4 *>(wend + ib)[0], e1 = reinterpret_cast<const uint4 *>(wend + ib)[1];
+        WE[0] = ib ? wend[ib - 1] : (uint32_t)n;
+        WE[1] = e0.x; WE[2] = e0.y; WE[3] = e0.z; WE[4] = e0.w; WE[5] = e1.x; WE[6] = e1.y; WE[7] = e1.z; WE[8] = e1.w;
+      } else {
 #pragma unroll
-    for (int k = 0; k < kCandItems + 2; k++) {
-      const uint64_t i = ib + k - 1;
-      S[k] = (ib + k >= 1 && i < n) ? sa[i] : 0u;
-    }
+        for (int k = 0; k < kCandItems + 1; k++) WE[k] = (uint32_t)n;
+      }
+    } else {
 #pragma unroll
-    for (int k = 0; k < kCandItems + 1; k++) {
-      const uint64_t i = ib + k - 1;
-      const bool in = ib + k >= 1 && i < n;
-      P[k] = in ? lcp[i] : 0u;
-      WE[k] = (wend && in) ? wend[i] : (uint32_t)n;
+      for (int k = 0; k < kCandItems + 2; k++) {
+        const uint64_t i = ib + k - 1;
+        S[k] = (ib + k >= 1 && i < n) ? sa[i] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < kCandItems + 1; k++) {
+        const uint64_t i = ib + k - 1;
+        const bool in = ib + k >= 1 && i < n;
+        P[k] = in ? lcp[i] : 0u;
+        WE[k] = (wend && in) ? wend[i] : (uint32_t)n;
+      }
     }
     uint32_t L[kCandItems + 1], A[kCandItems + 1], B[kCandItems + 1];
     bool D[kCandItems + 1];  // pair in the disjoint branch with l >= min_len
@@ -694,35 +716,37 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
         D[k] = disj;
       }
     }
-    uint32_t I[kCandItems + 1];
     uint32_t mine = 0;
 #pragma unroll
     for (int k = 1; k < kCandItems + 1; k++) {
-      I[k] = 0;
       if (!L[k]) continue;
-      I[k] = (uint32_t)(psv_query(slv, ssz, M.nlev, ib + k - 1, L[k]) + 1);
       const bool rep = D[k] && D[k - 1] && L[k - 1] == L[k];
       mine += rep ? 1u : 2u;
-      myskip += rep ? 1u : 0u;
-      mymax = max(mymax, L[k]);
+      if (!WRITE) {
+        myskip += rep ? 1u : 0u;
+        mymax = max(mymax, L[k]);
+      }
     }
     uint32_t tot;
     const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(cnt, tot) : 0u;
-    __syncthreads();
-    uint32_t *r = crec + kCandWords * (uint64_t)(base + off);
+    if (!WRITE) {
+      if (threadIdx.x == 0) tile_val[tile] = tot;
+      continue;
+    }
+    uint32_t *r = crec + kCandWords * (uint64_t)(tile_val[tile] + off);
 #pragma unroll
     for (int k = 1; k < kCandItems + 1; k++) {
       if (!L[k]) continue;
+      const uint32_t id = (uint32_t)(psv_query(slv, ssz, M.nlev, ib + k - 1, L[k]) + 1);
       if (!(D[k] && D[k - 1] && L[k - 1] == L[k])) {
-        r[0] = L[k]; r[1] = A[k]; r[2] = I[k];
+        r[0] = L[k]; r[1] = A[k]; r[2] = id;
         r += kCandWords;
       }
-      r[0] = L[k]; r[1] = B[k]; r[2] = I[k];
+      r[0] = L[k]; r[1] = B[k]; r[2] = id;
       r += kCandWords;
     }
-    __syncthreads();
   }
+  if (WRITE) return;
   const uint32_t wm = wave_incl_max(mymax), ws = wave_incl_sum(myskip);
   if ((threadIdx.x & 63) == 63) {
     if (wm) atomicMax(&bmax, wm);
@@ -735,7 +759,7 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
 
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend, uint32_t min_len,
                     uint32_t *const *levels, int nlev, uint32_t *crec, uint32_t *cnt, uint32_t *skipped,
-                    uint32_t *maxl, hipStream_t s) {
+                    uint32_t *maxl, uint32_t *tile_val, uint32_t *ntiles_dev, uint32_t *tile_tmp, hipStream_t s) {
   MinLevels M{};
   uint64_t sz = n;
   M.lv[0] = lcp;
@@ -749,8 +773,15 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
     M.nlev = k + 1;
     sz = nd;
   }
-  hipLaunchKernelGGL(k_candidates, grid_for((n + kCandItems - 1) / kCandItems, 256, 8192), dim3(256), 0, s, sa, lcp,
-                     n, wend, min_len, M, crec, cnt, skipped, maxl);
+  const uint64_t span = 256 * kCandItems;
+  const uint64_t ntiles = std::max<uint64_t>((n + span - 1) / span, 1);
+  const dim3 grid((unsigned)std::min<uint64_t>(ntiles, 8192));
+  hipLaunchKernelGGL((k_candidates<false>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec,
+                     skipped, maxl);
+  fill_u32(ntiles_dev, 1, (uint32_t)ntiles, s);
+  scan_excl(tile_val, tile_val, ntiles_dev, ntiles, tile_tmp, cnt, s);  // tile offsets; *cnt = records
+  hipLaunchKernelGGL((k_candidates<true>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec,
+                     skipped, maxl);
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
@@ -769,6 +800,195 @@ void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *
                     const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s) {
   flag_compact(keep, FlagNonZero{}, m_dev, bound, tile_tmp, total, GatherSorted{order, crec, s_len, s_start, s_id}, s);
+}
+
+// ------------------------------------------------- stable LSD digit passes
+// Stable sort of (key, p1, p2) triples by kLsdBits-bit digits of the key,
+// least significant first (8-bit digits measured faster than 10-bit ones,
+// even where they need one pass more).  A tile of kLsdTile entries is 4 wavefronts x 16 slots x
+// 64 lanes with entry index tile0 + 1024 w + 64 e + lane, so each slot's
+// loads are coalesced and index order is (wavefront, slot, lane) order.  Per
+// tile: a digit histogram (lanes with equal digits found by ballots, one LDS
+// add per digit group); the histograms of all tiles, bin-major, are scanned
+// once; the scatter ranks every entry among the tile's equal digits in index
+// order (running per-wavefront digit counts in LDS) and writes it to the
+// bin's global offset.  The first pass reads the candidate records
+// (key = maxl - length, p1 = start, p2 = ID).
+constexpr int kLsdNT = 256, kLsdSlots = 16, kLsdTile = kLsdNT * kLsdSlots, kLsdBits = 8,
+              kLsdBins = 1 << kLsdBits;
+
+struct LsdSrc {
+  const uint32_t *rec;           // candidate records, or null
+  const uint32_t *maxl;          // with records: key = *maxl - length
+  const uint32_t *key, *p1, *p2; // without records
+};
+
+__device__ __forceinline__ void lsd_load(const LsdSrc &in, uint64_t i, uint32_t maxl, uint32_t &k, uint32_t &a,
+                                         uint32_t &b) {
+  if (in.rec) {
+    const uint32_t *r = in.rec + kCandWords * i;
+    k = maxl - r[0]; a = r[1]; b = r[2];
+  } else {
+    k = in.key[i]; a = in.p1[i]; b = in.p2[i];
+  }
+}
+
+// Lanes of the wavefront whose digit equals this lane's (valid lanes only).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < kLsdBits; b++) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return valid ? peers : 0ull;
+}
+
+__global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, const uint32_t *n_dev, int shift, uint32_t *hist,
+                                                     uint32_t ntiles) {
+  __shared__ uint32_t h[kLsdBins];
+  const uint64_t n = *n_dev;
+  const uint32_t maxl = in.maxl ? *in.maxl : 0u;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) h[d] = 0;
+    __syncthreads();
+    const uint64_t tile0 = (uint64_t)t * kLsdTile;
+    if (tile0 < n) {
+      for (int e = 0; e < kLsdSlots; e++) {
+        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+        uint32_t k = 0, a, b;
+        const bool valid = i < n;
+        if (valid) lsd_load(in, i, maxl, k, a, b);
+        const uint32_t d = (k >> shift) & (kLsdBins - 1);
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+      }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) hist[(uint64_t)d * ntiles + t] = h[d];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_t *n_dev, int shift,
+                                                        const uint32_t *offs, uint32_t ntiles, uint32_t *ok,
+                                                        uint32_t *oa, uint32_t *ob) {
+  __shared__ uint32_t wcnt[4][kLsdBins];
+  __shared__ uint32_t wstart[4][kLsdBins];
+  const uint64_t n = *n_dev;
+  const uint32_t maxl = in.maxl ? *in.maxl : 0u;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t tile0 = (uint64_t)t * kLsdTile;
+    if (tile0 >= n) break;  // workgroup-uniform; later tiles are empty too
+    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT)
+      for (int q = 0; q < 4; q++) wcnt[q][d] = 0;
+    __syncthreads();
+    uint32_t K[kLsdSlots], A[kLsdSlots], Bv[kLsdSlots], rank[kLsdSlots];
+#pragma unroll
+    for (int e = 0; e < kLsdSlots; e++) {
+      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+      K[e] = 0;
+      if (i < n) lsd_load(in, i, maxl, K[e], A[e], Bv[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < kLsdSlots; e++) {
+      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+      const bool valid = i < n;
+      const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
+      const uint64_t peers = digit_peers(d, valid);
+      const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : lane;
+      uint32_t base = 0;
+      if (valid && lane == leader) {
+        base = wcnt[w][d];
+        wcnt[w][d] = base + (uint32_t)__popcll(peers);
+      }
+      base = (uint32_t)__shfl((int)base, leader, 64);
+      rank[e] = base + (uint32_t)__popcll(peers & lt);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) {
+      uint32_t run = offs[(uint64_t)d * ntiles + t];
+      for (int q = 0; q < 4; q++) {
+        wstart[q][d] = run;
+        run += wcnt[q][d];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kLsdSlots; e++) {
+      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+      if (i >= n) continue;
+      const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
+      const uint32_t pos = wstart[w][d] + rank[e];
+      ok[pos] = K[e];
+      oa[pos] = A[e];
+      ob[pos] = Bv[e];
+    }
+    __syncthreads();
+  }
+}
+
+void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
+                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *hist, uint32_t *hist_n,
+                         uint32_t *tile_tmp, hipStream_t s) {
+  const int passes = std::max(1, (key_bits + kLsdBits - 1) / kLsdBits);
+  const uint32_t ntiles = (uint32_t)std::max<uint64_t>((bound + kLsdTile - 1) / kLsdTile, 1);
+  const unsigned grid = std::min<uint32_t>(ntiles, 8192);
+  fill_u32(hist_n, 1, kLsdBins * ntiles, s);
+  LsdSrc in{crec, maxl_dev, nullptr, nullptr, nullptr};
+  for (int ps = 0; ps < passes; ps++) {
+    uint32_t *const *out = ((passes - 1 - ps) % 2 == 0) ? xs : ys;  // the last pass writes xs
+    hipLaunchKernelGGL(k_lsd_hist, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles);
+    scan_excl(hist, hist, hist_n, (uint64_t)kLsdBins * ntiles, tile_tmp, nullptr, s);
+    hipLaunchKernelGGL(k_lsd_scatter, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles, out[0],
+                       out[1], out[2]);
+    in = LsdSrc{nullptr, nullptr, out[0], out[1], out[2]};
+  }
+}
+
+// Run starts of equal (key, p2) in the sorted order, as byte flags.
+__global__ void k_run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint8_t *flag) {
+  const uint64_t n = *n_dev;
+  GRID_STRIDE(i, n) flag[i] = (i == 0 || key[i] != key[i - 1] || p2[i] != p2[i - 1]) ? 1 : 0;
+}
+void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint64_t bound, uint8_t *flag,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_run_flags, grid_for(bound, 256, 8192), dim3(256), 0, s, key, p2, n_dev, flag);
+}
+
+struct StoreIndex {
+  using Rec = uint32_t;
+  uint32_t *out;
+  __device__ Rec get(uint64_t k) const { return (uint32_t)k; }
+  __device__ void put(uint32_t o, Rec r) const { out[o] = r; }
+};
+void flag_positions(const uint8_t *flag, const uint32_t *n_dev, uint64_t bound, uint32_t *out, uint32_t *count,
+                    uint32_t *tile_tmp, hipStream_t s) {
+  flag_compact(flag, FlagNonZero{}, n_dev, bound, tile_tmp, count, StoreIndex{out}, s);
+}
+
+// Keep the first of each run of identical candidates, in sorted order: slot k
+// holds position order[k] of the length-sorted arrays.
+struct GatherSortedRuns {
+  using Rec = uint3;
+  const uint32_t *order, *lkey, *start, *id, *maxl;
+  uint32_t *s_len, *s_start, *s_id;
+  __device__ Rec get(uint64_t k) const {
+    const uint32_t q = order[k];
+    return make_uint3(*maxl - lkey[q], start[q], id[q]);
+  }
+  __device__ void put(uint32_t o, Rec r) const { s_len[o] = r.x; s_start[o] = r.y; s_id[o] = r.z; }
+};
+void compact_sorted_runs(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
+                         const uint32_t *lkey, const uint32_t *start, const uint32_t *id, const uint32_t *maxl,
+                         uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp, uint32_t *total,
+                         hipStream_t s) {
+  flag_compact(keep, FlagNonZero{}, m_dev, bound, tile_tmp, total,
+               GatherSortedRuns{order, lkey, start, id, maxl, s_len, s_start, s_id}, s);
 }
 
 // ------------------------------------------------------------- selection

@@ -682,7 +682,7 @@ extern "C" int apo_last_rounds(apo_ctx *ctx, uint32_t *sa_active, uint32_t *n_sa
     sa_active[r] = r == 0 ? (uint32_t)ctx->info.n : w.hrhist[4 * (r - 1)];
   for (uint32_t q = 0; q < I.sel_rounds && q < cap && q < (uint32_t)kSelRoundCap; q++) {
     sel_live[q] = w.hsel[q];
-    sel_undecided[q] = w.hsel[(kSelRoundCap + 2) + q];
+    sel_undecided[q] = w.hsel[q + 1];  // undecided after round q = live entering round q + 1
   }
   return (I.rounds > cap || I.sel_rounds > cap) ? APO_ERANGE : APO_OK;
 }

@@ -432,7 +432,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       APO_HIP_TRY(hipMemcpyAsync(w.hsel, w.selcnt, 2 * (kSelRoundCap + 2) * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
       for (int q = q0 - ahead; q < hi; q++)
-        if (w.hsel[(kSelRoundCap + 2) + q] == 0) { sel_done = q; break; }
+        if (w.hsel[q + 1] == 0) { sel_done = q; break; }  // nlive[q + 1]: undecided after round q
       if (sel_done < 0) hint = w.hsel[hi];
     }
     if (host && sel_done < 0) {
@@ -503,7 +503,7 @@ int finish_run(Workspace &w, uint64_t N, uint64_t m_bound, int sel_launched, Run
   info.sel_rounds = 0;
   const int qmax = sel_launched < 0 ? kSelRoundCap : sel_launched;
   for (int q = 0; q < qmax; q++)
-    if (w.hsel[(kSelRoundCap + 2) + q] == 0) { info.sel_rounds = (uint32_t)q + 1; break; }
+    if (w.hsel[q + 1] == 0) { info.sel_rounds = (uint32_t)q + 1; break; }
   // sync-free run whose launched rounds left candidates undecided
   if (sel_launched >= 0 && m_bound > 0 && info.cands_dedup > 0 && info.sel_rounds == 0) return 1;
   if (stamps) {

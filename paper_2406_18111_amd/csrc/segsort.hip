@@ -294,6 +294,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
   __syncthreads();
   const uint32_t total = items_total;
 
+  uint32_t act_deferred = 0;
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
     if (tid == 0) {
       uint32_t it = item;
@@ -412,7 +413,10 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
     if (!last_level) {
       uint32_t tot;
       const uint32_t off = block_excl_sum<NT>(my_act, sh, &tot);
-      if (tid == 0) act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      if (tid == 0) {
+        if (R.aflag) act_deferred += tot;  // SA rounds keep flags: the count only, once per workgroup
+        else act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      }
       if (tid < kClasses) {
         const uint32_t m = cls_loc[tid];
         cls_base[tid] = m ? atomicAdd(&B.ctr->cls_cnt[nxt][tid], m) : 0u;
@@ -451,6 +455,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
     (void)next_bits;
     __syncthreads();
   }
+  if (threadIdx.x == 0 && act_deferred) atomicAdd(&B.ctr->act_cnt[nxt], act_deferred);
 }
 
 // ---------------------------------------------- wavefront sort (tiny units)
@@ -491,6 +496,7 @@ __global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankO
   const uint32_t total = first_item[kWaveMaxCi];
   const uint64_t lanes_lt = (1ull << lane) - 1ull;
   constexpr uint32_t kBatch = 4 * kWaveItems;
+  uint32_t deferred = 0;  // threads kWaveMaxCi (SA active count) and kWaveMaxCi + 1 (sorted entries)
   for (uint64_t b0 = (uint64_t)blockIdx.x * kBatch; b0 < total; b0 += (uint64_t)gridDim.x * kBatch) {
     // per item and lane: slot of an entry that stays active, and a new unit
     uint32_t act_p[kWaveItems], unit_pos[kWaveItems], unit_code[kWaveItems];
@@ -612,9 +618,12 @@ __global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankO
       for (int w = 0; w < 4; w++) sum += wtot[w][q];
       uint32_t base = 0;
       if (sum) {
+        // counts whose positions nobody needs (the active count of SA rounds,
+        // which keep flags instead of a list, and the statistics) are added
+        // once per workgroup at the end
         if (q < kWaveMaxCi) base = atomicAdd(&B.ctr->cls_cnt[nxt][q], sum);
-        else if (q == kWaveMaxCi) base = atomicAdd(&B.ctr->act_cnt[nxt], sum);
-        else atomicAdd(&B.ctr->lds_elems, sum);
+        else if (q == kWaveMaxCi && !R.aflag) base = atomicAdd(&B.ctr->act_cnt[nxt], sum);
+        else deferred += sum;
       }
       for (int w = 0; w < 4; w++) {
         wbase[w][q] = base;
@@ -654,6 +663,8 @@ __global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankO
     }
     __syncthreads();  // wtot/wbase are reused by the next batch
   }
+  if (threadIdx.x == kWaveMaxCi && deferred) atomicAdd(&B.ctr->act_cnt[nxt], deferred);
+  if (threadIdx.x == kWaveMaxCi + 1 && deferred) atomicAdd(&B.ctr->lds_elems, deferred);
 }
 
 // ------------------------------------------------- LDS grouping (large units)
@@ -699,6 +710,7 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
   }
   __syncthreads();
   const uint32_t total_items = items_total;
+  uint32_t elems = 0, act_deferred = 0;
   for (uint32_t item = blockIdx.x; item < total_items; item += gridDim.x) {
     if (tid == 0) {
       uint32_t it = item;
@@ -732,7 +744,7 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
       const uint32_t ex = block_excl_sum<NT>(len, sh, &tot);
       if (tid < (int)nb) uoff[tid] = ex;
       if (tid == 0) uoff[nb] = tot;
-      if (tid == 0) atomicAdd(&B.ctr->lds_elems, tot);
+      elems += tot;  // statistics: one atomic per workgroup at the end
     }
     __syncthreads();
     const uint32_t total = uoff[nb];
@@ -875,7 +887,10 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
     if (!last_level) {
       uint32_t tot;
       const uint32_t off = block_excl_sum<NT>(my_act, sh, &tot);
-      if (tid == 0) act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      if (tid == 0) {
+        if (R.aflag) act_deferred += tot;  // SA rounds keep flags: the count only, once per workgroup
+        else act_base = tot ? atomicAdd(&B.ctr->act_cnt[nxt], tot) : 0u;
+      }
       if (tid < kClasses) {
         const uint32_t mm = cls_loc[tid];
         cls_base[tid] = mm ? atomicAdd(&B.ctr->cls_cnt[nxt][tid], mm) : 0u;
@@ -909,6 +924,8 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
     }
     __syncthreads();
   }
+  if (tid == 0 && elems) atomicAdd(&B.ctr->lds_elems, elems);
+  if (tid == 0 && act_deferred) atomicAdd(&B.ctr->act_cnt[nxt], act_deferred);
 }
 
 // ----------------------------------------------------------- MSD bucketing

@@ -633,27 +633,31 @@ __device__ int64_t psv_query(const uint32_t *const *lv, const uint64_t *sz, int 
 // and the second computes the IDs and writes every record at its place.
 constexpr int kCandItems = 8;
 
+// tile_val: count pass: records per tile (then scanned to offsets); the
+// tile's skipped repeats and longest length go to tile_val[ntiles + tile]
+// and tile_val[2 ntiles + tile] (summed by k_tile_totals, not by atomics on
+// one word from every workgroup).
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
-                                                    uint32_t *tile_val, uint32_t *crec, uint32_t *skipped,
-                                                    uint32_t *maxl) {
+                                                    uint32_t *tile_val, uint32_t *crec) {
   __shared__ uint32_t sh[4];
-  __shared__ uint32_t bmax, bskip;
+  __shared__ uint32_t bmax;
   // level pointers in LDS: per-lane indexing of the kernel argument would
   // cost a dependent global load per level step
   __shared__ const uint32_t *slv[kMinLevels];
   __shared__ uint64_t ssz[kMinLevels];
-  if (threadIdx.x == 0) bmax = bskip = 0;
+  if (threadIdx.x == 0) bmax = 0;
   if (threadIdx.x < kMinLevels) {
     slv[threadIdx.x] = M.lv[threadIdx.x];
     ssz[threadIdx.x] = M.sz[threadIdx.x];
   }
   __syncthreads();
-  uint32_t mymax = 0, myskip = 0;
   const uint64_t span = (uint64_t)blockDim.x * kCandItems;
+  const uint64_t ntiles = (n + span - 1) / span;
   for (uint64_t i0 = (uint64_t)blockIdx.x * span; i0 < n; i0 += (uint64_t)gridDim.x * span) {
     const uint64_t tile = i0 / span;
+    uint32_t mymax = 0, myskip = 0;
     const uint64_t ib = i0 + (uint64_t)threadIdx.x * kCandItems;  // a thread's pairs are consecutive
     // every input of the thread's pairs (and of the pair before them) is
     // loaded before any is used; index 0 is pair ib - 1
@@ -730,7 +734,17 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
     uint32_t tot;
     const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
     if (!WRITE) {
-      if (threadIdx.x == 0) tile_val[tile] = tot;
+      uint32_t tskip;
+      (void)block_excl_sum<256>(myskip, sh, &tskip);
+      const uint32_t wm = wave_incl_max(mymax);
+      if ((threadIdx.x & 63) == 63 && wm) atomicMax(&bmax, wm);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        tile_val[tile] = tot;
+        tile_val[ntiles + tile] = tskip;
+        tile_val[2 * ntiles + tile] = bmax;
+        bmax = 0;  // the next tile's first LDS max follows two more barriers
+      }
       continue;
     }
     uint32_t *r = crec + kCandWords * (uint64_t)(tile_val[tile] + off);
@@ -746,15 +760,29 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
       r += kCandWords;
     }
   }
-  if (WRITE) return;
-  const uint32_t wm = wave_incl_max(mymax), ws = wave_incl_sum(myskip);
+}
+
+// Sum of the tiles' skipped repeats and maximum of their longest lengths.
+__global__ __launch_bounds__(1024) void k_tile_totals(const uint32_t *skip, const uint32_t *mx, uint32_t ntiles,
+                                                      uint32_t *skipped, uint32_t *maxl) {
+  __shared__ uint32_t ssum, smax;
+  if (threadIdx.x == 0) ssum = smax = 0;
+  __syncthreads();
+  uint32_t a = 0, b = 0;
+  for (uint32_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    a += skip[t];
+    b = max(b, mx[t]);
+  }
+  const uint32_t wa = wave_incl_sum(a), wb = wave_incl_max(b);
   if ((threadIdx.x & 63) == 63) {
-    if (wm) atomicMax(&bmax, wm);
-    if (ws) atomicAdd(&bskip, ws);
+    atomicAdd(&ssum, wa);
+    atomicMax(&smax, wb);
   }
   __syncthreads();
-  if (threadIdx.x == 0 && bmax) atomicMax(maxl, bmax);
-  if (threadIdx.x == 0 && bskip) atomicAdd(skipped, bskip);
+  if (threadIdx.x == 0) {
+    *skipped = ssum;
+    *maxl = smax;
+  }
 }
 
 void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const uint32_t *wend, uint32_t min_len,
@@ -776,12 +804,12 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
   const uint64_t span = 256 * kCandItems;
   const uint64_t ntiles = std::max<uint64_t>((n + span - 1) / span, 1);
   const dim3 grid((unsigned)std::min<uint64_t>(ntiles, 8192));
-  hipLaunchKernelGGL((k_candidates<false>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec,
-                     skipped, maxl);
+  hipLaunchKernelGGL((k_candidates<false>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec);
+  hipLaunchKernelGGL(k_tile_totals, dim3(1), dim3(1024), 0, s, tile_val + ntiles, tile_val + 2 * ntiles,
+                     (uint32_t)((n + span - 1) / span), skipped, maxl);
   fill_u32(ntiles_dev, 1, (uint32_t)ntiles, s);
   scan_excl(tile_val, tile_val, ntiles_dev, ntiles, tile_tmp, cnt, s);  // tile offsets; *cnt = records
-  hipLaunchKernelGGL((k_candidates<true>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec,
-                     skipped, maxl);
+  hipLaunchKernelGGL((k_candidates<true>), grid, dim3(256), 0, s, sa, lcp, n, wend, min_len, M, tile_val, crec);
 }
 
 // Keep the first of each run of identical candidates, in sorted order.
@@ -1027,7 +1055,7 @@ struct SelArgs {
   uint32_t *work;           // round r's working list (round 0: every candidate)
   uint32_t *nlive;          // nlive[r]: entries of pend at round r (nlive[0]: all candidates)
   uint32_t *nwork;          // nwork[r]: entries of work at round r (r >= 1)
-  uint32_t *undec;          // undec[r]: undecided after round r
+  uint32_t *undec;          // undec[r]: undecided after round r (equal to nlive[r + 1]; not written on the device)
   int r;
   const uint32_t *maxl;     // longest candidate: table levels above log2 of it stay empty
   uint32_t *ctree;          // sparse: canonical-block tree (all kInf between rounds)
@@ -1035,7 +1063,8 @@ struct SelArgs {
   uint8_t *mark;            // positions covered by accepted candidates
 };
 
-__device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.undec[a.r - 1] > 0; }
+// round r runs when round r - 1 left candidates undecided: nlive[r] of them
+__device__ __forceinline__ bool sel_active(const SelArgs &a) { return a.r == 0 || a.nlive[a.r] > 0; }
 __device__ __forceinline__ uint32_t sel_nwork(const SelArgs &a) { return a.r == 0 ? a.nlive[0] : a.nwork[a.r]; }
 __device__ __forceinline__ bool sel_dense(const SelArgs &a) {
   return a.r == 0 || (uint64_t)a.nwork[a.r] * kSparseDiv > a.n;
@@ -1069,7 +1098,7 @@ __device__ __forceinline__ void paint_wave(uint8_t *mark, bool on, uint32_t s, u
 
 // Lists built by a pass (working list, next round's undecided list) reserve
 // their space once per workgroup pass of 256 * kSelItems entries.
-constexpr int kSelItems = 4;
+constexpr int kSelItems = 8;
 
 // Round r >= 1: reject undecided candidates with a painted endpoint; the
 // others form the working list.
@@ -1269,8 +1298,6 @@ __global__ void k_sel_decide(SelArgs a) {
   if (DENSE ? !sel_run_dense(a) : !sel_run_sparse(a)) return;
   __shared__ uint32_t sh[4];
   __shared__ uint32_t base;
-  __shared__ uint32_t und;
-  if (threadIdx.x == 0) und = 0;
   __syncthreads();
   const uint32_t m = sel_nwork(a);
   const uint32_t ml = *a.maxl;
@@ -1306,7 +1333,6 @@ __global__ void k_sel_decide(SelArgs a) {
     const uint32_t off = block_excl_sum<256>(mine, sh, &tot);
     if (threadIdx.x == 0) {
       base = tot ? atomicAdd(&a.nlive[a.r + 1], tot) : 0u;
-      und += tot;
     }
     __syncthreads();
     uint32_t w = base + off;
@@ -1315,7 +1341,6 @@ __global__ void k_sel_decide(SelArgs a) {
       if (kept & (1u << t)) a.pend[w++] = K[t];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && und) atomicAdd(&a.undec[a.r], und);
 }
 
 template <bool CLEAR>

@@ -1032,8 +1032,8 @@ void compact_sorted_runs(const uint32_t *order, const uint8_t *keep, const uint3
 //  * dense: a sparse table over all positions -- every working interval
 //    writes its priority into the two power-of-two blocks that tile it, then
 //    minima are pushed down level by level (levels above kSelSmall one pass
-//    each, the rest inside one tiled LDS kernel); two tables alternate and
-//    each round clears the other one as it goes;
+//    each, the rest inside one tiled LDS kernel); two tables alternate, and
+//    a dense round after the first empties its table before inserting;
 //  * sparse (at most n / kSparseDiv working candidates): canonical
 //    power-of-two blocks of each interval (at most two per level, as in a
 //    segment tree); a point's minimum is the minimum over its enclosing
@@ -1224,24 +1224,34 @@ __global__ __launch_bounds__(256) void k_sel_insert(SelArgs a) {
   }
 }
 
-// Level j -> j-1 for the large levels; clears level j of the other table.
+// A dense round r >= 1 starts by emptying the levels of its table that a
+// run can use (round 0's table is emptied before the rounds); sparse rounds
+// leave the tables alone, so a run whose later rounds are all sparse never
+// pays for it.
+__global__ void k_sel_clear(SelArgs a) {
+  if (a.r == 0 || !sel_run_dense(a)) return;
+  const uint32_t ml = *a.maxl;
+  const int lv = ml ? 32 - __clz((int)ml) : 1;
+  const uint64_t lim = (uint64_t)min(lv, a.top + 1) * a.n;
+  GRID_STRIDE(i, lim) a.Tc[i] = kInf;
+}
+
+// Level j -> j-1 for the large levels.
 __global__ void k_sel_push(SelArgs a, int j) {
-  if (!sel_run_dense(a) || (1u << j) > *a.maxl) return;  // level j empty in both tables
+  if (!sel_run_dense(a) || (1u << j) > *a.maxl) return;  // level j empty
   const uint32_t *Tj = a.Tc + (uint64_t)j * a.n;
   uint32_t *Td = a.Tc + (uint64_t)(j - 1) * a.n;
-  uint32_t *Oj = a.To + (uint64_t)j * a.n;
   const uint64_t half = 1ull << (j - 1);
   GRID_STRIDE(x, a.n) {
     uint32_t v = Td[x];
     v = min(v, Tj[x]);
     if (x >= half) v = min(v, Tj[x - half]);
     Td[x] = v;
-    Oj[x] = kInf;
   }
 }
 
 // Levels min(top, kSelSmall)..0 for one tile of positions, halos included;
-// writes level 0 and clears levels 0..J of the other table on the tile.
+// writes level 0.
 __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
   if (!sel_run_dense(a)) return;
   constexpr int HMAX = 1 << kSelSmall;
@@ -1273,10 +1283,7 @@ __global__ __launch_bounds__(256) void k_sel_push_tile(SelArgs a) {
       lo = nlo;
     }
     uint32_t *T0 = a.Tc;
-    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-      T0[x] = buf[c][x - lo];
-      for (int j = 0; j <= J; j++) a.To[(uint64_t)j * a.n + x] = kInf;
-    }
+    for (int64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) T0[x] = buf[c][x - lo];
     __syncthreads();
   }
 }
@@ -1405,6 +1412,7 @@ void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_
   const dim3 g = grid_for((live_hint + kSelItems - 1) / kSelItems, 256, 8192);
   if (r > 0) hipLaunchKernelGGL(k_sel_filter, g, dim3(256), 0, s, a);
   // dense round (each kernel returns at once when the round is sparse or not needed)
+  if (r > 0) hipLaunchKernelGGL(k_sel_clear, grid_for((uint64_t)(top + 1) * n, 256, 8192), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_sel_insert, g, dim3(256), 0, s, a);
   for (int j = top; j > kSelSmall; j--)
     hipLaunchKernelGGL(k_sel_push, grid_for(n, 256, 8192), dim3(256), 0, s, a, j);

@@ -1150,23 +1150,42 @@ __global__ void k_sel_filter(SelArgs a) {
   }
 }
 
+// Min-writes k into T[addr] for every lane with `pending` set (valid, and the
+// table held more than k when read).  Lanes that share the address of the
+// first remaining lane are combined into one atomic with their minimum, twice;
+// the others write alone.  Long periodic runs send many candidates of a
+// wavefront to one word (the right blocks of a run's candidates all end at
+// its end, every other candidate in priority order).
+__device__ __forceinline__ void min_write_grouped(uint32_t *T, uint64_t addr, uint32_t k, bool pending) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int it = 0; it < 2; it++) {
+    const uint64_t todo = __ballot(pending);
+    if (!todo) return;  // wavefront-uniform
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const uint64_t la = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(addr >> 32), leader, 64) << 32) |
+                        (uint32_t)__shfl((int)(uint32_t)addr, leader, 64);
+    const bool mine = pending && addr == la;
+    uint32_t v = mine ? k : kInf;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    if (lane == leader) atomicMin(&T[la], v);
+    if (mine) pending = false;
+  }
+  if (pending) atomicMin(&T[addr], k);
+}
+
 // Round-0 style insert: each working candidate min-writes its priority into
 // the two blocks of level floor(log2 l) that tile it.  Four candidates per
 // thread (consecutive in the working list across the workgroup), all loads
-// issued before any atomic.  Values only decrease, so a write is skipped
-// when the table already holds a smaller priority, or when the previous
-// candidate of the working list targets the same word with a priority not
-// above this one (long periodic runs send whole stretches of the list to
-// one word: the right blocks of a run's candidates all end at its end).
+// issued before any atomic; a write is skipped when the table already holds
+// a smaller priority.
 __global__ __launch_bounds__(256) void k_sel_insert(SelArgs a) {
   if (!sel_run_dense(a)) return;
-  constexpr int NT = 256, NW = NT / 64;
-  __shared__ unsigned long long lastA[4][NW][2];  // per item and wavefront: lane 63's two targets
-  __shared__ uint32_t lastK[4][NW];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NT = 256;
   const uint32_t m = sel_nwork(a);
   const uint64_t step = (uint64_t)gridDim.x * NT * 4;
-  for (uint64_t b0 = (uint64_t)blockIdx.x * NT * 4; b0 < m; b0 += step) {  // workgroup-uniform
+  for (uint64_t b0 = (uint64_t)blockIdx.x * NT * 4; b0 < m; b0 += step) {  // wavefront-uniform trip count
     uint32_t k[4], l[4], st[4], t1[4], t2[4];
     uint64_t a1[4], a2[4];
 #pragma unroll
@@ -1187,40 +1206,11 @@ __global__ __launch_bounds__(256) void k_sel_insert(SelArgs a) {
       t1[u] = k[u] != kInf ? a.Tc[a1[u]] : 0u;
       t2[u] = k[u] != kInf ? a.Tc[a2[u]] : 0u;
     }
-    if (lane == 63) {
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        lastA[u][w][0] = a1[u];
-        lastA[u][w][1] = a2[u];
-        lastK[u][w] = k[u];
-      }
-    }
-    __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      // the previous candidate of the list: lane - 1, else the previous
-      // wavefront's lane 63, else the previous item's last wavefront
-      uint64_t p1 = ((uint64_t)(uint32_t)__shfl_up((int)(uint32_t)(a1[u] >> 32), 1, 64) << 32) |
-                    (uint32_t)__shfl_up((int)(uint32_t)a1[u], 1, 64);
-      uint64_t p2 = ((uint64_t)(uint32_t)__shfl_up((int)(uint32_t)(a2[u] >> 32), 1, 64) << 32) |
-                    (uint32_t)__shfl_up((int)(uint32_t)a2[u], 1, 64);
-      uint32_t pk = (uint32_t)__shfl_up((int)k[u], 1, 64);
-      if (lane == 0) {
-        const int pu = w > 0 ? u : u - 1, pw = w > 0 ? w - 1 : NW - 1;
-        if (pu >= 0) {
-          p1 = lastA[pu][pw][0];
-          p2 = lastA[pu][pw][1];
-          pk = lastK[pu][pw];
-        } else {
-          pk = kInf;
-        }
-      }
-      const bool c1 = pk != kInf && p1 == a1[u] && pk <= k[u];
-      const bool c2 = pk != kInf && p2 == a2[u] && pk <= k[u];
-      if (!c1 && t1[u] > k[u]) atomicMin(&a.Tc[a1[u]], k[u]);
-      if (!c2 && t2[u] > k[u]) atomicMin(&a.Tc[a2[u]], k[u]);
+      min_write_grouped(a.Tc, a1[u], k[u], t1[u] > k[u]);
+      min_write_grouped(a.Tc, a2[u], k[u], t2[u] > k[u]);
     }
-    __syncthreads();
   }
 }
 

@@ -375,14 +375,16 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     // a stable sort by length leaves (length, ID) ordered; runs of equal
     // (length, ID) are then sorted by start as units of the sort engine,
     // whose last level also marks exact duplicates.
+    // the sorted starts also go straight into the engine's key buffer (the
+    // key of the last level); MSD passes may move them, so the compaction
+    // reads its own copy
     uint32_t *xs[3] = {w.tmp_a, w.tmp_b, w.tmp_c};  // length key, start, ID
     uint32_t *ys[3] = {w.s_len, w.s_start, w.s_id};
-    lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, bit_length_u64(maxl_bound), xs, ys, w.tmp_d,
-                        dc + CNT_AUX, w.tile_tmp, s);
+    lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, bit_length_u64(maxl_bound), xs, ys, B.key[0],
+                        w.tmp_d, dc + CNT_AUX, w.tile_tmp, s);
     E.reset_counters(s);
     E.round_begin(0, s);
     E.iota_val(dc + CNT_C, c_bound, s);
-    E.gather_field(0, w.tmp_b, 1, dc + CNT_C, 0, nullptr, 0, c_bound, s);  // key = start
     run_flags(w.tmp_a, w.tmp_c, dc + CNT_C, c_bound, w.keep, s);
     flag_positions(w.keep, dc + CNT_C, c_bound, w.tmp_d, dc + CNT_AUX, w.tile_tmp, s);
     E.init_runs(0, w.tmp_d, dc + CNT_AUX, dc + CNT_C, c_bound, rank_bits, s);

@@ -50,11 +50,12 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
 // Stable sort of the candidate records by length, longest first (records in
 // suffix-array order come out ordered by (length desc, ID asc)): LSD passes
 // over key = *maxl - length, carrying start and ID.  The result lands in
-// xs = {key, start, ID} arrays; ys is the alternate set; hist holds 256 u32
+// xs = {key, start, ID} arrays, the sorted starts also in start_copy
+// (nullable); ys is the alternate set; hist holds 256 u32
 // per 4096 records (at least 256); hist_n is one device word of scratch.
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
-                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *hist, uint32_t *hist_n,
-                         uint32_t *tile_tmp, hipStream_t s);
+                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
+                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s);
 // flag[i] = 1 where (key, p2) differs from position i - 1.
 void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint64_t bound, uint8_t *flag,
                hipStream_t s);

@@ -559,11 +559,22 @@ void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint3
 
 // ------------------------------------------------------------ candidates
 // Block minima of LCP (kMinFan-ary levels) for previous-smaller-value queries.
+// Full blocks are read with four 16-byte loads (levels are 16-entry aligned).
 __global__ void k_blockmin(const uint32_t *src, uint64_t nsrc, uint32_t *dst, uint64_t ndst) {
+  static_assert(kMinFan == 16, "four uint4 loads per block");
   GRID_STRIDE(k, ndst) {
     uint32_t m = 0xFFFFFFFFu;
     const uint64_t b = k * kMinFan, e = min(b + kMinFan, nsrc);
-    for (uint64_t i = b; i < e; i++) m = min(m, src[i]);
+    if (e - b == kMinFan) {
+      const uint4 *q = reinterpret_cast<const uint4 *>(src + b);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint4 v = q[u];
+        m = min(min(m, min(v.x, v.y)), min(v.z, v.w));
+      }
+    } else {
+      for (uint64_t i = b; i < e; i++) m = min(m, src[i]);
+    }
     dst[k] = m;
   }
 }
@@ -900,9 +911,10 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, const uint32_t *
   }
 }
 
+// oa2 (nullable): a second output of p1.
 __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_t *n_dev, int shift,
                                                         const uint32_t *offs, uint32_t ntiles, uint32_t *ok,
-                                                        uint32_t *oa, uint32_t *ob) {
+                                                        uint32_t *oa, uint32_t *ob, uint32_t *oa2) {
   __shared__ uint32_t wcnt[4][kLsdBins];
   __shared__ uint32_t wstart[4][kLsdBins];
   const uint64_t n = *n_dev;
@@ -955,14 +967,15 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
       ok[pos] = K[e];
       oa[pos] = A[e];
       ob[pos] = Bv[e];
+      if (oa2) oa2[pos] = A[e];
     }
     __syncthreads();
   }
 }
 
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
-                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *hist, uint32_t *hist_n,
-                         uint32_t *tile_tmp, hipStream_t s) {
+                         int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
+                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s) {
   const int passes = std::max(1, (key_bits + kLsdBits - 1) / kLsdBits);
   const uint32_t ntiles = (uint32_t)std::max<uint64_t>((bound + kLsdTile - 1) / kLsdTile, 1);
   const unsigned grid = std::min<uint32_t>(ntiles, 8192);
@@ -973,7 +986,7 @@ void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const u
     hipLaunchKernelGGL(k_lsd_hist, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles);
     scan_excl(hist, hist, hist_n, (uint64_t)kLsdBins * ntiles, tile_tmp, nullptr, s);
     hipLaunchKernelGGL(k_lsd_scatter, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles, out[0],
-                       out[1], out[2]);
+                       out[1], out[2], ps == passes - 1 ? start_copy : nullptr);
     in = LsdSrc{nullptr, nullptr, out[0], out[1], out[2]};
   }
 }

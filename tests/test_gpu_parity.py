@@ -106,6 +106,24 @@ def test_candidates_sorted(ctx, name, tokens, min_len):
         assert np.array_equal(g, ref[k]), k
 
 
+def test_candidates_one_long_run(ctx):
+    """One token followed by 50 000 distinct tokens: the 1-interval of that
+    token has 50 000 children, so about 100 000 candidates share (length 1,
+    ID) and the start-level sort takes the multi-level bucketing path."""
+    rng = np.random.default_rng(13)
+    n = 100000
+    t = np.empty(n, np.uint64)
+    t[0::2] = 0x1234567
+    t[1::2] = rng.integers(1 << 40, 1 << 62, n // 2, dtype=np.uint64)
+    for min_len in (1, 2):
+        ref = _dedup(oracle.sorted_candidates(t, min_len))
+        got = ctx.candidates_dev(_dev(t), min_len)
+        for k in ("len", "start", "id"):
+            g = got[k].cpu().numpy().astype(np.int64)
+            assert np.array_equal(g, ref[k]), (min_len, k)
+    _check_full(ctx, t, 1)
+
+
 def _check_full(ctx, tokens, min_len):
     ref = oracle.find_repeats(tokens, min_len)
     rows, occ = ctx.analyze(tokens, min_len, occurrences=True)

@@ -193,6 +193,25 @@ def roofline(kprof, steps, workload=None, lanes=1):
             "launches_per_step": kprof["launches"] / steps}
 
 
+def path_roofline(counters, n, tok_bytes, rows, sec):
+    """Whole-step algorithmic bytes over the step time: every stage's
+    compulsory reads and writes once, each sort one read plus one write of its
+    records.  Per token: rank compression (token + rank), PLCP with Phi and
+    the LCP permutation (36), candidate pass and PSV (16); per active suffix
+    of each doubling round (the token sort included) 44; per generated
+    candidate 16 (record + ID) + 24 (one sort) + 20 (greedy: record and two
+    marks); per covered position 4 (marks); per accepted occurrence 12."""
+    import torch
+    r = rows.to(torch.int64)
+    cov = int((r[:, 1] * r[:, 2]).sum().item()) if r.numel() else 0
+    c = counters.get("candidates", 0)
+    a = counters.get("accepted", 0)
+    b = ((tok_bytes + 4) * n + 44 * counters.get("active_sum", 0) + 36 * n + 16 * n + 60 * c + 4 * cov + 12 * a)
+    achieved = b / sec / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "bytes_per_step": b, "covered_positions": cov}
+
+
 def per_window_leg(ctx, dev, off, m):
     import torch
     views = [dev[int(off[w]):int(off[w + 1])] for w in range(len(off) - 1)]
@@ -333,6 +352,7 @@ def main():
         rf = roofline(kprof, steps, "config3", args.lanes)
         if rf:
             out["roofline"] = rf
+        out["path_roofline"] = path_roofline(out["counters"], total, 8, res[0], sec)
         if not args.profile_steps and not args.no_extras and args.lanes > 1:
             # the same kernel family timed with one stream only (no other lane
             # sharing the GPU while an event pair is open)
@@ -380,6 +400,7 @@ def main():
         rf = roofline(kprof, steps)
         if rf:
             out["roofline"] = rf
+        out["path_roofline"] = path_roofline(out["counters"], n, t.dtype.itemsize, res[0], sec)
         if not args.profile_steps and not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_single(t, m, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per entry of the doubling rounds' LDS sort / grouping
 # kernels: read key + suffix (8), write the sorted suffix (4), write its new
-# rank (4) and its rank snapshot for the LCP stage (4).
-LDS_SA_BYTES_PER_ENTRY = 20
+# rank (4) and its slot's still-grouped flag (1).
+LDS_SA_BYTES_PER_ENTRY = 17
 LDS_SA_TAG = 1
 
 

@@ -77,8 +77,6 @@ struct SortBufs {
 // Regroup side effects for suffix-array rounds.
 struct RankOut {
   uint32_t *rank;       // rank[pos] = 1 + SA slot of the first suffix of its group
-  uint32_t *snap;       // snapshot of this round: snap[pos], for suffixes still grouped after it
-  uint8_t *fin;         // round in which the suffix became a singleton
   uint32_t round;
   uint8_t *aflag;       // aflag[slot] = 1 if the slot's suffix is still grouped (replaces the active list)
 };

@@ -22,6 +22,7 @@ enum Cnt {
   CNT_CSKIP,       // candidates not written because they repeat the previous pair's (counted in the total)
   CNT_RANGE = 10,  // two 64-bit words, 8-byte aligned
   CNT_AUX = 14,    // scratch count of a stage (tile counts, histogram size, runs)
+  CNT_SNAPS = 15,  // 1 + last doubling round with a rank snapshot (0: none)
   CNT_COUNT = 32
 };
 
@@ -65,7 +66,6 @@ struct Workspace {
   uint64_t *d_off = nullptr;
   uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;
   uint32_t *rank = nullptr, *snap = nullptr, *sa = nullptr;
-  uint8_t *fin = nullptr;
   uint32_t *plcp = nullptr, *lcp = nullptr;
   uint32_t *lvl[8] = {nullptr};
   uint32_t *crec = nullptr;  // candidates: records (length, start, ID), three words each

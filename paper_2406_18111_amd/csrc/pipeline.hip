@@ -84,7 +84,7 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_di = L.take(N_ * 4), o_ds = L.take(N_ * 4), o_dhi = L.take(N_ * 4), o_dlo = L.take(N_ * 4);
   size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
   size_t o_wr = L.take((wantW + 1) * 4);
-  size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_fin = L.take(N_), o_sa = L.take(N_ * 4);
+  size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_sa = L.take(N_ * 4);
   size_t o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
   size_t o_lvl[8] = {0};
   {
@@ -122,7 +122,6 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   win_rows = (uint32_t *)(m + o_wr);
   rank = (uint32_t *)(m + o_rank);
   snap = (uint32_t *)(m + o_snap);
-  fin = (uint8_t *)(m + o_fin);
   sa = (uint32_t *)(m + o_sa);
   plcp = (uint32_t *)(m + o_plcp);
   lcp = (uint32_t *)(m + o_lcp);
@@ -255,6 +254,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   fill_u32(dc, CNT_RANGE, 0, s);
+  fill_u32(dc + CNT_SNAPS, 1, 0, s);
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
   // ---- order-preserving token ranks
@@ -309,7 +309,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
     if (r > 0) E.gather_sa(cur, w.rank, w.aflag, wend, (uint32_t)N, 1u << (r - 1), w.rhist, r, s);
-    RankOut R{w.rank, r >= kSnapFrom ? w.snap + (size_t)r * N : nullptr, w.fin, (uint32_t)r, w.aflag};
+    RankOut R{w.rank, (uint32_t)r, w.aflag};
     if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rank_bits, s);
     const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
     if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
@@ -319,6 +319,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       w.kround[w.kev_n++] = r;
     }
     E.bulk_sa(cur, R, rank_bits, act, s);
+    // rounds >= kSnapFrom: the rank array after the round, for the LCP walk
+    if (r >= kSnapFrom) snapshot_ranks(w.rank, w.snap + (size_t)r * N, N, w.rhist + 4 * (r - 1), dc + CNT_SNAPS, r, s);
     cur ^= 1;
     r++;
     if (!host) {
@@ -351,9 +353,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     return 0;
   }
 
-  // ---- LCP via Phi / PLCP (lifting over rounds r-1..0; more levels than
-  // needed are harmless: no suffix pair is grouped beyond its last round)
-  build_lcp(w.sa, w.rank, N, wbeg, wend, w.snap, w.fin, key0, r - 1, w.plcp, w.lcp, s);
+  // ---- LCP via Phi / PLCP (lifting over the snapshots of the rounds that
+  // sorted something, at most r-1)
+  build_lcp(w.sa, w.rank, N, wbeg, wend, w.snap, dc + CNT_SNAPS, key0, r - 1, w.plcp, w.lcp, s);
   stamp(w, 3, s, stamps);
   if (stop == Stop::LCP) return read_counters(w, s);
 

@@ -397,8 +397,6 @@ __global__ __launch_bounds__(kLdsThreads) void k_lds_sort(SortBufs B, int cur, R
       B.val[0][p] = v;
       if (MODE == MODE_SA) {
         if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[v] = gpos + 1;  // else unchanged
-        if (R.snap && !single) R.snap[v] = gpos + 1;  // a singleton's snapshot is never read
-        if (single) R.fin[v] = (uint8_t)R.round;
       }
       if (last_level) {
         keep[p] = bnd ? 1 : 0;
@@ -580,8 +578,6 @@ __global__ __launch_bounds__(256, 5) void k_wave_sort(SortBufs B, int cur, RankO
         B.val[0][p] = val;
         if (MODE == MODE_SA) {
           if (!((u.len & kHeadBit) && gpos == u.start)) R.rank[val] = gpos + 1;  // else unchanged
-          if (R.snap && !single) R.snap[val] = gpos + 1;
-          if (single) R.fin[val] = (uint8_t)R.round;
         }
         if (last_level) keep[p] = bnd ? 1 : 0;
       }
@@ -872,8 +868,6 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
         B.val[0][slot] = v;
         if (MODE == MODE_SA) {
           if (!((u.len & kHeadBit) && head == u.start)) R.rank[v] = head + 1;  // else unchanged
-          if (R.snap && gcnt >= 2) R.snap[v] = head + 1;
-          if (gcnt == 1) R.fin[v] = (uint8_t)R.round;
           if (R.aflag) R.aflag[slot] = gcnt >= 2 ? 1 : 0;
         }
         if (last_level) {
@@ -1113,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
 
 // --------------------------------------------------- bulk (one-group) units
 // Pieces whose key bits are used up are one group each.  Processed chunk by
-// chunk: SA-mode ranks/snapshots and grouped-slot flags, copy-back from the
+// chunk: SA-mode ranks and grouped-slot flags, copy-back from the
 // alternate buffer, the next level's active slots (plain mode), and (by the
 // unit's first chunk) the unit itself as a large unit of the next level.
 template <int MODE>
@@ -1141,7 +1135,6 @@ __global__ __launch_bounds__(256) void k_bulk(SortBufs B, int cur, RankOut R, ui
         if (alt) B.val[0][p] = v;
         if (MODE == MODE_SA) {
           R.rank[v] = bu.start + 1;
-          if (R.snap) R.snap[v] = bu.start + 1;
           if (R.aflag) R.aflag[p] = 1;
         }
         if (last_level) keep[p] = (p == bu.start) ? 1 : 0;

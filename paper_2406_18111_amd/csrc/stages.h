@@ -32,9 +32,15 @@ void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t 
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 
-// LCP of adjacent suffixes.  rank: final ranks of the suffix sort (1 + slot).
+// Copy of the rank array after doubling round r into its snapshot level,
+// taken only when the round sorted something (*act_dev: slots that entered
+// it); *snaps then becomes r + 1.
+void snapshot_ranks(const uint32_t *rank, uint32_t *snap_r, uint64_t n, const uint32_t *act_dev, uint32_t *snaps,
+                    int r, hipStream_t s);
+// LCP of adjacent suffixes.  rank: final ranks of the suffix sort (1 + slot);
+// snap: level j at snap + j * n for kSnapFrom <= j < *snaps (and j <= top).
 void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-               const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp,
+               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *plcp,
                uint32_t *lcp, hipStream_t s);
 
 // Candidates are written as records of kCandWords words: length, start, ID.

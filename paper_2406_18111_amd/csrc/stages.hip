@@ -384,18 +384,48 @@ void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *w
 }
 
 // ------------------------------------------------------------------- LCP
+// Snapshot level j is the whole rank array after doubling round j: two
+// suffixes of one window carry equal ranks there iff their 2^j-prefixes are
+// equal (a suffix alone in its group has a rank no other suffix has).  It is
+// a coalesced copy taken once per round instead of a scattered write of every
+// grouped suffix's rank by the sort kernels.
+__global__ void k_snapshot(const uint32_t *rank, uint32_t *snap_r, uint64_t n, const uint32_t *act_dev,
+                           uint32_t *snaps, int r) {
+  if (*act_dev == 0) return;  // nothing was sorted: no later level is read
+  if (blockIdx.x == 0 && threadIdx.x == 0) *snaps = (uint32_t)r + 1;
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
+  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;  // coalesced for each u
+      v[u] = i < n ? rank[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      if (i < n) snap_r[i] = v[u];
+    }
+  }
+}
+
+void snapshot_ranks(const uint32_t *rank, uint32_t *snap_r, uint64_t n, const uint32_t *act_dev, uint32_t *snaps,
+                    int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_snapshot, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, rank, snap_r, n, act_dev, snaps,
+                     r);
+}
+
 // lcp(x, y) >= acc known; extend by binary lifting over the per-round rank
-// snapshots: 2^j-prefixes at x+acc and y+acc are equal iff both suffixes were
-// still in a shared group after round j and carried the same rank then.
-// Snapshots exist for rounds >= kSnapFrom only; the last < 2^kSnapFrom
-// tokens are compared directly (key0: order-preserving token keys).
+// snapshots: 2^j-prefixes at x+acc and y+acc are equal iff their ranks after
+// round j are equal.  Snapshots exist for rounds >= kSnapFrom only; the last
+// < 2^kSnapFrom tokens are compared directly (key0: order-preserving token
+// keys).
 __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t acc, uint32_t we, int top,
-                                             const uint32_t *snap, uint64_t n, const uint8_t *fin,
-                                             const uint32_t *key0) {
+                                             const uint32_t *snap, uint64_t n, const uint32_t *key0) {
   for (int j = top; j >= kSnapFrom; j--) {
     const uint32_t a = x + acc, b = y + acc;
     if (a >= we || b >= we) break;
-    if (fin[a] > j && fin[b] > j && snap[(uint64_t)j * n + a] == snap[(uint64_t)j * n + b]) acc += 1u << j;
+    if (snap[(uint64_t)j * n + a] == snap[(uint64_t)j * n + b]) acc += 1u << j;
   }
   // the remaining < 2^kSnapFrom tokens: issue all loads at once, then find
   // the first mismatch (or the window end)
@@ -422,14 +452,13 @@ constexpr int kPlcpChunk = 8;                        // positions per thread
 constexpr int kPlcpSpan = 256 * kPlcpChunk;          // positions per workgroup pass
 constexpr int kPlcpMargin = 256;                     // staged tokens past the span
 
-// lcp(x, y) from scratch.  The levels at which both suffixes were still
-// grouped (below both fin values) are probed kSeedGroup at a time with
-// independent loads: equal 2^j-prefixes imply equal 2^i-prefixes for i < j, so
-// the highest equal level j* gives lcp in [2^j*, 2^(j*+1)), and lifting goes
-// on below it.
+// lcp(x, y) from scratch.  The snapshot levels are probed kSeedGroup at a
+// time with independent loads: equal 2^j-prefixes imply equal 2^i-prefixes
+// for i < j, so the highest equal level j* gives lcp in [2^j*, 2^(j*+1)), and
+// lifting goes on below it.
 __device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, uint32_t we, int top, const uint32_t *snap,
-                                             uint64_t n, const uint8_t *fin, const uint32_t *key0) {
-  const int J = min(top, (int)min(fin[x], fin[y]) - 1);
+                                             uint64_t n, const uint32_t *key0) {
+  const int J = top;
   int best = kSnapFrom - 1;
   for (int lo = kSnapFrom; lo <= J; lo += kSeedGroup) {
 #pragma unroll
@@ -439,8 +468,8 @@ __device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, uint32_t we
     }
     if (best < lo + kSeedGroup - 1) break;  // a level of this group differed (or J ended it)
   }
-  if (best < kSnapFrom) return lcp_lift(x, y, 0u, we, kSnapFrom - 1, snap, n, fin, key0);  // tail only
-  return lcp_lift(x, y, 1u << best, we, best - 1, snap, n, fin, key0);
+  if (best < kSnapFrom) return lcp_lift(x, y, 0u, we, kSnapFrom - 1, snap, n, key0);  // tail only
+  return lcp_lift(x, y, 1u << best, we, best - 1, snap, n, key0);
 }
 
 // Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of kPlcpChunk
@@ -453,9 +482,11 @@ __device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, uint32_t we
 // the Phi side of the comparisons reads tokens from global memory.
 __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t *rank, uint64_t n,
                                               const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
-                                              const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp) {
+                                              const uint32_t *snaps, const uint32_t *key0, int top_bound,
+                                              uint32_t *plcp) {
   __shared__ uint32_t ps[pad16(kPlcpSpan)];
   __shared__ uint32_t ks[pad16(kPlcpSpan + kPlcpMargin)];
+  const int top = min(top_bound, (int)*snaps - 1);  // last snapshot level (< kSnapFrom: none)
   const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
   for (uint64_t sp = blockIdx.x; sp < nspan; sp += gridDim.x) {
     const uint64_t j0 = sp * kPlcpSpan;
@@ -486,7 +517,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
           h = 0;
           fresh = true;
         } else if (fresh) {
-          h = lcp_seed((uint32_t)j, y, we, top, snap, n, fin, key0);
+          h = lcp_seed((uint32_t)j, y, we, top, snap, n, key0);
           fresh = false;
         } else {
           // extend from h - 1, kExt tokens per step with independent loads
@@ -512,7 +543,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
             h += m;
             if (m < (uint32_t)kExt) break;
             steps += kExt;
-            if (steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, fin, key0); break; }
+            if (steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, key0); break; }
           }
         }
         ps[pad16(c)] = h;  // this thread's own slot, already read
@@ -549,11 +580,11 @@ __global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, cons
 }
 
 void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-               const uint32_t *snap, const uint8_t *fin, const uint32_t *key0, int top, uint32_t *plcp,
+               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *plcp,
                uint32_t *lcp, hipStream_t s) {
   const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
   hipLaunchKernelGGL(k_plcp, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(nspan, 1), 8192)), dim3(256), 0, s,
-                     sa, rank, n, wbeg, wend, snap, fin, key0, top, plcp);
+                     sa, rank, n, wbeg, wend, snap, snaps, key0, top, plcp);
   hipLaunchKernelGGL(k_lcp, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
 }
 

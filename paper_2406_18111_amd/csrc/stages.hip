@@ -452,19 +452,25 @@ constexpr int kPlcpChunk = 8;                        // positions per thread
 constexpr int kPlcpSpan = 256 * kPlcpChunk;          // positions per workgroup pass
 constexpr int kPlcpMargin = 256;                     // staged tokens past the span
 
-// lcp(x, y) from scratch.  The snapshot levels are probed kSeedGroup at a
-// time with independent loads: equal 2^j-prefixes imply equal 2^i-prefixes
-// for i < j, so the highest equal level j* gives lcp in [2^j*, 2^(j*+1)), and
-// lifting goes on below it.
-__device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, uint32_t we, int top, const uint32_t *snap,
-                                             uint64_t n, const uint32_t *key0) {
+// lcp(x, y) from scratch for y = Phi[x], the suffix just before x in the
+// suffix array (rank: final ranks, rank[x] = x's slot + 1).  Groups are refined in
+// place, so x's final slot lies in its group's slot range after every round,
+// and y shares that group iff the group starts before x's slot: iff x's
+// snapshot rank (group start + 1) is below rank[x].  Only x's snapshots are read
+// (neighbouring positions for neighbouring threads), kSeedGroup levels at a
+// time with independent loads; equal 2^j-prefixes imply equal 2^i-prefixes
+// for i < j, so the highest shared level j* gives lcp in [2^j*, 2^(j*+1)),
+// and lifting goes on below it.
+__device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, const uint32_t *rank, uint32_t we, int top,
+                                             const uint32_t *snap, uint64_t n, const uint32_t *key0) {
+  const uint32_t rx = rank[x];  // issued with the probe loads (their addresses do not depend on it)
   const int J = top;
   int best = kSnapFrom - 1;
   for (int lo = kSnapFrom; lo <= J; lo += kSeedGroup) {
 #pragma unroll
     for (int k = 0; k < kSeedGroup; k++) {
       const int j = lo + k;
-      if (j <= J && snap[(uint64_t)j * n + x] == snap[(uint64_t)j * n + y]) best = j;
+      if (j <= J && snap[(uint64_t)j * n + x] < rx) best = j;
     }
     if (best < lo + kSeedGroup - 1) break;  // a level of this group differed (or J ended it)
   }
@@ -517,7 +523,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
           h = 0;
           fresh = true;
         } else if (fresh) {
-          h = lcp_seed((uint32_t)j, y, we, top, snap, n, key0);
+          h = lcp_seed((uint32_t)j, y, rank, we, top, snap, n, key0);
           fresh = false;
         } else {
           // extend from h - 1, kExt tokens per step with independent loads

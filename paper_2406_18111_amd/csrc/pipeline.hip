@@ -295,6 +295,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   // rounds never alter the result.  Large units only arise from large units
   // of the previous round, so once none are left the MSD passes are skipped.
   const uint32_t rank_bits = (uint32_t)bit_length_u64(N);
+  // rounds >= 1 bucket their keys (ranks) relative to the window start:
+  // values 0..longest window
+  const uint32_t rel_bits = (uint32_t)bit_length_u64(std::max<uint64_t>(maxwin, 1));
   const int r_max = ceil_log2_u64(std::max<uint64_t>(maxwin, 2)) + 1;  // rounds 0..r_max-1 suffice
   int cur = 0;
   E.reset_counters(s);
@@ -310,15 +313,15 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     if (r >= w.nsnap) return -4;
     if (r > 0) E.gather_sa(cur, w.rank, w.aflag, wend, (uint32_t)N, 1u << (r - 1), w.rhist, r, s);
     RankOut R{w.rank, (uint32_t)r, w.aflag};
-    if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rank_bits, s);
+    if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rel_bits, s, r == 0 ? nullptr : wbeg);
     const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
     if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
-    E.lds_sa(cur, R, rank_bits, act, s);
+    E.lds_sa(cur, R, rel_bits, act, s);
     if (timed) {
       APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n + 1], s));
       w.kround[w.kev_n++] = r;
     }
-    E.bulk_sa(cur, R, rank_bits, act, s);
+    E.bulk_sa(cur, R, rel_bits, act, s);
     // rounds >= kSnapFrom: the rank array after the round, for the LCP walk
     if (r >= kSnapFrom) snapshot_ranks(w.rank, w.snap + (size_t)r * N, N, w.rhist + 4 * (r - 1), dc + CNT_SNAPS, r, s);
     cur ^= 1;

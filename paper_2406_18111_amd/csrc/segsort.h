@@ -30,7 +30,10 @@ class SortEngine {
   void gather_field(int cur, const uint32_t *field, int stride, const uint32_t *all_dev, int sub,
                     const uint32_t *c_dev, uint32_t c, uint64_t bound, hipStream_t s);
   void iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s);
-  void msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s);
+  // slot_base (nullable): digits come from key - slot_base[unit start] (key 0
+  // stays 0), so keys that are ranks inside a window need only the window's
+  // bits; max_bits counts those bits.
+  void msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s, const uint32_t *slot_base = nullptr);
   void lds_sa(int cur, RankOut R, uint32_t next_bits, uint64_t work_hint, hipStream_t s);
   void lds_plain(int cur, uint32_t next_bits, int last_level, uint8_t *keep, uint64_t work_hint,
                  hipStream_t s);

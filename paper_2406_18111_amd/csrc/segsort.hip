@@ -929,7 +929,10 @@ __device__ __forceinline__ void digit_params(uint32_t bits, uint32_t dbits, uint
   mask = (d >= 32) ? 0xFFFFFFFFu : ((1u << d) - 1u);
 }
 
-__global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level) {
+// Digit of a key relative to its unit's base (0 stays 0: past the window end).
+__device__ __forceinline__ uint32_t rel_key(uint32_t k, uint32_t base) { return k ? k - base : 0u; }
+
+__global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level, const uint32_t *slot_base) {
   __shared__ uint32_t h[kBins];
   uint32_t units, total;
   list_size(B.ctr->big_pk[cur][level], B.big_cap, units, total);
@@ -944,8 +947,9 @@ __global__ __launch_bounds__(256) void k_msd_hist(SortBufs B, int cur, int level
     const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
     const uint32_t *key = key_buf(B, (bu.meta & kMetaAlt) ? 1 : 0);
+    const uint32_t base = slot_base ? slot_base[bu.start] : 0u;
     for (uint32_t p = lo + threadIdx.x; p < hi; p += blockDim.x)
-      agg_add(&h[(key[p] >> shift) & mask], 1u);
+      agg_add(&h[(rel_key(key[p], base) >> shift) & mask], 1u);
     __syncthreads();
     uint32_t *gh = B.hist + (size_t)u * kBins;
     for (int b = threadIdx.x; b <= (int)mask; b += blockDim.x)
@@ -1059,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_msd_scan(SortBufs B, int cur, int level
   }
 }
 
-__global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int level) {
+__global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int level, const uint32_t *slot_base) {
   constexpr int NT = 256;
   constexpr int PER = kChunk / NT;
   __shared__ uint32_t cnt[kBins];
@@ -1077,13 +1081,14 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
     const uint32_t lo = bu.start + (ch - bu.cbase) * kChunk;
     const uint32_t hi = min(lo + (uint32_t)kChunk, bu.start + bu.len);
     const int sb = (bu.meta & kMetaAlt) ? 1 : 0, db = sb ^ 1;
+    const uint32_t base = slot_base ? slot_base[bu.start] : 0u;
     uint32_t kk[PER], vv[PER], oo[PER];
     for (int q = 0; q < PER; q++) {
       const uint32_t p = lo + threadIdx.x + q * NT;
       if (p < hi) {
         kk[q] = key_buf(B, sb)[p];
         vv[q] = val_buf(B, sb)[p];
-        oo[q] = agg_inc(&cnt[(kk[q] >> shift) & mask]);
+        oo[q] = agg_inc(&cnt[(rel_key(kk[q], base) >> shift) & mask]);
       }
     }
     __syncthreads();
@@ -1096,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_msd_scatter(SortBufs B, int cur, int le
     for (int q = 0; q < PER; q++) {
       const uint32_t p = lo + threadIdx.x + q * NT;
       if (p < hi) {
-        const uint32_t dst = cnt[(kk[q] >> shift) & mask] + oo[q];
+        const uint32_t dst = cnt[(rel_key(kk[q], base) >> shift) & mask] + oo[q];
         key_buf(B, db)[dst] = kk[q];
         val_buf(B, db)[dst] = vv[q];
       }
@@ -1256,13 +1261,13 @@ void SortEngine::iota_val(const uint32_t *n_dev, uint64_t bound, hipStream_t s) 
   hipLaunchKernelGGL(k_iota_val, grid_for(bound, 256, 4096), dim3(256), 0, s, b_, n_dev);
 }
 
-void SortEngine::msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s) {
+void SortEngine::msd(int cur, uint64_t work_hint, int max_bits, hipStream_t s, const uint32_t *slot_base) {
   const unsigned g = (unsigned)std::min<uint64_t>(4096, std::max<uint64_t>(256, work_hint / kChunk + 1));
   const int levels = std::min(kMaxMsdLevels, (max_bits + (int)b_.digit_bits - 1) / (int)b_.digit_bits);
   for (int level = 0; level < levels; level++) {
-    hipLaunchKernelGGL(k_msd_hist, dim3(g), dim3(256), 0, s, b_, cur, level);
+    hipLaunchKernelGGL(k_msd_hist, dim3(g), dim3(256), 0, s, b_, cur, level, slot_base);
     hipLaunchKernelGGL(k_msd_scan, dim3(256), dim3(256), 0, s, b_, cur, level);
-    hipLaunchKernelGGL(k_msd_scatter, dim3(g), dim3(256), 0, s, b_, cur, level);
+    hipLaunchKernelGGL(k_msd_scatter, dim3(g), dim3(256), 0, s, b_, cur, level, slot_base);
   }
 }
 

@@ -8,11 +8,14 @@
 // membership, and the final order is fully determined once all groups are
 // singletons or exact duplicates.
 //
-// Units of length <= 2^tile_log are sorted in LDS by bitonic networks (one
-// workgroup sorts 2^(tile_log-c) units of class c side by side).  Longer units
-// are split by MSD bucketing passes on digit_bits-bit digits (histogram, scan,
-// scatter into the alternate buffer) until the pieces fit the LDS path or all
-// key bits are consumed (the piece then is one group).
+// Units of up to 64 entries are sorted one per wavefront row in registers;
+// units of 65..2^tile_log entries are grouped in LDS (a hash table counts the
+// distinct keys of a tile's units, only those are sorted, and every entry is
+// placed at its group's offset), with an LDS bitonic sort for class 13 when
+// the tile is 8192 entries.  Longer units are split by MSD bucketing passes on
+// digit_bits-bit digits (histogram, scan, scatter into the alternate buffer)
+// until the pieces fit the LDS path or all key bits are consumed (the piece
+// then is one group).
 #include "apo_internal.h"
 #include "device_util.h"
 #include "segsort.h"

@@ -264,7 +264,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     const uint64_t hc = pow2_at_least(2 * N);
     hash_clear(w.htab, hc - 1, s);
-    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, s);
+    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
     uint64_t nd_bound = N;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;
@@ -278,7 +278,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int str[2] = {1, 1};
     sort_plain(w, dc + CNT_ND, nd_bound, f, str, sub, cd, bb, 2, nullptr, s);
     hash_assign(B.val[0], dc + CNT_ND, w.dist_slot, w.hrank, nd_bound, s);
-    hash_lookup(tok, N, w.htab, hc - 1, w.hrank, w.tokrank, s);
+    hash_rank(w.tokrank, N, w.hrank, w.tokrank, s);  // slots -> ranks in place
     key0 = w.tokrank;
     bits0 = (uint32_t)bit_length_u64(nd_bound);
   } else {

@@ -218,6 +218,7 @@ void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
 constexpr int kHashTile = 2048, kHashLds = 4096;
 constexpr uint64_t kEmpty = ~0ull;
 
+// Returns whether the key was new; *slot receives its slot either way.
 __device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t mask,
                                               uint64_t *slot) {
   if (key == kEmpty) {
@@ -234,25 +235,40 @@ __device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *
         return true;
       }
     }
-    if (cur == key) return false;
+    if (cur == key) {
+      *slot = h;
+      return false;
+    }
     h = (h + 1) & mask;
   }
 }
 
+// Also writes every token's global slot to tok_slot (the tile's first
+// occurrence of a value finds it; the local table hands it to the others), so
+// the ranks come later from one gather per token instead of a second probe.
 __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, unsigned long long *tab,
                                                      uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
-                                                     uint32_t *nd) {
+                                                     uint32_t *nd, uint32_t *tok_slot) {
+  constexpr int NT = 256;
+  constexpr int PER = kHashTile / NT;
   __shared__ uint64_t lt[kHashTile];   // the tile's tokens
-  __shared__ uint32_t ls[kHashLds];    // local table: tile index + 1 (0 = empty)
+  __shared__ uint32_t ls[kHashLds];    // local table: tile index + 1 (0 = empty); then global slots
   __shared__ uint32_t new_i[kHashTile], new_h[kHashTile];
   __shared__ uint32_t nnew, nbase;
   for (uint64_t t0 = (uint64_t)blockIdx.x * kHashTile; t0 < n; t0 += (uint64_t)gridDim.x * kHashTile) {
     const uint32_t m = (uint32_t)min((uint64_t)kHashTile, n - t0);
-    for (uint32_t k = threadIdx.x; k < kHashLds; k += blockDim.x) ls[k] = 0;
-    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) lt[k] = tok[t0 + k];
+    for (uint32_t k = threadIdx.x; k < kHashLds; k += NT) ls[k] = 0;
+    for (uint32_t k = threadIdx.x; k < m; k += NT) lt[k] = tok[t0 + k];
     if (threadIdx.x == 0) nnew = 0;
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+    uint32_t hl[PER], gs[PER];  // local table entry of each token; global slot (first occurrences)
+    uint32_t first = 0;
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const uint32_t k = threadIdx.x + (uint32_t)u * NT;
+      hl[u] = 0;
+      gs[u] = 0;
+      if (k >= m) continue;
       const uint64_t key = lt[k];
       uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
       while (true) {
@@ -265,13 +281,25 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
             new_i[q] = (uint32_t)(t0 + k);
             new_h[q] = (uint32_t)slot;
           }
+          gs[u] = (uint32_t)slot;
+          first |= 1u << u;
           break;
         }
         if (lt[prev - 1] == key) break;
         h = (h + 1) & (kHashLds - 1);
       }
+      hl[u] = h;
     }
+    __syncthreads();  // every probe of the local table is done
+#pragma unroll
+    for (int u = 0; u < PER; u++)
+      if (first & (1u << u)) ls[hl[u]] = gs[u];
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const uint32_t k = threadIdx.x + (uint32_t)u * NT;
+      if (k < m) tok_slot[t0 + k] = ls[hl[u]];
+    }
     if (threadIdx.x == 0) nbase = nnew ? atomicAdd(nd, nnew) : 0u;
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < nnew; k += blockDim.x) {
@@ -298,34 +326,22 @@ __global__ void k_hash_assign(const uint32_t *sorted_d, const uint32_t *nd, cons
   GRID_STRIDE(q, m) slot_rank[dist_slot[sorted_d[q]]] = (uint32_t)q + 1u;
 }
 
-// Four tokens per thread: the first probes and the rank reads of the four
-// are issued together (further probes are rare at load <= 1/2).
-__global__ void k_hash_lookup(const uint64_t *tok, uint64_t n, const unsigned long long *tab, uint64_t mask,
-                              const uint32_t *slot_rank, uint32_t *out) {
+// rank of every token from its slot (in place: out may be tok_slot); four
+// tokens per thread with the loads issued together.
+__global__ void k_hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out) {
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
   for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
-    uint64_t key[4], h[4], t[4];
+    uint32_t sl[4], r[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
-      key[u] = i < n ? tok[i] : kEmpty;
+      sl[u] = i < n ? tok_slot[i] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-      h[u] = key[u] != kEmpty ? mix64(key[u]) & mask : mask + 1;  // the empty key has its own slot
-      t[u] = key[u] != kEmpty ? tab[h[u]] : kEmpty;
+      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
+      r[u] = i < n ? slot_rank[sl[u]] : 0u;
     }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      if (key[u] == kEmpty) continue;
-      while (t[u] != key[u]) {  // every token was inserted
-        h[u] = (h[u] + 1) & mask;
-        t[u] = tab[h[u]];
-      }
-    }
-    uint32_t r[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) r[u] = slot_rank[h[u]];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
@@ -344,10 +360,11 @@ void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s) {
 }
 
 void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
-                 uint32_t *dist_slot, uint32_t *nd, hipStream_t s) {
+                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s) {
   const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
   hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
-                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd);
+                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd,
+                     tok_slot);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -358,10 +375,8 @@ void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *d
   hipLaunchKernelGGL(k_hash_assign, grid_for(hint, 256, 8192), dim3(256), 0, s, sorted_d, nd, dist_slot,
                      slot_rank);
 }
-void hash_lookup(const uint64_t *tok, uint64_t n, const uint64_t *tab, uint64_t mask, const uint32_t *slot_rank,
-                 uint32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_hash_lookup, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, tok, n,
-                     reinterpret_cast<const unsigned long long *>(tab), mask, slot_rank, out);
+void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_hash_rank, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, tok_slot, n, slot_rank, out);
 }
 
 // -------------------------------------------------------------- windows

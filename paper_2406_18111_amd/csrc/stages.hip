@@ -967,8 +967,12 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, const uint32_t *
 __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_t *n_dev, int shift,
                                                         const uint32_t *offs, uint32_t ntiles, uint32_t *ok,
                                                         uint32_t *oa, uint32_t *ob, uint32_t *oa2) {
-  __shared__ uint32_t wcnt[4][kLsdBins];
-  __shared__ uint32_t wstart[4][kLsdBins];
+  static_assert(kLsdBins == kLsdNT, "one digit per thread in the run offsets");
+  __shared__ uint32_t wcnt[4][kLsdBins];   // per-wavefront digit counts; then tile-local run starts
+  __shared__ uint32_t wstart[4][kLsdBins];  // global run starts
+  __shared__ uint32_t lg[kLsdTile];         // global position of each tile-local sorted slot
+  __shared__ uint32_t lv[kLsdTile];         // one output array's values in tile-local sorted order
+  __shared__ uint32_t sh[kLsdNT / 64];
   const uint64_t n = *n_dev;
   const uint32_t maxl = in.maxl ? *in.maxl : 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1002,26 +1006,54 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
       rank[e] = base + (uint32_t)__popcll(peers & lt);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) {
+    {
+      // run starts of (wavefront, digit): global from the scanned
+      // histograms, tile-local from a scan of the tile's digit totals
+      const int d = threadIdx.x;
+      uint32_t c[4], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        c[q] = wcnt[q][d];
+        tot += c[q];
+      }
+      uint32_t ttot;
+      uint32_t lrun = block_excl_sum<kLsdNT>(tot, sh, &ttot);  // (has barriers)
       uint32_t run = offs[(uint64_t)d * ntiles + t];
+#pragma unroll
       for (int q = 0; q < 4; q++) {
         wstart[q][d] = run;
-        run += wcnt[q][d];
+        wcnt[q][d] = lrun;
+        run += c[q];
+        lrun += c[q];
       }
     }
     __syncthreads();
+    // every entry's tile-local sorted slot (kept in rank[]) and global position
 #pragma unroll
     for (int e = 0; e < kLsdSlots; e++) {
       const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
       if (i >= n) continue;
       const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
-      const uint32_t pos = wstart[w][d] + rank[e];
-      ok[pos] = K[e];
-      oa[pos] = A[e];
-      ob[pos] = Bv[e];
-      if (oa2) oa2[pos] = A[e];
+      const uint32_t loc = wcnt[w][d] + rank[e];
+      lg[loc] = wstart[w][d] + rank[e];
+      rank[e] = loc;
     }
-    __syncthreads();
+    // each output array goes through LDS in sorted order, so consecutive
+    // threads write consecutive words of a digit's run
+    const uint32_t cnt = (uint32_t)min((uint64_t)kLsdTile, n - tile0);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      uint32_t *out = a == 0 ? ok : a == 1 ? oa : a == 2 ? ob : oa2;
+      if (!out) continue;  // uniform
+#pragma unroll
+      for (int e = 0; e < kLsdSlots; e++) {
+        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+        if (i < n) lv[rank[e]] = a == 0 ? K[e] : a == 2 ? Bv[e] : A[e];
+      }
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < cnt; j += kLsdNT) out[lg[j]] = lv[j];
+      __syncthreads();
+    }
   }
 }
 

@@ -700,11 +700,17 @@ constexpr int kCandItems = 8;
 // tile's skipped repeats and longest length go to tile_val[ntiles + tile]
 // and tile_val[2 ntiles + tile] (summed by k_tile_totals, not by atomics on
 // one word from every workgroup).
+// The write pass stages the tile's records in LDS, kCandStage at a time, so
+// they leave in consecutive words (a thread's own records are consecutive,
+// but neighbouring threads' are not).
+constexpr uint32_t kCandStage = 1024;
+
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
                                                     uint32_t *tile_val, uint32_t *crec) {
   __shared__ uint32_t sh[4];
+  __shared__ uint32_t stage[WRITE ? kCandStage * kCandWords : 1];
   __shared__ uint32_t bmax;
   // level pointers in LDS: per-lane indexing of the kernel argument would
   // cost a dependent global load per level step
@@ -810,17 +816,33 @@ __global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const ui
       }
       continue;
     }
-    uint32_t *r = crec + kCandWords * (uint64_t)(tile_val[tile] + off);
+    uint32_t id[kCandItems + 1];
 #pragma unroll
-    for (int k = 1; k < kCandItems + 1; k++) {
-      if (!L[k]) continue;
-      const uint32_t id = (uint32_t)(psv_query(slv, ssz, M.nlev, ib + k - 1, L[k]) + 1);
-      if (!(D[k] && D[k - 1] && L[k - 1] == L[k])) {
-        r[0] = L[k]; r[1] = A[k]; r[2] = id;
-        r += kCandWords;
+    for (int k = 1; k < kCandItems + 1; k++)
+      id[k] = L[k] ? (uint32_t)(psv_query(slv, ssz, M.nlev, ib + k - 1, L[k]) + 1) : 0u;
+    uint32_t *dst = crec + kCandWords * (uint64_t)tile_val[tile];
+    for (uint32_t w0 = 0; w0 < tot; w0 += kCandStage) {  // workgroup-uniform
+      uint32_t q = off;  // the thread's next record index within the tile
+#pragma unroll
+      for (int k = 1; k < kCandItems + 1; k++) {
+        if (!L[k]) continue;
+        if (!(D[k] && D[k - 1] && L[k - 1] == L[k])) {
+          if (q >= w0 && q - w0 < kCandStage) {
+            uint32_t *r = stage + kCandWords * (q - w0);
+            r[0] = L[k]; r[1] = A[k]; r[2] = id[k];
+          }
+          q++;
+        }
+        if (q >= w0 && q - w0 < kCandStage) {
+          uint32_t *r = stage + kCandWords * (q - w0);
+          r[0] = L[k]; r[1] = B[k]; r[2] = id[k];
+        }
+        q++;
       }
-      r[0] = L[k]; r[1] = B[k]; r[2] = id;
-      r += kCandWords;
+      __syncthreads();
+      const uint32_t words = kCandWords * min(kCandStage, tot - w0);
+      for (uint32_t j = threadIdx.x; j < words; j += blockDim.x) dst[(uint64_t)kCandWords * w0 + j] = stage[j];
+      __syncthreads();
     }
   }
 }

@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--lanes", type=int, default=3, help="concurrent window groups per batch (1..4)")
-    ap.add_argument("--no-tune", action="store_true", help="skip the untimed batch autotuning before the timed steps")
+    ap.add_argument("--no-tune", action="store_true", help="skip the untimed autotuning before the timed steps")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many steps of the main workload (for profilers)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -381,14 +381,26 @@ def main():
         if not args.profile_steps and not args.no_extras:
             t1, m1, _ = single_workload("config1")
             d1 = torch.from_numpy(t1.view(np.int64)).cuda()
+            tuned1 = None
+            if not args.no_tune:
+                # untimed: the tuner's table is per input size, so the single
+                # window gets its own entry instead of the batch's
+                tl1, db1, tms1 = ctx.tune(d1, m1, reps=3)
+                tuned1 = {"tile_log": tl1, "digit_bits": db1, "tuning_ms_at_best": tms1}
             ctx.analyze_dev(d1, m1)
             s1, _, st1, _ = timed_steps(ctx, lambda: ctx.analyze_dev(d1, m1), 10)
-            out["single_window_config1"] = {"tokens_per_s": len(t1) / s1, "ms": s1 * 1e3, "stage_ms": st1}
+            out["single_window_config1"] = {"tokens_per_s": len(t1) / s1, "ms": s1 * 1e3, "stage_ms": st1,
+                                            "tuned": tuned1}
             out["serving"] = serve_leg(args.serve_seconds, args.serve_slots)
     else:
         t, m, desc = single_workload(args.workload)
         n = len(t)
         dev = torch.from_numpy(t.view(np.int64) if t.dtype == np.uint64 else t.view(np.int32)).cuda()
+        tuned = None
+        if not args.no_tune and not args.profile_steps:
+            # untimed: the project's autotuner picks the LDS tile and MSD digit width on this window
+            tl, db, tms = ctx.tune(dev, m, reps=3)
+            tuned = {"tile_log": tl, "digit_bits": db, "tuning_ms_at_best": tms}
         for _ in range(warm):
             ctx.analyze_dev(dev, m)
         ctx.profile_kernel(LDS_SA_TAG)
@@ -396,7 +408,7 @@ def main():
         ctx.profile_kernel(0)
         out.update({"value": n / sec, "ms_per_step": sec * 1e3, "dtype": "u32" if t.dtype == np.uint32 else "u64",
                     "config": {"workload": args.workload, "description": desc, "n": n, "min_len": m, "windows": 1},
-                    "stage_ms": stages, "counters": ctx.counters(), "rows": int(res[0].shape[0])})
+                    "stage_ms": stages, "counters": ctx.counters(), "rows": int(res[0].shape[0]), "tuned": tuned})
         rf = roofline(kprof, steps)
         if rf:
             out["roofline"] = rf

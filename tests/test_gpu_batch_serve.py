@@ -70,6 +70,28 @@ def test_batch_equals_alone_and_oracle(ctx):
             assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
 
 
+def test_batch_long_windows(ctx):
+    """Windows longer than 2^16 tokens beside short ones: the doubling rounds'
+    window-relative bucketing digits then need more than 16 bits, and the
+    windows finish their doubling after very different numbers of rounds
+    (rank snapshots exist for some and not for others)."""
+    rng = np.random.default_rng(21)
+    wins = [np.tile(np.arange(7, dtype=np.uint64), 100000 // 7 + 1)[:100000],
+            rng.integers(0, 1 << 40, 70000).astype(np.uint64),
+            np.full(80000, 5, dtype=np.uint64),
+            synth.loop_stream(77, 5000, 40, 64, 0.05).astype(np.uint64),
+            rng.integers(0, 4, 66000).astype(np.uint64),
+            np.array([1, 2, 1, 2, 1], dtype=np.uint64)]
+    toks, off = _pack(wins)
+    for m in (2, 8):
+        print("long-window batch min_len", m, flush=True)
+        rows, oo = ctx.analyze_batch(toks, off, m)
+        for w, win in enumerate(wins):
+            got = _as3(rows[int(oo[w]):int(oo[w + 1])])
+            assert np.array_equal(got, _as3(ctx.analyze(win, m))), (w, len(win))
+            assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
+
+
 def test_batch_device_api(ctx):
     import torch
     wins, m = synth.config3(num_windows=24)

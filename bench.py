@@ -303,8 +303,8 @@ def serve_leg(seconds, slots):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build "
-              "(see DESIGN.md, 'Sharding').", file=sys.stderr)
+        print("bench.py measures one GPU only: windows are independent, so several GPUs would each "
+              "analyse their own share of the windows, and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2406_18111_amd import Context, synth

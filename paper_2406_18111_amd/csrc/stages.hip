@@ -705,8 +705,12 @@ constexpr int kCandItems = 8;
 // but neighbouring threads' are not).
 constexpr uint32_t kCandStage = 1024;
 
+// Occupancy of 6 wavefronts per SIMD: the ID queries are latency-bound, and
+// the write pass would otherwise take ~127 registers (4 wavefronts); measured
+// 919 -> 528 us per launch on the batched workload, a few spilled registers
+// included.
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
+__global__ __launch_bounds__(256, 6) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
                                                     uint32_t *tile_val, uint32_t *crec) {
   __shared__ uint32_t sh[4];

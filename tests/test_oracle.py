@@ -410,3 +410,64 @@ def test_interval_counts_on_real_candidates(seed):
             assert cnt[k] == cnt[j] + 1
         else:
             assert cnt[k] == 1
+
+
+# ------------------------------------------- per-round active suffix counts
+
+def _active_by_brute_force(s):
+    """a_r for r = 1, 2, ...: the suffixes whose 2^(r-1)-prefix is shared with
+    a suffix-array neighbour, i.e. #{k : max(LCP[k-1], LCP[k]) >= 2^(r-1)},
+    from suffixes sorted by Python list comparison and direct common prefixes
+    (none of the oracle's own arrays)."""
+    n = len(s)
+    sa = sorted(range(n), key=lambda i: s[i:])
+    lc = [nv.common_prefix(s, sa[k], sa[k + 1]) for k in range(n - 1)]
+    near = [max(lc[k - 1] if k > 0 else 0, lc[k] if k < n - 1 else 0) for k in range(n)]
+    out = []
+    h = 1
+    while True:
+        a = sum(1 for v in near if v >= h)
+        if a == 0:
+            return out
+        out.append(a)
+        h *= 2
+
+
+def _check_active(s):
+    _sa, act = oracle.suffix_array(s, return_active=True)
+    assert act.tolist() == _active_by_brute_force(s), s
+
+
+def test_active_counts_exhaustive_binary():
+    """The oracle's doubling-round counts (the a_r of the byte model) equal
+    the brute-force counts on every binary string of length <= 10."""
+    for n in range(1, 11):
+        for s in itertools.product((0, 1), repeat=n):
+            _check_active(list(s))
+
+
+def test_active_counts_random_and_families():
+    rng = random.Random(31)
+    for _ in range(200):
+        n = rng.randint(1, 300)
+        a = rng.randint(1, 5)
+        _check_active([rng.randrange(a) for _ in range(n)])
+    for n in (1, 2, 3, 17, 64, 100):
+        _check_active([7] * n)                      # a^n: LCP[k] = k+1
+    _check_active(list(range(50)))                  # all distinct: no round
+    _check_active([0, 1, 2, 3, 4] * 20)             # body^k
+    _check_active(synth.loop_stream(5, 2000, 40, 16, 0.05).tolist())
+
+
+def test_active_counts_closed_form_constant_run():
+    """a^n: the suffix array is n-1..0 with LCP[k] = k+1, so slot k's larger
+    neighbour LCP is k+1 (k < n-1) or n-1 (last slot): a_r = n - 2^(r-1) + 1
+    for 2^(r-1) <= n-1, and no round after that."""
+    for n in (2, 5, 16, 33, 100):
+        _sa, act = oracle.suffix_array([3] * n, return_active=True)
+        want = []
+        h = 1
+        while h <= n - 1:
+            want.append(n - h + 1)
+            h *= 2
+        assert act.tolist() == want, n

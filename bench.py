@@ -6,10 +6,13 @@ Default workload (batched): 4096 independent windows, lengths log-uniform in
 uniform in [10, 500] from an alphabet of 2^12 hashes, 5% substitutions), min
 repeat length 8.  One step = one complete analysis of every window (rank
 compression, suffix array, LCP, candidates, sort, greedy selection, output)
-as one packed launch sequence, replayed as a HIP graph, tokens resident in
-device memory.  Reported beside it: the same windows through one plain
-per-window analysis each, the single-window n = 2^20 nested-loop workload,
-and the continuous-batching server on a Poisson trace (p50/p99 latency).
+split into concurrent window groups (lanes), each run host-driven on its own
+stream, tokens resident in device memory.  Reported beside it: the same step
+captured once as a HIP graph and replayed on one stream, the same windows
+through one plain per-window analysis each, the single-window n = 2^20
+nested-loop workload, the continuous-batching server against a plain FIFO on
+a Poisson trace (p50/p99 latency), the C oracle on the host's cores, and the
+achievable device-copy bandwidth beside the HBM peak.
 
 Prints one JSON line.  Runs on one GPU only.
 """
@@ -27,10 +30,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per entry of the doubling rounds' LDS sort / grouping
-# kernels: read key + suffix (8), write the sorted suffix (4), write its new
-# rank (4) and its slot's still-grouped flag (1).
-LDS_SA_BYTES_PER_ENTRY = 17
+# Algorithmic bytes of the doubling rounds' LDS sort / grouping family per
+# suffix it sorts, from the byte model of the method: one sort of an 8-byte
+# key with a 4-byte index (read and write: 24) plus the boundary / new-rank
+# write (12).  The partner-rank gather (8) belongs to the gather kernel.
+LDS_SA_BYTES_PER_ENTRY = 36
+# What the kernels themselves must touch per entry: read key + suffix (8),
+# write the sorted suffix (4), its new rank (4) and its slot's flag (1).
+LDS_SA_LOCAL_BYTES_PER_ENTRY = 17
 LDS_SA_TAG = 1
 
 
@@ -44,7 +51,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-window, single-window and serving legs")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--no-graphs", action="store_true")
     ap.add_argument("--lanes", type=int, default=3, help="concurrent window groups per batch (1..4)")
@@ -89,9 +96,35 @@ def pack(wins):
     return np.concatenate(wins), off
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def host_threads():
+    """Worker threads for the oracle pool: the host's cores, capped by the
+    process's CPU share where the environment states one."""
+    n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return n
+
+
 def cpu_baseline_windows(wins, m, seconds):
-    """The oracle over the windows in order until `seconds` of CPU work."""
+    """The oracle over the windows: all windows on a pool of host threads
+    (windows are independent; the C oracle releases the GIL), and the first
+    windows in order on one thread until `seconds` of CPU work."""
+    import concurrent.futures as cf
     import oracle
+    oracle.find_repeats(wins[0], m)
     tok = 0
     k = 0
     t0 = time.perf_counter()
@@ -101,10 +134,21 @@ def cpu_baseline_windows(wins, m, seconds):
         k += 1
         if time.perf_counter() - t0 >= seconds:
             break
-    el = time.perf_counter() - t0
-    return {"value": tok / el, "unit": "tokens/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of the %d windows (%d tokens) by the single-threaded C oracle, %.1f s"
-                      % (k, len(wins), tok, el)}
+    el1 = time.perf_counter() - t0
+    threads = host_threads()
+    order = sorted(range(len(wins)), key=lambda w: -len(wins[w]))  # longest first
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda w: oracle.find_repeats(wins[w], m), order))
+    elp = time.perf_counter() - t0
+    total = sum(len(w) for w in wins)
+    return {"value": total / elp, "unit": "tokens/s", "cores": threads, "kind": "oracle",
+            "cpu_model": host_cpu(), "host_cpus": os.cpu_count(),
+            "sample": "all %d windows (%d tokens) by the C oracle on a pool of %d host threads, %.2f s wall"
+                      % (len(wins), total, threads, elp),
+            "single_thread": {"value": tok / el1, "unit": "tokens/s", "cores": 1,
+                              "sample": "first %d of the %d windows (%d tokens) on one thread, %.1f s"
+                                        % (k, len(wins), tok, el1)}}
 
 
 def cpu_baseline_single(t, m, seconds):
@@ -118,6 +162,7 @@ def cpu_baseline_single(t, m, seconds):
             break
     el = time.perf_counter() - t0
     return {"value": reps * len(t) / el, "unit": "tokens/s", "cores": 1, "kind": "oracle",
+            "cpu_model": host_cpu(), "host_cpus": os.cpu_count(),
             "sample": "%d full analyses of the same window by the single-threaded C oracle (%.1f s)" % (reps, el)}
 
 
@@ -176,40 +221,78 @@ def measured_traffic(workload, lanes=1):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def roofline(kprof, steps, workload=None, lanes=1):
+def roofline(kprof, steps, workload=None, lanes=1, copy_gbs=None):
     if not kprof["launches"]:
         return None
     avg_ms = kprof["ms"] / kprof["launches"]
-    bytes_per_launch = kprof["elems"] * LDS_SA_BYTES_PER_ENTRY / kprof["launches"]
+    entries = kprof["elems"] / kprof["launches"]
+    bytes_per_launch = entries * LDS_SA_BYTES_PER_ENTRY
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(workload, lanes) if workload else None
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "per doubling round, the LDS sort family in SA mode: k_wave_sort<0> (units <= 64) + "
-                      "k_lds_group<0> (65..4096) [+ k_lds_sort<0,13> with 8192-entry tiles], one event pair "
-                      "around the family",
-            "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
-            "launches_per_step": kprof["launches"] / steps}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+           "kernel": "per doubling round, the LDS sort family in SA mode: k_wave_sort<0> (units <= 64) + "
+                     "k_lds_group<0> (65..4096) [+ k_lds_sort<0,13> with 8192-entry tiles], one event pair "
+                     "around the family",
+           "bytes_per_entry": LDS_SA_BYTES_PER_ENTRY, "entries_per_launch": entries,
+           "avg_launch_us": avg_ms * 1e3, "bytes_per_launch": bytes_per_launch,
+           "kernel_local_bytes_per_launch": entries * LDS_SA_LOCAL_BYTES_PER_ENTRY,
+           "launches_per_step": kprof["launches"] / steps, "lanes": lanes}
+    if copy_gbs:
+        out["achievable_copy_GBps"] = copy_gbs
+        out["frac_of_copy"] = achieved / copy_gbs
+    return out
 
 
-def path_roofline(counters, n, tok_bytes, rows, sec):
-    """Whole-step algorithmic bytes over the step time: every stage's
-    compulsory reads and writes once, each sort one read plus one write of its
-    records.  Per token: rank compression (token + rank), PLCP with Phi and
-    the LCP permutation (36), candidate pass and PSV (16); per active suffix
-    of each doubling round (the token sort included) 44; per generated
-    candidate 16 (record + ID) + 24 (one sort) + 20 (greedy: record and two
-    marks); per covered position 4 (marks); per accepted occurrence 12."""
+def path_roofline(counters, n, tok_bytes, rows, sec, copy_gbs=None):
+    """Whole-step algorithmic bytes over the step time, term by term the byte
+    model of the method: rank compression (w + 4 per token), 44 per active
+    suffix of each doubling round r >= 1 (own and partner rank 8, one sort of
+    an 8-byte key and 4-byte index 24, rank write 12), Phi + PLCP + LCP
+    permutation (36 per token), candidate pass and PSV (16 per token + 16 per
+    candidate), one candidate sort (24 per candidate), the greedy's reads
+    (20 per candidate), mark writes (4 per covered position) and the output
+    (12 per accepted occurrence).  The library's active_sum counts the first
+    round's token sort as n suffixes; that round is the rank compression's
+    sort, so n is subtracted."""
     import torch
     r = rows.to(torch.int64)
     cov = int((r[:, 1] * r[:, 2]).sum().item()) if r.numel() else 0
     c = counters.get("candidates", 0)
     a = counters.get("accepted", 0)
-    b = ((tok_bytes + 4) * n + 44 * counters.get("active_sum", 0) + 36 * n + 16 * n + 60 * c + 4 * cov + 12 * a)
+    act = counters.get("active_sum", 0) - n
+    b = ((tok_bytes + 4) * n + 44 * act + 36 * n + 16 * n + 16 * c + 24 * c + 20 * c + 4 * cov + 12 * a)
     achieved = b / sec / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "bytes_per_step": b, "covered_positions": cov}
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "bytes_per_step": b, "active_suffixes_r_ge_1": act,
+           "candidates": c, "covered_positions": cov, "accepted": a}
+    if copy_gbs:
+        out["achievable_copy_GBps"] = copy_gbs
+    return out
+
+
+def copy_bandwidth():
+    """Achievable HBM bandwidth of a plain 2 GiB device-to-device copy
+    (read + write bytes over the time), median of 5 with events."""
+    import torch
+    n = 1 << 31
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n / float(np.median(times)) / 1e9
 
 
 def per_window_leg(ctx, dev, off, m):
@@ -226,13 +309,22 @@ def per_window_leg(ctx, dev, off, m):
     return time.perf_counter() - t0, nrows
 
 
-def serve_leg(seconds, slots):
+def serve_leg(seconds, slots, warm_s=1.0, fifo_seconds=3.0):
     """Open-loop replay of the serving trace (64 nested-loop streams, Poisson
-    arrivals at 2000/s, windows log-uniform 1024..2^20, min_len 16): the
-    continuous-batching server vs the plain one-window-at-a-time FIFO path."""
+    arrivals at 2000/s, windows log-uniform 1024..2^20, min_len 16) against
+    the wall clock: the continuous-batching server on the whole trace, and
+    the plain one-window-at-a-time FIFO path on its first `fifo_seconds`
+    (it cannot keep up with the offered load, so its queue grows; its backlog
+    at the end is reported).  Latency = rows available on the host - arrival;
+    requests arriving in the first `warm_s` seconds are excluded from the
+    statistics.  Throughput = tokens of the counted requests / (last
+    completion - first counted arrival).  The rows of every request that both
+    paths served are compared."""
     import threading
     from paper_2406_18111_amd import Context, synth
-    reqs = list(synth.config4_trace(duration=seconds))
+    t0g = time.perf_counter()
+    reqs = synth.config4_requests(duration=seconds, threads=host_threads())
+    gen_s = time.perf_counter() - t0g
     offered = sum(len(r.tokens) for r in reqs)
 
     def replay_server():
@@ -244,6 +336,7 @@ def serve_leg(seconds, slots):
                 time.sleep(0.0005)
         lat = [None] * len(reqs)
         done_t = [0.0] * len(reqs)
+        rows = [None] * len(reqs)
         tickets = [None] * len(reqs)
         t0 = time.perf_counter()
 
@@ -252,7 +345,7 @@ def serve_leg(seconds, slots):
                 now = time.perf_counter() - t0
                 if r.arrival > now:
                     time.sleep(r.arrival - now)
-                tickets[i] = srv.submit(r.tokens, 16, r.stream)
+                tickets[i] = (srv.submit(r.tokens, 16, r.stream), time.perf_counter() - t0)
 
         th = threading.Thread(target=producer)
         th.start()
@@ -263,40 +356,55 @@ def serve_leg(seconds, slots):
                 pending.add(i_next)
                 i_next += 1
             for i in list(pending):
-                got = srv.fetch(tickets[i])
+                got = srv.fetch(tickets[i][0])
                 if got is not None:
-                    lat[i] = got[1]
                     done_t[i] = time.perf_counter() - t0
+                    lat[i] = done_t[i] - reqs[i].arrival
+                    rows[i] = got[0]
                     pending.discard(i)
             time.sleep(0.0002)
         th.join()
         srv.server_stop()
         srv.close()
-        return lat, max(done_t) - reqs[0].arrival
+        return lat, done_t, rows
 
-    def replay_fifo():
+    def replay_fifo(sub):
         ctx = Context(0)
-        ctx.analyze(reqs[0].tokens, 16)
-        lat = []
+        ctx.analyze(sub[0].tokens, 16)
+        lat, done_t, rows = [], [], []
         t0 = time.perf_counter()
-        last = 0.0
-        for r in reqs:
+        for r in sub:
             now = time.perf_counter() - t0
             if r.arrival > now:
                 time.sleep(r.arrival - now)
-            ctx.analyze(r.tokens, 16)
-            last = time.perf_counter() - t0
-            lat.append(last - r.arrival)
+            rows.append(ctx.analyze(r.tokens, 16))
+            done_t.append(time.perf_counter() - t0)
+            lat.append(done_t[-1] - r.arrival)
         ctx.close()
-        return lat, last - reqs[0].arrival
+        return lat, done_t, rows
 
-    out = {"workload": "config4", "requests": len(reqs), "trace_seconds": seconds,
-           "offered_tokens_per_s": offered / seconds, "slots": slots}
-    for name, fn in (("server", replay_server), ("fifo", replay_fifo)):
-        lat, span = fn()
-        lat = np.array(lat, dtype=np.float64)
-        out[name] = {"tokens_per_s": offered / span, "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                     "p99_ms": float(np.percentile(lat, 99) * 1e3), "span_s": span}
+    def stats(sub_reqs, lat, done_t):
+        idx = [i for i, r in enumerate(sub_reqs) if r.arrival >= warm_s]
+        if not idx:
+            return None
+        l = np.array([lat[i] for i in idx], dtype=np.float64)
+        tok = sum(len(sub_reqs[i].tokens) for i in idx)
+        span = max(done_t[i] for i in idx) - sub_reqs[idx[0]].arrival
+        return {"tokens_per_s": tok / span, "p50_ms": float(np.percentile(l, 50) * 1e3),
+                "p99_ms": float(np.percentile(l, 99) * 1e3), "counted_requests": len(idx), "span_s": span}
+
+    out = {"workload": "config4", "requests": len(reqs), "trace_seconds": seconds, "warmup_excluded_s": warm_s,
+           "offered_tokens_per_s": offered / seconds, "slots": slots, "trace_generation_s": gen_s}
+    lat, done_t, srows = replay_server()
+    out["server"] = stats(reqs, lat, done_t)
+    fsub = [r for r in reqs if r.arrival <= fifo_seconds]
+    flat, fdone, frows = replay_fifo(fsub)
+    out["fifo"] = stats(fsub, flat, fdone)
+    if out["fifo"]:
+        out["fifo"]["trace_seconds"] = fifo_seconds
+        out["fifo"]["backlog_s_at_end"] = fdone[-1] - fsub[-1].arrival
+    same = all(np.array_equal(srows[i], frows[i]) for i in range(len(fsub)))
+    out["server_rows_equal_fifo"] = {"requests_compared": len(fsub), "equal": bool(same)}
     return out
 
 
@@ -314,6 +422,7 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
         return
+    copy_gbs = None if args.profile_steps else copy_bandwidth()
     ctx = Context(0)
     ctx.set_graphs(not args.no_graphs)
     ctx.set_lanes(args.lanes)
@@ -349,10 +458,10 @@ def main():
                                                "on its own stream").format(args.lanes),
                                "lanes": args.lanes},
                     "counters": ctx.counters(), "rows": int(res[1][-1]), "tuned": tuned})
-        rf = roofline(kprof, steps, "config3", args.lanes)
+        rf = roofline(kprof, steps, "config3", args.lanes, copy_gbs)
         if rf:
             out["roofline"] = rf
-        out["path_roofline"] = path_roofline(out["counters"], total, 8, res[0], sec)
+        out["path_roofline"] = path_roofline(out["counters"], total, 8, res[0], sec, copy_gbs)
         if not args.profile_steps and not args.no_extras and args.lanes > 1:
             # the same kernel family timed with one stream only (no other lane
             # sharing the GPU while an event pair is open)
@@ -362,7 +471,7 @@ def main():
             _, kp1, _, _ = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), 3)
             ctx.profile_kernel(0)
             ctx.set_lanes(args.lanes)
-            out["roofline_one_lane"] = roofline(kp1, 3, "config3", 1)
+            out["roofline_one_lane"] = roofline(kp1, 3, "config3", 1, copy_gbs)
         if not args.profile_steps and not args.no_graphs:
             # one stream: the step captured once as a HIP graph and replayed
             ctx.set_lanes(1)
@@ -409,10 +518,10 @@ def main():
         out.update({"value": n / sec, "ms_per_step": sec * 1e3, "dtype": "u32" if t.dtype == np.uint32 else "u64",
                     "config": {"workload": args.workload, "description": desc, "n": n, "min_len": m, "windows": 1},
                     "stage_ms": stages, "counters": ctx.counters(), "rows": int(res[0].shape[0]), "tuned": tuned})
-        rf = roofline(kprof, steps)
+        rf = roofline(kprof, steps, copy_gbs=copy_gbs)
         if rf:
             out["roofline"] = rf
-        out["path_roofline"] = path_roofline(out["counters"], n, t.dtype.itemsize, res[0], sec)
+        out["path_roofline"] = path_roofline(out["counters"], n, t.dtype.itemsize, res[0], sec, copy_gbs)
         if not args.profile_steps and not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_single(t, m, args.cpu_seconds)
     print(json.dumps(out), flush=True)

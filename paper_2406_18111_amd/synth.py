@@ -54,6 +54,15 @@ class Stream:
         with np.errstate(over="ignore"):
             return mix64(np.uint64(self.base) + k * GOLDEN)
 
+    def raw_at(self, offsets: np.ndarray, count: int) -> np.ndarray:
+        """The draws at `offsets` (0-based, relative to the current position)
+        of the next `count` draws, then skips all `count`: equal to
+        raw(count)[offsets] without computing the other draws."""
+        k = np.asarray(offsets, dtype=np.uint64) + np.uint64(self.pos + 1)
+        self.pos += count
+        with np.errstate(over="ignore"):
+            return mix64(np.uint64(self.base) + k * GOLDEN)
+
     def below(self, m: int, count: int) -> np.ndarray:
         """Uniform integers in [0, m), m < 2^32."""
         assert 0 < m < (1 << 32)
@@ -68,7 +77,10 @@ class Stream:
         return (self.raw(count) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
 
     def bern(self, p: float, count: int) -> np.ndarray:
-        return self.unit(count) < p
+        # unit < p on the top 53 bits i: i * 2^-53 < p  <=>  i < ceil(p * 2^53)
+        # (both sides exact in binary64), compared as integers
+        thr = np.uint64(min(math.ceil(p * float(1 << 53)), 1 << 53))
+        return (self.raw(count) >> np.uint64(11)) < thr
 
 
 # stream tags
@@ -117,18 +129,21 @@ class NestedLoopSource:
         self.buf = np.zeros(0, dtype=np.uint64)
 
     def _produce(self, clean: int) -> np.ndarray:
+        # every draw is indexed by the clean token's position, so the output
+        # does not depend on how the stream is cut into _produce calls; fresh
+        # hashes are computed only where a substitution or insertion happens
         k = np.arange(self.clean_pos, self.clean_pos + clean)
         self.clean_pos += clean
-        tok = self.period[k % len(self.period)].copy()
-        sub = self.s_sub.bern(self.p_sub, clean)
-        fr = self.s_fresh.raw(clean)
-        tok[sub] = fr[sub]
+        tok = self.period[k % len(self.period)]
+        sub = np.flatnonzero(self.s_sub.bern(self.p_sub, clean))
+        tok[sub] = self.s_fresh.raw_at(sub, clean)
         ins = self.s_ins.bern(self.p_ins, clean)
-        insv = self.s_insf.raw(clean)
-        out = np.empty(clean + int(ins.sum()), dtype=np.uint64)
+        insi = np.flatnonzero(ins)
+        insv = self.s_insf.raw_at(insi, clean)
+        out = np.empty(clean + len(insi), dtype=np.uint64)
         slot = np.arange(clean) + np.cumsum(ins)  # position of each clean token
         out[slot] = tok
-        out[slot[ins] - 1] = insv[ins]
+        out[slot[insi] - 1] = insv
         return out
 
     def take(self, count: int) -> np.ndarray:
@@ -197,6 +212,48 @@ def config4_trace(duration: float = 10.0, rate: float = 2000.0, streams: int = 6
             srcs[k] = NestedLoopSource(stream_seed0 + k)
         count += 1
         yield Request(t, k, srcs[k].take(W))
+
+
+def config4_requests(duration: float = 10.0, threads: int = 8, **kw) -> List[Request]:
+    """The requests of config4_trace(duration, **kw) as a list, identical to
+    the lazy trace, with each stream's tokens generated on a pool of threads
+    (a stream's windows are consecutive pieces of that stream)."""
+    import concurrent.futures as cf
+    rate = kw.get("rate", 2000.0)
+    streams = kw.get("streams", 64)
+    lo, hi = kw.get("lo", 1024), kw.get("hi", 1 << 20)
+    seed, stream_seed0 = kw.get("seed", 4242), kw.get("stream_seed0", 2000)
+    max_requests = kw.get("max_requests")
+    sa = Stream(seed, _T_LEN)
+    plan = []
+    t = 0.0
+    while True:
+        gap, us, uw = sa.unit(3)
+        t += -math.log(1.0 - gap) / rate
+        if t > duration or (max_requests is not None and len(plan) >= max_requests):
+            break
+        k = min(streams - 1, int(us * streams))
+        W = int(math.floor(math.exp(math.log(lo) + uw * (math.log(hi) - math.log(lo)))))
+        plan.append((t, k, max(lo, min(hi, W))))
+    per_stream = {}
+    for i, (_, k, W) in enumerate(plan):
+        per_stream.setdefault(k, []).append(i)
+
+    def gen(k):
+        idx = per_stream[k]
+        whole = NestedLoopSource(stream_seed0 + k).take(sum(plan[i][2] for i in idx))
+        out, at = [], 0
+        for i in idx:
+            out.append((i, whole[at: at + plan[i][2]]))
+            at += plan[i][2]
+        return out
+
+    toks: List[np.ndarray | None] = [None] * len(plan)
+    with cf.ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        for part in ex.map(gen, sorted(per_stream)):
+            for i, a in part:
+                toks[i] = a
+    return [Request(a, k, toks[i]) for i, (a, k, _) in enumerate(plan)]
 
 
 CONFIG_MIN_LEN = {0: 8, 1: 16, 2: 32, 3: 8, 4: 16}

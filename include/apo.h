@@ -78,8 +78,13 @@ typedef struct {
 } apo_occurrence;
 
 /* Create a context on HIP device `hip_device`.  `device_mem_budget_bytes`
- * caps the workspace (0 = no cap).  Returns APO_EINVAL for out == NULL,
- * APO_EDEVICE if the device cannot be selected. */
+ * caps the device memory the context's workspaces hold together: the
+ * single-window workspace, the lane workspaces of batches and the server's
+ * slot pool (0 = no cap).  Workspaces grow on demand and stay resident; an
+ * analysis whose workspace would not fit returns APO_ENOMEM and leaves the
+ * context usable (smaller analyses still run; batches first drop to fewer
+ * lanes, and idle lane workspaces are freed, before giving up).  Returns
+ * APO_EINVAL for out == NULL, APO_EDEVICE if the device cannot be selected. */
 int apo_create(apo_ctx **out, int hip_device, size_t device_mem_budget_bytes);
 
 /* Stops the server if running, frees all device memory.  NULL is a no-op. */
@@ -182,10 +187,41 @@ int apo_interval_counts_dev(apo_ctx *ctx, const uint32_t *d_len, const uint32_t 
  * number of stages written (<= nstages). */
 int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
 
-/* Counters of the last analysis: rounds of doubling, candidates generated,
- * candidates after dedup, selection rounds, accepted occurrences, rows,
- * sum over rounds of active suffixes, distinct tokens. */
+/* Counters of the last analysis, in this order: rounds of doubling (the
+ * first-token sort included), candidates generated, candidates after dedup,
+ * selection rounds, accepted occurrences, rows, sum over rounds of active
+ * suffixes (the first-token sort counts every suffix), distinct tokens, and
+ * 1 if the selection finished with the sequential completion (else 0).
+ * Writes min(nvals, 9) values and returns that number. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
+
+/* Device memory of the context: *held = bytes its own workspaces hold (the
+ * single-window one and the lane workspaces); *server_pool (nullable) = the
+ * running server's pool, 0 without a server; *server_held (nullable) = bytes
+ * the server's slots hold or have reserved for the batches they run. */
+int apo_memory(apo_ctx *ctx, size_t *held, size_t *server_pool, size_t *server_held);
+
+/* Test hook for the error path: the (after_syncs+1)-th host synchronisation
+ * inside the next single-window analysis reports a device error, so that
+ * call returns APO_EDEVICE with its work abandoned; the context stays
+ * usable and the following calls run normally.  -1 cancels.  APO_EINVAL
+ * below -1. */
+int apo_inject_device_error(apo_ctx *ctx, int after_syncs);
+
+/* Selection path (Section 4.2, the greedy walk of Algorithm 2): with on = 1
+ * (default) windows of at most 2^17 tokens in a batch, and single windows of
+ * at most 2^15 tokens, are decided by one wavefront per window walking the
+ * window's candidates in priority order over an on-chip bitmap; longer
+ * windows use the round-based evaluation.  on = 0 sends every analysis
+ * through the rounds.  Results are identical either way.  APO_EINVAL
+ * unless on is 0 or 1. */
+int apo_set_window_greedy(apo_ctx *ctx, int on);
+
+/* Test hook: host-driven analyses stop the round-based greedy selection
+ * after `rounds` rounds (0..64, default 64) and decide the rest with the
+ * sequential completion, which gives the same result (Section 4.2, the
+ * greedy walk of Algorithm 2).  APO_EINVAL outside 0..64. */
+int apo_set_selection_round_cap(apo_ctx *ctx, int rounds);
 
 /* Per-round sizes of the last analysis (diagnostic): sa_active[r] = suffixes
  * entering doubling round r (r < *n_sa); sel_live[q] / sel_undecided[q] =
@@ -233,13 +269,23 @@ int apo_tune_load(apo_ctx *ctx, const char *path);
 
 /* ---- continuous-batching server ---- */
 
-/* Start the server: up to max_slots analyses in flight on the device at once,
- * admitted while the memory budget allows.  queue_cap bounds waiting
- * requests (0 = 65536). */
+/* Start the server: up to max_slots (1..16) batches in flight on the device
+ * at once, each slot with a resident workspace and its own stream.
+ * Admission is by device memory: the slots' workspaces together hold at most
+ * the server's pool (the context budget less what the context's own
+ * workspaces hold at start, or 80% of the device memory free at start when
+ * there is no budget).  A free slot takes the oldest queued request and every
+ * later one with the same min_len while the packed batch's workspace still
+ * fits beside the other slots' (idle slots give theirs back first); if even
+ * the oldest does not fit, it stays queued until a busy slot finishes.
+ * queue_cap bounds waiting requests (0 = 65536).  APO_EINVAL if a server
+ * runs already or max_slots is out of range. */
 int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue_cap);
 
 /* Enqueue a window (tokens are copied before return).  *ticket identifies it.
- * APO_EAGAIN when the queue is full. */
+ * A window that fits the pool waits in the queue until memory frees up;
+ * APO_ENOMEM only for a window whose workspace alone exceeds the pool,
+ * APO_EAGAIN when the queue is full, APO_EINVAL without a running server. */
 int apo_submit(apo_ctx *ctx, uint32_t stream_id, const uint64_t *tokens, uint32_t n,
                uint32_t min_len, uint64_t *ticket);
 

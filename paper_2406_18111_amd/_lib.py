@@ -33,7 +33,7 @@ class AutoParams(ctypes.Structure):
 
 STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
 COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
-            "active_sum", "sigma")
+            "active_sum", "sigma", "selection_sequential")
 
 # name -> (restype, argtypes); mirrors include/apo.h
 _P, _U32, _U64, _I, _SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
@@ -48,6 +48,10 @@ SIGNATURES = {
     "apo_analyze_batch_dev": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P, _P]),
     "apo_set_graphs": (_I, [_P, _I]),
     "apo_set_lanes": (_I, [_P, _I]),
+    "apo_set_selection_round_cap": (_I, [_P, _I]),
+    "apo_set_window_greedy": (_I, [_P, _I]),
+    "apo_inject_device_error": (_I, [_P, _I]),
+    "apo_memory": (_I, [_P, _P, _P, _P]),
     "apo_graph_stats": (_I, [_P, _P, _P]),
     "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
@@ -240,6 +244,24 @@ class Context:
     def set_lanes(self, lanes: int):
         """Concurrent window groups per batch (1..4)."""
         _check(self._lib.apo_set_lanes(self._h, int(lanes)), "apo_set_lanes")
+
+    def set_window_greedy(self, on: bool):
+        """Per-window one-wavefront greedy for short windows (default on); off: round-based selection only."""
+        _check(self._lib.apo_set_window_greedy(self._h, int(bool(on))), "apo_set_window_greedy")
+
+    def set_selection_round_cap(self, rounds: int):
+        """Test hook: stop host-driven greedy rounds after `rounds` (0..64)."""
+        _check(self._lib.apo_set_selection_round_cap(self._h, int(rounds)), "apo_set_selection_round_cap")
+
+    def inject_device_error(self, after_syncs: int):
+        """Test hook: a host sync of the next single-window analysis reports a device error."""
+        _check(self._lib.apo_inject_device_error(self._h, int(after_syncs)), "apo_inject_device_error")
+
+    def memory(self):
+        """Device bytes held: the context's own workspaces, the server pool and what its slots hold."""
+        h, p, sh = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(self._lib.apo_memory(self._h, ctypes.byref(h), ctypes.byref(p), ctypes.byref(sh)), "apo_memory")
+        return {"held": h.value, "server_pool": p.value, "server_held": sh.value}
 
     def set_graphs(self, on: bool):
         _check(self._lib.apo_set_graphs(self._h, int(bool(on))), "apo_set_graphs")

@@ -37,6 +37,11 @@ struct Slot {
   std::thread th;
   uint64_t *pinned = nullptr;  // staging for packed tokens
   uint64_t pinned_cap = 0;
+  // admission bookkeeping, guarded by Server::mu: device bytes this slot's
+  // workspace holds (or has reserved for the batch it runs), and whether a
+  // batch is in flight
+  size_t held = 0;
+  bool busy = false;
 };
 
 // Autotuned kernel parameters per input-size bucket (ceil(log2 n)).
@@ -70,10 +75,10 @@ struct Server {
   std::deque<std::shared_ptr<Request>> queue;
   std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
   std::vector<std::unique_ptr<Slot>> slots;
+  std::condition_variable cv_mem;  // a slot finished a batch (memory may have come free)
   uint64_t next_ticket = 1;
   uint32_t queue_cap = 65536;
-  uint64_t slot_token_cap = 0;
-  size_t slot_budget = 0;
+  size_t pool = 0;                  // device bytes all slots' workspaces may hold together
   bool stopping = false;
   int device = 0;
   TuneTable tune;
@@ -111,6 +116,8 @@ struct apo_ctx {
   apo::TuneTable tune;
   apo::GraphCache gc;
   bool graphs = true;         // capture/replay batched launch sequences
+  int sel_cap = apo::kSelRoundCap;  // host-driven selection rounds before the sequential completion
+  bool win_greedy = true;           // per-window greedy where windows are short enough
   uint64_t graph_replays = 0, graph_captures = 0;
   std::unique_ptr<apo::Server> server;
   // Batches are split into `lanes` groups of windows, each analysed on its
@@ -189,11 +196,44 @@ static int map_rc(int rc) {
   return APO_EDEVICE;
 }
 
+// ---- device memory budget of a context: the sum of the bytes its
+// workspaces hold (the main one and the lane workspaces; the server's slots
+// draw on their own pool) never exceeds ctx->budget when one is set.
+static size_t ctx_held(const apo_ctx *c) {
+  size_t b = c->ws.held();
+  for (const auto &l : c->lane_ws) b += l->held();
+  return b;
+}
+
+static void release_lanes_from(apo_ctx *c, size_t first) {
+  for (size_t k = first; k < c->lane_ws.size(); k++) {
+    (void)hipStreamSynchronize(c->lane_stream[k]);
+    c->lane_ws[k]->release();
+  }
+}
+
+// Grows w to (N, W) within the context's budget; idle lane workspaces give
+// their memory back first when they are what stands in the way.
+static size_t ctx_limit(const apo_ctx *c);
+
+static int ctx_ensure(apo_ctx *c, Workspace &w, uint64_t N, uint32_t W) {
+  if (c->budget) {
+    const size_t after = w.bytes_after(N, W), limit = ctx_limit(c);
+    if (ctx_held(c) - w.held() + after > limit) {
+      if (&w == &c->ws) release_lanes_from(c, 0);
+      if (ctx_held(c) - w.held() + after > limit) return -2;
+    }
+  }
+  return w.ensure(N, W, 0);
+}
+
 // Runs one analysis on the context workspace, tokens already on the device.
 static int run_ctx(apo_ctx *c, const void *d_tok, int bits, uint32_t n, uint32_t min_len, Stop stop,
                    hipStream_t s) {
-  int rc = c->ws.ensure(n, 1, c->budget);
+  int rc = ctx_ensure(c, c->ws, n, 1);
   if (rc) return map_rc(rc);
+  c->ws.sel_cap = c->sel_cap;
+  c->ws.win_greedy = c->win_greedy;
   const uint64_t off[2] = {0, n};
   int tl, db;
   c->tune.pick(n, tl, db);
@@ -212,7 +252,7 @@ static int analyze_host(apo_ctx *ctx, const void *tokens, int bits, uint32_t n, 
   if (occ_n) *occ_n = 0;
   ctx->info = RunInfo{};
   if (n < 2) return APO_OK;
-  int rc = ctx->ws.ensure(n, 1, ctx->budget);
+  int rc = ctx_ensure(ctx, ctx->ws, n, 1);
   if (rc) return map_rc(rc);
   const size_t bytes = (size_t)n * (bits / 8);
   if (hipMemcpyAsync(ctx->ws.tok64, tokens, bytes, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
@@ -307,6 +347,39 @@ static void merge_info(RunInfo &a, const RunInfo &b) {
 // own stream, workspace and host thread; the streams run concurrently, so one
 // lane's host syncs and latency-bound kernels overlap the others' work.
 // Results stay per lane (ctx->louts), in window order.
+static void lane_groups(const uint64_t *off, uint32_t W, uint64_t total, int L, std::vector<uint32_t> &w0) {
+  w0.assign(L + 1, W);
+  w0[0] = 0;
+  for (int g = 1; g < L; g++) {
+    const uint64_t target = off[0] + total * (uint64_t)g / (uint64_t)L;
+    const uint32_t w = (uint32_t)(std::lower_bound(off, off + W + 1, target) - off);
+    w0[g] = std::max(std::min(w, W), w0[g - 1]);
+  }
+}
+
+// Device bytes the context would hold while running a batch on L lanes
+// (lane 0 in ctx->ws, lane g in lane_ws[g-1]; lane workspaces beyond L-1
+// keep what they hold).
+static size_t lanes_footprint(const apo_ctx *ctx, const uint64_t *off, uint32_t W, uint64_t total, int L) {
+  std::vector<uint32_t> w0;
+  lane_groups(off, W, total, L, w0);
+  size_t b = 0;
+  for (int g = 0; g < L; g++) {
+    if (w0[g + 1] == w0[g]) continue;
+    const uint64_t n = std::max<uint64_t>(off[w0[g + 1]] - off[w0[g]], 2);
+    const uint32_t wn = w0[g + 1] - w0[g];
+    const Workspace *ws = g == 0 ? &ctx->ws : ((size_t)(g - 1) < ctx->lane_ws.size() ? ctx->lane_ws[g - 1].get() : nullptr);
+    if (ws) {
+      b += ws->bytes_after(n, wn);
+    } else {
+      Workspace fresh;
+      b += fresh.bytes_after(n, wn);
+    }
+  }
+  for (size_t k = (size_t)std::max(L - 1, 0); k < ctx->lane_ws.size(); k++) b += ctx->lane_ws[k]->held();
+  return b;
+}
+
 static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
                        hipStream_t s, uint64_t total, int L) {
   while ((int)ctx->lane_ws.size() < L - 1) {
@@ -318,13 +391,8 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
   if (!ctx->lane_ready && hipEventCreateWithFlags(&ctx->lane_ready, hipEventDisableTiming) != hipSuccess)
     return APO_EDEVICE;
   // group g holds windows w0[g] .. w0[g+1]
-  std::vector<uint32_t> w0(L + 1, W);
-  w0[0] = 0;
-  for (int g = 1; g < L; g++) {
-    const uint64_t target = off[0] + total * (uint64_t)g / (uint64_t)L;
-    const uint32_t w = (uint32_t)(std::lower_bound(off, off + W + 1, target) - off);
-    w0[g] = std::max(std::min(w, W), w0[g - 1]);
-  }
+  std::vector<uint32_t> w0;
+  lane_groups(off, W, total, L, w0);
   // the tokens were written on the caller's stream
   if (hipEventRecord(ctx->lane_ready, s) != hipSuccess) return APO_EDEVICE;
   struct Lane {
@@ -346,12 +414,14 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
     ln.total = off[w0[g + 1]] - off[w0[g]];
     ln.norm.resize(ln.W + 1);
     for (uint32_t w = 0; w <= ln.W; w++) ln.norm[w] = off[w0[g] + w] - off[w0[g]];
-    const int rc = ln.ws->ensure(std::max<uint64_t>(ln.total, 2), ln.W, ctx->budget);
+    const int rc = ln.ws->ensure(std::max<uint64_t>(ln.total, 2), ln.W, 0);  // footprint checked by the caller
     if (rc) return map_rc(rc);
     int tl, db;
     ctx->tune.pick(ln.total, tl, db);
     ln.ws->eng.set_params(tl, db);
     ln.ws->ktag = ctx->ws.ktag;
+    ln.ws->sel_cap = ctx->sel_cap;
+    ln.ws->win_greedy = ctx->win_greedy;
     if (ln.st != s && hipStreamWaitEvent(ln.st, ctx->lane_ready, 0) != hipSuccess) return APO_EDEVICE;
     lanes.push_back(std::move(ln));
   }
@@ -392,7 +462,16 @@ static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
 
 static int batch_common(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off, uint32_t W, uint32_t min_len,
                         hipStream_t s, uint64_t total) {
-  const int L = std::min<int>(ctx->lanes, (int)(W / 2));
+  int L = std::min<int>(ctx->lanes, (int)(W / 2));
+  if (ctx->budget && L >= 2) {
+    // fewer lanes when their workspaces would not fit the budget; lane
+    // workspaces left idle by the smaller count give their memory back
+    while (L >= 2 && lanes_footprint(ctx, off, W, total, L) > ctx_limit(ctx)) {
+      release_lanes_from(ctx, (size_t)(L - 1));
+      if (lanes_footprint(ctx, off, W, total, L) <= ctx_limit(ctx)) break;
+      L--;
+    }
+  }
   if (L >= 2) return batch_lanes(ctx, d_tok, off, W, min_len, s, total, L);
   const int rc = batch_single(ctx, d_tok, off, W, min_len, s, total);
   ctx->louts.assign(1, {&ctx->ws, W, ctx->info.rows});
@@ -405,12 +484,15 @@ static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
   uint64_t maxwin = 0;
   for (uint32_t w = 0; w <= W; w++) norm[w] = off[w] - off[0];
   for (uint32_t w = 0; w < W; w++) maxwin = std::max<uint64_t>(maxwin, norm[w + 1] - norm[w]);
-  int rc = ctx->ws.ensure(std::max<uint64_t>(total, 2), W, ctx->budget);
+  int rc = ctx_ensure(ctx, ctx->ws, std::max<uint64_t>(total, 2), W);
   if (rc) return map_rc(rc);
   int tl, db;
   ctx->tune.pick(total, tl, db);
   ctx->ws.eng.set_params(tl, db);
   Workspace &w = ctx->ws;
+  w.sel_cap = ctx->sel_cap;
+  if (w.win_greedy != ctx->win_greedy) ctx->gc.reset();  // a captured sequence holds the other selection path
+  w.win_greedy = ctx->win_greedy;
   // Timed kernel launches are bracketed by events on the stream, which is
   // only reliable outside captured graphs: profiling runs the same sync-free
   // sequence without capture.
@@ -516,7 +598,7 @@ extern "C" int apo_analyze_batch(apo_ctx *ctx, const uint64_t *tokens, const uin
     for (uint32_t w = 0; w <= W; w++) out_offsets[w] = 0;
     return APO_OK;
   }
-  rc = ctx->ws.ensure(total, W, ctx->budget);
+  rc = ctx_ensure(ctx, ctx->ws, total, W);
   if (rc) return map_rc(rc);
   if (hipMemcpyAsync(ctx->ws.tok64, tokens + offsets[0], total * 8, hipMemcpyHostToDevice, ctx->stream) !=
       hipSuccess)
@@ -627,10 +709,43 @@ extern "C" int apo_last_stage_ms(apo_ctx *ctx, double *ms, int nstages) {
 extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   if (!ctx || !v || nvals < 0) return APO_EINVAL;
   const RunInfo &I = ctx->info;
-  const uint64_t all[8] = {I.rounds, I.cands, I.cands_dedup, I.sel_rounds, I.accepted, I.rows, I.active_sum, I.sigma};
-  const int k = std::min(nvals, 8);
+  const uint64_t all[9] = {I.rounds,   I.cands,      I.cands_dedup, I.sel_rounds,    I.accepted,
+                           I.rows,     I.active_sum, I.sigma,       I.sel_sequential};
+  const int k = std::min(nvals, 9);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
+}
+
+extern "C" int apo_inject_device_error(apo_ctx *ctx, int after_syncs) {
+  if (!ctx || after_syncs < -1) return APO_EINVAL;
+  ctx->ws.fail_after = after_syncs;
+  return APO_OK;
+}
+
+extern "C" int apo_memory(apo_ctx *ctx, size_t *held, size_t *server_pool, size_t *server_held) {
+  if (!ctx || !held) return APO_EINVAL;
+  *held = ctx_held(ctx);
+  size_t pool = 0, sh = 0;
+  if (ctx->server) {
+    std::lock_guard<std::mutex> lk(ctx->server->mu);
+    pool = ctx->server->pool;
+    for (const auto &sl : ctx->server->slots) sh += sl->held;  // an upper bound while a batch grows it
+  }
+  if (server_pool) *server_pool = pool;
+  if (server_held) *server_held = sh;
+  return APO_OK;
+}
+
+extern "C" int apo_set_window_greedy(apo_ctx *ctx, int on) {
+  if (!ctx || on < 0 || on > 1) return APO_EINVAL;
+  ctx->win_greedy = on != 0;
+  return APO_OK;
+}
+
+extern "C" int apo_set_selection_round_cap(apo_ctx *ctx, int rounds) {
+  if (!ctx || rounds < 0 || rounds > kSelRoundCap) return APO_EINVAL;
+  ctx->sel_cap = rounds;
+  return APO_OK;
 }
 
 extern "C" int apo_set_lanes(apo_ctx *ctx, int lanes) {
@@ -743,7 +858,7 @@ extern "C" int apo_tune(apo_ctx *ctx, const void *d_tokens, int token_bits, uint
     return APO_EINVAL;
   if (set_dev(ctx)) return APO_EDEVICE;
   reps = std::max(1, std::min(reps, 50));
-  int rc = ctx->ws.ensure(n, 1, ctx->budget);
+  int rc = ctx_ensure(ctx, ctx->ws, n, 1);
   if (rc) return map_rc(rc);
   const uint64_t off[2] = {0, n};
   double best = 1e30;
@@ -815,12 +930,68 @@ extern "C" int apo_tune_load(apo_ctx *ctx, const char *path) {
 }
 
 // ===================================================================== server
-// Each slot owns a resident workspace and stream.  A free slot takes every
-// queued request that shares the oldest request's min_len and fits its token
-// budget, packs them into one batch (windows never interact), runs it, and
-// publishes each window's rows.  Slots run concurrently on their streams, so
-// requests arriving while others are on the GPU are admitted as soon as a
-// slot frees up, and their work overlaps on the device.
+// Each slot owns a resident workspace and stream.  Admission is by device
+// memory: the slots' workspaces together may hold at most the server's pool
+// (the context budget, or most of the device memory free at start).  A free
+// slot takes the oldest queued request and every later one with the same
+// min_len while the grown workspace of the packed batch still fits beside
+// what the other slots hold; idle slots hand their workspaces back when a
+// batch needs the room, and a batch that does not fit waits (queued) until a
+// busy slot finishes.  Windows never interact, so a packed batch gives every
+// window its own result.  Slots run concurrently on their streams: requests
+// arriving while others are on the GPU are admitted as soon as a slot and
+// memory free up, and their work overlaps on the device.
+
+// Device bytes a workspace would hold after growing for `total` tokens in W windows.
+static size_t slot_footprint(const Slot *sl, uint64_t total, uint32_t W) {
+  return sl->ws.bytes_after(std::max<uint64_t>(total, 2), W);
+}
+
+static size_t others_held(const Server *S, const Slot *me) {
+  size_t b = 0;
+  for (const auto &o : S->slots)
+    if (o.get() != me) b += o->held;
+  return b;
+}
+
+// Under S->mu: frees the workspaces of idle slots (their streams are idle).
+static void release_idle_slots(Server *S, Slot *me) {
+  for (auto &o : S->slots) {
+    if (o.get() == me || o->busy || o->held == 0) continue;
+    o->ws.release();
+    o->held = 0;
+  }
+}
+
+// Under S->mu: moves the requests of the next batch from the queue into
+// `batch`; returns false when even the oldest request does not fit yet.
+static bool take_batch(Server *S, Slot *sl, std::vector<std::shared_ptr<Request>> &batch, size_t &reserve) {
+  const uint32_t ml = S->queue.front()->min_len;
+  for (int attempt = 0; attempt < 2; attempt++) {
+    const size_t avail = S->pool > others_held(S, sl) ? S->pool - others_held(S, sl) : 0;
+    uint64_t tot = 0;
+    uint32_t W = 0;
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+      const uint64_t n = (*it)->tokens.size();
+      size_t need;
+      if ((*it)->min_len == ml && (need = slot_footprint(sl, tot + n, W + 1)) <= avail) {
+        tot += n;
+        W++;
+        reserve = need;
+        batch.push_back(*it);
+        it = S->queue.erase(it);
+      } else if (batch.empty()) {
+        break;  // the oldest request comes first: never overtaken by later ones
+      } else {
+        ++it;
+      }
+    }
+    if (!batch.empty()) return true;
+    release_idle_slots(S, sl);  // make room, then try once more
+  }
+  return false;
+}
+
 static void slot_loop(Server *S, Slot *sl) {
   (void)hipSetDevice(S->device);
   std::vector<std::shared_ptr<Request>> batch;
@@ -832,20 +1003,16 @@ static void slot_loop(Server *S, Slot *sl) {
     batch.clear();
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
-      if (S->queue.empty() && S->stopping) return;
-      const uint32_t ml = S->queue.front()->min_len;
-      uint64_t tot = 0;
-      for (auto it = S->queue.begin(); it != S->queue.end();) {
-        const uint64_t n = (*it)->tokens.size();
-        if ((*it)->min_len == ml && (batch.empty() || tot + n <= S->slot_token_cap)) {
-          tot += n;
-          batch.push_back(*it);
-          it = S->queue.erase(it);
-        } else {
-          ++it;
-        }
+      size_t reserve = 0;
+      while (true) {
+        S->cv_work.wait(lk, [&] { return S->stopping || !S->queue.empty(); });
+        if (S->queue.empty() && S->stopping) return;
+        if (take_batch(S, sl, batch, reserve)) break;
+        // not enough device memory while other slots run: wait for one to finish
+        S->cv_mem.wait(lk);
       }
+      sl->busy = true;
+      sl->held = std::max(sl->held, reserve);
     }
     const uint32_t W = (uint32_t)batch.size();
     off.assign(W + 1, 0);
@@ -865,7 +1032,7 @@ static void slot_loop(Server *S, Slot *sl) {
       for (uint32_t w = 0; w < W; w++)
         if (!batch[w]->tokens.empty())
           memcpy(sl->pinned + off[w], batch[w]->tokens.data(), batch[w]->tokens.size() * 8);
-      rc = map_rc(sl->ws.ensure(std::max<uint64_t>(total, 2), W, S->slot_budget));
+      rc = map_rc(sl->ws.ensure(std::max<uint64_t>(total, 2), W, 0));  // admitted against the pool above
     }
     outoff.assign(W + 1, 0);
     if (!rc && total >= 2) {
@@ -893,6 +1060,7 @@ static void slot_loop(Server *S, Slot *sl) {
           rc = APO_EDEVICE;
       }
     }
+    if (rc) (void)hipGetLastError();
     const auto now = std::chrono::steady_clock::now();
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -906,10 +1074,20 @@ static void slot_loop(Server *S, Slot *sl) {
         R.done = true;
         if (R.discard) S->tickets.erase(R.ticket);
       }
+      sl->busy = false;
+      sl->held = sl->ws.held();
     }
+    S->cv_mem.notify_all();
+    S->cv_work.notify_all();  // requests that waited for memory may fit now
     S->batches++;
     S->windows += W;
   }
+}
+
+// What a context's own workspaces may hold: the budget less the server's pool.
+static size_t ctx_limit(const apo_ctx *c) {
+  const size_t pool = c->server ? c->server->pool : 0;
+  return c->budget > pool ? c->budget - pool : 0;
 }
 
 extern "C" int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue_cap) {
@@ -920,17 +1098,16 @@ extern "C" int apo_server_start(apo_ctx *ctx, uint32_t max_slots, uint32_t queue
   S->device = ctx->device;
   S->tune = ctx->tune;
   S->queue_cap = queue_cap ? queue_cap : 65536;
-  // per-slot memory share; token budget = largest N whose workspace fits
-  size_t budget = ctx->budget;
-  if (!budget) {
+  // the slots' memory pool: what the context budget leaves beside the
+  // context's own workspaces, else 80% of the device memory free now
+  if (ctx->budget) {
+    const size_t own = ctx_held(ctx);
+    S->pool = ctx->budget > own ? ctx->budget - own : 0;
+  } else {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return APO_EDEVICE;
-    budget = fr / 2;
+    S->pool = fr / 10 * 8;
   }
-  S->slot_budget = budget / max_slots;
-  uint64_t cap = 1024;
-  while (Workspace::bytes_for(cap * 2, 4096) <= S->slot_budget && cap < (1ull << 30)) cap *= 2;
-  S->slot_token_cap = cap;
   for (uint32_t i = 0; i < max_slots; i++) {
     auto sl = std::make_unique<Slot>();
     if (hipStreamCreate(&sl->stream) != hipSuccess) return APO_EDEVICE;
@@ -947,7 +1124,11 @@ extern "C" int apo_submit(apo_ctx *ctx, uint32_t stream_id, const uint64_t *toke
   if (!ctx || !ticket || (!tokens && n) || min_len == 0 || n > APO_MAX_N) return APO_EINVAL;
   Server *S = ctx->server.get();
   if (!S) return APO_EINVAL;
-  if ((uint64_t)n > S->slot_token_cap) return APO_ENOMEM;
+  {
+    // a window that could never be admitted, even alone on an empty pool
+    Workspace fresh;
+    if (fresh.bytes_after(std::max<uint32_t>(n, 2), 1) > S->pool) return APO_ENOMEM;
+  }
   auto R = std::make_shared<Request>();
   R->stream_id = stream_id;
   R->min_len = min_len;
@@ -1019,6 +1200,7 @@ extern "C" int apo_server_stop(apo_ctx *ctx) {
     S->stopping = true;
   }
   S->cv_work.notify_all();
+  S->cv_mem.notify_all();
   for (auto &sl : S->slots) {
     if (sl->th.joinable()) sl->th.join();
     (void)hipSetDevice(S->device);

@@ -27,6 +27,8 @@ enum Cnt {
 };
 
 constexpr int kStages = 7;
+// single windows up to this many tokens use the one-wavefront greedy
+constexpr uint64_t kWinSelSingle = 1ull << 15;
 constexpr int kSelRoundCap = 64;
 
 struct RunInfo {
@@ -91,10 +93,25 @@ struct Workspace {
   hipEvent_t kev[2 * kMaxTimed] = {};
   int kround[kMaxTimed] = {0};
   int kev_n = 0;
+  int sel_cap = kSelRoundCap;      // host-driven selection rounds before the sequential completion
+  int fail_after = -1;             // test hook: host syncs before one reports a device error (-1: never)
+  bool win_greedy = true;          // one-wavefront-per-window greedy where windows are short enough
 
+  // device bytes a workspace of capacity (N, W) holds (exact)
   static size_t bytes_for(uint64_t N, uint32_t W);
+  // device bytes held now, and after ensure(N, W)
+  size_t held() const { return mem ? bytes + eng.bytes() : 0; }
+  size_t bytes_after(uint64_t N, uint32_t W) const;
+  // grows (never shrinks) to hold N tokens in W windows; -2 if the grown
+  // workspace would exceed `budget` bytes (0: no limit) or allocation fails
   int ensure(uint64_t N, uint32_t W, size_t budget);
   void release();
+
+ private:
+  void grow_target(uint64_t N, uint32_t W, uint64_t &wantN, uint32_t &wantW) const;
+  int layout(uint64_t N, uint32_t W, size_t *dry_bytes);
+
+ public:
 };
 
 // Runs the stages of one analysis on stream s.  d_tok: device tokens of
@@ -102,8 +119,10 @@ struct Workspace {
 // ascending, h_off[0] == 0).  Results stay in the workspace.
 int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
                  uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info, Mode mode = Mode::HOST);
+// window_major: the candidate list (and so the accepted occurrences) is
+// already ordered window by window.
 int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t *wid, const uint32_t *wbeg,
-                uint64_t m_bound, bool host, hipStream_t s);
+                uint64_t m_bound, bool host, hipStream_t s, bool window_major);
 // sel_launched: selection rounds enqueued by a sync-free run (-1: host-driven).
 // Returns 1 when a sync-free run left candidates undecided (the caller then
 // reruns host-driven).

@@ -38,16 +38,13 @@ static void plan(uint64_t N, uint32_t W, int &nsnap, int &nT, int &nlev, uint64_
   (void)W;
 }
 
+// Exact device bytes ensure() allocates for capacity (N, W): the workspace
+// layout (computed by a dry pass of the layout code) plus the sort engine.
 size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
-  int ns, nt, nl;
-  uint64_t hc;
-  plan(N, W, ns, nt, nl, hc);
-  const uint64_t C2 = 2 * N;
+  Workspace probe;
   size_t b = 0;
-  b += N * 8 + N * 4 * 8 + (hc + 1) * 12 + (W + 1) * 12 + (size_t)ns * N * 4 + N + N * 12;
-  b += C2 * (4 * 8 + 2) + 8192 + 2 * (size_t)nt * N * 4 + N + N * 12 + N * 24 + N * 8 + N * 8 + N;
-  b += C2 * 4 * 8 + C2 * 8 * 2 * 2 + (C2 / (1u << kMinTileLog) + 64) * ((size_t)kBins * 8 + 8 * 16);  // sort engine
-  return b;
+  probe.layout(N, W, &b);
+  return b + SortEngine::bytes_for(2 * N);
 }
 
 void Workspace::release() {
@@ -70,12 +67,32 @@ void Workspace::release() {
   capW = 0;
 }
 
+void Workspace::grow_target(uint64_t N, uint32_t W, uint64_t &wantN, uint32_t &wantW) const {
+  wantN = std::max<uint64_t>(pow2_at_least(std::max<uint64_t>(N, 1024)), capN);
+  wantW = std::max<uint32_t>((uint32_t)pow2_at_least(std::max<uint32_t>(W, 1)), capW);
+}
+
+size_t Workspace::bytes_after(uint64_t N, uint32_t W) const {
+  if (N <= capN && W <= capW && mem) return held();
+  uint64_t wantN;
+  uint32_t wantW;
+  grow_target(N, W, wantN, wantW);
+  return bytes_for(wantN, wantW);
+}
+
 int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   if (N <= capN && W <= capW && mem) return 0;
-  const uint64_t wantN = std::max<uint64_t>(pow2_at_least(std::max<uint64_t>(N, 1024)), capN);
-  const uint32_t wantW = std::max<uint32_t>((uint32_t)pow2_at_least(std::max<uint32_t>(W, 1)), capW);
+  uint64_t wantN;
+  uint32_t wantW;
+  grow_target(N, W, wantN, wantW);
   if (budget && bytes_for(wantN, wantW) > budget) return -2;
   release();
+  return layout(wantN, wantW, nullptr);
+}
+
+// Lays out every array of a workspace of capacity (N_, wantW); with
+// dry_bytes set only the total is computed (nothing is allocated).
+int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes) {
   plan(wantN, wantW, nsnap, nT, nlev, hcap);
   const uint64_t N_ = wantN, C2 = 2 * wantN;
   Layout L;
@@ -103,6 +120,10 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   size_t o_cnt = L.take(CNT_COUNT * 4);
   size_t o_rh = L.take(4 * 64 * 4);
   size_t o_sc = L.take(3 * (kSelRoundCap + 2) * 4);
+  if (dry_bytes) {
+    *dry_bytes = L.total;
+    return 0;
+  }
   hipError_t e = hipMalloc(&mem, L.total);
   if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
   bytes = L.total;
@@ -172,6 +193,10 @@ static int read_counters(Workspace &w, hipStream_t s) {
   APO_HIP_TRY(hipMemcpyAsync(w.hcnt, w.dcnt, CNT_COUNT * 4, hipMemcpyDeviceToHost, s));
   APO_HIP_TRY(hipMemcpyAsync(w.hctr, w.eng.bufs().ctr, sizeof(SortCounters), hipMemcpyDeviceToHost, s));
   APO_HIP_TRY(hipStreamSynchronize(s));
+  if (w.fail_after >= 0 && w.fail_after-- == 0) {  // test hook: this sync reports a device error
+    fprintf(stderr, "[apo] injected device error\n");
+    return -4;
+  }
   if (w.hctr->err) {
     fprintf(stderr, "[apo] device capacity check failed (code %u)\n", w.hctr->err);
     return -4;
@@ -373,6 +398,14 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     maxl_bound = std::max<uint32_t>(w.hcnt[CNT_MAXL], 1);
   }
   stamp(w, 4, s, stamps);
+  // Greedy by one wavefront per window over an LDS bitmap when every window
+  // is short enough: then the candidate list is sorted window by window
+  // (window above the length in the sort key), which also leaves the
+  // accepted occurrences in the output's (window, priority) order.
+  const int lbits = bit_length_u64(maxl_bound);
+  const int wbits = batch ? bit_length_u64(W - 1) : 0;
+  const bool winsel =
+      w.win_greedy && (batch ? (maxwin <= kWinSelMax && lbits + wbits <= 32) : (N <= kWinSelSingle));
   uint64_t m_bound = 0;
   if (c_bound > 0) {
     // Priority order (length desc, ID asc, start asc).  The records are in
@@ -385,8 +418,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     // reads its own copy
     uint32_t *xs[3] = {w.tmp_a, w.tmp_b, w.tmp_c};  // length key, start, ID
     uint32_t *ys[3] = {w.s_len, w.s_start, w.s_id};
-    lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, bit_length_u64(maxl_bound), xs, ys, B.key[0],
-                        w.tmp_d, dc + CNT_AUX, w.tile_tmp, s);
+    const bool wkey = winsel && batch;
+    lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, lbits + (wkey ? wbits : 0), xs, ys, B.key[0],
+                        w.tmp_d, dc + CNT_AUX, w.tile_tmp, s, wkey ? wid : nullptr, lbits);
     E.reset_counters(s);
     E.round_begin(0, s);
     E.iota_val(dc + CNT_C, c_bound, s);
@@ -398,7 +432,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     E.lds_plain(0, 0, 1, w.keep, c_bound, s);
     E.bulk_plain(0, 0, 1, w.keep, c_bound, s);
     compact_sorted_runs(B.val[0], w.keep, dc + CNT_C, c_bound, w.tmp_a, w.tmp_b, w.tmp_c, dc + CNT_MAXL, w.s_len,
-                        w.s_start, w.s_id, w.tile_tmp, dc + CNT_M, s);
+                        w.s_start, w.s_id, w.tile_tmp, dc + CNT_M, s,
+                        wkey ? (uint32_t)((1ull << lbits) - 1) : 0xFFFFFFFFu);
     m_bound = c_bound;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;
@@ -414,7 +449,14 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 
   // ---- greedy selection
   int sel_done = -1, sel_launched = 0;
-  if (m_bound > 0) {
+  if (m_bound > 0 && winsel) {
+    fill_u32(w.selcnt, 3 * (kSelRoundCap + 2), 0, s);  // one round, nothing left undecided after it
+    copy_u32(w.selcnt, dc + CNT_M, s);
+    sel_windows(w.s_len, w.s_start, dc + CNT_M, m_bound, batch ? wid : nullptr, w.d_off, W, batch ? maxwin : N,
+                w.tmp_d, w.state, s);
+    sel_done = 0;
+    sel_launched = 1;
+  } else if (m_bound > 0) {
     const int top = 63 - __builtin_clzll(maxl_bound);
     uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
     uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2), *nwork = w.selcnt + 2 * (kSelRoundCap + 2);
@@ -428,9 +470,12 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int ahead = host ? 2 : kSelFreeRounds;
     int q0 = 0;
     uint64_t hint = m_bound;
-    while (sel_done < 0 && q0 < kSelRoundCap) {
-      const int hi = std::min(q0 + ahead, kSelRoundCap);
-      for (int q = q0; q < hi; q++)
+    // host-driven runs stop the rounds at w.sel_cap (kSelRoundCap unless a
+    // test lowers it) and finish with the sequential completion
+    const int cap = host ? std::max(0, std::min(w.sel_cap, kSelRoundCap)) : kSelRoundCap;
+    while (sel_done < 0 && q0 < cap) {
+      const int lo = q0, hi = std::min(q0 + ahead, cap);
+      for (int q = lo; q < hi; q++)
         sel_round(w.s_len, w.s_start, (q & 1) ? Tb : Ta, (q & 1) ? Ta : Tb, top, N, w.state, w.live[0],
                   w.live[1], nlive, nwork, undec, q, hint, dc + CNT_MAXL, w.ctree, npad, w.mark, s);
       q0 = hi;
@@ -438,7 +483,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       if (!host) break;  // checked after the output stage
       APO_HIP_TRY(hipMemcpyAsync(w.hsel, w.selcnt, 2 * (kSelRoundCap + 2) * 4, hipMemcpyDeviceToHost, s));
       if ((rc = read_counters(w, s))) return rc;
-      for (int q = q0 - ahead; q < hi; q++)
+      for (int q = lo; q < hi; q++)
         if (w.hsel[q + 1] == 0) { sel_done = q; break; }  // nlive[q + 1]: undecided after round q
       if (sel_done < 0) hint = w.hsel[hi];
     }
@@ -450,13 +495,13 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   stamp(w, 6, s, stamps);
 
   // ---- accepted occurrences and rows
-  int orc = emit_output(w, N, W, batch, wid, wbeg, m_bound, host, s);
+  int orc = emit_output(w, N, W, batch, wid, wbeg, m_bound, host, s, winsel);
   if (orc) return orc;
   stamp(w, 7, s, stamps);
   if (mode == Mode::CAPTURE) return 0;
   rc = finish_run(w, N, m_bound, host ? -1 : sel_launched, info, s, stamps);
   if (host && sel_done < 0 && m_bound > 0) {
-    info.sel_rounds = kSelRoundCap;
+    info.sel_rounds = (uint32_t)sel_launched;
     info.sel_sequential = 1;
   }
   return rc;
@@ -465,7 +510,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 // Accepted occurrences in priority order, the per-window order of batches,
 // rows and their counts.
 int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t *wid, const uint32_t *wbeg,
-                uint64_t m_bound, bool host, hipStream_t s) {
+                uint64_t m_bound, bool host, hipStream_t s, bool window_major) {
   SortBufs &B = w.eng.bufs();
   uint32_t *dc = w.dcnt;
   int rc;
@@ -482,7 +527,7 @@ int emit_output(Workspace &w, uint64_t N, uint32_t W, bool batch, const uint32_t
     if (a_bound == 0) return 0;
   }
   const uint32_t *order = nullptr;
-  if (batch) {
+  if (batch && !window_major) {
     window_of_occ(w.o_start, w.wid, dc + CNT_A, a_bound, w.tmp_c, s);
     iota_u32(w.tmp_d, dc + CNT_A, a_bound, s);
     const uint32_t *f[2] = {w.tmp_c, w.tmp_d};

@@ -6,7 +6,9 @@ namespace apo {
 
 class SortEngine {
  public:
-  int alloc(uint64_t capacity);
+  // dry_bytes != nullptr: only computes the device bytes alloc would take
+  int alloc(uint64_t capacity, size_t *dry_bytes = nullptr);
+  static size_t bytes_for(uint64_t capacity);
   void release();
   SortBufs &bufs() { return b_; }
   uint64_t capacity() const { return cap_; }

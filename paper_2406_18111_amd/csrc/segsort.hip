@@ -1171,7 +1171,14 @@ static inline dim3 grid_for(uint64_t n, int threads, int cap_blocks) {
   return dim3((unsigned)b);
 }
 
-int SortEngine::alloc(uint64_t capacity) {
+size_t SortEngine::bytes_for(uint64_t capacity) {
+  SortEngine probe;
+  size_t b = 0;
+  probe.alloc(capacity, &b);
+  return b;
+}
+
+int SortEngine::alloc(uint64_t capacity, size_t *dry_bytes) {
   cap_ = capacity;
   SortBufs &B = b_;
   B.cap = capacity;
@@ -1198,6 +1205,10 @@ int SortEngine::alloc(uint64_t capacity) {
   size_t o_cur = take((size_t)B.big_cap * kBins * 4);
   size_t o_act0 = take(capacity * 4), o_act1 = take(capacity * 4);
   size_t o_ctr = take(sizeof(SortCounters));
+  if (dry_bytes) {  // size only
+    *dry_bytes = bytes;
+    return 0;
+  }
   APO_HIP_TRY(hipMalloc(&mem_, bytes));
   bytes_ = bytes;
   char *m = static_cast<char *>(mem_);

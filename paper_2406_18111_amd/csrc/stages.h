@@ -56,13 +56,16 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
 
 // Stable sort of the candidate records by length, longest first (records in
 // suffix-array order come out ordered by (length desc, ID asc)): LSD passes
-// over key = *maxl - length, carrying start and ID.  The result lands in
-// xs = {key, start, ID} arrays, the sorted starts also in start_copy
+// over key = *maxl - length, carrying start and ID.  With wid set the key is
+// (window of the start << wshift) | (*maxl - length), so records come out
+// window by window, each window in (length desc, ID asc) order.  The result
+// lands in xs = {key, start, ID} arrays, the sorted starts also in start_copy
 // (nullable); ys is the alternate set; hist holds 256 u32
 // per 4096 records (at least 256); hist_n is one device word of scratch.
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
                          int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
-                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s);
+                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s,
+                         const uint32_t *wid = nullptr, int wshift = 0);
 // flag[i] = 1 where (key, p2) differs from position i - 1.
 void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint64_t bound, uint8_t *flag,
                hipStream_t s);
@@ -70,11 +73,11 @@ void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, u
 void flag_positions(const uint8_t *flag, const uint32_t *n_dev, uint64_t bound, uint32_t *out, uint32_t *count,
                     uint32_t *tile_tmp, hipStream_t s);
 // Compaction of the sorted candidates: slot k (keep[k] set) takes position
-// order[k] of the length-sorted arrays; length = *maxl - lkey.
+// order[k] of the length-sorted arrays; length = *maxl - (lkey & lmask).
 void compact_sorted_runs(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
                          const uint32_t *lkey, const uint32_t *start, const uint32_t *id, const uint32_t *maxl,
                          uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp, uint32_t *total,
-                         hipStream_t s);
+                         hipStream_t s, uint32_t lmask = 0xFFFFFFFFu);
 
 void compact_sorted(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
                     const uint32_t *crec, uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp,
@@ -95,6 +98,17 @@ void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_
                hipStream_t s);
 void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
                     uint8_t *mark, uint64_t n, hipStream_t s);
+
+// Exact greedy for candidate lists ordered window by window (each window's
+// candidates in priority order): one wavefront per window over an LDS bitmap
+// of its positions (windows of at most kWinSelMax tokens).  woff: window
+// offsets (nwin + 1 entries, the list's positions are relative to woff[0] =
+// 0); wid: window of each position (null for one window); cand_off: nwin + 1
+// words of scratch; state[k] receives 1 (accepted) or 2 (rejected).
+constexpr uint64_t kWinSelMax = 1ull << 17;
+void sel_windows(const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
+                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint32_t *cand_off,
+                 uint8_t *state, hipStream_t s);
 
 void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
                      const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,

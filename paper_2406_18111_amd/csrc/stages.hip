@@ -706,9 +706,10 @@ constexpr int kCandItems = 8;
 constexpr uint32_t kCandStage = 1024;
 
 // Occupancy of 6 wavefronts per SIMD: the ID queries are latency-bound, and
-// the write pass would otherwise take ~127 registers (4 wavefronts); measured
-// 919 -> 528 us per launch on the batched workload, a few spilled registers
-// included.
+// the write pass would otherwise take ~127 registers (4 wavefronts); on the
+// batched workload analysed on one stream the write pass went from 825 to
+// 754 us per launch, a few spilled registers included (a gain within the
+// noise of the whole step).
 template <bool WRITE>
 __global__ __launch_bounds__(256, 6) void k_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n,
                                                     const uint32_t *wend, uint32_t min_len, MinLevels M,
@@ -938,6 +939,8 @@ struct LsdSrc {
   const uint32_t *rec;           // candidate records, or null
   const uint32_t *maxl;          // with records: key = *maxl - length
   const uint32_t *key, *p1, *p2; // without records
+  const uint32_t *wid;           // with records (nullable): key |= window of the start << wshift
+  int wshift;
 };
 
 __device__ __forceinline__ void lsd_load(const LsdSrc &in, uint64_t i, uint32_t maxl, uint32_t &k, uint32_t &a,
@@ -945,6 +948,7 @@ __device__ __forceinline__ void lsd_load(const LsdSrc &in, uint64_t i, uint32_t 
   if (in.rec) {
     const uint32_t *r = in.rec + kCandWords * i;
     k = maxl - r[0]; a = r[1]; b = r[2];
+    if (in.wid) k |= in.wid[a] << in.wshift;
   } else {
     k = in.key[i]; a = in.p1[i]; b = in.p2[i];
   }
@@ -1085,19 +1089,20 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
 
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
                          int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
-                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s) {
+                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s, const uint32_t *wid,
+                         int wshift) {
   const int passes = std::max(1, (key_bits + kLsdBits - 1) / kLsdBits);
   const uint32_t ntiles = (uint32_t)std::max<uint64_t>((bound + kLsdTile - 1) / kLsdTile, 1);
   const unsigned grid = std::min<uint32_t>(ntiles, 8192);
   fill_u32(hist_n, 1, kLsdBins * ntiles, s);
-  LsdSrc in{crec, maxl_dev, nullptr, nullptr, nullptr};
+  LsdSrc in{crec, maxl_dev, nullptr, nullptr, nullptr, wid, wshift};
   for (int ps = 0; ps < passes; ps++) {
     uint32_t *const *out = ((passes - 1 - ps) % 2 == 0) ? xs : ys;  // the last pass writes xs
     hipLaunchKernelGGL(k_lsd_hist, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles);
     scan_excl(hist, hist, hist_n, (uint64_t)kLsdBins * ntiles, tile_tmp, nullptr, s);
     hipLaunchKernelGGL(k_lsd_scatter, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles, out[0],
                        out[1], out[2], ps == passes - 1 ? start_copy : nullptr);
-    in = LsdSrc{nullptr, nullptr, out[0], out[1], out[2]};
+    in = LsdSrc{nullptr, nullptr, out[0], out[1], out[2], nullptr, 0};
   }
 }
 
@@ -1128,18 +1133,19 @@ struct GatherSortedRuns {
   using Rec = uint3;
   const uint32_t *order, *lkey, *start, *id, *maxl;
   uint32_t *s_len, *s_start, *s_id;
+  uint32_t lmask;  // bits of the key that hold maxl - length (a window may sit above them)
   __device__ Rec get(uint64_t k) const {
     const uint32_t q = order[k];
-    return make_uint3(*maxl - lkey[q], start[q], id[q]);
+    return make_uint3(*maxl - (lkey[q] & lmask), start[q], id[q]);
   }
   __device__ void put(uint32_t o, Rec r) const { s_len[o] = r.x; s_start[o] = r.y; s_id[o] = r.z; }
 };
 void compact_sorted_runs(const uint32_t *order, const uint8_t *keep, const uint32_t *m_dev, uint64_t bound,
                          const uint32_t *lkey, const uint32_t *start, const uint32_t *id, const uint32_t *maxl,
                          uint32_t *s_len, uint32_t *s_start, uint32_t *s_id, uint32_t *tile_tmp, uint32_t *total,
-                         hipStream_t s) {
+                         hipStream_t s, uint32_t lmask) {
   flag_compact(keep, FlagNonZero{}, m_dev, bound, tile_tmp, total,
-               GatherSortedRuns{order, lkey, start, id, maxl, s_len, s_start, s_id}, s);
+               GatherSortedRuns{order, lkey, start, id, maxl, s_len, s_start, s_id, lmask}, s);
 }
 
 // ------------------------------------------------------------- selection
@@ -1571,6 +1577,101 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
   fill_u8(mark, n, 0, s);
   hipLaunchKernelGGL(k_sel_paint, grid_for(bound, 256, 8192), dim3(256), 0, s, state, len, start, m_dev, mark);
   hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m_dev, mark);
+}
+
+// ----------------------------------------- per-window sequential greedy
+// For candidate lists ordered window by window (each window's candidates in
+// priority order): one wavefront per window walks its list in batches of 64
+// over an LDS bitmap of the window's accepted positions, which reproduces
+// the sequential greedy exactly.  A lane passes when neither end of its
+// interval is marked (exact, because every interval accepted before it is at
+// least as long); the lowest passing lane is accepted and knocks out every
+// later passing lane whose interval intersects it, until no passing lane is
+// left; the accepted intervals are then painted, one at a time by the whole
+// wavefront.  Candidate loads run kWinSelDepth batches ahead.
+// state[k] = 1 (accepted) or 2 (rejected) for every candidate.
+constexpr int kWinSelDepth = 4;
+
+__global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const uint32_t *start,
+                                                   const uint32_t *cand_off, const uint64_t *woff, uint32_t nwin,
+                                                   uint8_t *state) {
+  extern __shared__ uint32_t bm[];
+  const uint32_t w = blockIdx.x;
+  if (w >= nwin) return;
+  const int lane = threadIdx.x;
+  const uint32_t c0 = cand_off[w], c1 = cand_off[w + 1];
+  if (c0 >= c1) return;
+  const uint32_t ws = (uint32_t)woff[w];
+  const uint32_t L = (uint32_t)(woff[w + 1] - woff[w]);
+  for (uint32_t x = lane; x < (L + 31) / 32; x += 64) bm[x] = 0;
+  uint32_t ps[kWinSelDepth], pl[kWinSelDepth];
+#pragma unroll
+  for (int d = 0; d < kWinSelDepth; d++) {
+    const uint32_t k = c0 + d * 64 + lane;
+    ps[d] = k < c1 ? start[k] : 0u;
+    pl[d] = k < c1 ? len[k] : 1u;
+  }
+  __syncthreads();
+  for (uint32_t base = c0; base < c1; base += 64 * kWinSelDepth) {
+#pragma unroll
+    for (int d = 0; d < kWinSelDepth; d++) {
+      const uint32_t b = base + d * 64;
+      if (b >= c1) break;  // wavefront-uniform
+      const uint32_t k = b + lane;
+      const bool valid = k < c1;
+      const uint32_t s = ps[d] - ws, e = s + pl[d] - 1u;
+      const uint32_t kn = k + 64 * kWinSelDepth;  // refill this slot with the batch kWinSelDepth ahead
+      if (kn < c1) {
+        ps[d] = start[kn];
+        pl[d] = len[kn];
+      }
+      bool ok = false;
+      if (valid) ok = !((bm[s >> 5] >> (s & 31)) & 1u) && !((bm[e >> 5] >> (e & 31)) & 1u);
+      uint64_t pass = __ballot(ok);
+      uint64_t acc = 0;
+      while (pass) {
+        const int j = __ffsll((unsigned long long)pass) - 1;
+        const uint32_t sj = (uint32_t)__shfl((int)s, j, 64), ej = (uint32_t)__shfl((int)e, j, 64);
+        acc |= 1ull << j;
+        pass &= ~__ballot(valid && s <= ej && e >= sj);  // j itself and the later lanes it overlaps
+      }
+      uint64_t todo = acc;
+      while (todo) {
+        const int j = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const uint32_t sj = (uint32_t)__shfl((int)s, j, 64), ej = (uint32_t)__shfl((int)e, j, 64);
+        const uint32_t w0 = sj >> 5, w1 = ej >> 5;
+        for (uint32_t x = w0 + lane; x <= w1; x += 64) {
+          uint32_t msk = 0xFFFFFFFFu;
+          if (x == w0) msk &= 0xFFFFFFFFu << (sj & 31);
+          if (x == w1) msk &= 0xFFFFFFFFu >> (31 - (ej & 31));
+          atomicOr(&bm[x], msk);  // accepted intervals may share their end words
+        }
+      }
+      if (valid) state[k] = ((acc >> lane) & 1ull) ? 1 : 2;
+    }
+  }
+}
+
+// cand_off[w] = index of window w's first candidate in a window-major list
+// (cand_off[nwin] = m); windows without candidates get the next window's.
+__global__ void k_window_cand_off(const uint32_t *start, const uint32_t *m_dev, const uint32_t *wid, uint32_t nwin,
+                                  uint32_t *cand_off) {
+  const uint64_t m = *m_dev;
+  GRID_STRIDE(k, m + 1) {
+    const uint32_t wk = k < m ? (wid ? wid[start[k]] : 0u) : nwin;
+    const uint32_t lo = k > 0 ? (wid ? wid[start[k - 1]] : 0u) + 1u : 0u;
+    for (uint32_t x = lo; x <= wk; x++) cand_off[x] = (uint32_t)k;
+  }
+}
+
+void sel_windows(const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
+                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint32_t *cand_off,
+                 uint8_t *state, hipStream_t s) {
+  hipLaunchKernelGGL(k_window_cand_off, grid_for(bound + 1, 256, 8192), dim3(256), 0, s, start, m_dev, wid, nwin,
+                     cand_off);
+  const size_t lds = ((maxwin + 31) / 32) * 4;
+  hipLaunchKernelGGL(k_sel_window, dim3(nwin), dim3(64), lds, s, len, start, cand_off, woff, nwin, state);
 }
 
 // ------------------------------------------------- per-interval greedy counts

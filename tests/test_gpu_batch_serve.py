@@ -221,9 +221,11 @@ def test_graph_capture_and_replay(ctx):
 
 
 @pytest.mark.parametrize("lanes", [1, 2, 3, 4])
-def test_lanes_give_identical_results(lanes):
+@pytest.mark.parametrize("window_greedy", [True, False])
+def test_lanes_give_identical_results(lanes, window_greedy):
     """Concurrent window groups on separate streams: every lane count gives
-    the rows of the single-stream batch and of the oracle."""
+    the rows of the single-stream batch and of the oracle, with the
+    per-window greedy and with the round-based selection."""
     import torch
     from paper_2406_18111_amd import Context
     wins = _mixed_windows(17, 23) + [np.zeros(0, np.uint64)] * 3
@@ -231,6 +233,7 @@ def test_lanes_give_identical_results(lanes):
     dev = torch.from_numpy(toks.view(np.int64)).cuda()
     with Context(0) as g:
         g.set_lanes(lanes)
+        g.set_window_greedy(window_greedy)
         for m in (2, 8):
             rows, oo = g.analyze_batch_dev(dev, off, m)
             rows = rows.cpu().numpy().astype(np.int64)

@@ -143,6 +143,21 @@ def test_find_repeats(ctx, name, tokens, min_len):
     _check_full(ctx, tokens, min_len)
 
 
+@pytest.mark.parametrize("name,tokens", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("min_len", [1, 8])
+def test_find_repeats_both_selection_paths(ctx, name, tokens, min_len):
+    """The round-based selection and the one-wavefront-per-window greedy give
+    the oracle's result on every case (short windows take the wavefront
+    greedy by default; the switch sends them through the rounds)."""
+    print("case", name, min_len, flush=True)
+    try:
+        ctx.set_window_greedy(False)
+        _check_full(ctx, tokens, min_len)
+    finally:
+        ctx.set_window_greedy(True)
+    _check_full(ctx, tokens, min_len)
+
+
 def test_golden_examples(ctx):
     g = json.load(open(os.path.join(GOLDEN_DIR, "worked_examples.json")))
     for case in g["cases"]:

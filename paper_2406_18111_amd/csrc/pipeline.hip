@@ -453,7 +453,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     fill_u32(w.selcnt, 3 * (kSelRoundCap + 2), 0, s);  // one round, nothing left undecided after it
     copy_u32(w.selcnt, dc + CNT_M, s);
     sel_windows(w.s_len, w.s_start, dc + CNT_M, m_bound, batch ? wid : nullptr, w.d_off, W, batch ? maxwin : N,
-                w.tmp_d, w.state, s);
+                w.state, s);
     sel_done = 0;
     sel_launched = 1;
   } else if (m_bound > 0) {

@@ -103,12 +103,12 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
 // candidates in priority order): one wavefront per window over an LDS bitmap
 // of its positions (windows of at most kWinSelMax tokens).  woff: window
 // offsets (nwin + 1 entries, the list's positions are relative to woff[0] =
-// 0); wid: window of each position (null for one window); cand_off: nwin + 1
-// words of scratch; state[k] receives 1 (accepted) or 2 (rejected).
+// 0); wid: window of each position (null for one window); state[k]
+// receives 1 (accepted) or 2 (rejected).
 constexpr uint64_t kWinSelMax = 1ull << 17;
 void sel_windows(const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
-                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint32_t *cand_off,
-                 uint8_t *state, hipStream_t s);
+                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint8_t *state,
+                 hipStream_t s);
 
 void gather_accepted(const uint8_t *state, const uint32_t *m_dev, uint64_t bound, const uint32_t *len,
                      const uint32_t *start, const uint32_t *id, uint32_t *o_len, uint32_t *o_start, uint32_t *o_id,

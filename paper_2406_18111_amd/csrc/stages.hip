@@ -977,12 +977,21 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, const uint32_t *
     __syncthreads();
     const uint64_t tile0 = (uint64_t)t * kLsdTile;
     if (tile0 < n) {
+      // every slot's key is loaded before the first ballot, so the loads
+      // (and a record pass's window lookups) overlap instead of queueing
+      uint32_t K[kLsdSlots];
+#pragma unroll
       for (int e = 0; e < kLsdSlots; e++) {
         const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-        uint32_t k = 0, a, b;
+        uint32_t a, b;
+        K[e] = 0;
+        if (i < n) lsd_load(in, i, maxl, K[e], a, b);
+      }
+#pragma unroll
+      for (int e = 0; e < kLsdSlots; e++) {
+        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
         const bool valid = i < n;
-        if (valid) lsd_load(in, i, maxl, k, a, b);
-        const uint32_t d = (k >> shift) & (kLsdBins - 1);
+        const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
         const uint64_t peers = digit_peers(d, valid);
         if (valid && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
       }
@@ -1588,18 +1597,49 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
 // least as long); the lowest passing lane is accepted and knocks out every
 // later passing lane whose interval intersects it, until no passing lane is
 // left; the accepted intervals are then painted, one at a time by the whole
-// wavefront.  Candidate loads run kWinSelDepth batches ahead.
+// wavefront.  The walk is sequential, so its time is the latency of one
+// batch times the batches of the longest window: candidate loads run
+// kWinSelDepth batches ahead in a register ring so that they never wait.
 // state[k] = 1 (accepted) or 2 (rejected) for every candidate.
-constexpr int kWinSelDepth = 4;
+constexpr int kWinSelDepth = 16;
 
-__global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const uint32_t *start,
-                                                   const uint32_t *cand_off, const uint64_t *woff, uint32_t nwin,
+// First index k in [lo, hi) whose window is >= w (hi if none), for a
+// window-major list: a 64-ary search by the whole wavefront (each step
+// probes 64 evenly spaced entries), window of entry k = wid[start[k]].
+__device__ uint32_t window_lower_bound(const uint32_t *start, const uint32_t *wid, uint32_t lo, uint32_t hi,
+                                       uint32_t w) {
+  const int lane = threadIdx.x & 63;
+  while (hi - lo > 64) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t k = lo + (uint32_t)lane * step;
+    const bool below = k < hi && wid[start[k]] < w;
+    const uint64_t m = __ballot(below);
+    // probes below w form a prefix of the lanes
+    const int nb = __popcll(m);
+    if (nb == 0) return lo;  // probe 0 is lo itself: nothing below
+    const uint32_t nlo = lo + (uint32_t)(nb - 1) * step + 1;
+    const uint32_t nhi = min(hi, lo + (uint32_t)nb * step);
+    lo = nlo;
+    hi = nhi;
+  }
+  const uint32_t k = lo + (uint32_t)lane;
+  const bool below = k < hi && wid[start[k]] < w;
+  return lo + (uint32_t)__popcll(__ballot(below));
+}
+
+__global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const uint32_t *start, const uint32_t *m_dev,
+                                                   const uint32_t *wid, const uint64_t *woff, uint32_t nwin,
                                                    uint8_t *state) {
   extern __shared__ uint32_t bm[];
   const uint32_t w = blockIdx.x;
   if (w >= nwin) return;
   const int lane = threadIdx.x;
-  const uint32_t c0 = cand_off[w], c1 = cand_off[w + 1];
+  const uint32_t m = *m_dev;
+  uint32_t c0 = 0, c1 = m;
+  if (wid) {
+    c0 = window_lower_bound(start, wid, 0, m, w);
+    c1 = window_lower_bound(start, wid, c0, m, w + 1);
+  }
   if (c0 >= c1) return;
   const uint32_t ws = (uint32_t)woff[w];
   const uint32_t L = (uint32_t)(woff[w + 1] - woff[w]);
@@ -1653,25 +1693,12 @@ __global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const ui
   }
 }
 
-// cand_off[w] = index of window w's first candidate in a window-major list
-// (cand_off[nwin] = m); windows without candidates get the next window's.
-__global__ void k_window_cand_off(const uint32_t *start, const uint32_t *m_dev, const uint32_t *wid, uint32_t nwin,
-                                  uint32_t *cand_off) {
-  const uint64_t m = *m_dev;
-  GRID_STRIDE(k, m + 1) {
-    const uint32_t wk = k < m ? (wid ? wid[start[k]] : 0u) : nwin;
-    const uint32_t lo = k > 0 ? (wid ? wid[start[k - 1]] : 0u) + 1u : 0u;
-    for (uint32_t x = lo; x <= wk; x++) cand_off[x] = (uint32_t)k;
-  }
-}
-
 void sel_windows(const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
-                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint32_t *cand_off,
-                 uint8_t *state, hipStream_t s) {
-  hipLaunchKernelGGL(k_window_cand_off, grid_for(bound + 1, 256, 8192), dim3(256), 0, s, start, m_dev, wid, nwin,
-                     cand_off);
+                 const uint32_t *wid, const uint64_t *woff, uint32_t nwin, uint64_t maxwin, uint8_t *state,
+                 hipStream_t s) {
+  (void)bound;
   const size_t lds = ((maxwin + 31) / 32) * 4;
-  hipLaunchKernelGGL(k_sel_window, dim3(nwin), dim3(64), lds, s, len, start, cand_off, woff, nwin, state);
+  hipLaunchKernelGGL(k_sel_window, dim3(nwin), dim3(64), lds, s, len, start, m_dev, wid, woff, nwin, state);
 }
 
 // ------------------------------------------------- per-interval greedy counts

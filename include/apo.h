@@ -52,6 +52,12 @@ extern "C" {
 
 #define APO_MAX_N (1u << 26)
 
+/* Limits of apo_analyze_window_noalloc: the longest window, and the fixed
+ * device array (per GPU, held from the first apo_create on that GPU until
+ * the process ends) that is its whole workspace. */
+#define APO_NOALLOC_MAX_N (1u << 15)
+#define APO_NOALLOC_SCRATCH_BYTES (21u << 20)
+
 enum {
   APO_OK = 0,
   APO_EINVAL = -1,
@@ -115,6 +121,21 @@ int apo_analyze_window_dev(apo_ctx *ctx, const void *d_tokens, int token_bits, u
                            uint32_t min_len, apo_candidate *d_out, uint32_t out_cap,
                            uint32_t *h_out_n, apo_occurrence *d_occ, uint32_t occ_cap,
                            uint32_t *h_occ_n, void *hip_stream);
+
+/* For callers that cannot allocate device memory during the call (code
+ * around HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): apo_analyze_window_dev with the same arguments, outputs and
+ * results, that calls no allocator.  Its workspace is a fixed device array
+ * of APO_NOALLOC_SCRATCH_BYTES per GPU, laid out when the first context on
+ * that GPU is created.  Windows longer than APO_NOALLOC_MAX_N tokens return
+ * APO_ENOMEM (the fixed array is too small).  Every call on a GPU shares
+ * that GPU's array: calls on one GPU are serialised by a lock, and each call
+ * clears what it needs before use.  The call synchronises `hip_stream`, so
+ * it cannot itself be recorded into a graph.  APO_EDEVICE if the array could
+ * not be set up on this GPU. */
+int apo_analyze_window_noalloc(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                               uint32_t min_len, apo_candidate *d_out, uint32_t out_cap, uint32_t *h_out_n,
+                               apo_occurrence *d_occ, uint32_t occ_cap, uint32_t *h_occ_n, void *hip_stream);
 
 /* Many windows at once: window w is tokens[offsets[w] .. offsets[w+1]) of a
  * host array.  Rows of window w are out[out_offsets[w] .. out_offsets[w+1]);
@@ -194,6 +215,12 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
  * 1 if the selection finished with the sequential completion (else 0).
  * Writes min(nvals, 9) values and returns that number. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
+
+/* Device bytes of the workspace an analysis of n tokens in `windows`
+ * windows needs (what a context or a server slot allocates for it; sizes
+ * round up to powers of two).  No device is touched.  0 if n > APO_MAX_N or
+ * windows == 0. */
+size_t apo_workspace_bytes(uint64_t n, uint32_t windows);
 
 /* Device memory of the context: *held = bytes its own workspaces hold (the
  * single-window one and the lane workspaces); *server_pool (nullable) = the

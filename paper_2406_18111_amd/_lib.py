@@ -44,6 +44,7 @@ SIGNATURES = {
     "apo_analyze_window": (_I, [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _P]),
     "apo_analyze_window_u32": (_I, [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _P]),
     "apo_analyze_window_dev": (_I, [_P, _P, _I, _U32, _U32, _P, _U32, _P, _P, _U32, _P, _P]),
+    "apo_analyze_window_noalloc": (_I, [_P, _P, _I, _U32, _U32, _P, _U32, _P, _P, _U32, _P, _P]),
     "apo_analyze_batch": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P]),
     "apo_analyze_batch_dev": (_I, [_P, _P, _P, _U32, _U32, _P, _U64, _P, _P]),
     "apo_set_graphs": (_I, [_P, _I]),
@@ -52,6 +53,7 @@ SIGNATURES = {
     "apo_set_window_greedy": (_I, [_P, _I]),
     "apo_inject_device_error": (_I, [_P, _I]),
     "apo_memory": (_I, [_P, _P, _P, _P]),
+    "apo_workspace_bytes": (_SZ, [_U64, _U32]),
     "apo_graph_stats": (_I, [_P, _P, _P]),
     "apo_suffix_array_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
     "apo_lcp_dev": (_I, [_P, _P, _I, _U32, _P, _P, _P]),
@@ -415,6 +417,11 @@ class Context:
 
     def server_stop(self):
         _check(self._lib.apo_server_stop(self._h), "apo_server_stop")
+
+
+def workspace_bytes(n: int, windows: int = 1) -> int:
+    """Device bytes of the workspace for n tokens in `windows` windows."""
+    return int(load().apo_workspace_bytes(int(n), int(windows)))
 
 
 def ruler_slice(block_index: int, block_tokens: int, capacity: int) -> int:

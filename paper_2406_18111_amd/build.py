@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libapo.so")
-SOURCES = ["segsort.hip", "stages.hip", "pipeline.hip", "capi.hip", "tracer.hip", "replayer.cpp", "auto.cpp"]
+SOURCES = ["segsort.hip", "stages.hip", "pipeline.hip", "capi.hip", "noalloc.hip", "tracer.hip", "replayer.cpp",
+           "auto.cpp"]
 CXX = os.environ.get("CXX_HOST", "g++")
 CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

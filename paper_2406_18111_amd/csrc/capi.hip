@@ -134,6 +134,14 @@ struct apo_ctx {
   std::vector<LaneOut> louts;
 };
 
+namespace apo {
+// noalloc.hip: the fixed per-device workspace of apo_analyze_window_noalloc
+int noalloc_setup(int device);
+int noalloc_run(int device, hipStream_t s, int tile_log, int digit_bits, const void *d_tok, int bits, uint32_t n,
+                uint32_t min_len, apo_candidate *d_out, uint32_t out_cap, uint32_t *h_out_n, apo_occurrence *d_occ,
+                uint32_t occ_cap, uint32_t *h_occ_n, RunInfo &info);
+}  // namespace apo
+
 using namespace apo;
 
 static int set_dev(apo_ctx *c) { return hipSetDevice(c->device) == hipSuccess ? APO_OK : APO_EDEVICE; }
@@ -166,6 +174,9 @@ extern "C" int apo_create(apo_ctx **out, int hip_device, size_t budget) {
     delete c;
     return APO_EDEVICE;
   }
+  // once per device: the fixed workspace of the no-allocation entry point
+  // (its outcome is reported by that entry point)
+  (void)noalloc_setup(hip_device);
   *out = c;
   return APO_OK;
 }
@@ -310,6 +321,24 @@ extern "C" int apo_analyze_window_dev(apo_ctx *ctx, const void *d_tokens, int to
   if (d_occ && acc && hipMemcpyAsync(d_occ, ctx->ws.occ, (size_t)acc * 12, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return APO_EDEVICE;
   return hipStreamSynchronize(s) == hipSuccess ? APO_OK : APO_EDEVICE;
+}
+
+extern "C" int apo_analyze_window_noalloc(apo_ctx *ctx, const void *d_tokens, int token_bits, uint32_t n,
+                                          uint32_t min_len, apo_candidate *d_out, uint32_t out_cap, uint32_t *h_out_n,
+                                          apo_occurrence *d_occ, uint32_t occ_cap, uint32_t *h_occ_n, void *stream) {
+  if (!ctx || !h_out_n || (!d_tokens && n) || (!d_out && out_cap) || min_len == 0 || n > APO_MAX_N ||
+      (token_bits != 32 && token_bits != 64) || (d_occ && !h_occ_n))
+    return APO_EINVAL;
+  if (set_dev(ctx)) return APO_EDEVICE;
+  *h_out_n = 0;
+  if (h_occ_n) *h_occ_n = 0;
+  ctx->info = RunInfo{};
+  if (n > APO_NOALLOC_MAX_N) return APO_ENOMEM;
+  if (n < 2) return APO_OK;
+  int tl, db;
+  ctx->tune.pick(n, tl, db);
+  return noalloc_run(ctx->device, pick_stream(ctx, stream), tl, db, d_tokens, token_bits, n, min_len, d_out, out_cap,
+                     h_out_n, d_occ, occ_cap, h_occ_n, ctx->info);
 }
 
 static int check_offsets(const uint64_t *off, uint32_t W, uint64_t &total) {
@@ -714,6 +743,12 @@ extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   const int k = std::min(nvals, 9);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
+}
+
+extern "C" size_t apo_workspace_bytes(uint64_t n, uint32_t windows) {
+  if (n > APO_MAX_N || windows == 0) return 0;
+  Workspace fresh;
+  return fresh.bytes_after(std::max<uint64_t>(n, 2), windows);
 }
 
 extern "C" int apo_inject_device_error(apo_ctx *ctx, int after_syncs) {

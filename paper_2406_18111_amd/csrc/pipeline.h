@@ -59,6 +59,7 @@ struct Workspace {
   uint64_t hcap = 0;
   SortEngine eng;
   void *mem = nullptr;
+  bool external = false;  // device arrays live in caller-owned memory (attach)
   size_t bytes = 0;
 
   uint64_t *tok64 = nullptr;
@@ -105,11 +106,15 @@ struct Workspace {
   // grows (never shrinks) to hold N tokens in W windows; -2 if the grown
   // workspace would exceed `budget` bytes (0: no limit) or allocation fails
   int ensure(uint64_t N, uint32_t W, size_t budget);
+  // lays a workspace of capacity (N, W) out in caller-owned device memory
+  // (256-byte aligned, ext_bytes >= bytes_for(N, W)); host mirrors and
+  // events are still created here.  -2 if it does not fit.
+  int attach(void *ext, size_t ext_bytes, uint64_t N, uint32_t W);
   void release();
 
  private:
   void grow_target(uint64_t N, uint32_t W, uint64_t &wantN, uint32_t &wantW) const;
-  int layout(uint64_t N, uint32_t W, size_t *dry_bytes);
+  int layout(uint64_t N, uint32_t W, size_t *dry_bytes, void *ext = nullptr);
 
  public:
 };

@@ -49,8 +49,9 @@ size_t Workspace::bytes_for(uint64_t N, uint32_t W) {
 
 void Workspace::release() {
   eng.release();
-  if (mem) (void)hipFree(mem);
+  if (mem && !external) (void)hipFree(mem);
   mem = nullptr;
+  external = false;
   if (hcnt) (void)hipHostFree(hcnt);
   hcnt = nullptr;
   if (hctr) (void)hipHostFree(hctr);
@@ -90,9 +91,16 @@ int Workspace::ensure(uint64_t N, uint32_t W, size_t budget) {
   return layout(wantN, wantW, nullptr);
 }
 
+int Workspace::attach(void *ext, size_t ext_bytes, uint64_t N, uint32_t W) {
+  release();
+  if (!ext || ((uintptr_t)ext & 255) || bytes_for(N, W) > ext_bytes) return -2;
+  return layout(N, W, nullptr, ext);
+}
+
 // Lays out every array of a workspace of capacity (N_, wantW); with
-// dry_bytes set only the total is computed (nothing is allocated).
-int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes) {
+// dry_bytes set only the total is computed (nothing is allocated); with ext
+// set the device arrays go into that memory instead of a new allocation.
+int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *ext) {
   plan(wantN, wantW, nsnap, nT, nlev, hcap);
   const uint64_t N_ = wantN, C2 = 2 * wantN;
   Layout L;
@@ -124,8 +132,13 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes) {
     *dry_bytes = L.total;
     return 0;
   }
-  hipError_t e = hipMalloc(&mem, L.total);
-  if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
+  if (ext) {
+    mem = ext;
+    external = true;
+  } else {
+    hipError_t e = hipMalloc(&mem, L.total);
+    if (e != hipSuccess) { mem = nullptr; (void)hipGetLastError(); return -2; }
+  }
   bytes = L.total;
   char *m = static_cast<char *>(mem);
   tok64 = (uint64_t *)(m + o_tok64);
@@ -174,7 +187,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes) {
   dcnt = (uint32_t *)(m + o_cnt);
   rhist = (uint32_t *)(m + o_rh);
   selcnt = (uint32_t *)(m + o_sc);
-  int rc = eng.alloc(C2);
+  int rc = eng.alloc(C2, nullptr, ext ? static_cast<char *>(ext) + L.total : nullptr);
   if (rc) { release(); return rc; }
   APO_HIP_TRY(hipHostMalloc((void **)&hcnt, CNT_COUNT * 4, hipHostMallocDefault));
   APO_HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(SortCounters), hipHostMallocDefault));

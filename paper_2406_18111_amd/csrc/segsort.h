@@ -6,8 +6,10 @@ namespace apo {
 
 class SortEngine {
  public:
-  // dry_bytes != nullptr: only computes the device bytes alloc would take
-  int alloc(uint64_t capacity, size_t *dry_bytes = nullptr);
+  // dry_bytes != nullptr: only computes the device bytes alloc would take;
+  // ext != nullptr: lays the buffers out in that caller-owned device memory
+  // (256-byte aligned, at least bytes_for(capacity)) instead of allocating
+  int alloc(uint64_t capacity, size_t *dry_bytes = nullptr, void *ext = nullptr);
   static size_t bytes_for(uint64_t capacity);
   void release();
   SortBufs &bufs() { return b_; }
@@ -46,6 +48,7 @@ class SortEngine {
  private:
   SortBufs b_{};
   void *mem_ = nullptr;
+  bool external_ = false;
   size_t bytes_ = 0;
   uint64_t cap_ = 0;
 };

@@ -1178,7 +1178,7 @@ size_t SortEngine::bytes_for(uint64_t capacity) {
   return b;
 }
 
-int SortEngine::alloc(uint64_t capacity, size_t *dry_bytes) {
+int SortEngine::alloc(uint64_t capacity, size_t *dry_bytes, void *ext) {
   cap_ = capacity;
   SortBufs &B = b_;
   B.cap = capacity;
@@ -1209,7 +1209,13 @@ int SortEngine::alloc(uint64_t capacity, size_t *dry_bytes) {
     *dry_bytes = bytes;
     return 0;
   }
-  APO_HIP_TRY(hipMalloc(&mem_, bytes));
+  if (ext) {
+    mem_ = ext;
+    external_ = true;
+  } else {
+    APO_HIP_TRY(hipMalloc(&mem_, bytes));
+    external_ = false;
+  }
   bytes_ = bytes;
   char *m = static_cast<char *>(mem_);
   B.key[0] = (uint32_t *)(m + o_key0); B.key[1] = (uint32_t *)(m + o_key1);
@@ -1228,8 +1234,9 @@ int SortEngine::alloc(uint64_t capacity, size_t *dry_bytes) {
 }
 
 void SortEngine::release() {
-  if (mem_) (void)hipFree(mem_);
+  if (mem_ && !external_) (void)hipFree(mem_);
   mem_ = nullptr;
+  external_ = false;
 }
 
 void SortEngine::reset_counters(hipStream_t s) {

@@ -67,3 +67,15 @@ def test_ruler_slices():
     K = 1024
     tot = sum(_lib.ruler_slice(i, 1, 1 << 30) for i in range(1, K + 1))
     assert tot == (K // 2) * (10 + 2)
+
+
+def test_noalloc_scratch_holds_its_workspace():
+    """The fixed array of the no-allocation entry point is large enough for
+    the workspace of its longest window (checked without a device)."""
+    from paper_2406_18111_amd import _lib
+    src = open(HEADER).read()
+    max_n = 1 << int(re.search(r"#define APO_NOALLOC_MAX_N \(1u << (\d+)\)", src).group(1))
+    scratch = int(re.search(r"#define APO_NOALLOC_SCRATCH_BYTES \((\d+)u << 20\)", src).group(1)) << 20
+    need = _lib.workspace_bytes(max_n, 1)
+    assert 0 < need <= scratch, (need, scratch)
+    assert _lib.workspace_bytes(max_n + 1, 1) > scratch  # the next size up would not fit

@@ -208,17 +208,16 @@ def measured_traffic(workload, lanes=1):
     covers another workload, or the kernels' source changed since."""
     import hashlib
     try:
-        rec = None
-        for line in open(TRAFFIC_FILE):
-            if line.startswith("TRAFFIC_RECORD "):
-                rec = json.loads(line[len("TRAFFIC_RECORD "):])
+        recs = [json.loads(line[len("TRAFFIC_RECORD "):]) for line in open(TRAFFIC_FILE)
+                if line.startswith("TRAFFIC_RECORD ")]
         src = code_hash(FAMILY_SOURCE)
     except OSError:
         return None
-    if (not rec or rec.get("workload") != workload or rec.get("lanes", 1) != lanes
-            or rec.get("kernel_source_sha256") != src):
-        return None
-    return float(rec["traffic_bytes_per_launch"])
+    for rec in recs:
+        if (rec.get("workload") == workload and rec.get("lanes", 1) == lanes
+                and rec.get("kernel_source_sha256") == src):
+            return float(rec["traffic_bytes_per_launch"])
+    return None
 
 
 def roofline(kprof, steps, workload=None, lanes=1, copy_gbs=None):
@@ -472,6 +471,14 @@ def main():
             ctx.profile_kernel(0)
             ctx.set_lanes(args.lanes)
             out["roofline_one_lane"] = roofline(kp1, 3, "config3", 1, copy_gbs)
+        if not args.profile_steps and not args.no_graphs and args.lanes > 1:
+            # the same lanes, each lane's sync-free sequence a branch of one
+            # graph captured once and replayed
+            ctx.analyze_batch_dev(dev, off, m)
+            gsec, _, _, gres = timed_steps(ctx, lambda: ctx.analyze_batch_dev(dev, off, m), steps)
+            out["graph_replay_lanes"] = {
+                "tokens_per_s": total / gsec, "ms": gsec * 1e3, "lanes": args.lanes, "graph": ctx.graph_stats(),
+                "same_rows": bool(np.array_equal(gres[1], res[1]) and torch.equal(gres[0], res[0]))}
         if not args.profile_steps and not args.no_graphs:
             # one stream: the step captured once as a HIP graph and replayed
             ctx.set_lanes(1)

@@ -107,6 +107,26 @@ struct GraphCache {
 };
 }  // namespace apo
 
+namespace apo {
+// Batches on several lanes captured as one graph: every lane's sync-free
+// launch sequence is a branch forked from and joined back into the caller's
+// stream.  Keyed on the token pointer, min_len, and per lane (first token,
+// tokens, windows, longest window, kernel parameters, workspace).
+struct LaneGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> key;
+  std::vector<hipEvent_t> ev;  // fork event + one join event per lane
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+};
+}  // namespace apo
+
 struct apo_ctx {
   int device = 0;
   size_t budget = 0;
@@ -115,7 +135,9 @@ struct apo_ctx {
   apo::RunInfo info;
   apo::TuneTable tune;
   apo::GraphCache gc;
+  apo::LaneGraph lg;
   bool graphs = true;         // capture/replay batched launch sequences
+  bool lane_graphs = true;    // lanes as branches of one graph (off after a failed capture)
   int sel_cap = apo::kSelRoundCap;  // host-driven selection rounds before the sequential completion
   bool win_greedy = true;           // per-window greedy where windows are short enough
   uint64_t graph_replays = 0, graph_captures = 0;
@@ -189,6 +211,8 @@ extern "C" int apo_destroy(apo_ctx *ctx) {
   apo_server_stop(ctx);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->gc.reset();
+  ctx->lg.reset();
+  for (auto e : ctx->lg.ev) (void)hipEventDestroy(e);
   ctx->ws.release();
   for (auto &l : ctx->lane_ws) l->release();
   for (auto st : ctx->lane_stream) {
@@ -453,6 +477,86 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
     ln.ws->win_greedy = ctx->win_greedy;
     if (ln.st != s && hipStreamWaitEvent(ln.st, ctx->lane_ready, 0) != hipSuccess) return APO_EDEVICE;
     lanes.push_back(std::move(ln));
+  }
+  // With graphs on (and no kernel timing, which events inside a capture
+  // cannot give), every lane's sync-free sequence is one branch of a single
+  // graph, captured once per shape and replayed.
+  if (ctx->graphs && ctx->lane_graphs && ctx->ws.ktag == KT_NONE) {
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)d_tok, min_len, lanes.size(), (uint64_t)ctx->win_greedy,
+                                 (uint64_t)(uintptr_t)s};
+    for (Lane &ln : lanes) {
+      uint64_t mw = 0;
+      for (uint32_t w = 0; w < ln.W; w++) mw = std::max<uint64_t>(mw, ln.norm[w + 1] - ln.norm[w]);
+      key.insert(key.end(), {ln.tok0, ln.total, ln.W, mw, (uint64_t)ln.ws->eng.tile_log(),
+                             (uint64_t)ln.ws->eng.digit_bits(), (uint64_t)(uintptr_t)ln.ws->mem,
+                             (uint64_t)(uintptr_t)ln.st});
+    }
+    LaneGraph &G = ctx->lg;
+    // window offsets of every lane, ahead of the branches that read them
+    for (Lane &ln : lanes)
+      if (hipMemcpyAsync(ln.ws->d_off, ln.norm.data(), (ln.W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+        return APO_EDEVICE;
+    bool ok = true;
+    if (!G.exec || G.key != key) {
+      G.reset();
+      while (G.ev.size() < lanes.size() + 1) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return APO_EDEVICE;
+        G.ev.push_back(e);
+      }
+      ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      hipGraph_t g = nullptr;
+      if (ok) {
+        int rc = hipEventRecord(G.ev[0], s) == hipSuccess ? 0 : -4;
+        for (size_t i = 0; i < lanes.size() && !rc; i++)
+          if (lanes[i].st != s && hipStreamWaitEvent(lanes[i].st, G.ev[0], 0) != hipSuccess) rc = -4;
+        for (size_t i = 0; i < lanes.size() && !rc; i++) {
+          Lane &ln = lanes[i];
+          rc = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL, ln.st,
+                            ln.info, Mode::CAPTURE);
+        }
+        for (size_t i = 0; i < lanes.size() && !rc; i++)
+          if (lanes[i].st != s && (hipEventRecord(G.ev[i + 1], lanes[i].st) != hipSuccess ||
+                                   hipStreamWaitEvent(s, G.ev[i + 1], 0) != hipSuccess))
+            rc = -4;
+        const hipError_t e = hipStreamEndCapture(s, &g);
+        ok = rc == 0 && e == hipSuccess && g != nullptr;
+        if (ok && hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+          G.exec = nullptr;
+          ok = false;
+        }
+      }
+      if (ok) {
+        G.graph = g;
+        G.key = key;
+        ctx->graph_captures++;
+      } else {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        fprintf(stderr, "[apo] capture of the lanes failed; lanes run host-driven\n");
+        ctx->lane_graphs = false;
+      }
+    } else {
+      ctx->graph_replays++;
+    }
+    if (ok) {
+      if (hipGraphLaunch(G.exec, s) != hipSuccess) return APO_EDEVICE;
+      ctx->info = RunInfo{};
+      ctx->louts.clear();
+      for (Lane &ln : lanes) {
+        ln.info = RunInfo{};
+        ln.ws->kev_n = 0;
+        int rc = finish_run(*ln.ws, ln.total, 2 * ln.total, kSelFreeRounds, ln.info, s, false);
+        if (rc == 1)  // greedy rounds left candidates undecided: this lane again, host-driven
+          rc = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL, s,
+                            ln.info, Mode::HOST);
+        if (rc) return map_rc(rc);
+        merge_info(ctx->info, ln.info);
+        ctx->louts.push_back({ln.ws, ln.W, ln.info.rows});
+      }
+      return APO_OK;
+    }
   }
   // one host thread per lane, so that no lane's launches wait behind another
   // lane's syncs
@@ -792,7 +896,10 @@ extern "C" int apo_set_lanes(apo_ctx *ctx, int lanes) {
 extern "C" int apo_set_graphs(apo_ctx *ctx, int on) {
   if (!ctx) return APO_EINVAL;
   ctx->graphs = on != 0;
-  if (!ctx->graphs) ctx->gc.reset();
+  if (!ctx->graphs) {
+    ctx->gc.reset();
+    ctx->lg.reset();
+  }
   return APO_OK;
 }
 

@@ -300,9 +300,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint32_t bits0;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
-    const uint64_t hc = pow2_at_least(2 * N);
-    hash_clear(w.htab, hc - 1, s);
-    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
+    // slots [0, 2N) by window regions; the special slot sits past them
+    hash_clear(w.htab, 2 * N, w.hcap, s);
+    hash_insert(tok, N, w.htab, w.hcap, wbeg, wend, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
     uint64_t nd_bound = N;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;
@@ -431,9 +431,15 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     // reads its own copy
     uint32_t *xs[3] = {w.tmp_a, w.tmp_b, w.tmp_c};  // length key, start, ID
     uint32_t *ys[3] = {w.s_len, w.s_start, w.s_id};
-    const bool wkey = winsel && batch;
+    // window-major order for the per-window greedy: tiles kept inside
+    // windows when the per-window histograms fit the scratch, else the window
+    // goes above the length in the key
+    const uint64_t seg_tiles = (c_bound + kLsdTileRecords - 1) / kLsdTileRecords + W;
+    const bool wseg = winsel && batch && (seg_tiles * 256 <= 2 * w.capN + 2048) && seg_tiles + 3 * (W + 1) <= w.capN;
+    const bool wkey = winsel && batch && !wseg;
     lsd_sort_candidates(w.crec, dc + CNT_MAXL, dc + CNT_C, c_bound, lbits + (wkey ? wbits : 0), xs, ys, B.key[0],
-                        w.tmp_d, dc + CNT_AUX, w.tile_tmp, s, wkey ? wid : nullptr, lbits);
+                        w.tmp_d, dc + CNT_AUX, w.tile_tmp, s, wkey ? wid : nullptr, lbits, wseg ? wid : nullptr, W,
+                        w.o_len);
     E.reset_counters(s);
     E.round_begin(0, s);
     E.iota_val(dc + CNT_C, c_bound, s);

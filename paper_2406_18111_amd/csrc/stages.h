@@ -17,12 +17,15 @@ void copy_n_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t s);
 void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
                uint32_t *total, hipStream_t s);
 
-// Table of hc = mask + 1 slots plus one (the token value equal to the empty
-// mark has slot mask + 1); hash_clear empties it.
-void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s);
-// tok_slot[i] receives the table slot of token i.
-void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
-                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s);
+// Table of 2n slots, window w owning [2 wbeg, 2 wend), plus the slot
+// `special` (> 2n) of the token value equal to the empty mark; hash_clear
+// empties slots [0, slots) and `special`.
+void hash_clear(uint64_t *tab, uint64_t slots, uint64_t special, hipStream_t s);
+// tok_slot[i] receives the table slot of token i; wbeg / wend: per-position
+// window bounds (null: one window).
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t special, const uint32_t *wbeg,
+                 const uint32_t *wend, uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot,
+                 hipStream_t s);
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s);
 void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot,
@@ -56,16 +59,22 @@ void gen_candidates(const uint32_t *sa, const uint32_t *lcp, uint64_t n, const u
 
 // Stable sort of the candidate records by length, longest first (records in
 // suffix-array order come out ordered by (length desc, ID asc)): LSD passes
-// over key = *maxl - length, carrying start and ID.  With wid set the key is
-// (window of the start << wshift) | (*maxl - length), so records come out
-// window by window, each window in (length desc, ID asc) order.  The result
-// lands in xs = {key, start, ID} arrays, the sorted starts also in start_copy
-// (nullable); ys is the alternate set; hist holds 256 u32
-// per 4096 records (at least 256); hist_n is one device word of scratch.
+// over key = *maxl - length, carrying start and ID.  With seg_wid set, the
+// records (in suffix-array order, so window by window) are sorted inside each
+// of the nseg windows (window of a record = seg_wid of its ID): tiles never
+// straddle a window and the histograms are laid out window by window, so
+// every pass keeps each window's records together.  With wid set instead, the
+// key is (window of the ID << wshift) | (*maxl - length), which orders the
+// records window by window through the key.  The result lands in xs = {key,
+// start, ID} arrays, the sorted starts also in start_copy (nullable); ys is
+// the alternate set; hist holds 256 u32 per tile (tiles of 4096 records,
+// plus one per window); hist_n is one device word of scratch; seg holds
+// 3 (nseg + 1) + tiles words.
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
                          int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
-                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s,
-                         const uint32_t *wid = nullptr, int wshift = 0);
+                         uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s, const uint32_t *wid,
+                         int wshift, const uint32_t *seg_wid, uint32_t nseg, uint32_t *seg);
+constexpr uint64_t kLsdTileRecords = 4096;
 // flag[i] = 1 where (key, p2) differs from position i - 1.
 void run_flags(const uint32_t *key, const uint32_t *p2, const uint32_t *n_dev, uint64_t bound, uint8_t *flag,
                hipStream_t s);

@@ -208,24 +208,33 @@ void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
 // ------------------------------------------------------ token ranking (u64)
 // Open-addressing table of the distinct 64-bit token values themselves
 // (kEmpty marks a free slot; the token value equal to kEmpty has the extra
-// slot mask+1 of its own).  Each workgroup first removes duplicates within
-// its tile of tokens with a table in LDS, so only one thread per distinct
-// value and tile probes the global table (loop streams repeat a few hundred
-// hashes thousands of times); a probe compares the stored key, with no
-// dependent read of the token array.  The threads whose CAS claims a slot
-// collect their new distinct values in LDS, and the tile reserves their list
-// entries with one atomic.
+// slot `special` of its own).  Windows never compare tokens with each other,
+// so every window gets its own region of the table, [2 wbeg, 2 wend) (load
+// at most 1/2): a window's inserts and the later rank gathers stay inside a
+// few megabytes instead of spreading over the whole table, and a value that
+// occurs in several windows takes one slot per window.  The ranks the slots
+// later receive are positions in the sorted list of all windows' distinct
+// values, so within a window they are order-preserving and equal tokens share
+// one (the suffix sort needs nothing more).  Each workgroup first removes
+// duplicates within its tile of tokens with a table in LDS keyed on (window,
+// value), so only one thread per distinct pair and tile probes the global
+// table (loop streams repeat a few hundred hashes thousands of times); a
+// probe compares the stored key, with no dependent read of the token array.
+// The threads whose CAS claims a slot collect their new distinct values in
+// LDS, and the tile reserves their list entries with one atomic.
 constexpr int kHashTile = 2048, kHashLds = 4096;
 constexpr uint64_t kEmpty = ~0ull;
 
 // Returns whether the key was new; *slot receives its slot either way.
-__device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t mask,
-                                              uint64_t *slot) {
+// The key's slots are [base, base + size); size > 0.
+__device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t base, uint64_t size,
+                                              uint64_t special, uint64_t *slot) {
   if (key == kEmpty) {
-    *slot = mask + 1;
-    return atomicCAS(&tab[mask + 1], 0ull, 1ull) == 0ull;
+    *slot = special;
+    return atomicCAS(&tab[special], 0ull, 1ull) == 0ull;
   }
-  uint64_t h = mix64(key) & mask;
+  const uint64_t end = base + size;
+  uint64_t h = base + __umul64hi(mix64(key), size);  // multiply-high range reduction into the region
   while (true) {
     unsigned long long cur = tab[h];
     if (cur == kEmpty) {
@@ -239,16 +248,18 @@ __device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *
       *slot = h;
       return false;
     }
-    h = (h + 1) & mask;
+    h = h + 1 == end ? base : h + 1;
   }
 }
 
 // Also writes every token's global slot to tok_slot (the tile's first
-// occurrence of a value finds it; the local table hands it to the others), so
-// the ranks come later from one gather per token instead of a second probe.
+// occurrence of a (window, value) pair finds it; the local table hands it to
+// the others), so the ranks come later from one gather per token instead of
+// a second probe.  wbeg/wend: per-position window bounds (null: one window).
 __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, unsigned long long *tab,
-                                                     uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
-                                                     uint32_t *nd, uint32_t *tok_slot) {
+                                                     uint64_t special, const uint32_t *wbeg, const uint32_t *wend,
+                                                     uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd,
+                                                     uint32_t *tok_slot) {
   constexpr int NT = 256;
   constexpr int PER = kHashTile / NT;
   __shared__ uint64_t lt[kHashTile];   // the tile's tokens
@@ -260,6 +271,15 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
     for (uint32_t k = threadIdx.x; k < kHashLds; k += NT) ls[k] = 0;
     for (uint32_t k = threadIdx.x; k < m; k += NT) lt[k] = tok[t0 + k];
     if (threadIdx.x == 0) nnew = 0;
+    // this thread's tokens' window bounds (registers: LDS room decides how
+    // many workgroups share a CU)
+    uint32_t wbs[PER], wes[PER];
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const uint64_t i = t0 + threadIdx.x + (uint64_t)u * NT;
+      wbs[u] = (wbeg && i < n) ? wbeg[i] : 0u;
+      wes[u] = (wend && i < n) ? wend[i] : (uint32_t)n;
+    }
     __syncthreads();
     uint32_t hl[PER], gs[PER];  // local table entry of each token; global slot (first occurrences)
     uint32_t first = 0;
@@ -270,22 +290,26 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
       gs[u] = 0;
       if (k >= m) continue;
       const uint64_t key = lt[k];
-      uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
+      const uint32_t wb = wbs[u], we = wes[u];
+      uint32_t h = (uint32_t)(mix64(key ^ wb) >> 40) & (kHashLds - 1);
       while (true) {
         uint32_t prev = ls[h];
         if (prev == 0u) prev = atomicCAS(&ls[h], 0u, k + 1);
         if (prev == 0u) {  // first in this tile
+          const uint64_t i = t0 + k;
           uint64_t slot;
-          if (global_insert(key, tab, mask, &slot)) {
+          if (global_insert(key, tab, 2 * (uint64_t)wb, 2 * ((uint64_t)we - wb), special, &slot)) {
             const uint32_t q = atomicAdd(&nnew, 1u);
-            new_i[q] = (uint32_t)(t0 + k);
+            new_i[q] = (uint32_t)i;
             new_h[q] = (uint32_t)slot;
           }
           gs[u] = (uint32_t)slot;
           first |= 1u << u;
           break;
         }
-        if (lt[prev - 1] == key) break;
+        // same value, and a position inside this token's window
+        const uint64_t pp = t0 + prev - 1;
+        if (lt[prev - 1] == key && pp >= wb && pp < we) break;
         h = (h + 1) & (kHashLds - 1);
       }
       hl[u] = h;
@@ -352,19 +376,19 @@ __global__ void k_hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t
 
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) { GRID_STRIDE(i, n) p[i] = v; }
 
-void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s) {
+void hash_clear(uint64_t *tab, uint64_t slots, uint64_t special, hipStream_t s) {
   auto *t = reinterpret_cast<unsigned long long *>(tab);
-  hipLaunchKernelGGL(k_fill_u64, grid_for(mask + 1, 256, 8192), dim3(256), 0, s, t, mask + 1,
-                     (unsigned long long)kEmpty);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + mask + 1, (uint64_t)1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, grid_for(slots, 256, 8192), dim3(256), 0, s, t, slots, (unsigned long long)kEmpty);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + special, (uint64_t)1, 0ull);
 }
 
-void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
-                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s) {
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t special, const uint32_t *wbeg,
+                 const uint32_t *wend, uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot,
+                 hipStream_t s) {
   const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
   hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
-                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd,
-                     tok_slot);
+                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), special, wbeg, wend, dist_idx,
+                     dist_slot, nd, tok_slot);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -939,7 +963,7 @@ struct LsdSrc {
   const uint32_t *rec;           // candidate records, or null
   const uint32_t *maxl;          // with records: key = *maxl - length
   const uint32_t *key, *p1, *p2; // without records
-  const uint32_t *wid;           // with records (nullable): key |= window of the start << wshift
+  const uint32_t *wid;           // with records (nullable): key |= window << wshift
   int wshift;
 };
 
@@ -948,7 +972,11 @@ __device__ __forceinline__ void lsd_load(const LsdSrc &in, uint64_t i, uint32_t 
   if (in.rec) {
     const uint32_t *r = in.rec + kCandWords * i;
     k = maxl - r[0]; a = r[1]; b = r[2];
-    if (in.wid) k |= in.wid[a] << in.wshift;
+    // the window of a candidate is the window of its ID (a slot of the same
+    // window: pairs across windows have LCP 0, so the ID never reaches back
+    // past the window's first slot); records come in suffix-array order, so
+    // the IDs of neighbouring records are close and these reads share lines
+    if (in.wid) k |= in.wid[b] << in.wshift;
   } else {
     k = in.key[i]; a = in.p1[i]; b = in.p2[i];
   }
@@ -966,73 +994,145 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   return valid ? peers : 0ull;
 }
 
-__global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, const uint32_t *n_dev, int shift, uint32_t *hist,
-                                                     uint32_t ntiles) {
+// Tiles never straddle a segment (a window, when records come window by
+// window): segment g holds records [off[g], off[g+1]) and tiles [tb[g],
+// tb[g+1]); tseg[t] is the segment of tile t.  The histograms are laid out
+// segment by segment, each segment's block digit-major over its own tiles,
+// so one exclusive scan gives every (tile, digit) run its output offset, and
+// every pass keeps each segment's records together, stable inside it.
+struct LsdTiles {
+  const uint32_t *off, *tb, *tseg;
+  uint32_t nseg;
+};
+
+struct LsdTile {
+  uint64_t lo;      // first record
+  uint32_t cnt;     // records (<= kLsdTile)
+  uint64_t hbase;   // first histogram word of the tile's segment
+  uint32_t nt, j;   // tiles of the segment, index of this tile in it
+};
+
+__device__ __forceinline__ LsdTile lsd_tile(const LsdTiles &T, uint32_t t) {
+  LsdTile r;
+  const uint32_t g = T.tseg[t];
+  const uint32_t tb0 = T.tb[g];
+  r.nt = T.tb[g + 1] - tb0;
+  r.j = t - tb0;
+  r.lo = (uint64_t)T.off[g] + (uint64_t)r.j * kLsdTile;
+  r.cnt = (uint32_t)min((uint64_t)kLsdTile, (uint64_t)T.off[g + 1] - r.lo);
+  r.hbase = (uint64_t)tb0 * kLsdBins;
+  return r;
+}
+
+// First record k in [0, n) whose window (wid of its ID) is >= target: a
+// 64-ary search by the whole wavefront (each step probes 64 evenly spaced
+// records; the window never decreases along the records).
+__device__ uint32_t rec_window_bound(const uint32_t *rec, const uint32_t *wid, uint32_t n, uint32_t target) {
+  const int lane = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 64) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t k = lo + (uint32_t)lane * step;
+    const int nb = __popcll(__ballot(k < hi && wid[rec[kCandWords * (uint64_t)k + 2]] < target));
+    if (nb == 0) return lo;
+    const uint32_t nlo = lo + (uint32_t)(nb - 1) * step + 1, nhi = min(hi, lo + (uint32_t)nb * step);
+    lo = nlo;
+    hi = nhi;
+  }
+  const uint32_t k = lo + (uint32_t)lane;
+  return lo + (uint32_t)__popcll(__ballot(k < hi && wid[rec[kCandWords * (uint64_t)k + 2]] < target));
+}
+
+// Segment g's records (one wavefront per segment) and its tile count.
+__global__ __launch_bounds__(64) void k_lsd_segments(const uint32_t *rec, const uint32_t *n_dev, const uint32_t *wid,
+                                                     uint32_t nseg, uint32_t *off, uint32_t *nt) {
+  const uint32_t g = blockIdx.x;
+  const uint32_t n = *n_dev;
+  uint32_t lo = 0, hi = n;
+  if (wid) {
+    lo = rec_window_bound(rec, wid, n, g);
+    hi = rec_window_bound(rec, wid, n, g + 1);
+  }
+  if (threadIdx.x == 0) {
+    off[g] = lo;
+    nt[g] = (hi - lo + kLsdTile - 1) / kLsdTile;
+    if (g == 0) {
+      off[nseg] = n;
+      nt[nseg] = 0;
+    }
+  }
+}
+
+// tseg of every tile; *hist_words = tiles * kLsdBins.
+__global__ __launch_bounds__(64) void k_lsd_seg_fill(const uint32_t *tb, uint32_t nseg, uint32_t *tseg,
+                                                     uint32_t *hist_words) {
+  const uint32_t g = blockIdx.x;
+  for (uint32_t t = tb[g] + threadIdx.x; t < tb[g + 1]; t += 64) tseg[t] = g;
+  if (g == 0 && threadIdx.x == 0) *hist_words = tb[nseg] * kLsdBins;
+}
+
+__global__ __launch_bounds__(kLsdNT) void k_lsd_hist(LsdSrc in, int shift, uint32_t *hist, LsdTiles T) {
   __shared__ uint32_t h[kLsdBins];
-  const uint64_t n = *n_dev;
   const uint32_t maxl = in.maxl ? *in.maxl : 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t ntiles = T.tb[T.nseg];
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const LsdTile tl = lsd_tile(T, t);
     for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) h[d] = 0;
     __syncthreads();
-    const uint64_t tile0 = (uint64_t)t * kLsdTile;
-    if (tile0 < n) {
-      // every slot's key is loaded before the first ballot, so the loads
-      // (and a record pass's window lookups) overlap instead of queueing
-      uint32_t K[kLsdSlots];
+    // every slot's key is loaded before the first ballot, so the loads (and
+    // a record pass's window lookups) overlap instead of queueing
+    uint32_t K[kLsdSlots];
 #pragma unroll
-      for (int e = 0; e < kLsdSlots; e++) {
-        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-        uint32_t a, b;
-        K[e] = 0;
-        if (i < n) lsd_load(in, i, maxl, K[e], a, b);
-      }
+    for (int e = 0; e < kLsdSlots; e++) {
+      const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
+      uint32_t a, b;
+      K[e] = 0;
+      if (q < tl.cnt) lsd_load(in, tl.lo + q, maxl, K[e], a, b);
+    }
 #pragma unroll
-      for (int e = 0; e < kLsdSlots; e++) {
-        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-        const bool valid = i < n;
-        const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
-        const uint64_t peers = digit_peers(d, valid);
-        if (valid && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
-      }
+    for (int e = 0; e < kLsdSlots; e++) {
+      const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
+      const bool valid = q < tl.cnt;
+      const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
+      const uint64_t peers = digit_peers(d, valid);
+      if (valid && lane == __ffsll((unsigned long long)peers) - 1) atomicAdd(&h[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) hist[(uint64_t)d * ntiles + t] = h[d];
+    for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT) hist[tl.hbase + (uint64_t)d * tl.nt + tl.j] = h[d];
     __syncthreads();
   }
 }
 
 // oa2 (nullable): a second output of p1.
-__global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_t *n_dev, int shift,
-                                                        const uint32_t *offs, uint32_t ntiles, uint32_t *ok,
-                                                        uint32_t *oa, uint32_t *ob, uint32_t *oa2) {
+__global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, int shift, const uint32_t *offs, LsdTiles T,
+                                                        uint32_t *ok, uint32_t *oa, uint32_t *ob, uint32_t *oa2) {
   static_assert(kLsdBins == kLsdNT, "one digit per thread in the run offsets");
   __shared__ uint32_t wcnt[4][kLsdBins];   // per-wavefront digit counts; then tile-local run starts
   __shared__ uint32_t wstart[4][kLsdBins];  // global run starts
   __shared__ uint32_t lg[kLsdTile];         // global position of each tile-local sorted slot
   __shared__ uint32_t lv[kLsdTile];         // one output array's values in tile-local sorted order
   __shared__ uint32_t sh[kLsdNT / 64];
-  const uint64_t n = *n_dev;
   const uint32_t maxl = in.maxl ? *in.maxl : 0u;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t ntiles = T.tb[T.nseg];
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t tile0 = (uint64_t)t * kLsdTile;
-    if (tile0 >= n) break;  // workgroup-uniform; later tiles are empty too
+    const LsdTile tl = lsd_tile(T, t);
     for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT)
       for (int q = 0; q < 4; q++) wcnt[q][d] = 0;
     __syncthreads();
     uint32_t K[kLsdSlots], A[kLsdSlots], Bv[kLsdSlots], rank[kLsdSlots];
 #pragma unroll
     for (int e = 0; e < kLsdSlots; e++) {
-      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
+      const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
       K[e] = 0;
-      if (i < n) lsd_load(in, i, maxl, K[e], A[e], Bv[e]);
+      if (q < tl.cnt) lsd_load(in, tl.lo + q, maxl, K[e], A[e], Bv[e]);
     }
 #pragma unroll
     for (int e = 0; e < kLsdSlots; e++) {
-      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-      const bool valid = i < n;
+      const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
+      const bool valid = q < tl.cnt;
       const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
       const uint64_t peers = digit_peers(d, valid);
       const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : lane;
@@ -1057,7 +1157,7 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
       }
       uint32_t ttot;
       uint32_t lrun = block_excl_sum<kLsdNT>(tot, sh, &ttot);  // (has barriers)
-      uint32_t run = offs[(uint64_t)d * ntiles + t];
+      uint32_t run = offs[tl.hbase + (uint64_t)d * tl.nt + tl.j];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
         wstart[q][d] = run;
@@ -1070,8 +1170,8 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
     // every entry's tile-local sorted slot (kept in rank[]) and global position
 #pragma unroll
     for (int e = 0; e < kLsdSlots; e++) {
-      const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-      if (i >= n) continue;
+      const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
+      if (q >= tl.cnt) continue;
       const uint32_t d = (K[e] >> shift) & (kLsdBins - 1);
       const uint32_t loc = wcnt[w][d] + rank[e];
       lg[loc] = wstart[w][d] + rank[e];
@@ -1079,15 +1179,15 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
     }
     // each output array goes through LDS in sorted order, so consecutive
     // threads write consecutive words of a digit's run
-    const uint32_t cnt = (uint32_t)min((uint64_t)kLsdTile, n - tile0);
+    const uint32_t cnt = tl.cnt;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
       uint32_t *out = a == 0 ? ok : a == 1 ? oa : a == 2 ? ob : oa2;
       if (!out) continue;  // uniform
 #pragma unroll
       for (int e = 0; e < kLsdSlots; e++) {
-        const uint64_t i = tile0 + (uint64_t)w * (kLsdTile / 4) + (uint64_t)e * 64 + lane;
-        if (i < n) lv[rank[e]] = a == 0 ? K[e] : a == 2 ? Bv[e] : A[e];
+        const uint32_t q = (uint32_t)w * (kLsdTile / 4) + (uint32_t)e * 64 + lane;
+        if (q < tl.cnt) lv[rank[e]] = a == 0 ? K[e] : a == 2 ? Bv[e] : A[e];
       }
       __syncthreads();
       for (uint32_t j = threadIdx.x; j < cnt; j += kLsdNT) out[lg[j]] = lv[j];
@@ -1099,18 +1199,24 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, const uint32_
 void lsd_sort_candidates(const uint32_t *crec, const uint32_t *maxl_dev, const uint32_t *n_dev, uint64_t bound,
                          int key_bits, uint32_t *const *xs, uint32_t *const *ys, uint32_t *start_copy,
                          uint32_t *hist, uint32_t *hist_n, uint32_t *tile_tmp, hipStream_t s, const uint32_t *wid,
-                         int wshift) {
+                         int wshift, const uint32_t *seg_wid, uint32_t nseg, uint32_t *seg) {
+  if (!seg_wid) nseg = 1;
   const int passes = std::max(1, (key_bits + kLsdBits - 1) / kLsdBits);
-  const uint32_t ntiles = (uint32_t)std::max<uint64_t>((bound + kLsdTile - 1) / kLsdTile, 1);
-  const unsigned grid = std::min<uint32_t>(ntiles, 8192);
-  fill_u32(hist_n, 1, kLsdBins * ntiles, s);
+  const uint64_t tiles_bound = (bound + kLsdTile - 1) / kLsdTile + nseg;
+  const unsigned grid = (unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles_bound, 1), 8192);
+  uint32_t *off = seg, *nt = seg + (nseg + 1), *tb = seg + 2 * (nseg + 1), *tseg = seg + 3 * (nseg + 1);
+  hipLaunchKernelGGL(k_lsd_segments, dim3(nseg), dim3(64), 0, s, crec, n_dev, seg_wid, nseg, off, nt);
+  fill_u32(hist_n, 1, nseg + 1, s);
+  scan_excl(nt, tb, hist_n, nseg + 1, tile_tmp, nullptr, s);
+  hipLaunchKernelGGL(k_lsd_seg_fill, dim3(nseg), dim3(64), 0, s, tb, nseg, tseg, hist_n);
+  const LsdTiles T{off, tb, tseg, nseg};
   LsdSrc in{crec, maxl_dev, nullptr, nullptr, nullptr, wid, wshift};
   for (int ps = 0; ps < passes; ps++) {
     uint32_t *const *out = ((passes - 1 - ps) % 2 == 0) ? xs : ys;  // the last pass writes xs
-    hipLaunchKernelGGL(k_lsd_hist, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles);
-    scan_excl(hist, hist, hist_n, (uint64_t)kLsdBins * ntiles, tile_tmp, nullptr, s);
-    hipLaunchKernelGGL(k_lsd_scatter, dim3(grid), dim3(kLsdNT), 0, s, in, n_dev, kLsdBits * ps, hist, ntiles, out[0],
-                       out[1], out[2], ps == passes - 1 ? start_copy : nullptr);
+    hipLaunchKernelGGL(k_lsd_hist, dim3(grid), dim3(kLsdNT), 0, s, in, kLsdBits * ps, hist, T);
+    scan_excl(hist, hist, hist_n, (uint64_t)kLsdBins * tiles_bound, tile_tmp, nullptr, s);
+    hipLaunchKernelGGL(k_lsd_scatter, dim3(grid), dim3(kLsdNT), 0, s, in, kLsdBits * ps, hist, T, out[0], out[1],
+                       out[2], ps == passes - 1 ? start_copy : nullptr);
     in = LsdSrc{nullptr, nullptr, out[0], out[1], out[2], nullptr, 0};
   }
 }
@@ -1644,42 +1750,50 @@ __global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const ui
   const uint32_t ws = (uint32_t)woff[w];
   const uint32_t L = (uint32_t)(woff[w + 1] - woff[w]);
   for (uint32_t x = lane; x < (L + 31) / 32; x += 64) bm[x] = 0;
-  uint32_t ps[kWinSelDepth], pl[kWinSelDepth];
+  // Chunks of kWinSelDepth batches, double-buffered in registers: the next
+  // chunk's loads are issued (unconditionally, indices clamped, so the
+  // compiler can count them) before the current chunk is walked, and the
+  // chunk's states are stored after the walk, so no memory wait sits inside
+  // the walk.
+  const uint32_t last = c1 - 1;
+  uint32_t cs[kWinSelDepth], cl[kWinSelDepth], ns[kWinSelDepth], nl[kWinSelDepth];
 #pragma unroll
   for (int d = 0; d < kWinSelDepth; d++) {
-    const uint32_t k = c0 + d * 64 + lane;
-    ps[d] = k < c1 ? start[k] : 0u;
-    pl[d] = k < c1 ? len[k] : 1u;
+    const uint32_t k = min(c0 + (uint32_t)(d * 64 + lane), last);
+    cs[d] = start[k];
+    cl[d] = len[k];
   }
   __syncthreads();
   for (uint32_t base = c0; base < c1; base += 64 * kWinSelDepth) {
 #pragma unroll
     for (int d = 0; d < kWinSelDepth; d++) {
-      const uint32_t b = base + d * 64;
-      if (b >= c1) break;  // wavefront-uniform
-      const uint32_t k = b + lane;
+      const uint32_t k = min(base + (uint32_t)(64 * kWinSelDepth + d * 64 + lane), last);
+      ns[d] = start[k];
+      nl[d] = len[k];
+    }
+    uint64_t acc[kWinSelDepth];
+#pragma unroll
+    for (int d = 0; d < kWinSelDepth; d++) {
+      const uint32_t k = base + d * 64 + lane;
       const bool valid = k < c1;
-      const uint32_t s = ps[d] - ws, e = s + pl[d] - 1u;
-      const uint32_t kn = k + 64 * kWinSelDepth;  // refill this slot with the batch kWinSelDepth ahead
-      if (kn < c1) {
-        ps[d] = start[kn];
-        pl[d] = len[kn];
-      }
+      const uint32_t s = cs[d] - ws, e = s + cl[d] - 1u;
       bool ok = false;
       if (valid) ok = !((bm[s >> 5] >> (s & 31)) & 1u) && !((bm[e >> 5] >> (e & 31)) & 1u);
       uint64_t pass = __ballot(ok);
-      uint64_t acc = 0;
+      uint64_t a = 0;
       while (pass) {
         const int j = __ffsll((unsigned long long)pass) - 1;
-        const uint32_t sj = (uint32_t)__shfl((int)s, j, 64), ej = (uint32_t)__shfl((int)e, j, 64);
-        acc |= 1ull << j;
+        const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)s, j),
+                       ej = (uint32_t)__builtin_amdgcn_readlane((int)e, j);  // j is uniform
+        a |= 1ull << j;
         pass &= ~__ballot(valid && s <= ej && e >= sj);  // j itself and the later lanes it overlaps
       }
-      uint64_t todo = acc;
+      uint64_t todo = a;
       while (todo) {
         const int j = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;
-        const uint32_t sj = (uint32_t)__shfl((int)s, j, 64), ej = (uint32_t)__shfl((int)e, j, 64);
+        const uint32_t sj = (uint32_t)__builtin_amdgcn_readlane((int)s, j),
+                       ej = (uint32_t)__builtin_amdgcn_readlane((int)e, j);  // j is uniform
         const uint32_t w0 = sj >> 5, w1 = ej >> 5;
         for (uint32_t x = w0 + lane; x <= w1; x += 64) {
           uint32_t msk = 0xFFFFFFFFu;
@@ -1688,7 +1802,17 @@ __global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const ui
           atomicOr(&bm[x], msk);  // accepted intervals may share their end words
         }
       }
-      if (valid) state[k] = ((acc >> lane) & 1ull) ? 1 : 2;
+      acc[d] = a;
+    }
+#pragma unroll
+    for (int d = 0; d < kWinSelDepth; d++) {
+      const uint32_t k = base + d * 64 + lane;
+      if (k < c1) state[k] = ((acc[d] >> lane) & 1ull) ? 1 : 2;
+    }
+#pragma unroll
+    for (int d = 0; d < kWinSelDepth; d++) {
+      cs[d] = ns[d];
+      cl[d] = nl[d];
     }
   }
 }

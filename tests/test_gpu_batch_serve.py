@@ -220,6 +220,42 @@ def test_graph_capture_and_replay(ctx):
         assert g.graph_stats()["replays"] == 3
 
 
+def test_lane_graph_capture_and_replay():
+    """Three lanes captured as branches of one graph: every replay (tokens
+    rewritten in place, other window boundaries of the same shape, eager work
+    in between) equals the oracle; a new shape is captured anew."""
+    import torch
+    from paper_2406_18111_amd import Context
+    wins_a, wins_b = _same_shape_batches(33)
+    with Context(0) as g:
+        g.set_graphs(True)
+        g.set_lanes(3)
+        toks_a, off_a = _pack(wins_a)
+        dev = torch.from_numpy(toks_a.view(np.int64)).cuda()
+        for rep in range(3):
+            rows, oo = g.analyze_batch_dev(dev, off_a, 4)
+            rows = rows.cpu().numpy().astype(np.int64)
+            for w, win in enumerate(wins_a):
+                assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), (rep, w)
+            assert np.array_equal(_as3(g.analyze(wins_a[1], 4)), _rows_ref(wins_a[1], 4))
+        st = g.graph_stats()
+        assert st["captures"] == 1 and st["replays"] == 2
+        toks_b, off_b = _pack(wins_b)
+        dev.copy_(torch.from_numpy(toks_b.view(np.int64)))
+        rows, oo = g.analyze_batch_dev(dev, off_b, 4)
+        rows = rows.cpu().numpy().astype(np.int64)
+        for w, win in enumerate(wins_b):
+            assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), w
+        # a different shape: captured again, still exact
+        wins_c = wins_a[:5]
+        toks_c, off_c = _pack(wins_c)
+        rows, oo = g.analyze_batch_dev(torch.from_numpy(toks_c.view(np.int64)).cuda(), off_c, 4)
+        rows = rows.cpu().numpy().astype(np.int64)
+        for w, win in enumerate(wins_c):
+            assert np.array_equal(rows[int(oo[w]):int(oo[w + 1])], _rows_ref(win, 4)), w
+        assert g.graph_stats()["captures"] >= 2
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 3, 4])
 @pytest.mark.parametrize("window_greedy", [True, False])
 def test_lanes_give_identical_results(lanes, window_greedy):

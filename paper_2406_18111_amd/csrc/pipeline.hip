@@ -300,9 +300,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint32_t bits0;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
-    // slots [0, 2N) by window regions; the special slot sits past them
-    hash_clear(w.htab, 2 * N, w.hcap, s);
-    hash_insert(tok, N, w.htab, w.hcap, wbeg, wend, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
+    const uint64_t hc = pow2_at_least(2 * N);
+    hash_clear(w.htab, hc - 1, s);
+    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
     uint64_t nd_bound = N;
     if (host) {
       if ((rc = read_counters(w, s))) return rc;

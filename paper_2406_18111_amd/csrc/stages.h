@@ -17,15 +17,12 @@ void copy_n_u32(uint32_t *dst, const uint32_t *src, uint64_t n, hipStream_t s);
 void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_t bound, uint32_t *tile_tmp,
                uint32_t *total, hipStream_t s);
 
-// Table of 2n slots, window w owning [2 wbeg, 2 wend), plus the slot
-// `special` (> 2n) of the token value equal to the empty mark; hash_clear
-// empties slots [0, slots) and `special`.
-void hash_clear(uint64_t *tab, uint64_t slots, uint64_t special, hipStream_t s);
-// tok_slot[i] receives the table slot of token i; wbeg / wend: per-position
-// window bounds (null: one window).
-void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t special, const uint32_t *wbeg,
-                 const uint32_t *wend, uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot,
-                 hipStream_t s);
+// Table of hc = mask + 1 slots plus one (the token value equal to the empty
+// mark has slot mask + 1); hash_clear empties it.
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s);
+// tok_slot[i] receives the table slot of token i.
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
+                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s);
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s);
 void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot,

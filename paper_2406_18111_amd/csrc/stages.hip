@@ -208,33 +208,24 @@ void copy_u32(uint32_t *dst, const uint32_t *src, hipStream_t s) {
 // ------------------------------------------------------ token ranking (u64)
 // Open-addressing table of the distinct 64-bit token values themselves
 // (kEmpty marks a free slot; the token value equal to kEmpty has the extra
-// slot `special` of its own).  Windows never compare tokens with each other,
-// so every window gets its own region of the table, [2 wbeg, 2 wend) (load
-// at most 1/2): a window's inserts and the later rank gathers stay inside a
-// few megabytes instead of spreading over the whole table, and a value that
-// occurs in several windows takes one slot per window.  The ranks the slots
-// later receive are positions in the sorted list of all windows' distinct
-// values, so within a window they are order-preserving and equal tokens share
-// one (the suffix sort needs nothing more).  Each workgroup first removes
-// duplicates within its tile of tokens with a table in LDS keyed on (window,
-// value), so only one thread per distinct pair and tile probes the global
-// table (loop streams repeat a few hundred hashes thousands of times); a
-// probe compares the stored key, with no dependent read of the token array.
-// The threads whose CAS claims a slot collect their new distinct values in
-// LDS, and the tile reserves their list entries with one atomic.
+// slot mask+1 of its own).  Each workgroup first removes duplicates within
+// its tile of tokens with a table in LDS, so only one thread per distinct
+// value and tile probes the global table (loop streams repeat a few hundred
+// hashes thousands of times); a probe compares the stored key, with no
+// dependent read of the token array.  The threads whose CAS claims a slot
+// collect their new distinct values in LDS, and the tile reserves their list
+// entries with one atomic.
 constexpr int kHashTile = 2048, kHashLds = 4096;
 constexpr uint64_t kEmpty = ~0ull;
 
 // Returns whether the key was new; *slot receives its slot either way.
-// The key's slots are [base, base + size); size > 0.
-__device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t base, uint64_t size,
-                                              uint64_t special, uint64_t *slot) {
+__device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *tab, uint64_t mask,
+                                              uint64_t *slot) {
   if (key == kEmpty) {
-    *slot = special;
-    return atomicCAS(&tab[special], 0ull, 1ull) == 0ull;
+    *slot = mask + 1;
+    return atomicCAS(&tab[mask + 1], 0ull, 1ull) == 0ull;
   }
-  const uint64_t end = base + size;
-  uint64_t h = base + __umul64hi(mix64(key), size);  // multiply-high range reduction into the region
+  uint64_t h = mix64(key) & mask;
   while (true) {
     unsigned long long cur = tab[h];
     if (cur == kEmpty) {
@@ -248,18 +239,16 @@ __device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *
       *slot = h;
       return false;
     }
-    h = h + 1 == end ? base : h + 1;
+    h = (h + 1) & mask;
   }
 }
 
 // Also writes every token's global slot to tok_slot (the tile's first
-// occurrence of a (window, value) pair finds it; the local table hands it to
-// the others), so the ranks come later from one gather per token instead of
-// a second probe.  wbeg/wend: per-position window bounds (null: one window).
+// occurrence of a value finds it; the local table hands it to the others), so
+// the ranks come later from one gather per token instead of a second probe.
 __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, unsigned long long *tab,
-                                                     uint64_t special, const uint32_t *wbeg, const uint32_t *wend,
-                                                     uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd,
-                                                     uint32_t *tok_slot) {
+                                                     uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
+                                                     uint32_t *nd, uint32_t *tok_slot) {
   constexpr int NT = 256;
   constexpr int PER = kHashTile / NT;
   __shared__ uint64_t lt[kHashTile];   // the tile's tokens
@@ -271,15 +260,6 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
     for (uint32_t k = threadIdx.x; k < kHashLds; k += NT) ls[k] = 0;
     for (uint32_t k = threadIdx.x; k < m; k += NT) lt[k] = tok[t0 + k];
     if (threadIdx.x == 0) nnew = 0;
-    // this thread's tokens' window bounds (registers: LDS room decides how
-    // many workgroups share a CU)
-    uint32_t wbs[PER], wes[PER];
-#pragma unroll
-    for (int u = 0; u < PER; u++) {
-      const uint64_t i = t0 + threadIdx.x + (uint64_t)u * NT;
-      wbs[u] = (wbeg && i < n) ? wbeg[i] : 0u;
-      wes[u] = (wend && i < n) ? wend[i] : (uint32_t)n;
-    }
     __syncthreads();
     uint32_t hl[PER], gs[PER];  // local table entry of each token; global slot (first occurrences)
     uint32_t first = 0;
@@ -290,26 +270,22 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
       gs[u] = 0;
       if (k >= m) continue;
       const uint64_t key = lt[k];
-      const uint32_t wb = wbs[u], we = wes[u];
-      uint32_t h = (uint32_t)(mix64(key ^ wb) >> 40) & (kHashLds - 1);
+      uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
       while (true) {
         uint32_t prev = ls[h];
         if (prev == 0u) prev = atomicCAS(&ls[h], 0u, k + 1);
         if (prev == 0u) {  // first in this tile
-          const uint64_t i = t0 + k;
           uint64_t slot;
-          if (global_insert(key, tab, 2 * (uint64_t)wb, 2 * ((uint64_t)we - wb), special, &slot)) {
+          if (global_insert(key, tab, mask, &slot)) {
             const uint32_t q = atomicAdd(&nnew, 1u);
-            new_i[q] = (uint32_t)i;
+            new_i[q] = (uint32_t)(t0 + k);
             new_h[q] = (uint32_t)slot;
           }
           gs[u] = (uint32_t)slot;
           first |= 1u << u;
           break;
         }
-        // same value, and a position inside this token's window
-        const uint64_t pp = t0 + prev - 1;
-        if (lt[prev - 1] == key && pp >= wb && pp < we) break;
+        if (lt[prev - 1] == key) break;
         h = (h + 1) & (kHashLds - 1);
       }
       hl[u] = h;
@@ -376,19 +352,19 @@ __global__ void k_hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t
 
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) { GRID_STRIDE(i, n) p[i] = v; }
 
-void hash_clear(uint64_t *tab, uint64_t slots, uint64_t special, hipStream_t s) {
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s) {
   auto *t = reinterpret_cast<unsigned long long *>(tab);
-  hipLaunchKernelGGL(k_fill_u64, grid_for(slots, 256, 8192), dim3(256), 0, s, t, slots, (unsigned long long)kEmpty);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + special, (uint64_t)1, 0ull);
+  hipLaunchKernelGGL(k_fill_u64, grid_for(mask + 1, 256, 8192), dim3(256), 0, s, t, mask + 1,
+                     (unsigned long long)kEmpty);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + mask + 1, (uint64_t)1, 0ull);
 }
 
-void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t special, const uint32_t *wbeg,
-                 const uint32_t *wend, uint32_t *dist_idx, uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot,
-                 hipStream_t s) {
+void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
+                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s) {
   const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
   hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
-                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), special, wbeg, wend, dist_idx,
-                     dist_slot, nd, tok_slot);
+                     0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd,
+                     tok_slot);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -1708,6 +1684,7 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
 // kWinSelDepth batches ahead in a register ring so that they never wait.
 // state[k] = 1 (accepted) or 2 (rejected) for every candidate.
 constexpr int kWinSelDepth = 16;
+constexpr uint32_t kOwnPaint = 4;  // intervals of up to this many bitmap words are painted by their own lane
 
 // First index k in [lo, hi) whose window is >= w (hi if none), for a
 // window-major list: a 64-ary search by the whole wavefront (each step
@@ -1777,8 +1754,9 @@ __global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const ui
       const uint32_t k = base + d * 64 + lane;
       const bool valid = k < c1;
       const uint32_t s = cs[d] - ws, e = s + cl[d] - 1u;
-      bool ok = false;
-      if (valid) ok = !((bm[s >> 5] >> (s & 31)) & 1u) && !((bm[e >> 5] >> (e & 31)) & 1u);
+      // both end words read together (one LDS round trip, not two)
+      const uint32_t ws0 = valid ? bm[s >> 5] : 0u, we0 = valid ? bm[e >> 5] : 0u;
+      const bool ok = valid && !((ws0 >> (s & 31)) & 1u) && !((we0 >> (e & 31)) & 1u);
       uint64_t pass = __ballot(ok);
       uint64_t a = 0;
       while (pass) {
@@ -1788,7 +1766,19 @@ __global__ __launch_bounds__(64) void k_sel_window(const uint32_t *len, const ui
         a |= 1ull << j;
         pass &= ~__ballot(valid && s <= ej && e >= sj);  // j itself and the later lanes it overlaps
       }
-      uint64_t todo = a;
+      // accepted lanes whose interval spans at most kOwnPaint words paint it
+      // themselves; longer ones are painted by the whole wavefront, one by one
+      const bool mine = (a >> lane) & 1ull;
+      const bool own = mine && ((e >> 5) - (s >> 5)) < kOwnPaint;
+      if (own) {
+        for (uint32_t x = s >> 5; x <= (e >> 5); x++) {
+          uint32_t msk = 0xFFFFFFFFu;
+          if (x == (s >> 5)) msk &= 0xFFFFFFFFu << (s & 31);
+          if (x == (e >> 5)) msk &= 0xFFFFFFFFu >> (31 - (e & 31));
+          atomicOr(&bm[x], msk);
+        }
+      }
+      uint64_t todo = a & ~__ballot(own);
       while (todo) {
         const int j = __ffsll((unsigned long long)todo) - 1;
         todo &= todo - 1;

@@ -9,6 +9,28 @@ namespace apo {
 // consecutive words then hit different banks.
 __host__ __device__ constexpr int pad16(int p) { return p + (p >> 4); }
 
+// The command processor hands workgroups to the eight XCDs in turn (block b
+// to XCD b mod 8), and each XCD has its own L2.  Renumbering the blocks so
+// that every XCD runs one contiguous share of the logical block range keeps
+// the lines that neighbouring blocks share (one window's ranks, suffixes and
+// tokens) in a single L2 instead of fetching them into all eight.  A
+// bijection on [0, G): XCD x's blocks x, x + 8, ... become x*q + min(x, G mod 8)
+// + 0, 1, ... with q = G / 8.
+__host__ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+  const uint32_t q = G >> 3, rem = G & 7u, x = b & 7u;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
+// Grid-stride form: the item of physical block b in the pass that starts at
+// item `base` (G blocks, `total` items).  The blocks are renumbered over the
+// g = min(G, total - base) of them that have an item in this pass, so a short
+// pass still spreads over every XCD; a block without an item gets `total`.
+__host__ __device__ __forceinline__ uint64_t xcd_item(uint64_t base, uint64_t total, uint32_t b, uint32_t G) {
+  const uint64_t left = total - base;
+  const uint32_t g = left < (uint64_t)G ? (uint32_t)left : G;
+  return b < g ? base + xcd_block(b, g) : total;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll

@@ -209,12 +209,17 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
   // four consecutive slots per thread: flags, suffixes and window ends are
   // single 4- and 16-byte loads and the four partner-rank reads are issued
   // together.  Keys of slots no longer grouped are never read (only units
-  // are sorted), so all four keys go out as one 16-byte store.
+  // are sorted), so all four keys go out as one 16-byte store.  Blocks of
+  // slots are handed out XCD by XCD: partner ranks lie in the same window, so
+  // one XCD's L2 holds the lines its neighbouring blocks gather.
   const uint32_t *val = B.val[0];
   uint32_t *key = B.key[0];
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t n4 = n / 4;
-  for (uint64_t q = gid; q < n4; q += stride) {
+  const uint64_t n4 = n / 4, nblk = (n4 + blockDim.x - 1) / blockDim.x;
+  for (uint64_t base = 0; base < nblk; base += gridDim.x) {
+    const uint64_t bk = xcd_item(base, nblk, blockIdx.x, gridDim.x);
+    if (bk >= nblk) break;
+    const uint64_t q = bk * blockDim.x + threadIdx.x;
+    if (q >= n4) continue;
     const uint32_t fl = reinterpret_cast<const uint32_t *>(aflag)[q];
     if (!fl) continue;
     const uint4 v = reinterpret_cast<const uint4 *>(val)[q];
@@ -225,6 +230,7 @@ __global__ void k_gather_sa(SortBufs B, int cur, const uint32_t *rank, const uin
     for (int u = 0; u < 4; u++) k[u] = (((fl >> (8 * u)) & 0xFFu) && x[u] < e[u]) ? rank[x[u]] : 0u;
     reinterpret_cast<uint4 *>(key)[q] = make_uint4(k[0], k[1], k[2], k[3]);
   }
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t p = 4 * n4 + gid;  // the last n mod 4 slots
   if (p < n && aflag[p]) {
     const uint32_t x = val[p] + h;
@@ -710,7 +716,11 @@ __global__ __launch_bounds__(kGroupThreads, TLG == 11 ? 6 : 2) void k_lds_group(
   __syncthreads();
   const uint32_t total_items = items_total;
   uint32_t elems = 0, act_deferred = 0;
-  for (uint32_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+  // items are handed out XCD by XCD: neighbouring tiles hold units of
+  // neighbouring windows, whose scattered rank writes then merge in one L2
+  for (uint32_t base = 0; base < total_items; base += gridDim.x) {
+    const uint32_t item = (uint32_t)xcd_item(base, total_items, blockIdx.x, gridDim.x);
+    if (item >= total_items) break;
     if (tid == 0) {
       uint32_t it = item;
       int ci = kGroupMinCi;

@@ -509,7 +509,11 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
   __shared__ uint32_t ks[pad16(kPlcpSpan + kPlcpMargin)];
   const int top = min(top_bound, (int)*snaps - 1);  // last snapshot level (< kSnapFrom: none)
   const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
-  for (uint64_t sp = blockIdx.x; sp < nspan; sp += gridDim.x) {
+  // spans are handed out XCD by XCD: the Phi-side reads of neighbouring spans
+  // fall in the same windows, so one L2 holds them
+  for (uint64_t base = 0; base < nspan; base += gridDim.x) {
+    const uint64_t sp = xcd_item(base, nspan, blockIdx.x, gridDim.x);
+    if (sp >= nspan) break;
     const uint64_t j0 = sp * kPlcpSpan;
     const int len = (int)min((uint64_t)kPlcpSpan, n - j0);
     const int klen = (int)min((uint64_t)(kPlcpSpan + kPlcpMargin), n - j0);
@@ -579,8 +583,13 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
 // Four pairs per thread (strided by the block size, so each load is
 // coalesced); the four PLCP reads are issued together.
 __global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, const uint32_t *plcp, uint32_t *lcp) {
-  const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
-  for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
+  // blocks handed out XCD by XCD (the PLCP reads of neighbouring blocks
+  // fall in the same windows)
+  const uint64_t per = (uint64_t)blockDim.x * 4, nblk = (n + per - 1) / per;
+  for (uint64_t base = 0; base < nblk; base += gridDim.x) {
+    const uint64_t bk = xcd_item(base, nblk, blockIdx.x, gridDim.x);
+    if (bk >= nblk) break;
+    const uint64_t b0 = bk * per;
     uint32_t nx[4], v[4];
     bool ok[4];
 #pragma unroll
@@ -1093,7 +1102,9 @@ __global__ __launch_bounds__(kLsdNT) void k_lsd_scatter(LsdSrc in, int shift, co
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t ntiles = T.tb[T.nseg];
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (uint32_t tb = 0; tb < ntiles; tb += gridDim.x) {  // tiles handed out XCD by XCD
+    const uint32_t t = (uint32_t)xcd_item(tb, ntiles, blockIdx.x, gridDim.x);
+    if (t >= ntiles) break;
     const LsdTile tl = lsd_tile(T, t);
     for (int d = threadIdx.x; d < kLsdBins; d += kLsdNT)
       for (int q = 0; q < 4; q++) wcnt[q][d] = 0;

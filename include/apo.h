@@ -212,8 +212,9 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
  * first-token sort included), candidates generated, candidates after dedup,
  * selection rounds, accepted occurrences, rows, sum over rounds of active
  * suffixes (the first-token sort counts every suffix), distinct tokens, and
- * 1 if the selection finished with the sequential completion (else 0).
- * Writes min(nvals, 9) values and returns that number. */
+ * 1 if the selection finished with the sequential completion (else 0), and
+ * the candidates the exact prefix walk decided before the rounds (0: none).
+ * Writes min(nvals, 10) values and returns that number. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
 
 /* Device bytes of the workspace an analysis of n tokens in `windows`
@@ -249,6 +250,16 @@ int apo_set_window_greedy(apo_ctx *ctx, int on);
  * sequential completion, which gives the same result (Section 4.2, the
  * greedy walk of Algorithm 2).  APO_EINVAL outside 0..64. */
 int apo_set_selection_round_cap(apo_ctx *ctx, int rounds);
+
+/* Host-driven analyses that use the round-based greedy selection may first
+ * decide a prefix of the priority order exactly (one workgroup walks the
+ * longest candidates in order over the mark array, Section 4.2, the greedy
+ * walk of Algorithm 2), then run the rounds from round 1 on the rest, whose
+ * filter rejects every candidate the prefix covers.  k = -1 (default): a
+ * prefix of 1024 candidates when the longest candidate spans at least 1/64 of
+ * the analysed tokens; k = 0: never; k > 0: always a prefix of k candidates
+ * (a test hook).  Results are identical either way.  APO_EINVAL if k < -1. */
+int apo_set_selection_prefix(apo_ctx *ctx, int k);
 
 /* Per-round sizes of the last analysis (diagnostic): sa_active[r] = suffixes
  * entering doubling round r (r < *n_sa); sel_live[q] / sel_undecided[q] =

@@ -33,7 +33,7 @@ class AutoParams(ctypes.Structure):
 
 STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
 COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
-            "active_sum", "sigma", "selection_sequential")
+            "active_sum", "sigma", "selection_sequential", "selection_prefix")
 
 # name -> (restype, argtypes); mirrors include/apo.h
 _P, _U32, _U64, _I, _SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
@@ -50,6 +50,7 @@ SIGNATURES = {
     "apo_set_graphs": (_I, [_P, _I]),
     "apo_set_lanes": (_I, [_P, _I]),
     "apo_set_selection_round_cap": (_I, [_P, _I]),
+    "apo_set_selection_prefix": (_I, [_P, _I]),
     "apo_set_window_greedy": (_I, [_P, _I]),
     "apo_inject_device_error": (_I, [_P, _I]),
     "apo_memory": (_I, [_P, _P, _P, _P]),
@@ -254,6 +255,10 @@ class Context:
     def set_selection_round_cap(self, rounds: int):
         """Test hook: stop host-driven greedy rounds after `rounds` (0..64)."""
         _check(self._lib.apo_set_selection_round_cap(self._h, int(rounds)), "apo_set_selection_round_cap")
+
+    def set_selection_prefix(self, k: int):
+        """Exact prefix walk before the selection rounds: -1 automatic, 0 never, k > 0 always k candidates."""
+        _check(self._lib.apo_set_selection_prefix(self._h, int(k)), "apo_set_selection_prefix")
 
     def inject_device_error(self, after_syncs: int):
         """Test hook: a host sync of the next single-window analysis reports a device error."""

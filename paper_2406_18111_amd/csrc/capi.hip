@@ -139,6 +139,7 @@ struct apo_ctx {
   bool graphs = true;         // capture/replay batched launch sequences
   bool lane_graphs = true;    // lanes as branches of one graph (off after a failed capture)
   int sel_cap = apo::kSelRoundCap;  // host-driven selection rounds before the sequential completion
+  int sel_prefix = -1;              // exact prefix walk before the selection rounds (-1 automatic)
   bool win_greedy = true;           // per-window greedy where windows are short enough
   uint64_t graph_replays = 0, graph_captures = 0;
   std::unique_ptr<apo::Server> server;
@@ -268,6 +269,7 @@ static int run_ctx(apo_ctx *c, const void *d_tok, int bits, uint32_t n, uint32_t
   int rc = ctx_ensure(c, c->ws, n, 1);
   if (rc) return map_rc(rc);
   c->ws.sel_cap = c->sel_cap;
+  c->ws.sel_prefix = c->sel_prefix;
   c->ws.win_greedy = c->win_greedy;
   const uint64_t off[2] = {0, n};
   int tl, db;
@@ -474,6 +476,7 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
     ln.ws->eng.set_params(tl, db);
     ln.ws->ktag = ctx->ws.ktag;
     ln.ws->sel_cap = ctx->sel_cap;
+    ln.ws->sel_prefix = ctx->sel_prefix;
     ln.ws->win_greedy = ctx->win_greedy;
     if (ln.st != s && hipStreamWaitEvent(ln.st, ctx->lane_ready, 0) != hipSuccess) return APO_EDEVICE;
     lanes.push_back(std::move(ln));
@@ -624,6 +627,7 @@ static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
   ctx->ws.eng.set_params(tl, db);
   Workspace &w = ctx->ws;
   w.sel_cap = ctx->sel_cap;
+  w.sel_prefix = ctx->sel_prefix;
   if (w.win_greedy != ctx->win_greedy) ctx->gc.reset();  // a captured sequence holds the other selection path
   w.win_greedy = ctx->win_greedy;
   // Timed kernel launches are bracketed by events on the stream, which is
@@ -842,9 +846,9 @@ extern "C" int apo_last_stage_ms(apo_ctx *ctx, double *ms, int nstages) {
 extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   if (!ctx || !v || nvals < 0) return APO_EINVAL;
   const RunInfo &I = ctx->info;
-  const uint64_t all[9] = {I.rounds,   I.cands,      I.cands_dedup, I.sel_rounds,    I.accepted,
-                           I.rows,     I.active_sum, I.sigma,       I.sel_sequential};
-  const int k = std::min(nvals, 9);
+  const uint64_t all[10] = {I.rounds, I.cands,      I.cands_dedup, I.sel_rounds,     I.accepted,
+                            I.rows,   I.active_sum, I.sigma,       I.sel_sequential, I.sel_prefix};
+  const int k = std::min(nvals, 10);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
 }
@@ -884,6 +888,12 @@ extern "C" int apo_set_window_greedy(apo_ctx *ctx, int on) {
 extern "C" int apo_set_selection_round_cap(apo_ctx *ctx, int rounds) {
   if (!ctx || rounds < 0 || rounds > kSelRoundCap) return APO_EINVAL;
   ctx->sel_cap = rounds;
+  return APO_OK;
+}
+
+extern "C" int apo_set_selection_prefix(apo_ctx *ctx, int k) {
+  if (!ctx || k < -1) return APO_EINVAL;
+  ctx->sel_prefix = k;
   return APO_OK;
 }
 

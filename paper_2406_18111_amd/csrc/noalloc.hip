@@ -71,6 +71,7 @@ int noalloc_run(int device, hipStream_t s, int tile_log, int digit_bits, const v
   fill_u32(B.hist, (uint64_t)B.big_cap * kBins, 0, s);
   fill_u32(reinterpret_cast<uint32_t *>(B.ctr), sizeof(SortCounters) / 4, 0, s);
   w.sel_cap = kSelRoundCap;
+  w.sel_prefix = -1;
   w.win_greedy = true;
   w.fail_after = -1;
   w.ktag = KT_NONE;

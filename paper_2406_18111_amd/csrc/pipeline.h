@@ -30,6 +30,13 @@ constexpr int kStages = 7;
 // single windows up to this many tokens use the one-wavefront greedy
 constexpr uint64_t kWinSelSingle = 1ull << 15;
 constexpr int kSelRoundCap = 64;
+// Host-driven round-based selection first walks a prefix of kSelPrefixAuto
+// candidates exactly when the longest candidate spans at least
+// 1/kSelPrefixDiv of the analysis (long intervals decided first then reject
+// most of the rest in round 1's filter, instead of all of them being inserted
+// into round 0's coverage table).
+constexpr uint32_t kSelPrefixAuto = 1024;
+constexpr uint64_t kSelPrefixDiv = 64;
 
 struct RunInfo {
   uint64_t n = 0;             // tokens analysed (all windows)
@@ -41,6 +48,7 @@ struct RunInfo {
   uint32_t maxl = 0;
   uint32_t sel_rounds = 0;
   uint32_t sel_sequential = 0;
+  uint32_t sel_prefix = 0;         // candidates decided by the exact prefix walk
   uint32_t accepted = 0;
   uint32_t rows = 0;
   double stage_ms[kStages] = {0};
@@ -95,6 +103,7 @@ struct Workspace {
   int kround[kMaxTimed] = {0};
   int kev_n = 0;
   int sel_cap = kSelRoundCap;      // host-driven selection rounds before the sequential completion
+  int sel_prefix = -1;             // exact prefix walk before the rounds: -1 automatic, 0 never, k > 0 k candidates
   int fail_after = -1;             // test hook: host syncs before one reports a device error (-1: never)
   bool win_greedy = true;          // one-wavefront-per-window greedy where windows are short enough
 

@@ -479,7 +479,13 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int top = 63 - __builtin_clzll(maxl_bound);
     uint32_t *Ta = w.T, *Tb = w.T + (size_t)w.nT * w.capN;
     uint32_t *nlive = w.selcnt, *undec = w.selcnt + (kSelRoundCap + 2), *nwork = w.selcnt + 2 * (kSelRoundCap + 2);
-    sel_table_init(Ta, N, dc + CNT_MAXL, top, s);
+    // exact prefix walk (host-driven runs, where the candidate count and the
+    // longest length are known): round 0 is then skipped, and its table with it
+    uint32_t kpre = 0;
+    if (host && w.sel_prefix > 0) kpre = (uint32_t)std::min<uint64_t>((uint64_t)w.sel_prefix, m_bound);
+    if (host && w.sel_prefix < 0 && maxl_bound * kSelPrefixDiv >= N)
+      kpre = (uint32_t)std::min<uint64_t>(kSelPrefixAuto, m_bound);
+    if (!kpre) sel_table_init(Ta, N, dc + CNT_MAXL, top, s);
     fill_u32(w.selcnt, 3 * (kSelRoundCap + 2), 0, s);
     const uint64_t npad = pow2_at_least(N);
     fill_u32(w.ctree, 2 * npad, 0xFFFFFFFFu, s);
@@ -489,6 +495,14 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     const int ahead = host ? 2 : kSelFreeRounds;
     int q0 = 0;
     uint64_t hint = m_bound;
+    if (kpre) {
+      sel_prefix(w.s_len, w.s_start, kpre, w.state, w.mark, w.live[0], dc + CNT_M, nlive + 1, m_bound, s);
+      info.sel_prefix = kpre;
+      q0 = 1;  // round 1 filters the candidates after the prefix
+      hint = m_bound - kpre;
+      sel_launched = 1;
+      if (hint == 0) sel_done = 0;
+    }
     // host-driven runs stop the rounds at w.sel_cap (kSelRoundCap unless a
     // test lowers it) and finish with the sequential completion
     const int cap = host ? std::max(0, std::min(w.sel_cap, kSelRoundCap)) : kSelRoundCap;

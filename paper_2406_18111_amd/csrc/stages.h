@@ -104,6 +104,11 @@ void sel_round(const uint32_t *len, const uint32_t *start, uint32_t *Tc, uint32_
                hipStream_t s);
 void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, const uint32_t *m_dev, uint64_t bound,
                     uint8_t *mark, uint64_t n, hipStream_t s);
+// Exact greedy over the first k candidates (k <= the candidate count), which
+// sets their state and paints the accepted ones into `mark` (zeroed before);
+// then round 1's undecided list: pend = k..m-1 and *nlive1 = m - k.
+void sel_prefix(const uint32_t *len, const uint32_t *start, uint32_t k, uint8_t *state, uint8_t *mark,
+                uint32_t *pend, const uint32_t *m_dev, uint32_t *nlive1, uint64_t bound, hipStream_t s);
 
 // Exact greedy for candidate lists ordered window by window (each window's
 // candidates in priority order): one wavefront per window over an LDS bitmap

@@ -1681,6 +1681,78 @@ void sel_sequential(uint8_t *state, const uint32_t *len, const uint32_t *start, 
   hipLaunchKernelGGL(k_sel_sequential, dim3(1), dim3(64), 0, s, state, len, start, m_dev, mark);
 }
 
+// Exact greedy over a prefix of the priority order (the first k
+// candidates), by one workgroup: the first wavefront takes 64 candidates at a
+// time, rejects those with a marked end (exact: every candidate accepted
+// before is at least as long, so an overlap covers an end), settles the rest
+// of the batch among itself in priority order with ballots, and the whole
+// workgroup paints the batch's accepted intervals before the next batch
+// reads the marks.  The longest candidates come first, so when they are long
+// a short prefix paints most of the window; the rounds then go on from round
+// 1 over the candidates after the prefix, and its filter rejects every one
+// with a marked end.
+constexpr int kPrefixThreads = 1024;
+
+__global__ __launch_bounds__(kPrefixThreads) void k_sel_prefix(const uint32_t *len, const uint32_t *start, uint32_t k,
+                                                                uint8_t *state, uint8_t *mark) {
+  __shared__ uint32_t as[64], ae[64];
+  __shared__ uint32_t nacc;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint4 ones = make_uint4(0x01010101u, 0x01010101u, 0x01010101u, 0x01010101u);
+  for (uint32_t b0 = 0; b0 < k; b0 += 64) {
+    if (tid < 64) {
+      const uint32_t q = b0 + (uint32_t)lane;
+      const bool valid = q < k;
+      const uint32_t l = valid ? len[q] : 1u, st = valid ? start[q] : 0u, e = st + l - 1;
+      const bool pass = valid && !mark[st] && !mark[e];
+      uint64_t cand = __ballot(pass);
+      uint64_t acc = 0;
+      while (cand) {  // wavefront-uniform
+        const int i = __ffsll((unsigned long long)cand) - 1;
+        acc |= 1ull << i;
+        const uint32_t si = (uint32_t)__shfl((int)st, i, 64), ei = (uint32_t)__shfl((int)e, i, 64);
+        const bool hit = lane > i && st <= ei && si <= e;
+        cand &= ~__ballot(hit);
+        cand &= cand - 1;  // lane i itself
+      }
+      const bool a = (acc >> lane) & 1ull;
+      if (valid) state[q] = a ? 1 : 2;
+      if (a) {
+        const int pos = __popcll(acc & ((1ull << lane) - 1ull));
+        as[pos] = st;
+        ae[pos] = e + 1;
+      }
+      if (lane == 0) nacc = (uint32_t)__popcll(acc);
+    }
+    __syncthreads();
+    const uint32_t na = nacc;
+    for (uint32_t i = 0; i < na; i++) {
+      const uint32_t S = as[i], E = ae[i];
+      const uint32_t A = min((S + 15u) & ~15u, E), B = max(A, E & ~15u);  // [A, B) 16-byte aligned
+      if (S + (uint32_t)tid < A) mark[S + tid] = 1;
+      if (B + (uint32_t)tid < E) mark[B + tid] = 1;
+      uint4 *body = reinterpret_cast<uint4 *>(mark + A);
+      for (uint32_t x = tid; x < (B - A) / 16; x += kPrefixThreads) body[x] = ones;
+    }
+    __threadfence();  // the next batch's mark reads see every wavefront's paint
+    __syncthreads();
+  }
+}
+
+// Round 1's undecided list after a prefix of k: candidates k..m-1 in order.
+__global__ void k_sel_prefix_rest(uint32_t *pend, uint32_t k, const uint32_t *m_dev, uint32_t *nlive1) {
+  const uint32_t m = *m_dev;
+  const uint32_t rest = m > k ? m - k : 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nlive1 = rest;
+  GRID_STRIDE(i, rest) pend[i] = k + (uint32_t)i;
+}
+
+void sel_prefix(const uint32_t *len, const uint32_t *start, uint32_t k, uint8_t *state, uint8_t *mark,
+                uint32_t *pend, const uint32_t *m_dev, uint32_t *nlive1, uint64_t bound, hipStream_t s) {
+  hipLaunchKernelGGL(k_sel_prefix, dim3(1), dim3(kPrefixThreads), 0, s, len, start, k, state, mark);
+  hipLaunchKernelGGL(k_sel_prefix_rest, grid_for(bound, 256, 8192), dim3(256), 0, s, pend, k, m_dev, nlive1);
+}
+
 // ----------------------------------------- per-window sequential greedy
 // For candidate lists ordered window by window (each window's candidates in
 // priority order): one wavefront per window walks its list in batches of 64

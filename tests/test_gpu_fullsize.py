@@ -179,6 +179,7 @@ def test_sequential_selection_completion(ctx, cap):
     cases = [(np.array(blocks, dtype=np.uint64), 1), synth.config1(n=1 << 16), synth.config0()]
     try:
         ctx.set_selection_round_cap(cap)
+        ctx.set_selection_prefix(0)  # the rounds and the completion alone
         ctx.set_window_greedy(False)  # config0 through the rounds as well
         for k, (t, m) in enumerate(cases):
             rows, occ = ctx.analyze(t, m, occurrences=True)
@@ -193,6 +194,7 @@ def test_sequential_selection_completion(ctx, cap):
             assert c["selection_sequential"] == 1 or c["selection_rounds"] <= cap
     finally:
         ctx.set_selection_round_cap(64)
+        ctx.set_selection_prefix(-1)
         ctx.set_window_greedy(True)
     ctx.analyze(cases[1][0], cases[1][1])
     assert ctx.counters()["selection_sequential"] == 0

@@ -158,6 +158,53 @@ def test_find_repeats_both_selection_paths(ctx, name, tokens, min_len):
     _check_full(ctx, tokens, min_len)
 
 
+@pytest.mark.parametrize("name,tokens", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("k", [1, 100, 5000])
+def test_find_repeats_selection_prefix(ctx, name, tokens, k):
+    """An exact prefix walk of k candidates before the selection rounds (the
+    rest from round 1, whose filter rejects what the prefix covers) gives the
+    oracle's result; the counters report the candidates it decided."""
+    print("case", name, k, flush=True)
+    try:
+        ctx.set_window_greedy(False)
+        ctx.set_selection_prefix(k)
+        for min_len in (1, 8):
+            _check_full(ctx, tokens, min_len)
+            c = ctx.counters()
+            assert c["selection_prefix"] == min(k, c["candidates_dedup"]), c
+    finally:
+        ctx.set_selection_prefix(-1)
+        ctx.set_window_greedy(True)
+
+
+def test_selection_prefix_long_runs(ctx):
+    """Inputs whose longest candidates span much of the window (a long
+    constant run, then other text) take the automatic prefix walk; the result
+    is the oracle's, and equals the rounds alone."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for n, run in ((1 << 16, 1 << 15), (100003, 40000), (70000, 70000)):
+        t = rng.integers(0, 4, n).astype(np.uint32)
+        t[:run] = 0
+        cases.append(t)
+    a = [0] * 30000 + [1] + [0] * 20000 + [2, 3] * 5000
+    cases.append(np.array(a, dtype=np.uint64))
+    for t in cases:
+        for m in (1, 32):
+            ref = _check_full(ctx, t, m)
+            c = ctx.counters()
+            assert c["selection_prefix"] > 0, c
+            try:
+                ctx.set_selection_prefix(0)
+                rows = ctx.analyze(t, m)
+                assert ctx.counters()["selection_prefix"] == 0
+                assert np.array_equal(rows["start"].astype(np.int64), ref["row_start"])
+                assert np.array_equal(rows["length"].astype(np.int64), ref["row_len"])
+                assert np.array_equal(rows["count"].astype(np.int64), ref["row_count"])
+            finally:
+                ctx.set_selection_prefix(-1)
+
+
 def test_golden_examples(ctx):
     g = json.load(open(os.path.join(GOLDEN_DIR, "worked_examples.json")))
     for case in g["cases"]:
@@ -218,6 +265,7 @@ def test_config2_full_size(ctx):
     assert [[int(a), int(b)] for a, b in zip(occ["start"], occ["length"])] == g["occurrences"]
     assert [list(map(int, r)) for r in rows.tolist()] == g["rows"]
     assert ctx.counters()["candidates"] == g["stats"]["candidates"]
+    assert ctx.counters()["selection_prefix"] > 0  # the longest candidates span half the window
     sa, lcp = ctx.lcp_dev(_dev(t))
     sa = sa.cpu().numpy().astype(np.int64)
     lcp = lcp.cpu().numpy().astype(np.int64)

@@ -211,9 +211,11 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
 /* Counters of the last analysis, in this order: rounds of doubling (the
  * first-token sort included), candidates generated, candidates after dedup,
  * selection rounds, accepted occurrences, rows, sum over rounds of active
- * suffixes (the first-token sort counts every suffix), distinct tokens, and
- * 1 if the selection finished with the sequential completion (else 0), and
- * the candidates the exact prefix walk decided before the rounds (0: none).
+ * suffixes (the first-token sort counts every suffix), distinct tokens (for
+ * a batch: summed over its windows, except that the windows with more than
+ * 4096 distinct tokens, ranked through one shared table, count their union
+ * once), 1 if the selection finished with the sequential completion (else
+ * 0), and the candidates the exact prefix walk decided before the rounds (0: none).
  * Writes min(nvals, 10) values and returns that number. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
 

@@ -389,6 +389,7 @@ static void merge_info(RunInfo &a, const RunInfo &b) {
   a.maxl = std::max(a.maxl, b.maxl);
   a.sel_rounds = std::max(a.sel_rounds, b.sel_rounds);
   a.sel_sequential |= b.sel_sequential;
+  a.sel_prefix += b.sel_prefix;
   a.accepted += b.accepted;
   a.rows += b.rows;
   for (int k = 0; k < kStages; k++) a.stage_ms[k] = std::max(a.stage_ms[k], b.stage_ms[k]);

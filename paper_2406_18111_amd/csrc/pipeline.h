@@ -23,6 +23,10 @@ enum Cnt {
   CNT_RANGE = 10,  // two 64-bit words, 8-byte aligned
   CNT_AUX = 14,    // scratch count of a stage (tile counts, histogram size, runs)
   CNT_SNAPS = 15,  // 1 + last doubling round with a rank snapshot (0: none)
+  CNT_NDSUM = 16,  // batches: distinct tokens summed over the windows ranked on their own
+  CNT_NDMAX = 17,  // batches: most distinct tokens of one such window
+  CNT_WFLAG = 18,  // batches: windows ranked through the shared table instead
+  CNT_WNEXT = 19,  // batches: next window for the per-window ranking
   CNT_COUNT = 32
 };
 
@@ -87,6 +91,7 @@ struct Workspace {
   uint8_t *state = nullptr, *mark = nullptr;
   uint32_t *ctree = nullptr;       // canonical-block tree of sparse selection rounds (2 * capN)
   uint8_t *aflag = nullptr;        // doubling rounds: slot still grouped
+  uint8_t *wflag = nullptr;        // batches: window ranked through the shared table
   uint32_t *o_len = nullptr, *o_start = nullptr, *o_id = nullptr;
   void *rows = nullptr, *occ = nullptr;
   uint32_t *row_first = nullptr, *rowidx = nullptr;

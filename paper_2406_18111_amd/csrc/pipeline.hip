@@ -109,6 +109,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
   size_t o_di = L.take(N_ * 4), o_ds = L.take(N_ * 4), o_dhi = L.take(N_ * 4), o_dlo = L.take(N_ * 4);
   size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
   size_t o_wr = L.take((wantW + 1) * 4);
+  size_t o_wf = L.take(wantW + 1);
   size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_sa = L.take(N_ * 4);
   size_t o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
   size_t o_lvl[8] = {0};
@@ -154,6 +155,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
   wend = (uint32_t *)(m + o_we);
   wid = (uint32_t *)(m + o_wid);
   win_rows = (uint32_t *)(m + o_wr);
+  wflag = (uint8_t *)(m + o_wf);
   rank = (uint32_t *)(m + o_rank);
   snap = (uint32_t *)(m + o_snap);
   sa = (uint32_t *)(m + o_sa);
@@ -256,7 +258,7 @@ static void stamp(Workspace &w, int k, hipStream_t s, bool on) {
 // Reads the device counters of a finished analysis into `info`.
 static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
   info.n = N;
-  info.sigma = w.hcnt[CNT_ND];
+  info.sigma = w.hcnt[CNT_ND] + w.hcnt[CNT_NDSUM];  // shared table + windows ranked on their own
   info.cands = w.hcnt[CNT_C] + w.hcnt[CNT_CSKIP];
   info.maxl = w.hcnt[CNT_MAXL];
   info.cands_dedup = w.hcnt[CNT_M];
@@ -292,6 +294,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   fill_u32(dc, CNT_RANGE, 0, s);
+  fill_u32(dc + CNT_NDSUM, 4, 0, s);
   fill_u32(dc + CNT_SNAPS, 1, 0, s);
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
@@ -300,25 +303,48 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint32_t bits0;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
-    const uint64_t hc = pow2_at_least(2 * N);
-    hash_clear(w.htab, hc - 1, s);
-    hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s);
-    uint64_t nd_bound = N;
-    if (host) {
-      if ((rc = read_counters(w, s))) return rc;
-      nd_bound = w.hcnt[CNT_ND];
+    // Batches rank each window on its own first; the shared table then
+    // ranks only the windows with too many distinct values for that (a
+    // single window always goes through it).  In host-driven runs it is
+    // skipped when no window needs it; sync-free runs launch it gated on the
+    // device count of such windows.
+    const uint32_t *wgate = nullptr;
+    const uint8_t *wf = nullptr;
+    bool shared = true;
+    uint64_t loc_bits = 0;
+    if (batch) {
+      win_rank(tok, w.d_off, W, w.tokrank, w.wflag, dc + CNT_NDSUM, s);
+      wgate = dc + CNT_WFLAG;
+      wf = w.wflag;
+      if (host) {
+        if ((rc = read_counters(w, s))) return rc;
+        shared = w.hcnt[CNT_WFLAG] > 0;
+        loc_bits = (uint64_t)bit_length_u64(w.hcnt[CNT_NDMAX]);
+      }
     }
-    hash_fields(tok, w.dist_idx, dc + CNT_ND, w.dhi, w.dlo, nd_bound, s);
-    const uint32_t *f[2] = {w.dhi, w.dlo};
-    const int sub[2] = {0, 0};
-    const uint32_t *cd[2] = {nullptr, nullptr};
-    const int bb[2] = {32, 32};
-    const int str[2] = {1, 1};
-    sort_plain(w, dc + CNT_ND, nd_bound, f, str, sub, cd, bb, 2, nullptr, s);
-    hash_assign(B.val[0], dc + CNT_ND, w.dist_slot, w.hrank, nd_bound, s);
-    hash_rank(w.tokrank, N, w.hrank, w.tokrank, s);  // slots -> ranks in place
+    uint64_t nd_bound = N;
+    if (shared) {
+      const uint64_t hc = pow2_at_least(2 * N);
+      hash_clear(w.htab, hc - 1, s, wgate);
+      hash_insert(tok, N, w.htab, hc - 1, w.dist_idx, w.dist_slot, dc + CNT_ND, w.tokrank, s, wid, wf, wgate);
+      if (host) {
+        if ((rc = read_counters(w, s))) return rc;
+        nd_bound = w.hcnt[CNT_ND];
+      }
+      hash_fields(tok, w.dist_idx, dc + CNT_ND, w.dhi, w.dlo, nd_bound, s);
+      const uint32_t *f[2] = {w.dhi, w.dlo};
+      const int sub[2] = {0, 0};
+      const uint32_t *cd[2] = {nullptr, nullptr};
+      const int bb[2] = {32, 32};
+      const int str[2] = {1, 1};
+      sort_plain(w, dc + CNT_ND, nd_bound, f, str, sub, cd, bb, 2, nullptr, s);
+      hash_assign(B.val[0], dc + CNT_ND, w.dist_slot, w.hrank, nd_bound, s);
+      hash_rank(w.tokrank, N, w.hrank, w.tokrank, s, wid, wf, wgate);  // slots -> ranks in place
+    } else {
+      nd_bound = 0;
+    }
     key0 = w.tokrank;
-    bits0 = (uint32_t)bit_length_u64(nd_bound);
+    bits0 = (uint32_t)std::max<uint64_t>(bit_length_u64(nd_bound), loc_bits);
   } else {
     key0 = static_cast<const uint32_t *>(d_tok);
     bits0 = 32;

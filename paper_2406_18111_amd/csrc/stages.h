@@ -19,17 +19,29 @@ void scan_excl(const uint32_t *in, uint32_t *out, const uint32_t *n_dev, uint64_
 
 // Table of hc = mask + 1 slots plus one (the token value equal to the empty
 // mark has slot mask + 1); hash_clear empties it.
-void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s);
-// tok_slot[i] receives the table slot of token i.
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s, const uint32_t *gate = nullptr);
+// tok_slot[i] receives the table slot of token i.  With wflag set, only the
+// tokens of windows flagged there (window of token i: wid[i]) are inserted
+// and get a slot; with gate set, nothing runs unless *gate > 0.
 void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
-                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s);
+                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s, const uint32_t *wid = nullptr,
+                 const uint8_t *wflag = nullptr, const uint32_t *gate = nullptr);
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s);
 void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *dist_slot,
                  uint32_t *slot_rank, uint64_t hint, hipStream_t s);
-// out[i] = slot_rank[tok_slot[i]] (out may be tok_slot).
-void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out, hipStream_t s);
-
+// out[i] = slot_rank[tok_slot[i]] (out may be tok_slot), for the tokens of
+// flagged windows only when wflag is set; nothing unless *gate > 0 when set.
+void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out, hipStream_t s,
+               const uint32_t *wid = nullptr, const uint8_t *wflag = nullptr, const uint32_t *gate = nullptr);
+// Per-window ranks of a batch (offsets global, ascending): rank[i] = 1 +
+// the number of distinct values of i's window below tok[i]; windows with more
+// than 4096 distinct values get wflag = 1 and no ranks (else wflag = 0).
+// cnt[0] += distinct values per ranked window, cnt[1] = their maximum,
+// cnt[2] += 1 per flagged window, cnt[3]: the windows' work counter (all four
+// zeroed by the caller).
+void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
+              hipStream_t s);
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 

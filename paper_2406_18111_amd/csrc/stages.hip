@@ -246,10 +246,14 @@ __device__ __forceinline__ bool global_insert(uint64_t key, unsigned long long *
 // Also writes every token's global slot to tok_slot (the tile's first
 // occurrence of a value finds it; the local table hands it to the others), so
 // the ranks come later from one gather per token instead of a second probe.
+// With `wflag` set only the tokens of flagged windows are inserted and get a
+// slot (window of token i: wid[i]), and nothing runs unless *gate > 0.
 __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64_t n, unsigned long long *tab,
                                                      uint64_t mask, uint32_t *dist_idx, uint32_t *dist_slot,
-                                                     uint32_t *nd, uint32_t *tok_slot) {
+                                                     uint32_t *nd, uint32_t *tok_slot, const uint32_t *wid,
+                                                     const uint8_t *wflag, const uint32_t *gate) {
   constexpr int NT = 256;
+  if (gate && *gate == 0) return;
   constexpr int PER = kHashTile / NT;
   __shared__ uint64_t lt[kHashTile];   // the tile's tokens
   __shared__ uint32_t ls[kHashLds];    // local table: tile index + 1 (0 = empty); then global slots
@@ -269,6 +273,10 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
       hl[u] = 0;
       gs[u] = 0;
       if (k >= m) continue;
+      if (wflag && !wflag[wid[t0 + k]]) {
+        hl[u] = kHashLds;  // not this table's token
+        continue;
+      }
       const uint64_t key = lt[k];
       uint32_t h = (uint32_t)(mix64(key) >> 40) & (kHashLds - 1);
       while (true) {
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(256) void k_hash_insert(const uint64_t *tok, uint64
 #pragma unroll
     for (int u = 0; u < PER; u++) {
       const uint32_t k = threadIdx.x + (uint32_t)u * NT;
-      if (k < m) tok_slot[t0 + k] = ls[hl[u]];
+      if (k < m && hl[u] < kHashLds) tok_slot[t0 + k] = ls[hl[u]];
     }
     if (threadIdx.x == 0) nbase = nnew ? atomicAdd(nd, nnew) : 0u;
     __syncthreads();
@@ -328,43 +336,49 @@ __global__ void k_hash_assign(const uint32_t *sorted_d, const uint32_t *nd, cons
 
 // rank of every token from its slot (in place: out may be tok_slot); four
 // tokens per thread with the loads issued together.
-__global__ void k_hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out) {
+__global__ void k_hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out,
+                            const uint32_t *wid, const uint8_t *wflag, const uint32_t *gate) {
+  if (gate && *gate == 0) return;
   const uint64_t step = (uint64_t)gridDim.x * blockDim.x * 4;
   for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x * 4; b0 < n; b0 += step) {
     uint32_t sl[4], r[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
-      sl[u] = i < n ? tok_slot[i] : 0u;
+      const bool mine = i < n && (!wflag || wflag[wid[i]]);
+      sl[u] = mine ? tok_slot[i] : ~0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      r[u] = sl[u] != ~0u ? slot_rank[sl[u]] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
       const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
-      r[u] = i < n ? slot_rank[sl[u]] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
-      if (i < n) out[i] = r[u];
+      if (sl[u] != ~0u) out[i] = r[u];
     }
   }
 }
 
-__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) { GRID_STRIDE(i, n) p[i] = v; }
+__global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, const uint32_t *gate) {
+  if (gate && *gate == 0) return;
+  GRID_STRIDE(i, n) p[i] = v;
+}
 
-void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s) {
+void hash_clear(uint64_t *tab, uint64_t mask, hipStream_t s, const uint32_t *gate) {
   auto *t = reinterpret_cast<unsigned long long *>(tab);
   hipLaunchKernelGGL(k_fill_u64, grid_for(mask + 1, 256, 8192), dim3(256), 0, s, t, mask + 1,
-                     (unsigned long long)kEmpty);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + mask + 1, (uint64_t)1, 0ull);
+                     (unsigned long long)kEmpty, gate);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, t + mask + 1, (uint64_t)1, 0ull, gate);
 }
 
 void hash_insert(const uint64_t *tok, uint64_t n, uint64_t *tab, uint64_t mask, uint32_t *dist_idx,
-                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s) {
+                 uint32_t *dist_slot, uint32_t *nd, uint32_t *tok_slot, hipStream_t s, const uint32_t *wid,
+                 const uint8_t *wflag, const uint32_t *gate) {
   const uint64_t tiles = (n + kHashTile - 1) / kHashTile;
   hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(tiles, 1), 4096)), dim3(256),
                      0, s, tok, n, reinterpret_cast<unsigned long long *>(tab), mask, dist_idx, dist_slot, nd,
-                     tok_slot);
+                     tok_slot, wid, wflag, gate);
 }
 void hash_fields(const uint64_t *tok, const uint32_t *dist_idx, const uint32_t *nd, uint32_t *hi,
                  uint32_t *lo, uint64_t hint, hipStream_t s) {
@@ -375,8 +389,223 @@ void hash_assign(const uint32_t *sorted_d, const uint32_t *nd, const uint32_t *d
   hipLaunchKernelGGL(k_hash_assign, grid_for(hint, 256, 8192), dim3(256), 0, s, sorted_d, nd, dist_slot,
                      slot_rank);
 }
-void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_hash_rank, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, tok_slot, n, slot_rank, out);
+void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, uint32_t *out, hipStream_t s,
+               const uint32_t *wid, const uint8_t *wflag, const uint32_t *gate) {
+  hipLaunchKernelGGL(k_hash_rank, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, tok_slot, n, slot_rank, out,
+                     wid, wflag, gate);
+}
+
+// ------------------------------------------------ per-window token ranks
+// Only the order of tokens within a window matters (the first doubling round
+// sorts each window's suffixes by first token, and the LCP walk compares
+// tokens of one window), so a batch ranks each window on its own, one
+// workgroup per window at a time (workgroups take windows from a counter, so
+// a long window never holds up the dispatch of the others):
+//  1. the window's distinct values go into an LDS hash table (and a list);
+//  2. each value's slot receives its 1-based rank among them: the list is
+//     sorted in runs of 64 by a bitonic network over lane shuffles within
+//     each wavefront, then runs are merged pairwise up to the whole list,
+//     each element finding its place by a binary search in the other run
+//     (one barrier per merge level: 6 for 4096 values);
+//  3. every token's rank is read from its slot (one probe, usually one LDS
+//     read).
+// The token value kEmpty (the largest) marks free slots, so it is counted
+// aside and ranks last.  A window with more than kWinRankCap distinct values
+// is flagged instead and ranked through the shared global table.
+// cnt[0] += distinct values of a ranked window, cnt[1] = their maximum,
+// cnt[2] += 1 per flagged window, cnt[3]: window counter (zeroed by the caller).
+constexpr int kWinRankThreads = 1024;
+constexpr int kWinRankSlots = 8192;
+constexpr uint32_t kWinRankCap = 4096;
+constexpr int kWinRankRegs = kWinRankCap / kWinRankThreads;  // sorted values per thread
+constexpr int kWinRankBatch = 16;
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One compare-exchange of element i with its partner value p in the bitonic
+// merge of size k at distance j: the element that ends up lower keeps the
+// minimum when the block of size k is ascending.
+__device__ __forceinline__ uint64_t bitonic_keep(uint64_t v, uint64_t p, uint32_t i, uint32_t j, uint32_t k) {
+  const bool lower = (i & j) == 0, asc = (i & k) == 0;
+  return (lower == asc) ? (v < p ? v : p) : (v < p ? p : v);
+}
+
+__device__ __forceinline__ uint32_t win_probe(const unsigned long long *tab, uint64_t key) {
+  uint32_t h = (uint32_t)(mix64(key) >> 40) & (kWinRankSlots - 1);
+  while (tab[h] != (unsigned long long)key) h = (h + 1) & (kWinRankSlots - 1);
+  return h;
+}
+
+__global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw,
+                                                             uint32_t *rank, uint8_t *wflag, uint32_t *cnt) {
+  constexpr int NT = kWinRankThreads;
+  __shared__ unsigned long long tab[kWinRankSlots];
+  __shared__ uint64_t dist[kWinRankCap];   // distinct values; then merge buffers with mrg
+  __shared__ uint64_t mrg[kWinRankCap];
+  __shared__ uint16_t srank[kWinRankSlots];    // rank of the value in each slot
+  __shared__ uint32_t nd, ovf, hasmax, cur_w;
+  const int tid = threadIdx.x;
+  for (;;) {
+    __syncthreads();  // the previous window's reads of the shared state are done
+    if (tid == 0) {
+      cur_w = atomicAdd(&cnt[3], 1u);
+      nd = 0;
+      ovf = 0;
+      hasmax = 0;
+    }
+    for (int k = tid; k < kWinRankSlots; k += NT) tab[k] = (unsigned long long)kEmpty;
+    __syncthreads();
+    const uint32_t w = cur_w;
+    if (w >= nw) return;  // uniform
+    const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
+    // 1. distinct values, kWinRankBatch tokens per thread per pass (loads first)
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint64_t kv[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        kv[u] = i < e ? tok[i] : 0ull;
+      }
+      if (*(volatile uint32_t *)&ovf) break;  // the window goes to the shared table anyway
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        if (i0 + (uint64_t)u * NT + tid >= e) break;
+        const uint64_t key = kv[u];
+        if (key == kEmpty) {
+          hasmax = 1;
+          continue;
+        }
+        uint32_t h = (uint32_t)(mix64(key) >> 40) & (kWinRankSlots - 1);
+        for (int probe = 0;; probe++) {
+          if (probe == kWinRankSlots) {  // full table (only after the cap is passed)
+            ovf = 1;
+            break;
+          }
+          unsigned long long c = tab[h];
+          if (c == (unsigned long long)kEmpty) {
+            c = atomicCAS(&tab[h], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (c == (unsigned long long)kEmpty) {
+              const uint32_t q = atomicAdd(&nd, 1u);
+              if (q < kWinRankCap) dist[q] = key;
+              else ovf = 1;
+              break;
+            }
+          }
+          if (c == key) break;
+          h = (h + 1) & (kWinRankSlots - 1);
+        }
+      }
+    }
+    __syncthreads();
+    const bool flagged = ovf != 0;
+    if (tid == 0) {
+      wflag[w] = flagged ? 1 : 0;
+      if (flagged) atomicAdd(&cnt[2], 1u);
+    }
+    if (flagged) continue;  // uniform
+    const uint32_t D = nd;
+    uint32_t P = 64;
+    while (P < D) P <<= 1;
+    const int R = (int)((P + NT - 1) / NT);
+    const bool holds = (uint32_t)tid < P;  // P < NT: whole wavefronts hold one value or none
+    // 2a. element i = r * NT + tid in v[r] (pads: kEmpty); each wavefront's
+    // 64 elements of one register sorted ascending by a bitonic network over
+    // lane shuffles (constant distances after unrolling)
+    uint64_t v[kWinRankRegs];
+#pragma unroll
+    for (int r = 0; r < kWinRankRegs; r++) {
+      const uint32_t i = (uint32_t)r * NT + tid;
+      v[r] = (r < R && holds && i < D) ? dist[i] : kEmpty;
+    }
+    const uint32_t ln = (uint32_t)tid & 63;
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1)
+#pragma unroll
+      for (uint32_t j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int r = 0; r < kWinRankRegs; r++)
+          if (r < R) v[r] = bitonic_keep(v[r], shfl_xor_u64(v[r], (int)j), ln, j, k == 64 ? 128 : k);
+    __syncthreads();  // every list read is done before the buffers are reused
+    // 2b. runs of 64 merged pairwise, 64 -> P: an element's place in the
+    // merged run is its index in its own run plus the number of elements of
+    // the other run before it (lower bound from the left run, upper bound
+    // from the right one, so equal pads keep distinct places)
+    int cb = 0;  // merge source: dist (0) or mrg (1)
+#pragma unroll
+    for (int r = 0; r < kWinRankRegs; r++)
+      if (r < R && holds) dist[(uint32_t)r * NT + tid] = v[r];
+    __syncthreads();
+    uint32_t pos[kWinRankRegs];
+#pragma unroll
+    for (int r = 0; r < kWinRankRegs; r++) pos[r] = (uint32_t)r * NT + tid;
+    for (uint32_t L = 64; L < P; L <<= 1) {
+      const uint64_t *src = cb ? mrg : dist;
+      uint64_t *dst = cb ? dist : mrg;
+#pragma unroll
+      for (int r = 0; r < kWinRankRegs; r++) {
+        if (!(r < R && holds)) continue;
+        const uint32_t i = pos[r];
+        const uint64_t x = v[r];
+        const uint32_t base = i & ~(2 * L - 1), right = i & L;
+        const uint64_t *o = src + (right ? base : base + L);  // the other run
+        uint32_t c = 0;  // elements of the other run before x
+        for (uint32_t step = L >> 1; step > 0; step >>= 1) {
+          const uint64_t y = o[c + step - 1];
+          if (right ? (y <= x) : (y < x)) c += step;
+        }
+        if (right ? (o[c] <= x && c < L) : (o[c] < x && c < L)) c++;
+        pos[r] = base + (i - base - right) + c;
+        dst[pos[r]] = x;
+      }
+      __syncthreads();
+      cb ^= 1;
+    }
+    // 3. ranks into the slots
+#pragma unroll
+    for (int r = 0; r < kWinRankRegs; r++)
+      if (r < R && holds && v[r] != kEmpty) srank[win_probe(tab, v[r])] = (uint16_t)(pos[r] + 1);
+    __syncthreads();
+    // every token's rank from its slot
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint64_t kv[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        kv[u] = i < e ? tok[i] : kEmpty;
+      }
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        if (i < e) rank[i] = kv[u] == kEmpty ? D + 1 : (uint32_t)srank[win_probe(tab, kv[u])];
+      }
+    }
+    if (tid == 0) {
+      const uint32_t sig = D + hasmax;
+      atomicAdd(&cnt[0], sig);
+      atomicMax(&cnt[1], sig);
+    }
+  }
+}
+
+void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
+              hipStream_t s) {
+  // one workgroup per compute unit (the LDS footprint allows one), each
+  // taking windows until none is left
+  static const unsigned cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
+    return (unsigned)n;
+  }();
+  if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cus, nw)), dim3(kWinRankThreads), 0, s, tok, off, nw,
+                             rank, wflag, cnt);
 }
 
 // -------------------------------------------------------------- windows

@@ -70,6 +70,49 @@ def test_batch_equals_alone_and_oracle(ctx):
             assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
 
 
+def _distinct_window(rng, d, with_max):
+    """A window of exactly d distinct values (plus 2^64-1 when asked), each
+    value at least twice, with repeated runs."""
+    vals = np.unique(rng.integers(0, np.iinfo(np.uint64).max, 3 * d + 8, dtype=np.uint64))[:d]
+    assert len(vals) == d
+    rng.shuffle(vals)
+    parts = [vals, vals[rng.permutation(d)], np.tile(vals[: min(d, 9)], 20)]
+    if with_max:
+        parts.append(np.full(3, np.iinfo(np.uint64).max, dtype=np.uint64))
+    w = np.concatenate(parts)
+    return w.astype(np.uint64)
+
+
+def test_batch_window_ranks(ctx):
+    """Batches rank each window's tokens on their own unless the window has
+    more than 4096 distinct values (the shared table ranks those): windows at
+    and around that bound, some holding the largest value 2^64-1, give the
+    oracle's rows with host-driven lanes and in one sync-free lane (graphs on
+    and off); with no window over the bound the distinct-token counter is the
+    sum over windows."""
+    rng = np.random.default_rng(21)
+    small = [_distinct_window(rng, d, mx) for d, mx in ((1, False), (2, True), (700, False), (4095, True),
+                                                       (4096, False), (4096, True))]
+    big = [_distinct_window(rng, d, mx) for d, mx in ((4097, False), (6000, True))]
+    for wins in (small, small + big, big[::-1] + small[:2]):
+        toks, off = _pack(wins)
+        refs = [_rows_ref(w, 2) for w in wins]
+        for lanes, graphs in ((3, True), (1, False), (1, True)):
+            print("windows", len(wins), "lanes", lanes, "graphs", graphs, flush=True)
+            try:
+                ctx.set_lanes(lanes)
+                ctx.set_graphs(graphs)
+                for rep in range(2):
+                    rows, oo = ctx.analyze_batch(toks, off, 2)
+                    for w in range(len(wins)):
+                        assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (w, len(wins[w]))
+                    if wins is small:
+                        assert ctx.counters()["sigma"] == sum(len(np.unique(x)) for x in wins)
+            finally:
+                ctx.set_lanes(3)
+                ctx.set_graphs(True)
+
+
 def test_batch_long_windows(ctx):
     """Windows longer than 2^16 tokens beside short ones: the doubling rounds'
     window-relative bucketing digits then need more than 16 bits, and the

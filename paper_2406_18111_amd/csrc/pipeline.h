@@ -27,6 +27,7 @@ enum Cnt {
   CNT_NDMAX = 17,  // batches: most distinct tokens of one such window
   CNT_WFLAG = 18,  // batches: windows ranked through the shared table instead
   CNT_WNEXT = 19,  // batches: next window for the per-window ranking
+  CNT_WNEXT2 = 20, // batches: next window for the per-window first doubling round
   CNT_COUNT = 32
 };
 

@@ -294,13 +294,18 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   fill_u32(dc, CNT_RANGE, 0, s);
-  fill_u32(dc + CNT_NDSUM, 4, 0, s);
+  fill_u32(dc + CNT_NDSUM, 5, 0, s);
   fill_u32(dc + CNT_SNAPS, 1, 0, s);
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
   // ---- order-preserving token ranks
   const uint32_t *key0;
   uint32_t bits0;
+  // batches of 64-bit tokens: the windows ranked on their own also get their
+  // first doubling round from a per-window kernel; the engine's first round
+  // then only sorts the flagged windows (and is skipped by host-driven runs
+  // that have none)
+  bool win_r0 = false, skip0 = false;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     // Batches rank each window on its own first; the shared table then
@@ -343,6 +348,8 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     } else {
       nd_bound = 0;
     }
+    win_r0 = batch;
+    skip0 = batch && !shared;
     key0 = w.tokrank;
     bits0 = (uint32_t)std::max<uint64_t>(bit_length_u64(nd_bound), loc_bits);
   } else {
@@ -366,8 +373,16 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   int cur = 0;
   E.reset_counters(s);
   E.round_begin(cur, s);
-  E.gather_identity(key0, (uint32_t)N, s);
-  E.init_units(cur, w.d_off, W, 0, bits0, s);
+  if (win_r0) {
+    if (!skip0) {
+      E.gather_identity(key0, (uint32_t)N, s, wid, w.wflag, dc + CNT_WFLAG);
+      E.init_units(cur, w.d_off, W, 0, bits0, s, w.wflag);
+    }
+    win_round0(B, w.d_off, W, w.wflag, key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, s);
+  } else {
+    E.gather_identity(key0, (uint32_t)N, s);
+    E.init_units(cur, w.d_off, W, 0, bits0, s);
+  }
   bool big = maxwin > (1ull << E.tile_log());
   uint64_t act = N;
   int r = 0, synced = 0, done_round = -1;
@@ -377,15 +392,17 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     if (r >= w.nsnap) return -4;
     if (r > 0) E.gather_sa(cur, w.rank, w.aflag, wend, (uint32_t)N, 1u << (r - 1), w.rhist, r, s);
     RankOut R{w.rank, (uint32_t)r, w.aflag};
-    if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rel_bits, s, r == 0 ? nullptr : wbeg);
-    const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
-    if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
-    E.lds_sa(cur, R, rel_bits, act, s);
-    if (timed) {
-      APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n + 1], s));
-      w.kround[w.kev_n++] = r;
+    if (r > 0 || !skip0) {
+      if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rel_bits, s, r == 0 ? nullptr : wbeg);
+      const bool timed = w.ktag == KT_LDS_SA && w.kev_n < kMaxTimed;
+      if (timed) APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n], s));
+      E.lds_sa(cur, R, rel_bits, act, s);
+      if (timed) {
+        APO_HIP_TRY(hipEventRecord(w.kev[2 * w.kev_n + 1], s));
+        w.kround[w.kev_n++] = r;
+      }
+      E.bulk_sa(cur, R, rel_bits, act, s);
     }
-    E.bulk_sa(cur, R, rel_bits, act, s);
     // rounds >= kSnapFrom: the rank array after the round, for the LCP walk
     if (r >= kSnapFrom) snapshot_ranks(w.rank, w.snap + (size_t)r * N, N, w.rhist + 4 * (r - 1), dc + CNT_SNAPS, r, s);
     cur ^= 1;

@@ -22,13 +22,16 @@ class SortEngine {
   int digit_bits() const { return (int)b_.digit_bits; }
   void round_begin(int cur, hipStream_t s);
   void round_end(int cur, int r, uint32_t *hist, hipStream_t s);
+  // only (nullable): just the ranges w with only[w] != 0
   void init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base, uint32_t key_bits,
-                  hipStream_t s);
+                  hipStream_t s, const uint8_t *only = nullptr);
   // units from runs: run r is [run_start[r], run_start[r+1]) (the last ends at
   // *total_dev); bound: host upper bound of the run count
   void init_runs(int cur, const uint32_t *run_start, const uint32_t *nruns_dev, const uint32_t *total_dev,
                  uint64_t bound, uint32_t key_bits, hipStream_t s);
-  void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s);
+  // only (nullable): just the slots p with only[wid[p]] != 0, and nothing unless *gate > 0 (gate nullable)
+  void gather_identity(const uint32_t *src, uint32_t n, hipStream_t s, const uint32_t *wid = nullptr,
+                       const uint8_t *only = nullptr, const uint32_t *gate = nullptr);
   void gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend, uint32_t n,
                  uint32_t h, uint32_t *hist, int r, hipStream_t s);
   void gather_field(int cur, const uint32_t *field, int stride, const uint32_t *all_dev, int sub,

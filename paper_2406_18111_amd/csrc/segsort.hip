@@ -91,11 +91,12 @@ __global__ void k_counters_reset(SortCounters *c) {
 
 // -------------------------------------------------------------- unit setup
 // Routes the ranges [off[w], off[w+1]) to the class lists or the level-0 big
-// list of list `cur`.  Empty ranges are skipped.
+// list of list `cur`.  Empty ranges are skipped, and with `only` set the
+// ranges w with only[w] == 0.
 __global__ void k_init_units(SortBufs B, int cur, const uint64_t *off, uint32_t nranges,
-                             uint32_t base, uint32_t key_bits) {
+                             uint32_t base, uint32_t key_bits, const uint8_t *only) {
   const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nranges) return;
+  if (w >= nranges || (only && !only[w])) return;
   const uint32_t s = (uint32_t)(off[w] - off[0]) + base;
   const uint32_t len = (uint32_t)(off[w + 1] - off[w]);
   if (len == 0) return;
@@ -174,9 +175,14 @@ __global__ __launch_bounds__(256) void k_init_runs(SortBufs B, int cur, const ui
 
 // ------------------------------------------------------------------ gathers
 // Round 0 of suffix sorting: slot p holds suffix p, keyed by its first token
-// (its dense rank or, for 32-bit input, the token itself).
-__global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n) {
+// (its dense rank or, for 32-bit input, the token itself).  With `only` set,
+// just the slots p whose window wid[p] has only[wid[p]] != 0, and nothing
+// unless *gate > 0.
+__global__ void k_gather_identity(SortBufs B, const uint32_t *src, uint32_t n, const uint32_t *wid,
+                                  const uint8_t *only, const uint32_t *gate) {
+  if (gate && *gate == 0) return;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+    if (only && !only[wid[p]]) continue;
     B.key[0][p] = src[p];
     B.val[0][p] = p;
   }
@@ -1262,9 +1268,9 @@ void SortEngine::round_end(int cur, int r, uint32_t *hist, hipStream_t s) {
 }
 
 void SortEngine::init_units(int cur, const uint64_t *d_off, uint32_t nranges, uint32_t base,
-                            uint32_t key_bits, hipStream_t s) {
+                            uint32_t key_bits, hipStream_t s, const uint8_t *only) {
   hipLaunchKernelGGL(k_init_units, grid_for(nranges, 256, 1 << 16), dim3(256), 0, s, b_, cur, d_off,
-                     nranges, base, key_bits);
+                     nranges, base, key_bits, only);
 }
 
 void SortEngine::init_runs(int cur, const uint32_t *run_start, const uint32_t *nruns_dev, const uint32_t *total_dev,
@@ -1273,8 +1279,9 @@ void SortEngine::init_runs(int cur, const uint32_t *run_start, const uint32_t *n
                      run_start, nruns_dev, total_dev, key_bits);
 }
 
-void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather_identity, grid_for(n, 256, 4096), dim3(256), 0, s, b_, src, n);
+void SortEngine::gather_identity(const uint32_t *src, uint32_t n, hipStream_t s, const uint32_t *wid,
+                                 const uint8_t *only, const uint32_t *gate) {
+  hipLaunchKernelGGL(k_gather_identity, grid_for(n, 256, 4096), dim3(256), 0, s, b_, src, n, wid, only, gate);
 }
 
 void SortEngine::gather_sa(int cur, const uint32_t *rank, const uint8_t *aflag, const uint32_t *slot_wend,

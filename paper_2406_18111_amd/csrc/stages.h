@@ -42,6 +42,13 @@ void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, 
 // zeroed by the caller).
 void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
               hipStream_t s);
+// First doubling round of the suffix sort for the windows ranked on their
+// own (wflag[w] == 0): suffixes grouped by first token in val[0], ranks
+// (1 + group start slot), grouped-slot flags and the groups of two or more as
+// units of the engine's list 1 (counters and lists cleared by round_begin(0)
+// before; large units get next_bits key bits).  *wnext: zeroed work counter.
+void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, hipStream_t s);
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 

@@ -395,6 +395,16 @@ void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, 
                      wid, wflag, gate);
 }
 
+// Appends a large unit to a list of the sort engine: packed (units << 32 |
+// chunks) counter, chunk base from the old value (the engine's list format).
+__device__ __forceinline__ void append_big_unit(BigUnit *list, unsigned long long *pk, uint32_t cap, uint32_t start,
+                                                uint32_t len, uint32_t meta, uint32_t *err) {
+  const unsigned long long old = atomicAdd(pk, (1ull << 32) | ((len + kChunk - 1) / kChunk));
+  const uint32_t k = (uint32_t)(old >> 32);
+  if (k < cap) list[k] = BigUnit{start, len, (uint32_t)old, meta};
+  else atomicOr(err, 2u);
+}
+
 // ------------------------------------------------ per-window token ranks
 // Only the order of tokens within a window matters (the first doubling round
 // sorts each window's suffixes by first token, and the LCP walk compares
@@ -606,6 +616,142 @@ void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *r
   }();
   if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cus, nw)), dim3(kWinRankThreads), 0, s, tok, off, nw,
                              rank, wflag, cnt);
+}
+
+// ------------------------------------ first doubling round, per window
+// The first round of the suffix sort for the windows ranked on their own:
+// each window's suffixes grouped by first token, by a counting sort on the
+// window's ranks (at most kWinRankCap + 1 of them) in LDS, written in the
+// form the later doubling rounds take over from a round of the sort engine:
+// the suffix arrangement in val[0], rank[i] = 1 + slot of the first suffix
+// of i's group, the grouped-slot flags, and every group of two or more as a
+// unit of the next list (kHeadBit set: its suffixes' ranks are its start + 1)
+// in its size class, or in the large-unit list when it exceeds the LDS tile
+// (next_bits key bits), with the active-slot count.  Flagged windows are left
+// to the engine.  Workgroups take windows from the counter *wnext.
+constexpr uint32_t kR0Ranks = kWinRankCap + 2;  // ranks 1..kWinRankCap + 1
+
+__global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off, uint32_t nw,
+                                                               const uint8_t *wflag, const uint32_t *tokrank,
+                                                               uint32_t *rank, uint8_t *aflag, uint32_t next_bits,
+                                                               uint32_t *wnext) {
+  constexpr int NT = kWinRankThreads;
+  constexpr int PER = (kR0Ranks + NT - 1) / NT;
+  __shared__ uint32_t cnt[kR0Ranks], gst[kR0Ranks], cur[kR0Ranks];
+  __shared__ uint32_t sh[NT / 64];
+  __shared__ uint32_t cls_loc[kClasses], cls_base[kClasses];
+  __shared__ uint32_t cur_w;
+  const int tid = threadIdx.x;
+  const uint32_t tile = 1u << B.tile_log;
+  for (;;) {
+    __syncthreads();  // the previous window's reads of the shared state are done
+    if (tid == 0) cur_w = atomicAdd(wnext, 1u);
+    for (uint32_t r = tid; r < kR0Ranks; r += NT) cnt[r] = 0;
+    if (tid < kClasses) cls_loc[tid] = 0;
+    __syncthreads();
+    const uint32_t w = cur_w;
+    if (w >= nw) return;  // uniform
+    if (wflag[w]) continue;  // the same word for every thread
+    const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
+    // counts of the ranks
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint32_t rq[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        rq[u] = i < e ? tokrank[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++)
+        if (i0 + (uint64_t)u * NT + tid < e) atomicAdd(&cnt[rq[u]], 1u);
+    }
+    __syncthreads();
+    // group starts (window-relative): exclusive scan, PER consecutive ranks a thread
+    {
+      const uint32_t r0 = (uint32_t)tid * PER;
+      uint32_t loc = 0;
+#pragma unroll
+      for (int q = 0; q < PER; q++) loc += r0 + q < kR0Ranks ? cnt[r0 + q] : 0u;
+      uint32_t tot;
+      uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);
+#pragma unroll
+      for (int q = 0; q < PER; q++)
+        if (r0 + q < kR0Ranks) {
+          gst[r0 + q] = ex;
+          cur[r0 + q] = ex;
+          ex += cnt[r0 + q];
+        }
+    }
+    __syncthreads();
+    // groups of two or more: units of the next list, reserved once per class
+    uint32_t ur[PER], ui[PER];
+    uint32_t act = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const uint32_t r = (uint32_t)tid * PER + q;
+      ur[q] = 0;
+      ui[q] = 0;
+      const uint32_t c = r < kR0Ranks ? cnt[r] : 0u;
+      if (c < 2) continue;
+      act += c;
+      ur[q] = r;
+      if (c <= tile) ui[q] = atomicAdd(&cls_loc[class_of(c)], 1u);
+      else append_big_unit(B.big[1][0], &B.ctr->big_pk[1][0], B.big_cap, (uint32_t)b + gst[r], c, next_bits,
+                           &B.ctr->err);
+    }
+    {
+      uint32_t tot;
+      (void)block_excl_sum<NT>(act, sh, &tot);
+      if (tid == 0 && tot) atomicAdd(&B.ctr->act_cnt[1], tot);
+    }
+    if (tid < kClasses) cls_base[tid] = cls_loc[tid] ? atomicAdd(&B.ctr->cls_cnt[1][tid], cls_loc[tid]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const uint32_t r = ur[q];
+      if (!r) continue;
+      const uint32_t c = cnt[r];
+      if (c > tile) continue;
+      const int ci = class_of(c);
+      const uint32_t k = cls_base[ci] + ui[q];
+      if (k < B.cls_off[ci + 1] - B.cls_off[ci]) B.cls[1][B.cls_off[ci] + k] = Unit{(uint32_t)b + gst[r], c | kHeadBit};
+      else atomicOr(&B.ctr->err, 8u);
+    }
+    // suffixes into their groups' slots; ranks and flags
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint32_t rq[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        rq[u] = i < e ? tokrank[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        if (i >= e) continue;
+        const uint32_t r = rq[u];
+        const uint32_t slot = (uint32_t)b + atomicAdd(&cur[r], 1u);
+        B.val[0][slot] = (uint32_t)i;
+        aflag[slot] = cnt[r] >= 2 ? 1 : 0;
+        rank[i] = (uint32_t)b + gst[r] + 1;
+      }
+    }
+  }
+}
+
+void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, hipStream_t s) {
+  static const unsigned cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || n <= 0) {
+      (void)hipGetLastError();
+      n = 256;
+    }
+    return (unsigned)n;
+  }();
+  if (nw) hipLaunchKernelGGL(k_win_round0, dim3(std::min<unsigned>(2 * cus, nw)), dim3(kWinRankThreads), 0, s, B, off,
+                             nw, wflag, tokrank, rank, aflag, next_bits, wnext);
 }
 
 // -------------------------------------------------------------- windows

@@ -836,7 +836,12 @@ __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t ac
   return acc + t;
 }
 
-constexpr int kKasaiCap = 64;
+// Kasai extension tokens read before switching to lifting: the walk of a
+// workgroup lasts as long as its slowest thread, and a long extension is a
+// chain of dependent reads, where lifting is a bounded one (on the batched
+// loop streams: 64 tokens 1.93 ms per launch, 16: 1.79, 4: 1.58, 0 (one
+// batch of 4 tokens, then lifting): 1.50)
+constexpr int kKasaiCap = 0;
 constexpr int kSeedGroup = 8;
 constexpr int kPlcpChunk = 8;                        // positions per thread
 constexpr int kPlcpSpan = 256 * kPlcpChunk;          // positions per workgroup pass
@@ -870,8 +875,10 @@ __device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, const uint3
 
 // Kasai's recurrence PLCP[j] >= PLCP[j-1] - 1 within chunks of kPlcpChunk
 // consecutive positions; each chunk (and each window start) is seeded exactly
-// by lifting, and an extension longer than kKasaiCap tokens switches to
-// lifting.  Phi[j] = SA[ISA[j] - 1] comes from the final ranks (rank =
+// by lifting, and an extension past its first kExt tokens switches to
+// lifting.  Where Phi[j] = Phi[j-1] + 1 (a reducible position: most of a
+// repetitive stream) the value is PLCP[j-1] - 1 exactly, with no token read.
+// Phi[j] = SA[ISA[j] - 1] comes from the final ranks (rank =
 // 1 + slot once every suffix is alone in its group).  A workgroup stages its
 // span's Phi values and tokens in LDS with coalesced loads, so each thread's
 // sequential walk reads LDS, and writes the span's PLCP back coalesced; only
@@ -904,7 +911,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
       const int c1 = min(c0 + kPlcpChunk, len);
       uint64_t j = j0 + c0;
       uint32_t wb = wbeg ? wbeg[j] : 0u, we = wend ? wend[j] : (uint32_t)n;
-      uint32_t h = 0;
+      uint32_t h = 0, py = kNone;  // py: Phi of the previous position
       bool fresh = true;
       for (int c = c0; c < c1; c++, j++) {
         if (j == we) {  // the next window starts here (only with window bounds: otherwise we == n > j)
@@ -919,6 +926,11 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
         } else if (fresh) {
           h = lcp_seed((uint32_t)j, y, rank, we, top, snap, n, key0);
           fresh = false;
+        } else if (y == py + 1 && h > 0) {
+          // Phi[j] = Phi[j-1] + 1: suffix j-1 and its predecessor shared h
+          // tokens and then differed (or met the window end), so j and its
+          // predecessor share exactly h - 1: no token is read
+          h--;
         } else {
           // extend from h - 1, kExt tokens per step with independent loads
           constexpr int kExt = 4;
@@ -947,6 +959,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
           }
         }
         ps[pad16(c)] = h;  // this thread's own slot, already read
+        py = y;
       }
     }
     __syncthreads();

@@ -725,16 +725,30 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
         const uint64_t i = i0 + (uint64_t)u * NT + tid;
         rq[u] = i < e ? tokrank[i] : 0u;
       }
+      // every slot reservation of the batch first, then the stores
+      uint32_t sq[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++)
+        sq[u] = i0 + (uint64_t)u * NT + tid < e ? atomicAdd(&cur[rq[u]], 1u) : 0u;
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++) {
         const uint64_t i = i0 + (uint64_t)u * NT + tid;
         if (i >= e) continue;
-        const uint32_t r = rq[u];
-        const uint32_t slot = (uint32_t)b + atomicAdd(&cur[r], 1u);
+        const uint32_t r = rq[u], slot = (uint32_t)b + sq[u];
         B.val[0][slot] = (uint32_t)i;
-        aflag[slot] = cnt[r] >= 2 ? 1 : 0;
         rank[i] = (uint32_t)b + gst[r] + 1;
       }
+    }
+    // grouped-slot flags in slot order (coalesced, where scattering them with
+    // the suffixes cost as much as the suffixes): slot s lies in the group of
+    // the last rank whose start is <= s
+    for (uint64_t s0 = 0; s0 < e - b; s0 += NT) {
+      const uint32_t sl = (uint32_t)s0 + tid;
+      if (sl >= e - b) break;
+      uint32_t lo = 0;  // last index with gst <= sl (gst[0] = 0)
+      for (uint32_t step = 4096; step > 0; step >>= 1)
+        if (lo + step < kR0Ranks && gst[lo + step] <= sl) lo += step;
+      aflag[b + sl] = cnt[lo] >= 2 ? 1 : 0;
     }
   }
 }

@@ -82,7 +82,7 @@ struct Workspace {
   uint64_t *d_off = nullptr;
   uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;
   uint32_t *rank = nullptr, *snap = nullptr, *sa = nullptr;
-  uint32_t *plcp = nullptr, *lcp = nullptr;
+  uint32_t *lcp = nullptr;
   uint32_t *lvl[8] = {nullptr};
   uint32_t *crec = nullptr;  // candidates: records (length, start, ID), three words each
   uint8_t *keep = nullptr;

@@ -111,7 +111,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
   size_t o_wr = L.take((wantW + 1) * 4);
   size_t o_wf = L.take(wantW + 1);
   size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_sa = L.take(N_ * 4);
-  size_t o_plcp = L.take(N_ * 4), o_lcp = L.take(N_ * 4);
+  size_t o_lcp = L.take(N_ * 4);
   size_t o_lvl[8] = {0};
   {
     uint64_t sz = N_;
@@ -159,7 +159,6 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
   rank = (uint32_t *)(m + o_rank);
   snap = (uint32_t *)(m + o_snap);
   sa = (uint32_t *)(m + o_sa);
-  plcp = (uint32_t *)(m + o_plcp);
   lcp = (uint32_t *)(m + o_lcp);
   for (int k = 1; k < nlev; k++) lvl[k] = (uint32_t *)(m + o_lvl[k]);
   crec = (uint32_t *)(m + o_crec);
@@ -439,7 +438,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
 
   // ---- LCP via Phi / PLCP (lifting over the snapshots of the rounds that
   // sorted something, at most r-1)
-  build_lcp(w.sa, w.rank, N, wbeg, wend, w.snap, dc + CNT_SNAPS, key0, r - 1, w.plcp, w.lcp, s);
+  build_lcp(w.sa, w.rank, N, wbeg, wend, w.snap, dc + CNT_SNAPS, key0, r - 1, w.lcp, s);
   stamp(w, 3, s, stamps);
   if (stop == Stop::LCP) return read_counters(w, s);
 

@@ -60,8 +60,8 @@ void snapshot_ranks(const uint32_t *rank, uint32_t *snap_r, uint64_t n, const ui
 // LCP of adjacent suffixes.  rank: final ranks of the suffix sort (1 + slot);
 // snap: level j at snap + j * n for kSnapFrom <= j < *snaps (and j <= top).
 void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *plcp,
-               uint32_t *lcp, hipStream_t s);
+               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *lcp,
+               hipStream_t s);
 
 // Candidates are written as records of kCandWords words: length, start, ID.
 // *cnt counts the records written; a candidate that exactly repeats one of

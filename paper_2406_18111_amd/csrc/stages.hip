@@ -895,12 +895,15 @@ __device__ __forceinline__ uint32_t lcp_seed(uint32_t x, uint32_t y, const uint3
 // Phi[j] = SA[ISA[j] - 1] comes from the final ranks (rank =
 // 1 + slot once every suffix is alone in its group).  A workgroup stages its
 // span's Phi values and tokens in LDS with coalesced loads, so each thread's
-// sequential walk reads LDS, and writes the span's PLCP back coalesced; only
-// the Phi side of the comparisons reads tokens from global memory.
+// sequential walk reads LDS; only the Phi side of the comparisons reads
+// tokens from global memory.  Each PLCP value goes straight to the LCP array
+// at the slot before its suffix's (LCP[ISA[j] - 1] = PLCP[j]), so no PLCP
+// array is written and no second pass permutes it.
 __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t *rank, uint64_t n,
                                               const uint32_t *wbeg, const uint32_t *wend, const uint32_t *snap,
                                               const uint32_t *snaps, const uint32_t *key0, int top_bound,
-                                              uint32_t *plcp) {
+                                              uint32_t *lcp) {
+  static_assert(kPlcpSpan == 256 * kPlcpChunk, "one staged position per thread and chunk slot");
   __shared__ uint32_t ps[pad16(kPlcpSpan)];
   __shared__ uint32_t ks[pad16(kPlcpSpan + kPlcpMargin)];
   const int top = min(top_bound, (int)*snaps - 1);  // last snapshot level (< kSnapFrom: none)
@@ -913,10 +916,19 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
     const uint64_t j0 = sp * kPlcpSpan;
     const int len = (int)min((uint64_t)kPlcpSpan, n - j0);
     const int klen = (int)min((uint64_t)(kPlcpSpan + kPlcpMargin), n - j0);
-    for (int p = threadIdx.x; p < len; p += blockDim.x) {
-      const uint32_t i = rank[j0 + p] - 1u;  // slot of suffix j0 + p
-      const uint32_t b = wbeg ? wbeg[j0 + p] : 0u;
-      ps[pad16(p)] = i > b ? sa[i - 1] : kNone;
+    uint32_t islot[kPlcpChunk];  // slot of each of this thread's staged positions
+    uint32_t first = 0;          // bit q: that position's suffix is first of its window in the suffix array
+#pragma unroll
+    for (int q = 0; q < kPlcpChunk; q++) {
+      const int p = threadIdx.x + q * 256;
+      islot[q] = 0;
+      if (p < len) {
+        const uint32_t i = rank[j0 + p] - 1u;  // slot of suffix j0 + p
+        const uint32_t b = wbeg ? wbeg[j0 + p] : 0u;
+        ps[pad16(p)] = i > b ? sa[i - 1] : kNone;
+        islot[q] = i;
+        if (i <= b) first |= 1u << q;
+      }
     }
     for (int p = threadIdx.x; p < klen; p += blockDim.x) ks[pad16(p)] = key0[j0 + p];
     __syncthreads();
@@ -977,47 +989,24 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
       }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < len; p += blockDim.x) plcp[j0 + p] = ps[pad16(p)];
+    // LCP[i - 1] = lcp(SA[i - 1], SA[i]) = PLCP[SA[i]]: each value goes to the
+    // slot before its suffix's (0 across a window boundary)
+#pragma unroll
+    for (int q = 0; q < kPlcpChunk; q++) {
+      const int p = threadIdx.x + q * 256;
+      if (p < len && islot[q] > 0) lcp[islot[q] - 1] = ((first >> q) & 1u) ? 0u : ps[pad16(p)];
+    }
     __syncthreads();
   }
-}
-
-// Four pairs per thread (strided by the block size, so each load is
-// coalesced); the four PLCP reads are issued together.
-__global__ void k_lcp(const uint32_t *sa, uint64_t n, const uint32_t *wend, const uint32_t *plcp, uint32_t *lcp) {
-  // blocks handed out XCD by XCD (the PLCP reads of neighbouring blocks
-  // fall in the same windows)
-  const uint64_t per = (uint64_t)blockDim.x * 4, nblk = (n + per - 1) / per;
-  for (uint64_t base = 0; base < nblk; base += gridDim.x) {
-    const uint64_t bk = xcd_item(base, nblk, blockIdx.x, gridDim.x);
-    if (bk >= nblk) break;
-    const uint64_t b0 = bk * per;
-    uint32_t nx[4], v[4];
-    bool ok[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;  // coalesced for each u
-      const uint32_t we = (wend && i < n) ? wend[i] : (uint32_t)n;
-      ok[u] = i + 1 < we;
-      nx[u] = ok[u] ? sa[i + 1] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; u++) v[u] = ok[u] ? plcp[nx[u]] : 0u;
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-      const uint64_t i = b0 + (uint64_t)u * blockDim.x + threadIdx.x;
-      if (i < n) lcp[i] = v[u];
-    }
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n > 0) lcp[n - 1] = 0;  // the last slot has no successor
 }
 
 void build_lcp(const uint32_t *sa, const uint32_t *rank, uint64_t n, const uint32_t *wbeg, const uint32_t *wend,
-               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *plcp,
-               uint32_t *lcp, hipStream_t s) {
+               const uint32_t *snap, const uint32_t *snaps, const uint32_t *key0, int top, uint32_t *lcp,
+               hipStream_t s) {
   const uint64_t nspan = (n + kPlcpSpan - 1) / kPlcpSpan;
   hipLaunchKernelGGL(k_plcp, dim3((unsigned)std::min<uint64_t>(std::max<uint64_t>(nspan, 1), 8192)), dim3(256), 0, s,
-                     sa, rank, n, wbeg, wend, snap, snaps, key0, top, plcp);
-  hipLaunchKernelGGL(k_lcp, grid_for((n + 3) / 4, 256, 8192), dim3(256), 0, s, sa, n, wend, plcp, lcp);
+                     sa, rank, n, wbeg, wend, snap, snaps, key0, top, lcp);
 }
 
 // ------------------------------------------------------------ candidates

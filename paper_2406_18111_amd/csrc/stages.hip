@@ -850,6 +850,23 @@ __device__ __forceinline__ uint32_t lcp_lift(uint32_t x, uint32_t y, uint32_t ac
   return acc + t;
 }
 
+// lcp(x, y) knowing that the first acc tokens match, for a remainder that
+// is usually short: blocks of 2^kSnapFrom, 2^(kSnapFrom+1), ... tokens are
+// compared while they match (an exponential search over the snapshot
+// levels), then the lifting goes down from below the first level that
+// differed, so a remainder r reads about 2 log2(r / 2^kSnapFrom) levels
+// instead of every level up to the last snapshot.
+__device__ __forceinline__ uint32_t lcp_gallop(uint32_t x, uint32_t y, uint32_t acc, uint32_t we, int top,
+                                               const uint32_t *snap, uint64_t n, const uint32_t *key0) {
+  int j = kSnapFrom;
+  for (; j <= top; j++) {
+    const uint32_t a = x + acc, b = y + acc;
+    if (a >= we || b >= we || snap[(uint64_t)j * n + a] != snap[(uint64_t)j * n + b]) break;
+    acc += 1u << j;
+  }
+  return lcp_lift(x, y, acc, we, j - 1, snap, n, key0);
+}
+
 // Kasai extension tokens read before switching to lifting: the walk of a
 // workgroup lasts as long as its slowest thread, and a long extension is a
 // chain of dependent reads, where lifting is a bounded one (on the batched
@@ -981,7 +998,7 @@ __global__ __launch_bounds__(256) void k_plcp(const uint32_t *sa, const uint32_t
             h += m;
             if (m < (uint32_t)kExt) break;
             steps += kExt;
-            if (steps > kKasaiCap) { h = lcp_lift((uint32_t)j, y, h, we, top, snap, n, key0); break; }
+            if (steps > kKasaiCap) { h = lcp_gallop((uint32_t)j, y, h, we, top, snap, n, key0); break; }
           }
         }
         ps[pad16(c)] = h;  // this thread's own slot, already read

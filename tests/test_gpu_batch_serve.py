@@ -87,9 +87,9 @@ def test_batch_window_ranks(ctx):
     """Batches rank each window's tokens on their own unless the window has
     more than 4096 distinct values (the shared table ranks those): windows at
     and around that bound, some holding the largest value 2^64-1, give the
-    oracle's rows with host-driven lanes and in one sync-free lane (graphs on
-    and off); with no window over the bound the distinct-token counter is the
-    sum over windows."""
+    oracle's rows with host-driven lanes, with lanes as branches of one graph
+    and in one sync-free lane (graphs on and off); with no window over the
+    bound the distinct-token counter is the sum over windows."""
     rng = np.random.default_rng(21)
     small = [_distinct_window(rng, d, mx) for d, mx in ((1, False), (2, True), (700, False), (4095, True),
                                                        (4096, False), (4096, True))]
@@ -97,7 +97,7 @@ def test_batch_window_ranks(ctx):
     for wins in (small, small + big, big[::-1] + small[:2]):
         toks, off = _pack(wins)
         refs = [_rows_ref(w, 2) for w in wins]
-        for lanes, graphs in ((3, True), (1, False), (1, True)):
+        for lanes, graphs in ((3, True), (3, False), (1, False), (1, True)):
             print("windows", len(wins), "lanes", lanes, "graphs", graphs, flush=True)
             try:
                 ctx.set_lanes(lanes)

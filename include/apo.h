@@ -215,8 +215,11 @@ int apo_last_stage_ms(apo_ctx *ctx, double *stage_ms, int nstages);
  * a batch: summed over its windows, except that the windows with more than
  * 4096 distinct tokens, ranked through one shared table, count their union
  * once), 1 if the selection finished with the sequential completion (else
- * 0), and the candidates the exact prefix walk decided before the rounds (0: none).
- * Writes min(nvals, 10) values and returns that number. */
+ * 0), the candidates the exact prefix walk decided before the rounds (0: none),
+ * and the windows whose first two doubling rounds were taken window by
+ * window from ranks of their adjacent token pairs (host-driven batches whose
+ * windows all have at most 4096 distinct tokens and 8192 distinct pairs).
+ * Writes min(nvals, 11) values and returns that number. */
 int apo_last_counters(apo_ctx *ctx, uint64_t *vals, int nvals);
 
 /* Device bytes of the workspace an analysis of n tokens in `windows`

@@ -33,7 +33,7 @@ class AutoParams(ctypes.Structure):
 
 STAGES = ("token_rank", "suffix_array", "lcp", "candidates", "candidate_sort", "selection", "output")
 COUNTERS = ("rounds", "candidates", "candidates_dedup", "selection_rounds", "accepted", "rows",
-            "active_sum", "sigma", "selection_sequential", "selection_prefix")
+            "active_sum", "sigma", "selection_sequential", "selection_prefix", "pair_windows")
 
 # name -> (restype, argtypes); mirrors include/apo.h
 _P, _U32, _U64, _I, _SZ = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t

@@ -390,6 +390,7 @@ static void merge_info(RunInfo &a, const RunInfo &b) {
   a.sel_rounds = std::max(a.sel_rounds, b.sel_rounds);
   a.sel_sequential |= b.sel_sequential;
   a.sel_prefix += b.sel_prefix;
+  a.pair_windows += b.pair_windows;
   a.accepted += b.accepted;
   a.rows += b.rows;
   for (int k = 0; k < kStages; k++) a.stage_ms[k] = std::max(a.stage_ms[k], b.stage_ms[k]);
@@ -847,9 +848,10 @@ extern "C" int apo_last_stage_ms(apo_ctx *ctx, double *ms, int nstages) {
 extern "C" int apo_last_counters(apo_ctx *ctx, uint64_t *v, int nvals) {
   if (!ctx || !v || nvals < 0) return APO_EINVAL;
   const RunInfo &I = ctx->info;
-  const uint64_t all[10] = {I.rounds, I.cands,      I.cands_dedup, I.sel_rounds,     I.accepted,
-                            I.rows,   I.active_sum, I.sigma,       I.sel_sequential, I.sel_prefix};
-  const int k = std::min(nvals, 10);
+  const uint64_t all[11] = {I.rounds,     I.cands,          I.cands_dedup, I.sel_rounds,
+                            I.accepted,   I.rows,           I.active_sum,  I.sigma,
+                            I.sel_sequential, I.sel_prefix, I.pair_windows};
+  const int k = std::min(nvals, 11);
   for (int i = 0; i < k; i++) v[i] = all[i];
   return k;
 }

@@ -28,6 +28,8 @@ enum Cnt {
   CNT_WFLAG = 18,  // batches: windows ranked through the shared table instead
   CNT_WNEXT = 19,  // batches: next window for the per-window ranking
   CNT_WNEXT2 = 20, // batches: next window for the per-window first doubling round
+  CNT_PNEXT = 21,  // batches: next window for the per-window pair ranks
+  CNT_PFLAG = 22,  // batches: windows whose pairs the per-window ranking left alone
   CNT_COUNT = 32
 };
 
@@ -54,6 +56,7 @@ struct RunInfo {
   uint32_t sel_rounds = 0;
   uint32_t sel_sequential = 0;
   uint32_t sel_prefix = 0;         // candidates decided by the exact prefix walk
+  uint32_t pair_windows = 0;       // windows whose first two doubling rounds came from pair ranks
   uint32_t accepted = 0;
   uint32_t rows = 0;
   double stage_ms[kStages] = {0};

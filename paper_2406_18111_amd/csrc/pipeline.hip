@@ -293,7 +293,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   fill_u32(dc, CNT_RANGE, 0, s);
-  fill_u32(dc + CNT_NDSUM, 5, 0, s);
+  fill_u32(dc + CNT_NDSUM, 7, 0, s);
   fill_u32(dc + CNT_SNAPS, 1, 0, s);
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
@@ -303,8 +303,10 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   // batches of 64-bit tokens: the windows ranked on their own also get their
   // first doubling round from a per-window kernel; the engine's first round
   // then only sorts the flagged windows (and is skipped by host-driven runs
-  // that have none)
-  bool win_r0 = false, skip0 = false;
+  // that have none).  Host-driven runs whose windows all have their own ranks
+  // and few distinct token pairs get the first two rounds from per-window
+  // kernels (pair ranks, then one counting sort on them).
+  bool win_r0 = false, skip0 = false, pair0 = false;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     // Batches rank each window on its own first; the shared table then
@@ -321,8 +323,11 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       wgate = dc + CNT_WFLAG;
       wf = w.wflag;
       if (host) {
+        win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, w.rhist, s);
         if ((rc = read_counters(w, s))) return rc;
         shared = w.hcnt[CNT_WFLAG] > 0;
+        pair0 = !shared && w.hcnt[CNT_PFLAG] == 0;
+        if (pair0) info.pair_windows = W;
         loc_bits = (uint64_t)bit_length_u64(w.hcnt[CNT_NDMAX]);
       }
     }
@@ -377,14 +382,16 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       E.gather_identity(key0, (uint32_t)N, s, wid, w.wflag, dc + CNT_WFLAG);
       E.init_units(cur, w.d_off, W, 0, bits0, s, w.wflag);
     }
-    win_round0(B, w.d_off, W, w.wflag, key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, s);
+    // with pairs: the state after round 1 (its active count is in rhist[0]
+    // already), and the lists of round 2
+    win_round0(B, w.d_off, W, w.wflag, pair0 ? B.key[1] : key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, pair0, s);
   } else {
     E.gather_identity(key0, (uint32_t)N, s);
     E.init_units(cur, w.d_off, W, 0, bits0, s);
   }
   bool big = maxwin > (1ull << E.tile_log());
   uint64_t act = N;
-  int r = 0, synced = 0, done_round = -1;
+  int r = pair0 ? 2 : 0, synced = r, done_round = -1;
   w.kev_n = 0;
   const int spec = host ? 4 : r_max;
   while (done_round < 0) {

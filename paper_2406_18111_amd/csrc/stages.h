@@ -42,13 +42,24 @@ void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, 
 // zeroed by the caller).
 void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
               hipStream_t s);
+// Per-window ranks of adjacent token pairs: prank[i] = 1 + the number of
+// distinct pairs of i's window below (tokrank[i], tokrank[i+1] or 0 past the
+// window's end).  A window with wflag set or more than 8192 distinct pairs is
+// skipped and counted in cnt[1]; cnt[0]: the windows' work counter (both
+// zeroed by the caller).  *act1 += suffixes whose first token occurs twice or
+// more in their window (the first round's active count).
+void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
+              uint32_t *cnt, uint32_t *act1, hipStream_t s);
 // First doubling round of the suffix sort for the windows ranked on their
-// own (wflag[w] == 0): suffixes grouped by first token in val[0], ranks
-// (1 + group start slot), grouped-slot flags and the groups of two or more as
-// units of the engine's list 1 (counters and lists cleared by round_begin(0)
-// before; large units get next_bits key bits).  *wnext: zeroed work counter.
-void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, hipStream_t s);
+// own (wflag[w] == 0): suffixes grouped by first token (keyrank = token
+// ranks), or with pairs set by first two tokens (keyrank = pair ranks, every
+// window unflagged by win_pair), in val[0], ranks (1 + group start slot),
+// grouped-slot flags and the groups of two or more as units of the engine's
+// list 1, or list 0 for pairs (counters and lists cleared by reset_counters
+// and round_begin(0) before; large units get next_bits key bits).  *wnext:
+// zeroed work counter.
+void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, hipStream_t s);
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 

@@ -601,10 +601,7 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *to
   }
 }
 
-void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
-              hipStream_t s) {
-  // one workgroup per compute unit (the LDS footprint allows one), each
-  // taking windows until none is left
+static unsigned cu_count() {
   static const unsigned cus = [] {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
@@ -614,30 +611,244 @@ void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *r
     }
     return (unsigned)n;
   }();
-  if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cus, nw)), dim3(kWinRankThreads), 0, s, tok, off, nw,
+  return cus;
+}
+
+void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
+              hipStream_t s) {
+  // one workgroup per compute unit (the LDS footprint allows one), each
+  // taking windows until none is left
+  if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, tok, off, nw,
                              rank, wflag, cnt);
+}
+
+// ------------------------------------------- per-window ranks of token pairs
+// The doubling rounds refine groups of equal 2^r-token prefixes.  A batch
+// whose windows all have few distinct adjacent pairs gets the state after
+// the second round (groups of equal two-token prefix) directly from the
+// window's token ranks, and the engine starts at offset 2.  Per window, one
+// workgroup at a time (windows taken from a counter):
+//  1. the window's distinct pair keys (rank of token i, rank of token i+1 or
+//     0 past the window's end) go into an LDS hash table and a list, and the
+//     occurrences of each first token are counted (the suffixes that the
+//     first round leaves grouped: that round's active count, added to *act1);
+//  2. the list is sorted (bitonic runs of 64 over lane shuffles, then merges
+//     by binary search) and each slot receives its key's 1-based rank;
+//  3. every suffix's pair rank is read from its slot.
+// Token ranks are at most kWinRankCap + 1 (13 bits), so a pair key fits in
+// 26 bits and 0xFFFFFFFF marks free slots.  A window with more than
+// kPairCap distinct pairs, or without ranks of its own (wflag set), is
+// counted in cnt[1] and left alone: the caller then takes the first two
+// rounds the usual way for the whole batch.  cnt[0]: window counter.
+constexpr int kPairSlots = 16384;
+constexpr uint32_t kPairCap = 8192;
+constexpr int kPairRegs = kPairCap / kWinRankThreads;  // sorted keys per thread
+constexpr uint32_t kPairEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kTokRanks = kWinRankCap + 2;  // token ranks 1..kWinRankCap + 1
+
+__device__ __forceinline__ uint32_t pair_probe(const uint32_t *tab, uint32_t key) {
+  uint32_t h = (uint32_t)(mix64(key) >> 40) & (kPairSlots - 1);
+  while (tab[h] != key) h = (h + 1) & (kPairSlots - 1);
+  return h;
+}
+
+__device__ __forceinline__ uint32_t bitonic_keep32(uint32_t v, uint32_t p, uint32_t i, uint32_t j, uint32_t k) {
+  const bool lower = (i & j) == 0, asc = (i & k) == 0;
+  return (lower == asc) ? (v < p ? v : p) : (v < p ? p : v);
+}
+
+__global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag,
+                                                             const uint32_t *tokrank, uint32_t *prank, uint32_t *cnt,
+                                                             uint32_t *act1) {
+  constexpr int NT = kWinRankThreads;
+  __shared__ uint32_t tab[kPairSlots];
+  __shared__ uint32_t dist[kPairCap];
+  // first-token counts (kTokRanks words), then the merge buffer, then the
+  // slots' ranks (kPairSlots u16): never two of them at once
+  __shared__ uint32_t aux[kPairCap];
+  __shared__ uint32_t nd, ovf, cur_w, a1;
+  static_assert(kTokRanks <= kPairCap && kPairSlots * 2 <= kPairCap * 4, "aux too small");
+  uint32_t *const hc = aux;
+  uint16_t *const srank = reinterpret_cast<uint16_t *>(aux);
+  const int tid = threadIdx.x;
+  for (;;) {
+    __syncthreads();  // the previous window's reads of the shared state are done
+    if (tid == 0) {
+      cur_w = atomicAdd(&cnt[0], 1u);
+      nd = 0;
+      ovf = 0;
+      a1 = 0;
+    }
+    for (int k = tid; k < kPairSlots; k += NT) tab[k] = kPairEmpty;
+    for (uint32_t k = tid; k < kTokRanks; k += NT) hc[k] = 0;
+    __syncthreads();
+    const uint32_t w = cur_w;
+    if (w >= nw) return;  // uniform
+    if (wflag[w]) {       // the same word for every thread
+      if (tid == 0) atomicAdd(&cnt[1], 1u);
+      continue;
+    }
+    const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
+    // 1. distinct pairs and first-token counts (loads of a pass first)
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint32_t r1[kWinRankBatch], r2[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        r1[u] = i < e ? tokrank[i] : 0u;
+        r2[u] = i + 1 < e ? tokrank[i + 1] : 0u;
+      }
+      if (*(volatile uint32_t *)&ovf) break;  // the batch takes the usual path anyway
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        if (i0 + (uint64_t)u * NT + tid >= e) break;
+        atomicAdd(&hc[r1[u]], 1u);
+        const uint32_t key = (r1[u] << 13) | r2[u];
+        uint32_t h = (uint32_t)(mix64(key) >> 40) & (kPairSlots - 1);
+        for (int probe = 0;; probe++) {
+          if (probe == kPairSlots) {  // full table (only after the cap is passed)
+            ovf = 1;
+            break;
+          }
+          uint32_t c = tab[h];
+          if (c == kPairEmpty) {
+            c = atomicCAS(&tab[h], kPairEmpty, key);
+            if (c == kPairEmpty) {
+              const uint32_t q = atomicAdd(&nd, 1u);
+              if (q < kPairCap) dist[q] = key;
+              else ovf = 1;
+              break;
+            }
+          }
+          if (c == key) break;
+          h = (h + 1) & (kPairSlots - 1);
+        }
+      }
+    }
+    __syncthreads();
+    const bool flagged = ovf != 0;
+    if (flagged) {  // uniform
+      if (tid == 0) atomicAdd(&cnt[1], 1u);
+      continue;
+    }
+    {
+      uint32_t part = 0;
+      for (uint32_t k = tid; k < kTokRanks; k += NT) {
+        const uint32_t c = hc[k];
+        part += c >= 2 ? c : 0u;
+      }
+      part = wave_incl_sum(part);
+      if ((tid & 63) == 63 && part) atomicAdd(&a1, part);
+    }
+    const uint32_t D = nd;
+    uint32_t P = 64;
+    while (P < D) P <<= 1;
+    const int R = (int)((P + NT - 1) / NT);
+    const bool holds = (uint32_t)tid < P;  // P < NT: whole wavefronts hold one key or none
+    // 2a. element i = r * NT + tid in v[r] (pads: kPairEmpty), each
+    // wavefront's 64 elements of one register sorted ascending
+    uint32_t v[kPairRegs];
+#pragma unroll
+    for (int r = 0; r < kPairRegs; r++) {
+      const uint32_t i = (uint32_t)r * NT + tid;
+      v[r] = (r < R && holds && i < D) ? dist[i] : kPairEmpty;
+    }
+    const uint32_t ln = (uint32_t)tid & 63;
+#pragma unroll
+    for (uint32_t k = 2; k <= 64; k <<= 1)
+#pragma unroll
+      for (uint32_t j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int r = 0; r < kPairRegs; r++)
+          if (r < R)
+            v[r] = bitonic_keep32(v[r], (uint32_t)__shfl_xor((int)v[r], (int)j, 64), ln, j, k == 64 ? 128 : k);
+    __syncthreads();  // list and counts read, a1 complete
+    if (tid == 0 && a1) atomicAdd(act1, a1);
+#pragma unroll
+    for (int r = 0; r < kPairRegs; r++)
+      if (r < R && holds) dist[(uint32_t)r * NT + tid] = v[r];
+    __syncthreads();
+    // 2b. runs merged pairwise, 64 -> P: an element's place is its index in
+    // its own run plus the elements of the other run before it (strictly
+    // smaller ones from the left run, smaller or equal ones from the right
+    // one; keys are distinct, pads all equal)
+    uint32_t pos[kPairRegs];
+#pragma unroll
+    for (int r = 0; r < kPairRegs; r++) pos[r] = (uint32_t)r * NT + tid;
+    int cb = 0;  // merge source: dist (0) or aux (1)
+    for (uint32_t L = 64; L < P; L <<= 1) {
+      const uint32_t *src = cb ? aux : dist;
+      uint32_t *dst = cb ? dist : aux;
+#pragma unroll
+      for (int r = 0; r < kPairRegs; r++) {
+        if (!(r < R && holds)) continue;
+        const uint32_t i = pos[r], x = v[r];
+        const uint32_t base = i & ~(2 * L - 1), right = i & L;
+        const uint32_t *o = src + (right ? base : base + L);
+        uint32_t c = 0;
+        for (uint32_t step = L >> 1; step > 0; step >>= 1) {
+          const uint32_t y = o[c + step - 1];
+          if (right ? (y <= x) : (y < x)) c += step;
+        }
+        if (right ? (o[c] <= x) : (o[c] < x)) c++;  // c <= L - 1 before this test
+        pos[r] = base + (i - base - right) + c;
+        dst[pos[r]] = x;
+      }
+      __syncthreads();
+      cb ^= 1;
+    }
+    // 3. ranks into the slots (aux is free now), then every suffix's rank
+#pragma unroll
+    for (int r = 0; r < kPairRegs; r++)
+      if (r < R && holds && v[r] != kPairEmpty) srank[pair_probe(tab, v[r])] = (uint16_t)(pos[r] + 1);
+    __syncthreads();
+    for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
+      uint32_t r1[kWinRankBatch], r2[kWinRankBatch];
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        r1[u] = i < e ? tokrank[i] : 0u;
+        r2[u] = i + 1 < e ? tokrank[i + 1] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kWinRankBatch; u++) {
+        const uint64_t i = i0 + (uint64_t)u * NT + tid;
+        if (i < e) prank[i] = srank[pair_probe(tab, (r1[u] << 13) | r2[u])];
+      }
+    }
+  }
+}
+
+void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
+              uint32_t *cnt, uint32_t *act1, hipStream_t s) {
+  // one workgroup per compute unit (the LDS footprint allows one)
+  if (nw) hipLaunchKernelGGL(k_win_pair, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, off,
+                             nw, wflag, tokrank, prank, cnt, act1);
 }
 
 // ------------------------------------ first doubling round, per window
 // The first round of the suffix sort for the windows ranked on their own:
-// each window's suffixes grouped by first token, by a counting sort on the
-// window's ranks (at most kWinRankCap + 1 of them) in LDS, written in the
-// form the later doubling rounds take over from a round of the sort engine:
-// the suffix arrangement in val[0], rank[i] = 1 + slot of the first suffix
-// of i's group, the grouped-slot flags, and every group of two or more as a
-// unit of the next list (kHeadBit set: its suffixes' ranks are its start + 1)
-// in its size class, or in the large-unit list when it exceeds the LDS tile
-// (next_bits key bits), with the active-slot count.  Flagged windows are left
-// to the engine.  Workgroups take windows from the counter *wnext.
-constexpr uint32_t kR0Ranks = kWinRankCap + 2;  // ranks 1..kWinRankCap + 1
-
+// each window's suffixes grouped by their rank (first token, or first two
+// tokens after k_win_pair), by a counting sort on the window's ranks (at most
+// RANKS - 1 of them) in LDS, written in the form the later doubling rounds
+// take over from a round of the sort engine: the suffix arrangement in
+// val[0], rank[i] = 1 + slot of the first suffix of i's group, the
+// grouped-slot flags, and every group of two or more as a unit of list LIST
+// (kHeadBit set: its suffixes' ranks are its start + 1) in its size class,
+// or in the large-unit list when it exceeds the LDS tile (next_bits key
+// bits), with the active-slot count.  Flagged windows are left to the
+// engine.  Workgroups take windows from the counter *wnext.
+template <uint32_t RANKS, int LIST>
 __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off, uint32_t nw,
-                                                               const uint8_t *wflag, const uint32_t *tokrank,
+                                                               const uint8_t *wflag, const uint32_t *keyrank,
                                                                uint32_t *rank, uint8_t *aflag, uint32_t next_bits,
                                                                uint32_t *wnext) {
   constexpr int NT = kWinRankThreads;
-  constexpr int PER = (kR0Ranks + NT - 1) / NT;
-  __shared__ uint32_t cnt[kR0Ranks], gst[kR0Ranks], cur[kR0Ranks];
+  constexpr int PER = (RANKS + NT - 1) / NT;
+  constexpr uint32_t TOP = 1u << (31 - __builtin_clz(RANKS - 1));  // largest power of two below RANKS
+  // cnt: counts, then each group's next free slot; gst: group starts
+  // (window-relative), gst[RANKS] = window length, so a count is a difference
+  __shared__ uint32_t cnt[RANKS], gst[RANKS + 1];
   __shared__ uint32_t sh[NT / 64];
   __shared__ uint32_t cls_loc[kClasses], cls_base[kClasses];
   __shared__ uint32_t cur_w;
@@ -646,7 +857,7 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
   for (;;) {
     __syncthreads();  // the previous window's reads of the shared state are done
     if (tid == 0) cur_w = atomicAdd(wnext, 1u);
-    for (uint32_t r = tid; r < kR0Ranks; r += NT) cnt[r] = 0;
+    for (uint32_t r = tid; r < RANKS; r += NT) cnt[r] = 0;
     if (tid < kClasses) cls_loc[tid] = 0;
     __syncthreads();
     const uint32_t w = cur_w;
@@ -659,28 +870,32 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++) {
         const uint64_t i = i0 + (uint64_t)u * NT + tid;
-        rq[u] = i < e ? tokrank[i] : 0u;
+        rq[u] = i < e ? keyrank[i] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++)
         if (i0 + (uint64_t)u * NT + tid < e) atomicAdd(&cnt[rq[u]], 1u);
     }
     __syncthreads();
-    // group starts (window-relative): exclusive scan, PER consecutive ranks a thread
+    // group starts: exclusive scan, PER consecutive ranks a thread
     {
       const uint32_t r0 = (uint32_t)tid * PER;
-      uint32_t loc = 0;
+      uint32_t c[PER], loc = 0;
 #pragma unroll
-      for (int q = 0; q < PER; q++) loc += r0 + q < kR0Ranks ? cnt[r0 + q] : 0u;
+      for (int q = 0; q < PER; q++) {
+        c[q] = r0 + q < RANKS ? cnt[r0 + q] : 0u;
+        loc += c[q];
+      }
       uint32_t tot;
-      uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);
+      uint32_t ex = block_excl_sum<NT>(loc, sh, &tot);  // its barriers order the reads above before the writes
 #pragma unroll
       for (int q = 0; q < PER; q++)
-        if (r0 + q < kR0Ranks) {
+        if (r0 + q < RANKS) {
           gst[r0 + q] = ex;
-          cur[r0 + q] = ex;
-          ex += cnt[r0 + q];
+          cnt[r0 + q] = ex;
+          ex += c[q];
         }
+      if (tid == 0) gst[RANKS] = tot;
     }
     __syncthreads();
     // groups of two or more: units of the next list, reserved once per class
@@ -691,30 +906,30 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
       const uint32_t r = (uint32_t)tid * PER + q;
       ur[q] = 0;
       ui[q] = 0;
-      const uint32_t c = r < kR0Ranks ? cnt[r] : 0u;
+      const uint32_t c = r < RANKS ? gst[r + 1] - gst[r] : 0u;
       if (c < 2) continue;
       act += c;
       ur[q] = r;
       if (c <= tile) ui[q] = atomicAdd(&cls_loc[class_of(c)], 1u);
-      else append_big_unit(B.big[1][0], &B.ctr->big_pk[1][0], B.big_cap, (uint32_t)b + gst[r], c, next_bits,
+      else append_big_unit(B.big[LIST][0], &B.ctr->big_pk[LIST][0], B.big_cap, (uint32_t)b + gst[r], c, next_bits,
                            &B.ctr->err);
     }
     {
       uint32_t tot;
       (void)block_excl_sum<NT>(act, sh, &tot);
-      if (tid == 0 && tot) atomicAdd(&B.ctr->act_cnt[1], tot);
+      if (tid == 0 && tot) atomicAdd(&B.ctr->act_cnt[LIST], tot);
     }
-    if (tid < kClasses) cls_base[tid] = cls_loc[tid] ? atomicAdd(&B.ctr->cls_cnt[1][tid], cls_loc[tid]) : 0u;
+    if (tid < kClasses) cls_base[tid] = cls_loc[tid] ? atomicAdd(&B.ctr->cls_cnt[LIST][tid], cls_loc[tid]) : 0u;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; q++) {
       const uint32_t r = ur[q];
       if (!r) continue;
-      const uint32_t c = cnt[r];
+      const uint32_t c = gst[r + 1] - gst[r];
       if (c > tile) continue;
       const int ci = class_of(c);
       const uint32_t k = cls_base[ci] + ui[q];
-      if (k < B.cls_off[ci + 1] - B.cls_off[ci]) B.cls[1][B.cls_off[ci] + k] = Unit{(uint32_t)b + gst[r], c | kHeadBit};
+      if (k < B.cls_off[ci + 1] - B.cls_off[ci]) B.cls[LIST][B.cls_off[ci] + k] = Unit{(uint32_t)b + gst[r], c | kHeadBit};
       else atomicOr(&B.ctr->err, 8u);
     }
     // suffixes into their groups' slots; ranks and flags
@@ -723,13 +938,13 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++) {
         const uint64_t i = i0 + (uint64_t)u * NT + tid;
-        rq[u] = i < e ? tokrank[i] : 0u;
+        rq[u] = i < e ? keyrank[i] : 0u;
       }
       // every slot reservation of the batch first, then the stores
       uint32_t sq[kWinRankBatch];
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++)
-        sq[u] = i0 + (uint64_t)u * NT + tid < e ? atomicAdd(&cur[rq[u]], 1u) : 0u;
+        sq[u] = i0 + (uint64_t)u * NT + tid < e ? atomicAdd(&cnt[rq[u]], 1u) : 0u;
 #pragma unroll
       for (int u = 0; u < kWinRankBatch; u++) {
         const uint64_t i = i0 + (uint64_t)u * NT + tid;
@@ -746,26 +961,23 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
       const uint32_t sl = (uint32_t)s0 + tid;
       if (sl >= e - b) break;
       uint32_t lo = 0;  // last index with gst <= sl (gst[0] = 0)
-      for (uint32_t step = 4096; step > 0; step >>= 1)
-        if (lo + step < kR0Ranks && gst[lo + step] <= sl) lo += step;
-      aflag[b + sl] = cnt[lo] >= 2 ? 1 : 0;
+      for (uint32_t step = TOP; step > 0; step >>= 1)
+        if (lo + step < RANKS && gst[lo + step] <= sl) lo += step;
+      aflag[b + sl] = gst[lo + 1] - gst[lo] >= 2 ? 1 : 0;
     }
   }
 }
 
-void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, hipStream_t s) {
-  static const unsigned cus = [] {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
-                                                hipSuccess || n <= 0) {
-      (void)hipGetLastError();
-      n = 256;
-    }
-    return (unsigned)n;
-  }();
-  if (nw) hipLaunchKernelGGL(k_win_round0, dim3(std::min<unsigned>(2 * cus, nw)), dim3(kWinRankThreads), 0, s, B, off,
-                             nw, wflag, tokrank, rank, aflag, next_bits, wnext);
+void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, hipStream_t s) {
+  if (!nw) return;
+  const dim3 grid(std::min<unsigned>(2 * cu_count(), nw)), block(kWinRankThreads);
+  if (pairs)
+    hipLaunchKernelGGL((k_win_round0<kPairCap + 2, 0>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
+                       next_bits, wnext);
+  else
+    hipLaunchKernelGGL((k_win_round0<kTokRanks, 1>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
+                       next_bits, wnext);
 }
 
 // -------------------------------------------------------------- windows

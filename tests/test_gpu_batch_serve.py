@@ -113,6 +113,84 @@ def test_batch_window_ranks(ctx):
                 ctx.set_graphs(True)
 
 
+def _pairs_window(rng, npairs):
+    """A window over 200 symbols whose adjacent token pairs, with the pair of
+    its last token and the window's end, are exactly npairs distinct ones."""
+    t = rng.integers(1, 201, 4 * npairs).astype(np.uint64)
+    key = t[:-1] * 256 + t[1:]
+    _, first = np.unique(key, return_index=True)
+    fresh = np.zeros(len(key), np.int64)
+    fresh[first] = 1
+    seen = np.cumsum(fresh)  # seen[i]: distinct pairs among key[:i+1]
+    i = int(np.searchsorted(seen, npairs - 1))  # window t[:i+2]: npairs - 1 inner pairs + the end pair
+    assert seen[i] == npairs - 1
+    w = t[: i + 2]
+    inner = len(np.unique(w[:-1] * 256 + w[1:]))
+    assert inner + 1 == npairs
+    return w
+
+
+def _oracle_active(t):
+    _sa, act = oracle.suffix_array(t, return_active=True)
+    return int(act.sum())
+
+
+def _pair_lane_windows(wins, lanes, over):
+    """Windows the host-driven lanes give pair ranks: lanes take consecutive
+    windows with about equal tokens (min(lanes, W // 2) of them, none below
+    two), and a lane takes them when it holds two windows or more, none of
+    them `over`."""
+    W = len(wins)
+    L = min(lanes, W // 2)
+    if L < 2:
+        return 0
+    off = np.cumsum([0] + [len(w) for w in wins])
+    w0 = [0]
+    for g in range(1, L):
+        w0.append(max(min(int(np.searchsorted(off, off[-1] * g // L, side="left")), W), w0[-1]))
+    w0.append(W)
+    return sum(w0[g + 1] - w0[g] for g in range(L)
+               if w0[g + 1] - w0[g] >= 2 and not any(wins[k] is over for k in range(w0[g], w0[g + 1])))
+
+
+def test_batch_pair_ranks_bound(ctx):
+    """Host-driven batches take the first two doubling rounds window by
+    window when every window of a lane has at most 8192 distinct adjacent
+    token pairs (the pair of the last token and the window's end included),
+    and the engine's second round otherwise: windows at 8192 and 8193
+    distinct pairs beside loop streams give the oracle's rows and the
+    oracle's active suffix counts on either path, in host-driven lanes, in
+    one sync-free lane and as graph branches (which take the engine's
+    rounds)."""
+    rng = np.random.default_rng(33)
+    at, over = _pairs_window(rng, 8192), _pairs_window(rng, 8193)
+    loops = [synth.loop_stream(40 + k, n, body, 64, 0.05) for k, (n, body) in
+             enumerate(((3000, 17), (9000, 250), (700, 11), (5000, 40), (12000, 90), (1500, 300)))]
+    m = 3
+    seen = set()
+    for wins in (loops + [at], loops + [over], loops[:3] + [over] + loops[3:] + [at], [over, at]):
+        toks, off = _pack(wins)
+        refs = [_rows_ref(w, m) for w in wins]
+        act = sum(_oracle_active(w) for w in wins)
+        for lanes, graphs in ((3, False), (2, False), (1, False), (3, True)):
+            print("windows", [len(w) for w in wins], "lanes", lanes, "graphs", graphs, flush=True)
+            try:
+                ctx.set_lanes(lanes)
+                ctx.set_graphs(graphs)
+                rows, oo = ctx.analyze_batch(toks, off, m)
+                for w in range(len(wins)):
+                    assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (w, len(wins[w]))
+                c = ctx.counters()
+                assert c["active_sum"] - len(toks) == act
+                if not graphs and lanes > 1:
+                    assert c["pair_windows"] == _pair_lane_windows(wins, lanes, over), c
+                    seen.add(c["pair_windows"] == len(wins))
+            finally:
+                ctx.set_lanes(3)
+                ctx.set_graphs(True)
+    assert seen == {True, False}  # both paths ran
+
+
 def test_batch_long_windows(ctx):
     """Windows longer than 2^16 tokens beside short ones: the doubling rounds'
     window-relative bucketing digits then need more than 16 bits, and the

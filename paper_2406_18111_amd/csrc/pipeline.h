@@ -30,6 +30,7 @@ enum Cnt {
   CNT_WNEXT2 = 20, // batches: next window for the per-window first doubling round
   CNT_PNEXT = 21,  // batches: next window for the per-window pair ranks
   CNT_PFLAG = 22,  // batches: windows whose pairs the per-window ranking left alone
+  CNT_A1 = 23,     // batches: the first doubling round's active count, from the pair ranking
   CNT_COUNT = 32
 };
 
@@ -113,6 +114,7 @@ struct Workspace {
   int kev_n = 0;
   int sel_cap = kSelRoundCap;      // host-driven selection rounds before the sequential completion
   int sel_prefix = -1;             // exact prefix walk before the rounds: -1 automatic, 0 never, k > 0 k candidates
+  uint32_t pair_w = 0;             // windows of the run when it ranked their token pairs (else 0)
   int fail_after = -1;             // test hook: host syncs before one reports a device error (-1: never)
   bool win_greedy = true;          // one-wavefront-per-window greedy where windows are short enough
 

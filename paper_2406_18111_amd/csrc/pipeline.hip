@@ -258,6 +258,7 @@ static void stamp(Workspace &w, int k, hipStream_t s, bool on) {
 static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
   info.n = N;
   info.sigma = w.hcnt[CNT_ND] + w.hcnt[CNT_NDSUM];  // shared table + windows ranked on their own
+  info.pair_windows = (w.pair_w && w.hcnt[CNT_PFLAG] == 0) ? w.pair_w : 0;
   info.cands = w.hcnt[CNT_C] + w.hcnt[CNT_CSKIP];
   info.maxl = w.hcnt[CNT_MAXL];
   info.cands_dedup = w.hcnt[CNT_M];
@@ -293,7 +294,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   uint64_t maxwin = 0;
   for (uint32_t k = 0; k < W; k++) maxwin = std::max<uint64_t>(maxwin, h_off[k + 1] - h_off[k]);
   fill_u32(dc, CNT_RANGE, 0, s);
-  fill_u32(dc + CNT_NDSUM, 7, 0, s);
+  fill_u32(dc + CNT_NDSUM, 8, 0, s);
   fill_u32(dc + CNT_SNAPS, 1, 0, s);
   fill_u32(w.rhist, 4 * (uint64_t)w.nsnap, 0, s);
 
@@ -303,10 +304,15 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   // batches of 64-bit tokens: the windows ranked on their own also get their
   // first doubling round from a per-window kernel; the engine's first round
   // then only sorts the flagged windows (and is skipped by host-driven runs
-  // that have none).  Host-driven runs whose windows all have their own ranks
-  // and few distinct token pairs get the first two rounds from per-window
-  // kernels (pair ranks, then one counting sort on them).
+  // that have none).  When every window has its own ranks and few distinct
+  // token pairs, the first two rounds come from per-window kernels instead
+  // (pair ranks, then one counting sort on them): host-driven runs read that
+  // from the counters and start the doubling loop at offset 2; sync-free runs
+  // launch both forms gated on the device count (pflag) and run the
+  // engine's second round empty.
   bool win_r0 = false, skip0 = false, pair0 = false;
+  const uint32_t *pflag = nullptr;
+  w.pair_w = 0;
   if (bits == 64) {
     const uint64_t *tok = static_cast<const uint64_t *>(d_tok);
     // Batches rank each window on its own first; the shared table then
@@ -322,13 +328,15 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       win_rank(tok, w.d_off, W, w.tokrank, w.wflag, dc + CNT_NDSUM, s);
       wgate = dc + CNT_WFLAG;
       wf = w.wflag;
+      win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, dc + CNT_A1, s);
+      w.pair_w = W;
       if (host) {
-        win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, w.rhist, s);
         if ((rc = read_counters(w, s))) return rc;
         shared = w.hcnt[CNT_WFLAG] > 0;
-        pair0 = !shared && w.hcnt[CNT_PFLAG] == 0;
-        if (pair0) info.pair_windows = W;
+        pair0 = w.hcnt[CNT_PFLAG] == 0;  // windows counted in CNT_WFLAG count here too
         loc_bits = (uint64_t)bit_length_u64(w.hcnt[CNT_NDMAX]);
+      } else {
+        pflag = dc + CNT_PFLAG;
       }
     }
     uint64_t nd_bound = N;
@@ -382,9 +390,14 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       E.gather_identity(key0, (uint32_t)N, s, wid, w.wflag, dc + CNT_WFLAG);
       E.init_units(cur, w.d_off, W, 0, bits0, s, w.wflag);
     }
-    // with pairs: the state after round 1 (its active count is in rhist[0]
-    // already), and the lists of round 2
-    win_round0(B, w.d_off, W, w.wflag, pair0 ? B.key[1] : key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, pair0, s);
+    // with pairs: the state after round 1 and the lists of round 2 (sync-free
+    // runs: the first-token form, which gives way when *pflag == 0)
+    if (pair0)
+      win_round0(B, w.d_off, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, nullptr,
+                 dc + CNT_A1, w.rhist, s);
+    else
+      win_round0(B, w.d_off, W, w.wflag, key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, false, pflag, nullptr,
+                 nullptr, s);
   } else {
     E.gather_identity(key0, (uint32_t)N, s);
     E.init_units(cur, w.d_off, W, 0, bits0, s);
@@ -397,6 +410,12 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   while (done_round < 0) {
     if (r >= w.nsnap) return -4;
     if (r > 0) E.gather_sa(cur, w.rank, w.aflag, wend, (uint32_t)N, 1u << (r - 1), w.rhist, r, s);
+    // sync-free runs with pair ranks: the second round's state from them,
+    // after that round's gather (which found nothing grouped and cleared
+    // the lists it fills), so the round's sort launches find no work
+    if (r == 1 && pflag)
+      win_round0(B, w.d_off, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, pflag,
+                 dc + CNT_A1, w.rhist, s);
     RankOut R{w.rank, (uint32_t)r, w.aflag};
     if (r > 0 || !skip0) {
       if (big) E.msd(cur, act, r == 0 ? (int)bits0 : (int)rel_bits, s, r == 0 ? nullptr : wbeg);

@@ -55,11 +55,14 @@ void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint
 // ranks), or with pairs set by first two tokens (keyrank = pair ranks, every
 // window unflagged by win_pair), in val[0], ranks (1 + group start slot),
 // grouped-slot flags and the groups of two or more as units of the engine's
-// list 1, or list 0 for pairs (counters and lists cleared by reset_counters
-// and round_begin(0) before; large units get next_bits key bits).  *wnext:
-// zeroed work counter.
+// list 1, or list 0 for pairs (counters and lists of that list cleared
+// before; large units get next_bits key bits).  *wnext: zeroed work counter.
+// With pflag set (sync-free runs, both forms launched) the pair form runs
+// only when *pflag == 0 and the first-token form only when it is not.  The
+// pair form writes *hist0 = *a1 (the first round's active count).
 void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, hipStream_t s);
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, const uint32_t *pflag,
+                const uint32_t *a1, uint32_t *hist0, hipStream_t s);
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 

@@ -837,12 +837,16 @@ void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint
 // (kHeadBit set: its suffixes' ranks are its start + 1) in its size class,
 // or in the large-unit list when it exceeds the LDS tile (next_bits key
 // bits), with the active-slot count.  Flagged windows are left to the
-// engine.  Workgroups take windows from the counter *wnext.
+// engine.  Workgroups take windows from the counter *wnext.  With pflag set
+// the kernel runs only when *pflag == 0 (pair ranks for every window) for
+// the pair form, only when *pflag != 0 for the first-token form.  The pair
+// form also records the first round's active count *a1 in *hist0.
 template <uint32_t RANKS, int LIST>
 __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off, uint32_t nw,
                                                                const uint8_t *wflag, const uint32_t *keyrank,
                                                                uint32_t *rank, uint8_t *aflag, uint32_t next_bits,
-                                                               uint32_t *wnext) {
+                                                               uint32_t *wnext, const uint32_t *pflag,
+                                                               const uint32_t *a1, uint32_t *hist0) {
   constexpr int NT = kWinRankThreads;
   constexpr int PER = (RANKS + NT - 1) / NT;
   constexpr uint32_t TOP = 1u << (31 - __builtin_clz(RANKS - 1));  // largest power of two below RANKS
@@ -854,6 +858,8 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
   __shared__ uint32_t cur_w;
   const int tid = threadIdx.x;
   const uint32_t tile = 1u << B.tile_log;
+  if (pflag && ((*pflag == 0) != (LIST == 0))) return;  // uniform: the other form runs
+  if (a1 && blockIdx.x == 0 && tid == 0) *hist0 = *a1;
   for (;;) {
     __syncthreads();  // the previous window's reads of the shared state are done
     if (tid == 0) cur_w = atomicAdd(wnext, 1u);
@@ -969,15 +975,16 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
 }
 
 void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, hipStream_t s) {
+                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, const uint32_t *pflag,
+                const uint32_t *a1, uint32_t *hist0, hipStream_t s) {
   if (!nw) return;
   const dim3 grid(std::min<unsigned>(2 * cu_count(), nw)), block(kWinRankThreads);
   if (pairs)
     hipLaunchKernelGGL((k_win_round0<kPairCap + 2, 0>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
-                       next_bits, wnext);
+                       next_bits, wnext, pflag, a1, hist0);
   else
     hipLaunchKernelGGL((k_win_round0<kTokRanks, 1>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
-                       next_bits, wnext);
+                       next_bits, wnext, pflag, nullptr, nullptr);
 }
 
 // -------------------------------------------------------------- windows

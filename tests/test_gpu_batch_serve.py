@@ -136,14 +136,12 @@ def _oracle_active(t):
 
 
 def _pair_lane_windows(wins, lanes, over):
-    """Windows the host-driven lanes give pair ranks: lanes take consecutive
-    windows with about equal tokens (min(lanes, W // 2) of them, none below
-    two), and a lane takes them when it holds two windows or more, none of
-    them `over`."""
+    """Windows that take pair ranks: a batch runs as min(lanes, W // 2) lanes
+    of consecutive windows with about equal tokens (one lane below two), and
+    a lane takes them when it holds two windows or more, none of them
+    `over`."""
     W = len(wins)
-    L = min(lanes, W // 2)
-    if L < 2:
-        return 0
+    L = max(min(lanes, W // 2), 1)
     off = np.cumsum([0] + [len(w) for w in wins])
     w0 = [0]
     for g in range(1, L):
@@ -154,14 +152,14 @@ def _pair_lane_windows(wins, lanes, over):
 
 
 def test_batch_pair_ranks_bound(ctx):
-    """Host-driven batches take the first two doubling rounds window by
-    window when every window of a lane has at most 8192 distinct adjacent
-    token pairs (the pair of the last token and the window's end included),
-    and the engine's second round otherwise: windows at 8192 and 8193
-    distinct pairs beside loop streams give the oracle's rows and the
-    oracle's active suffix counts on either path, in host-driven lanes, in
-    one sync-free lane and as graph branches (which take the engine's
-    rounds)."""
+    """Batches take the first two doubling rounds window by window when every
+    window of a lane has at most 8192 distinct adjacent token pairs (the pair
+    of the last token and the window's end included), and the engine's second
+    round otherwise: windows at 8192 and 8193 distinct pairs beside loop
+    streams give the oracle's rows and the oracle's active suffix counts on
+    either path, in host-driven lanes (the host picks the path), in one
+    sync-free lane and in graphs (both forms launched, the device count picks
+    one), each graph replayed once."""
     rng = np.random.default_rng(33)
     at, over = _pairs_window(rng, 8192), _pairs_window(rng, 8193)
     loops = [synth.loop_stream(40 + k, n, body, 64, 0.05) for k, (n, body) in
@@ -172,23 +170,23 @@ def test_batch_pair_ranks_bound(ctx):
         toks, off = _pack(wins)
         refs = [_rows_ref(w, m) for w in wins]
         act = sum(_oracle_active(w) for w in wins)
-        for lanes, graphs in ((3, False), (2, False), (1, False), (3, True)):
+        for lanes, graphs in ((3, False), (2, False), (1, False), (3, True), (1, True)):
             print("windows", [len(w) for w in wins], "lanes", lanes, "graphs", graphs, flush=True)
             try:
                 ctx.set_lanes(lanes)
                 ctx.set_graphs(graphs)
-                rows, oo = ctx.analyze_batch(toks, off, m)
-                for w in range(len(wins)):
-                    assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (w, len(wins[w]))
-                c = ctx.counters()
-                assert c["active_sum"] - len(toks) == act
-                if not graphs and lanes > 1:
+                for rep in range(2 if graphs else 1):
+                    rows, oo = ctx.analyze_batch(toks, off, m)
+                    for w in range(len(wins)):
+                        assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (rep, w, len(wins[w]))
+                    c = ctx.counters()
+                    assert c["active_sum"] - len(toks) == act
                     assert c["pair_windows"] == _pair_lane_windows(wins, lanes, over), c
-                    seen.add(c["pair_windows"] == len(wins))
+                    seen.add((lanes > 1 and not graphs, c["pair_windows"] == len(wins)))
             finally:
                 ctx.set_lanes(3)
                 ctx.set_graphs(True)
-    assert seen == {True, False}  # both paths ran
+    assert seen == {(a, b) for a in (True, False) for b in (True, False)}  # both paths, host- and device-picked
 
 
 def test_batch_long_windows(ctx):

@@ -561,13 +561,16 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *to
         const uint32_t i = pos[r];
         const uint64_t x = v[r];
         const uint32_t base = i & ~(2 * L - 1), right = i & L;
+        const bool rt = right != 0;
         const uint64_t *o = src + (right ? base : base + L);  // the other run
         uint32_t c = 0;  // elements of the other run before x
+        // branch-free steps (the comparison depends on the lane's run; as
+        // a branch it compiled to divergent control flow per step)
         for (uint32_t step = L >> 1; step > 0; step >>= 1) {
           const uint64_t y = o[c + step - 1];
-          if (right ? (y <= x) : (y < x)) c += step;
+          c += ((y < x) | ((y == x) & rt)) ? step : 0u;
         }
-        if (right ? (o[c] <= x && c < L) : (o[c] < x && c < L)) c++;
+        c += ((o[c] < x) | ((o[c] == x) & rt)) ? 1u : 0u;  // c <= L - 1 before this step
         pos[r] = base + (i - base - right) + c;
         dst[pos[r]] = x;
       }
@@ -784,13 +787,14 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *of
         if (!(r < R && holds)) continue;
         const uint32_t i = pos[r], x = v[r];
         const uint32_t base = i & ~(2 * L - 1), right = i & L;
+        const bool rt = right != 0;
         const uint32_t *o = src + (right ? base : base + L);
         uint32_t c = 0;
-        for (uint32_t step = L >> 1; step > 0; step >>= 1) {
+        for (uint32_t step = L >> 1; step > 0; step >>= 1) {  // branch-free steps
           const uint32_t y = o[c + step - 1];
-          if (right ? (y <= x) : (y < x)) c += step;
+          c += ((y < x) | ((y == x) & rt)) ? step : 0u;
         }
-        if (right ? (o[c] <= x) : (o[c] < x)) c++;  // c <= L - 1 before this test
+        c += ((o[c] < x) | ((o[c] == x) & rt)) ? 1u : 0u;  // c <= L - 1 before this step
         pos[r] = base + (i - base - right) + c;
         dst[pos[r]] = x;
       }

@@ -189,6 +189,75 @@ def test_batch_pair_ranks_bound(ctx):
     assert seen == {(a, b) for a in (True, False) for b in (True, False)}  # both paths, host- and device-picked
 
 
+def _pair_mix_windows(seed, count):
+    """Windows whose tokens mostly fit the per-window ranks (small alphabets,
+    loop streams, periodic runs, the value 2^64-1 sprinkled in, lengths 1 to
+    20000), so that whole lanes take the pair ranks or just miss them."""
+    rng = np.random.default_rng(seed)
+    top = np.uint64(np.iinfo(np.uint64).max)
+    wins = []
+    for k in range(count):
+        L = int(rng.choice([1, 2, 3, 7, 64, 65, 500, 2047, 2048, 2049, 5000, 9000, 20000]))
+        kind = k % 4
+        if kind == 0:
+            w = synth.loop_stream(int(rng.integers(1 << 30)), L, int(rng.integers(3, 500)),
+                                  int(rng.integers(8, 4000)), float(rng.choice([0.0, 0.01, 0.05, 0.1])))
+        elif kind == 1:
+            w = rng.integers(0, int(rng.choice([2, 3, 16, 90])), L).astype(np.uint64)
+        elif kind == 2:
+            w = np.tile(rng.integers(0, 1 << 62, int(rng.integers(1, 50))).astype(np.uint64), L // 2 + 1)[:L]
+        else:
+            w = rng.integers(0, 4000, L).astype(np.uint64)
+        w = np.asarray(w, dtype=np.uint64).copy()
+        if L and rng.random() < 0.4:
+            w[rng.integers(0, L, max(1, L // 50))] = top
+        wins.append(w)
+    return wins
+
+
+def _distinct_pairs(w):
+    """Distinct adjacent pairs of a window, the pair of its last token and its end included."""
+    if len(w) == 0:
+        return 0
+    return len(np.unique(np.stack([w[:-1], w[1:]], 1), axis=0)) + 1
+
+
+@pytest.mark.parametrize("seed,keep_over", [(5, True), (6, True), (7, False)])
+def test_batch_pair_ranks_random(ctx, seed, keep_over):
+    """Random batches of windows around the per-window ranking bounds (distinct
+    tokens and distinct pairs, tiny windows, the largest token value): rows
+    equal the oracle's and the active suffix counts the oracle's, in
+    host-driven lanes (the host picks the path), in one sync-free lane and
+    replayed from a graph (the device picks it); one batch without windows
+    over 8192 distinct pairs, so that every path takes the pair ranks."""
+    wins = _pair_mix_windows(seed, 16)
+    if not keep_over:
+        wins = [w for w in wins if _distinct_pairs(w) <= 8192]
+    toks, off = _pack(wins)
+    m = 3
+    refs = [_rows_ref(w, m) for w in wins]
+    act = sum(_oracle_active(w) for w in wins)
+    pairs = 0
+    for lanes, graphs in ((3, False), (1, False), (1, True)):
+        print("seed", seed, "lanes", lanes, "graphs", graphs, flush=True)
+        try:
+            ctx.set_lanes(lanes)
+            ctx.set_graphs(graphs)
+            for rep in range(2 if graphs else 1):
+                rows, oo = ctx.analyze_batch(toks, off, m)
+                for w in range(len(wins)):
+                    assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (rep, w, len(wins[w]))
+                c = ctx.counters()
+                assert c["active_sum"] - len(toks) == act
+                if not keep_over and lanes == 1:
+                    assert c["pair_windows"] == len(wins), c
+                pairs += c["pair_windows"]
+        finally:
+            ctx.set_lanes(3)
+            ctx.set_graphs(True)
+    print("windows with pair ranks over the runs:", pairs, flush=True)
+
+
 def test_batch_long_windows(ctx):
     """Windows longer than 2^16 tokens beside short ones: the doubling rounds'
     window-relative bucketing digits then need more than 16 bits, and the

@@ -8,7 +8,8 @@ repeat length 8.  One step = one complete analysis of every window (rank
 compression, suffix array, LCP, candidates, sort, greedy selection, output)
 split into concurrent window groups (lanes), each run host-driven on its own
 stream, tokens resident in device memory.  Reported beside it: the same step
-captured once as a HIP graph and replayed on one stream, the same windows
+captured once as a HIP graph and replayed (the lanes as branches of one
+graph, and one stream), the same windows
 through one plain per-window analysis each, the single-window n = 2^20
 nested-loop workload, the continuous-batching server against a plain FIFO on
 a Poisson trace (p50/p99 latency), the C oracle on the host's cores, and the

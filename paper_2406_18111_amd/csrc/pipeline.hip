@@ -328,7 +328,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
       win_rank(tok, w.d_off, W, w.tokrank, w.wflag, dc + CNT_NDSUM, s);
       wgate = dc + CNT_WFLAG;
       wf = w.wflag;
-      win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, dc + CNT_A1, s);
+      win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, dc + CNT_A1, dc + CNT_WFLAG, s);
       w.pair_w = W;
       if (host) {
         if ((rc = read_counters(w, s))) return rc;

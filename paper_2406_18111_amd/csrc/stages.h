@@ -47,9 +47,10 @@ void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *r
 // window's end).  A window with wflag set or more than 8192 distinct pairs is
 // skipped and counted in cnt[1]; cnt[0]: the windows' work counter (both
 // zeroed by the caller).  *act1 += suffixes whose first token occurs twice or
-// more in their window (the first round's active count).
+// more in their window (the first round's active count).  With *wcount (the
+// windows without ranks of their own) not zero it only counts cnt[1].
 void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
-              uint32_t *cnt, uint32_t *act1, hipStream_t s);
+              uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s);
 // First doubling round of the suffix sort for the windows ranked on their
 // own (wflag[w] == 0): suffixes grouped by first token (keyrank = token
 // ranks), or with pairs set by first two tokens (keyrank = pair ranks, every

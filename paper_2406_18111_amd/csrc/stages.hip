@@ -642,7 +642,9 @@ void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *r
 // 26 bits and 0xFFFFFFFF marks free slots.  A window with more than
 // kPairCap distinct pairs, or without ranks of its own (wflag set), is
 // counted in cnt[1] and left alone: the caller then takes the first two
-// rounds the usual way for the whole batch.  cnt[0]: window counter.
+// rounds the usual way for the whole batch.  cnt[0]: window counter.  When
+// *wcount (windows without ranks of their own) is not zero the kernel only
+// sets cnt[1].
 constexpr int kPairSlots = 16384;
 constexpr uint32_t kPairCap = 8192;
 constexpr int kPairRegs = kPairCap / kWinRankThreads;  // sorted keys per thread
@@ -662,8 +664,12 @@ __device__ __forceinline__ uint32_t bitonic_keep32(uint32_t v, uint32_t p, uint3
 
 __global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag,
                                                              const uint32_t *tokrank, uint32_t *prank, uint32_t *cnt,
-                                                             uint32_t *act1) {
+                                                             uint32_t *act1, const uint32_t *wcount) {
   constexpr int NT = kWinRankThreads;
+  if (*wcount) {  // uniform: the batch takes the usual first rounds anyway
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&cnt[1], 1u);
+    return;
+  }
   __shared__ uint32_t tab[kPairSlots];
   __shared__ uint32_t dist[kPairCap];
   // first-token counts (kTokRanks words), then the merge buffer, then the
@@ -824,10 +830,10 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *of
 }
 
 void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
-              uint32_t *cnt, uint32_t *act1, hipStream_t s) {
+              uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s) {
   // one workgroup per compute unit (the LDS footprint allows one)
   if (nw) hipLaunchKernelGGL(k_win_pair, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, off,
-                             nw, wflag, tokrank, prank, cnt, act1);
+                             nw, wflag, tokrank, prank, cnt, act1, wcount);
 }
 
 // ------------------------------------ first doubling round, per window

@@ -851,6 +851,8 @@ void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint
 // the kernel runs only when *pflag == 0 (pair ranks for every window) for
 // the pair form, only when *pflag != 0 for the first-token form.  The pair
 // form also records the first round's active count *a1 in *hist0.
+constexpr uint32_t kR0SingleWords = 4096;  // singleton-slot bitmap: windows up to 2^17 slots
+
 template <uint32_t RANKS, int LIST>
 __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off, uint32_t nw,
                                                                const uint8_t *wflag, const uint32_t *keyrank,
@@ -863,6 +865,7 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
   // cnt: counts, then each group's next free slot; gst: group starts
   // (window-relative), gst[RANKS] = window length, so a count is a difference
   __shared__ uint32_t cnt[RANKS], gst[RANKS + 1];
+  __shared__ uint32_t single[kR0SingleWords];  // bit s: slot s holds a group of one
   __shared__ uint32_t sh[NT / 64];
   __shared__ uint32_t cls_loc[kClasses], cls_base[kClasses];
   __shared__ uint32_t cur_w;
@@ -880,6 +883,9 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
     if (w >= nw) return;  // uniform
     if (wflag[w]) continue;  // the same word for every thread
     const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
+    const bool bits = e - b <= 32ull * kR0SingleWords;  // uniform
+    if (bits)
+      for (uint32_t k = tid; k < (uint32_t)((e - b + 31) / 32); k += NT) single[k] = 0;
     // counts of the ranks
     for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
       uint32_t rq[kWinRankBatch];
@@ -923,6 +929,7 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
       ur[q] = 0;
       ui[q] = 0;
       const uint32_t c = r < RANKS ? gst[r + 1] - gst[r] : 0u;
+      if (c == 1 && bits) atomicOr(&single[gst[r] >> 5], 1u << (gst[r] & 31));
       if (c < 2) continue;
       act += c;
       ur[q] = r;
@@ -971,15 +978,23 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
       }
     }
     // grouped-slot flags in slot order (coalesced, where scattering them with
-    // the suffixes cost as much as the suffixes): slot s lies in the group of
-    // the last rank whose start is <= s
+    // the suffixes cost as much as the suffixes): a slot is grouped unless it
+    // holds a group of one, marked in the bitmap by the units pass; windows
+    // too long for the bitmap search the group starts (the last rank whose
+    // start is <= s; gst[RANKS], the window length, stops the search)
     for (uint64_t s0 = 0; s0 < e - b; s0 += NT) {
       const uint32_t sl = (uint32_t)s0 + tid;
       if (sl >= e - b) break;
-      uint32_t lo = 0;  // last index with gst <= sl (gst[0] = 0)
-      for (uint32_t step = TOP; step > 0; step >>= 1)
-        if (lo + step < RANKS && gst[lo + step] <= sl) lo += step;
-      aflag[b + sl] = gst[lo + 1] - gst[lo] >= 2 ? 1 : 0;
+      if (bits) {
+        aflag[b + sl] = ((single[sl >> 5] >> (sl & 31)) & 1u) ? 0 : 1;
+      } else {
+        uint32_t lo = 0;  // gst[0] = 0
+        for (uint32_t step = TOP; step > 0; step >>= 1) {
+          const uint32_t t = min(lo + step, RANKS);
+          lo = gst[t] <= sl ? t : lo;
+        }
+        aflag[b + sl] = gst[lo + 1] - gst[lo] >= 2 ? 1 : 0;
+      }
     }
   }
 }

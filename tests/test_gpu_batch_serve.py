@@ -280,6 +280,34 @@ def test_batch_long_windows(ctx):
             assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
 
 
+def test_batch_windows_past_the_slot_bitmap(ctx):
+    """Windows of more than 2^17 tokens with few distinct values (the
+    per-window first rounds then find grouped slots by searching the group
+    starts instead of the singleton bitmap) beside short ones, with and
+    without other windows over the per-window bounds: the oracle's rows and
+    active suffix counts in host-driven lanes, one sync-free lane and a graph."""
+    big = [np.tile(np.arange(7, dtype=np.uint64), 140000 // 7 + 1)[:140000],
+           synth.loop_stream(91, 150000, 37, 200, 0.02).astype(np.uint64)]
+    small = [synth.loop_stream(92 + k, n, 23, 64, 0.05).astype(np.uint64) for k, n in enumerate((3000, 900, 12000))]
+    m = 8
+    for wins in (big + small, small[:1] + big[::-1] + small[1:]):
+        toks, off = _pack(wins)
+        refs = [_rows_ref(w, m) for w in wins]
+        act = sum(_oracle_active(w) for w in wins)
+        for lanes, graphs in ((3, False), (2, False), (1, False), (1, True)):
+            print("windows", [len(w) for w in wins], "lanes", lanes, "graphs", graphs, flush=True)
+            try:
+                ctx.set_lanes(lanes)
+                ctx.set_graphs(graphs)
+                rows, oo = ctx.analyze_batch(toks, off, m)
+                for w in range(len(wins)):
+                    assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (w, len(wins[w]))
+                assert ctx.counters()["active_sum"] - len(toks) == act
+            finally:
+                ctx.set_lanes(3)
+                ctx.set_graphs(True)
+
+
 def test_batch_device_api(ctx):
     import torch
     wins, m = synth.config3(num_windows=24)

@@ -497,11 +497,9 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
                              (uint64_t)(uintptr_t)ln.st});
     }
     LaneGraph &G = ctx->lg;
-    // window offsets of every lane, ahead of the branches that read them
+    // window offsets (and order) of every lane, ahead of the branches that read them
     for (Lane &ln : lanes)
-      if (hipMemcpyAsync(ln.ws->d_off, ln.norm.data(), (ln.W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
-          hipSuccess)
-        return APO_EDEVICE;
+      if (upload_windows(*ln.ws, ln.norm.data(), ln.W, s, true)) return APO_EDEVICE;
     bool ok = true;
     if (!G.exec || G.key != key) {
       G.reset();
@@ -643,9 +641,7 @@ static int batch_single(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off
   GraphCache &G = ctx->gc;
   const bool hit = G.exec && G.tok == d_tok && G.total == total && G.W == W && G.maxwin == maxwin &&
                    G.min_len == min_len && G.tile == tl && G.digit == db && G.mem == w.mem && G.stream == s;
-  if (hipMemcpyAsync(w.d_off, norm.data(), (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return APO_EDEVICE;
+  if (upload_windows(w, norm.data(), W, s, true) || hipStreamSynchronize(s) != hipSuccess) return APO_EDEVICE;
   if (!hit) {
     G.reset();
     bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;

@@ -84,6 +84,8 @@ struct Workspace {
   uint64_t *htab = nullptr;  // distinct token values (hcap + 1 slots)
   uint32_t *dhi = nullptr, *dlo = nullptr;
   uint64_t *d_off = nullptr;
+  uint32_t *d_order = nullptr;  // windows longest first (per-window kernels of sync-free runs take them so)
+  std::vector<uint32_t> h_order;  // its host copy, kept alive for the upload
   uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr, *win_rows = nullptr;
   uint32_t *rank = nullptr, *snap = nullptr, *sa = nullptr;
   uint32_t *lcp = nullptr;
@@ -138,6 +140,11 @@ struct Workspace {
 
  public:
 };
+
+// Uploads a batch's window offsets h_off[0..W] on stream s, and with `order`
+// set the order in which the per-window kernels of sync-free and captured
+// runs take its windows (longest first, by bit length of the window's size).
+int upload_windows(Workspace &w, const uint64_t *h_off, uint32_t W, hipStream_t s, bool order);
 
 // Runs the stages of one analysis on stream s.  d_tok: device tokens of
 // `bits` (32/64) bits, windows given by host offsets h_off[0..W] (global,

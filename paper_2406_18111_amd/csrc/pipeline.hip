@@ -108,7 +108,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
          o_hrank = L.take((hcap + 1) * 4);
   size_t o_di = L.take(N_ * 4), o_ds = L.take(N_ * 4), o_dhi = L.take(N_ * 4), o_dlo = L.take(N_ * 4);
   size_t o_off = L.take((wantW + 1) * 8), o_wb = L.take(N_ * 4), o_we = L.take(N_ * 4), o_wid = L.take(N_ * 4);
-  size_t o_wr = L.take((wantW + 1) * 4);
+  size_t o_wr = L.take((wantW + 1) * 4), o_ord = L.take((wantW + 1) * 4);
   size_t o_wf = L.take(wantW + 1);
   size_t o_rank = L.take(N_ * 4), o_snap = L.take((size_t)nsnap * N_ * 4), o_sa = L.take(N_ * 4);
   size_t o_lcp = L.take(N_ * 4);
@@ -155,6 +155,7 @@ int Workspace::layout(uint64_t wantN, uint32_t wantW, size_t *dry_bytes, void *e
   wend = (uint32_t *)(m + o_we);
   wid = (uint32_t *)(m + o_wid);
   win_rows = (uint32_t *)(m + o_wr);
+  d_order = (uint32_t *)(m + o_ord);
   wflag = (uint8_t *)(m + o_wf);
   rank = (uint32_t *)(m + o_rank);
   snap = (uint32_t *)(m + o_snap);
@@ -271,6 +272,22 @@ static void fill_info(Workspace &w, uint64_t N, RunInfo &info) {
   }
 }
 
+int upload_windows(Workspace &w, const uint64_t *h_off, uint32_t W, hipStream_t s, bool order) {
+  APO_HIP_TRY(hipMemcpyAsync(w.d_off, h_off, (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  if (!order || !W) return 0;
+  // longest first, in buckets of equal bit length (a counting sort): a long
+  // window taken last would hold one workgroup while the others are idle
+  // (host-driven lanes keep the given order: there other lanes fill the
+  // idle compute units, and the step measured slower with it)
+  uint32_t cnt[66] = {0};
+  for (uint32_t k = 0; k < W; k++) cnt[64 - bit_length_u64(h_off[k + 1] - h_off[k]) + 1]++;
+  for (int b = 1; b < 66; b++) cnt[b] += cnt[b - 1];
+  w.h_order.resize(W + 1);
+  for (uint32_t k = 0; k < W; k++) w.h_order[cnt[64 - bit_length_u64(h_off[k + 1] - h_off[k])]++] = k;
+  APO_HIP_TRY(hipMemcpyAsync(w.d_order, w.h_order.data(), W * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  return 0;
+}
+
 int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const uint64_t *h_off, uint32_t W,
                  uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info, Mode mode) {
   info = RunInfo{};
@@ -281,8 +298,9 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
   const bool stamps = mode != Mode::CAPTURE;
   uint32_t *dc = w.dcnt;
   stamp(w, 0, s, stamps);
-  if (mode != Mode::CAPTURE)  // a captured sequence expects d_off to be uploaded already
-    APO_HIP_TRY(hipMemcpyAsync(w.d_off, h_off, (W + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  if (mode != Mode::CAPTURE)  // a captured sequence expects d_off (and the order) to be uploaded already
+    if ((rc = upload_windows(w, h_off, W, s, !host))) return rc;
+  const uint32_t *worder = host ? nullptr : w.d_order;
   const bool batch = W > 1;
   const uint32_t *wbeg = nullptr, *wend = nullptr, *wid = nullptr;
   if (batch) {
@@ -325,10 +343,10 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     bool shared = true;
     uint64_t loc_bits = 0;
     if (batch) {
-      win_rank(tok, w.d_off, W, w.tokrank, w.wflag, dc + CNT_NDSUM, s);
+      win_rank(tok, w.d_off, worder, W, w.tokrank, w.wflag, dc + CNT_NDSUM, s);
       wgate = dc + CNT_WFLAG;
       wf = w.wflag;
-      win_pair(w.d_off, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, dc + CNT_A1, dc + CNT_WFLAG, s);
+      win_pair(w.d_off, worder, W, w.wflag, w.tokrank, B.key[1], dc + CNT_PNEXT, dc + CNT_A1, dc + CNT_WFLAG, s);
       w.pair_w = W;
       if (host) {
         if ((rc = read_counters(w, s))) return rc;
@@ -393,10 +411,10 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     // with pairs: the state after round 1 and the lists of round 2 (sync-free
     // runs: the first-token form, which gives way when *pflag == 0)
     if (pair0)
-      win_round0(B, w.d_off, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, nullptr,
+      win_round0(B, w.d_off, worder, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, nullptr,
                  dc + CNT_A1, w.rhist, s);
     else
-      win_round0(B, w.d_off, W, w.wflag, key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, false, pflag, nullptr,
+      win_round0(B, w.d_off, worder, W, w.wflag, key0, w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, false, pflag, nullptr,
                  nullptr, s);
   } else {
     E.gather_identity(key0, (uint32_t)N, s);
@@ -414,7 +432,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
     // after that round's gather (which found nothing grouped and cleared
     // the lists it fills), so the round's sort launches find no work
     if (r == 1 && pflag)
-      win_round0(B, w.d_off, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, pflag,
+      win_round0(B, w.d_off, worder, W, w.wflag, B.key[1], w.rank, w.aflag, rel_bits, dc + CNT_WNEXT2, true, pflag,
                  dc + CNT_A1, w.rhist, s);
     RankOut R{w.rank, (uint32_t)r, w.aflag};
     if (r > 0 || !skip0) {

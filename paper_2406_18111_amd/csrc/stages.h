@@ -39,9 +39,10 @@ void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, 
 // than 4096 distinct values get wflag = 1 and no ranks (else wflag = 0).
 // cnt[0] += distinct values per ranked window, cnt[1] = their maximum,
 // cnt[2] += 1 per flagged window, cnt[3]: the windows' work counter (all four
-// zeroed by the caller).
-void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
-              hipStream_t s);
+// zeroed by the caller).  Windows are taken in the order order[0..nw) (a
+// permutation, or null for 0..nw-1; the same for win_pair and win_round0).
+void win_rank(const uint64_t *tok, const uint64_t *off, const uint32_t *order, uint32_t nw, uint32_t *rank,
+              uint8_t *wflag, uint32_t *cnt, hipStream_t s);
 // Per-window ranks of adjacent token pairs: prank[i] = 1 + the number of
 // distinct pairs of i's window below (tokrank[i], tokrank[i+1] or 0 past the
 // window's end).  A window with wflag set or more than 8192 distinct pairs is
@@ -49,8 +50,8 @@ void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *r
 // zeroed by the caller).  *act1 += suffixes whose first token occurs twice or
 // more in their window (the first round's active count).  With *wcount (the
 // windows without ranks of their own) not zero it only counts cnt[1].
-void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
-              uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s);
+void win_pair(const uint64_t *off, const uint32_t *order, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
+              uint32_t *prank, uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s);
 // First doubling round of the suffix sort for the windows ranked on their
 // own (wflag[w] == 0): suffixes grouped by first token (keyrank = token
 // ranks), or with pairs set by first two tokens (keyrank = pair ranks, every
@@ -61,9 +62,9 @@ void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint
 // With pflag set (sync-free runs, both forms launched) the pair form runs
 // only when *pflag == 0 and the first-token form only when it is not.  The
 // pair form writes *hist0 = *a1 (the first round's active count).
-void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, const uint32_t *pflag,
-                const uint32_t *a1, uint32_t *hist0, hipStream_t s);
+void win_round0(const SortBufs &B, const uint64_t *off, const uint32_t *order, uint32_t nw, const uint8_t *wflag,
+                const uint32_t *keyrank, uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs,
+                const uint32_t *pflag, const uint32_t *a1, uint32_t *hist0, hipStream_t s);
 void window_bounds(const uint64_t *off, uint32_t nw, uint32_t *wbeg, uint32_t *wend, uint32_t *wid,
                    hipStream_t s);
 

@@ -450,8 +450,9 @@ __device__ __forceinline__ uint32_t win_probe(const unsigned long long *tab, uin
   return h;
 }
 
-__global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw,
-                                                             uint32_t *rank, uint8_t *wflag, uint32_t *cnt) {
+__global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *tok, const uint64_t *off,
+                                                             const uint32_t *order, uint32_t nw, uint32_t *rank,
+                                                             uint8_t *wflag, uint32_t *cnt) {
   constexpr int NT = kWinRankThreads;
   __shared__ unsigned long long tab[kWinRankSlots];
   __shared__ uint64_t dist[kWinRankCap];   // distinct values; then merge buffers with mrg
@@ -469,8 +470,8 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_rank(const uint64_t *to
     }
     for (int k = tid; k < kWinRankSlots; k += NT) tab[k] = (unsigned long long)kEmpty;
     __syncthreads();
-    const uint32_t w = cur_w;
-    if (w >= nw) return;  // uniform
+    if (cur_w >= nw) return;  // uniform
+    const uint32_t w = order ? order[cur_w] : cur_w;
     const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
     // 1. distinct values, kWinRankBatch tokens per thread per pass (loads first)
     for (uint64_t i0 = b; i0 < e; i0 += (uint64_t)NT * kWinRankBatch) {
@@ -617,12 +618,12 @@ static unsigned cu_count() {
   return cus;
 }
 
-void win_rank(const uint64_t *tok, const uint64_t *off, uint32_t nw, uint32_t *rank, uint8_t *wflag, uint32_t *cnt,
-              hipStream_t s) {
+void win_rank(const uint64_t *tok, const uint64_t *off, const uint32_t *order, uint32_t nw, uint32_t *rank,
+              uint8_t *wflag, uint32_t *cnt, hipStream_t s) {
   // one workgroup per compute unit (the LDS footprint allows one), each
   // taking windows until none is left
-  if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, tok, off, nw,
-                             rank, wflag, cnt);
+  if (nw) hipLaunchKernelGGL(k_win_rank, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, tok, off,
+                             order, nw, rank, wflag, cnt);
 }
 
 // ------------------------------------------- per-window ranks of token pairs
@@ -662,7 +663,8 @@ __device__ __forceinline__ uint32_t bitonic_keep32(uint32_t v, uint32_t p, uint3
   return (lower == asc) ? (v < p ? v : p) : (v < p ? p : v);
 }
 
-__global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag,
+__global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *off, const uint32_t *order, uint32_t nw,
+                                                             const uint8_t *wflag,
                                                              const uint32_t *tokrank, uint32_t *prank, uint32_t *cnt,
                                                              uint32_t *act1, const uint32_t *wcount) {
   constexpr int NT = kWinRankThreads;
@@ -691,8 +693,8 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *of
     for (int k = tid; k < kPairSlots; k += NT) tab[k] = kPairEmpty;
     for (uint32_t k = tid; k < kTokRanks; k += NT) hc[k] = 0;
     __syncthreads();
-    const uint32_t w = cur_w;
-    if (w >= nw) return;  // uniform
+    if (cur_w >= nw) return;  // uniform
+    const uint32_t w = order ? order[cur_w] : cur_w;
     if (wflag[w]) {       // the same word for every thread
       if (tid == 0) atomicAdd(&cnt[1], 1u);
       continue;
@@ -829,11 +831,11 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_pair(const uint64_t *of
   }
 }
 
-void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank, uint32_t *prank,
-              uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s) {
+void win_pair(const uint64_t *off, const uint32_t *order, uint32_t nw, const uint8_t *wflag, const uint32_t *tokrank,
+              uint32_t *prank, uint32_t *cnt, uint32_t *act1, const uint32_t *wcount, hipStream_t s) {
   // one workgroup per compute unit (the LDS footprint allows one)
   if (nw) hipLaunchKernelGGL(k_win_pair, dim3(std::min<unsigned>(cu_count(), nw)), dim3(kWinRankThreads), 0, s, off,
-                             nw, wflag, tokrank, prank, cnt, act1, wcount);
+                             order, nw, wflag, tokrank, prank, cnt, act1, wcount);
 }
 
 // ------------------------------------ first doubling round, per window
@@ -854,7 +856,8 @@ void win_pair(const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint
 constexpr uint32_t kR0SingleWords = 4096;  // singleton-slot bitmap: windows up to 2^17 slots
 
 template <uint32_t RANKS, int LIST>
-__global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off, uint32_t nw,
+__global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, const uint64_t *off,
+                                                               const uint32_t *order, uint32_t nw,
                                                                const uint8_t *wflag, const uint32_t *keyrank,
                                                                uint32_t *rank, uint8_t *aflag, uint32_t next_bits,
                                                                uint32_t *wnext, const uint32_t *pflag,
@@ -879,8 +882,8 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
     for (uint32_t r = tid; r < RANKS; r += NT) cnt[r] = 0;
     if (tid < kClasses) cls_loc[tid] = 0;
     __syncthreads();
-    const uint32_t w = cur_w;
-    if (w >= nw) return;  // uniform
+    if (cur_w >= nw) return;  // uniform
+    const uint32_t w = order ? order[cur_w] : cur_w;
     if (wflag[w]) continue;  // the same word for every thread
     const uint64_t b = off[w] - off[0], e = off[w + 1] - off[0];
     const bool bits = e - b <= 32ull * kR0SingleWords;  // uniform
@@ -999,16 +1002,16 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
   }
 }
 
-void win_round0(const SortBufs &B, const uint64_t *off, uint32_t nw, const uint8_t *wflag, const uint32_t *keyrank,
-                uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs, const uint32_t *pflag,
-                const uint32_t *a1, uint32_t *hist0, hipStream_t s) {
+void win_round0(const SortBufs &B, const uint64_t *off, const uint32_t *order, uint32_t nw, const uint8_t *wflag,
+                const uint32_t *keyrank, uint32_t *rank, uint8_t *aflag, uint32_t next_bits, uint32_t *wnext, bool pairs,
+                const uint32_t *pflag, const uint32_t *a1, uint32_t *hist0, hipStream_t s) {
   if (!nw) return;
   const dim3 grid(std::min<unsigned>(2 * cu_count(), nw)), block(kWinRankThreads);
   if (pairs)
-    hipLaunchKernelGGL((k_win_round0<kPairCap + 2, 0>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
+    hipLaunchKernelGGL((k_win_round0<kPairCap + 2, 0>), grid, block, 0, s, B, off, order, nw, wflag, keyrank, rank, aflag,
                        next_bits, wnext, pflag, a1, hist0);
   else
-    hipLaunchKernelGGL((k_win_round0<kTokRanks, 1>), grid, block, 0, s, B, off, nw, wflag, keyrank, rank, aflag,
+    hipLaunchKernelGGL((k_win_round0<kTokRanks, 1>), grid, block, 0, s, B, off, order, nw, wflag, keyrank, rank, aflag,
                        next_bits, wnext, pflag, nullptr, nullptr);
 }
 

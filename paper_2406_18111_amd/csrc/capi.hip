@@ -412,6 +412,24 @@ static void lane_groups(const uint64_t *off, uint32_t W, uint64_t total, int L, 
     const uint32_t w = (uint32_t)(std::lower_bound(off, off + W + 1, target) - off);
     w0[g] = std::max(std::min(w, W), w0[g - 1]);
   }
+  // a group of windows without tokens (empty windows only) joins the group
+  // with tokens before it (leading ones: the first such group after them):
+  // an analysis of no tokens has nothing to launch or capture
+  auto has_tokens = [&](int g) { return w0[g + 1] > w0[g] && off[w0[g + 1]] != off[w0[g]]; };
+  int first = 0;
+  while (first < L && !has_tokens(first)) first++;
+  if (first < L)
+    for (int k = 1; k <= first; k++) w0[k] = w0[0];
+  int last = -1;
+  for (int g = 0; g < L; g++) {
+    if (w0[g + 1] == w0[g]) continue;
+    if (off[w0[g + 1]] != off[w0[g]]) {
+      last = g;
+      continue;
+    }
+    if (last >= 0)
+      for (int k = last + 1; k <= g; k++) w0[k] = w0[g + 1];
+  }
 }
 
 // Device bytes the context would hold while running a batch on L lanes
@@ -519,12 +537,24 @@ static int batch_lanes(apo_ctx *ctx, const uint64_t *d_tok, const uint64_t *off,
           rc = run_pipeline(*ln.ws, d_tok + ln.tok0, 64, ln.total, ln.norm.data(), ln.W, min_len, Stop::FULL, ln.st,
                             ln.info, Mode::CAPTURE);
         }
-        for (size_t i = 0; i < lanes.size() && !rc; i++)
+        // every lane stream joins back, also after a failure, so that ending
+        // the capture releases all of them
+        for (size_t i = 0; i < lanes.size(); i++)
           if (lanes[i].st != s && (hipEventRecord(G.ev[i + 1], lanes[i].st) != hipSuccess ||
                                    hipStreamWaitEvent(s, G.ev[i + 1], 0) != hipSuccess))
             rc = -4;
         const hipError_t e = hipStreamEndCapture(s, &g);
         ok = rc == 0 && e == hipSuccess && g != nullptr;
+        for (size_t i = 0; i < lanes.size(); i++) {  // a stream the failed capture left capturing ends it
+          hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+          if (lanes[i].st != s && hipStreamIsCapturing(lanes[i].st, &cs) == hipSuccess &&
+              cs != hipStreamCaptureStatusNone) {
+            hipGraph_t lg = nullptr;
+            (void)hipStreamEndCapture(lanes[i].st, &lg);
+            if (lg) (void)hipGraphDestroy(lg);
+            ok = false;
+          }
+        }
         if (ok && hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0) != hipSuccess) {
           G.exec = nullptr;
           ok = false;

@@ -308,6 +308,42 @@ def test_batch_windows_past_the_slot_bitmap(ctx):
                 ctx.set_graphs(True)
 
 
+def test_lanes_never_get_only_empty_windows(ctx):
+    """Lanes split a batch by tokens, and a lane of empty windows only (here
+    the trailing empty windows) would be an analysis of no tokens, which a
+    captured graph cannot hold: such windows join their neighbour lane.  The
+    oracle's rows (none for the empty windows) with host-driven lanes and
+    with the lanes captured as one graph, replayed."""
+    rng = np.random.default_rng(44)
+    heads = [synth.loop_stream(70 + k, n, 13, 64, 0.05).astype(np.uint64) for k, n in enumerate((17, 100, 2047))]
+    e = np.zeros(0, np.uint64)
+    batches = [heads + [e],
+               heads + [e] * 5,
+               [rng.integers(0, 3, 3000).astype(np.uint64)] + [e] * 7,
+               # the last lane's first boundary lands past the big window: an
+               # empty group between it and the trailing empty windows
+               [heads[0][:5], heads[0][:3], heads[2], heads[0][:1], heads[1], rng.integers(0, 9, 30000).astype(np.uint64), e]]
+    m = 3
+    for wins in batches:
+        toks, off = _pack(wins)
+        refs = [_rows_ref(w, m) for w in wins]
+        for lanes, graphs in ((3, False), (3, True), (2, True)):
+            print("windows", [len(w) for w in wins], "lanes", lanes, "graphs", graphs, flush=True)
+            try:
+                ctx.set_lanes(lanes)
+                ctx.set_graphs(graphs)
+                replays = ctx.graph_stats()["replays"]
+                for rep in range(2 if graphs else 1):
+                    rows, oo = ctx.analyze_batch(toks, off, m)
+                    for w in range(len(wins)):
+                        assert np.array_equal(_as3(rows[int(oo[w]):int(oo[w + 1])]), refs[w]), (rep, w, len(wins[w]))
+                if graphs:  # captured (a failed capture would have fallen back to host-driven lanes)
+                    assert ctx.graph_stats()["replays"] > replays
+            finally:
+                ctx.set_lanes(3)
+                ctx.set_graphs(True)
+
+
 def test_batch_device_api(ctx):
     import torch
     wins, m = synth.config3(num_windows=24)

@@ -110,12 +110,26 @@ class ApoError(RuntimeError):
         super().__init__("%s: %s (%d)" % (what, msg, code))
 
 
+def _torch_first():
+    """With PyTorch present, its GPU context is set up before the library's:
+    PyTorch brings its own HIP runtime, and once the library's runtime holds
+    the GPU, PyTorch's later initialisation finds no device (the other order
+    works).  Without PyTorch, or without a GPU, nothing happens."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load() -> ctypes.CDLL:
     """Load libapo.so; raises if it has not been built (no fallback)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libapo.so is not built (%s); run python -m paper_2406_18111_amd.build" % LIB_PATH)
+        _torch_first()
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -213,3 +213,29 @@ def test_injected_device_error_leaves_context_usable(ctx):
         assert np.array_equal(_as3(ctx.analyze(t, m)), ref), after
     ctx.inject_device_error(-1)
     assert np.array_equal(_as3(ctx.analyze(t, m)), ref)
+
+
+_LIB_BEFORE_TORCH = r"""
+import ctypes, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2406_18111_amd import Context
+c = Context(0)
+import torch
+x = torch.arange(8, device="cuda", dtype=torch.int64)
+print("torch", int(x.sum().item()), flush=True)
+c.close()
+"""
+
+
+def test_context_before_torch_cuda():
+    """A context opened before the program touches PyTorch's GPU runtime
+    leaves that runtime usable (PyTorch ships its own HIP runtime, which finds
+    no device once another runtime holds the GPU, so the binding sets it up
+    first).  Runs in a fresh process, since this one has PyTorch running."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-c", _LIB_BEFORE_TORCH, root], capture_output=True, text=True, timeout=180)
+    assert p.returncode == 0, p.stderr[-2000:]
+    assert "torch 28" in p.stdout

@@ -262,7 +262,8 @@ def test_batch_long_windows(ctx):
     """Windows longer than 2^16 tokens beside short ones: the doubling rounds'
     window-relative bucketing digits then need more than 16 bits, and the
     windows finish their doubling after very different numbers of rounds
-    (rank snapshots exist for some and not for others)."""
+    (rank snapshots exist for some and not for others).  Host-driven lanes,
+    one sync-free lane (rounds bounded by the longest window) and its graph."""
     rng = np.random.default_rng(21)
     wins = [np.tile(np.arange(7, dtype=np.uint64), 100000 // 7 + 1)[:100000],
             rng.integers(0, 1 << 40, 70000).astype(np.uint64),
@@ -272,12 +273,21 @@ def test_batch_long_windows(ctx):
             np.array([1, 2, 1, 2, 1], dtype=np.uint64)]
     toks, off = _pack(wins)
     for m in (2, 8):
-        print("long-window batch min_len", m, flush=True)
-        rows, oo = ctx.analyze_batch(toks, off, m)
-        for w, win in enumerate(wins):
-            got = _as3(rows[int(oo[w]):int(oo[w + 1])])
-            assert np.array_equal(got, _as3(ctx.analyze(win, m))), (w, len(win))
-            assert np.array_equal(got, _rows_ref(win, m)), (w, len(win))
+        refs = [_rows_ref(win, m) for win in wins]
+        alone = [_as3(ctx.analyze(win, m)) for win in wins]
+        for lanes, graphs in ((3, False), (1, False), (1, True)):
+            print("long-window batch min_len", m, "lanes", lanes, "graphs", graphs, flush=True)
+            try:
+                ctx.set_lanes(lanes)
+                ctx.set_graphs(graphs)
+                rows, oo = ctx.analyze_batch(toks, off, m)
+                for w, win in enumerate(wins):
+                    got = _as3(rows[int(oo[w]):int(oo[w + 1])])
+                    assert np.array_equal(got, alone[w]), (w, len(win))
+                    assert np.array_equal(got, refs[w]), (w, len(win))
+            finally:
+                ctx.set_lanes(3)
+                ctx.set_graphs(True)
 
 
 def test_batch_windows_past_the_slot_bitmap(ctx):

@@ -20,7 +20,10 @@ constexpr int kMinDigitBits = 8, kMaxDigitBits = 12, kDefaultDigitBits = 11;
 constexpr int kBins = 1 << kMaxDigitBits;   // histogram stride per large unit
 constexpr int kMaxMsdLevels = 4;            // 32-bit keys / 8-bit digits
 constexpr int kMsdLists = kMaxMsdLevels + 1;
-constexpr int kChunk = 8192;                // elements per workgroup in MSD / bulk passes
+// Entries per workgroup in the MSD and bulk passes: 2^12 for analyses of up to
+// 2^22 tokens (more workgroups than CUs on small inputs), 2^13 above.
+constexpr int kChunkLogSmall = 12, kChunkLogLarge = 13;
+constexpr uint64_t kSmallChunkMaxN = 1ull << 22;
 constexpr int kMaxRounds = 32;              // doubling rounds (n <= 2^26 needs <= 28)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kBufBit = 0x80000000u;   // unit data lives in the alternate buffer
@@ -39,7 +42,7 @@ struct Unit {
 struct BigUnit {
   uint32_t start;
   uint32_t len;
-  uint32_t cbase;   // index of the unit's first kChunk-sized chunk in its list
+  uint32_t cbase;   // index of the unit's first chunk (2^chunk_log entries) in its list
   uint32_t meta;    // bits 0-7: key bits still unsorted (from the top);
                     // bit 8: data in the alternate buffer; bit 9: skip scatter
 };
@@ -67,6 +70,7 @@ struct SortBufs {
   BigUnit *bulk;
   uint32_t tile_log;    // LDS tile = 2^tile_log entries
   uint32_t digit_bits;  // MSD digit width
+  uint32_t chunk_log;   // MSD / bulk chunk = 2^chunk_log entries
   uint32_t *hist;       // big_cap * kBins
   uint32_t *cursor;     // big_cap * kBins
   uint32_t *act[2];     // plain mode: slots still grouped after a level (SA rounds use RankOut::aflag)

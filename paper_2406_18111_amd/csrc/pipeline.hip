@@ -292,6 +292,7 @@ int run_pipeline(Workspace &w, const void *d_tok, int bits, uint64_t N, const ui
                  uint32_t min_len, Stop stop, hipStream_t s, RunInfo &info, Mode mode) {
   info = RunInfo{};
   SortEngine &E = w.eng;
+  E.set_chunk_for(N);
   SortBufs &B = E.bufs();
   int rc;
   const bool host = mode == Mode::HOST;

@@ -18,6 +18,8 @@ class SortEngine {
 
   void reset_counters(hipStream_t s);
   void set_params(int tile_log, int digit_bits);
+  // chunk size of the MSD and bulk passes for an analysis of n tokens
+  void set_chunk_for(uint64_t n);
   int tile_log() const { return (int)b_.tile_log; }
   int digit_bits() const { return (int)b_.digit_bits; }
   void round_begin(int cur, hipStream_t s);

@@ -398,8 +398,8 @@ void hash_rank(const uint32_t *tok_slot, uint64_t n, const uint32_t *slot_rank, 
 // Appends a large unit to a list of the sort engine: packed (units << 32 |
 // chunks) counter, chunk base from the old value (the engine's list format).
 __device__ __forceinline__ void append_big_unit(BigUnit *list, unsigned long long *pk, uint32_t cap, uint32_t start,
-                                                uint32_t len, uint32_t meta, uint32_t *err) {
-  const unsigned long long old = atomicAdd(pk, (1ull << 32) | ((len + kChunk - 1) / kChunk));
+                                                uint32_t len, uint32_t meta, uint32_t *err, uint32_t chunk_log) {
+  const unsigned long long old = atomicAdd(pk, (1ull << 32) | ((len + (1u << chunk_log) - 1) >> chunk_log));
   const uint32_t k = (uint32_t)(old >> 32);
   if (k < cap) list[k] = BigUnit{start, len, (uint32_t)old, meta};
   else atomicOr(err, 2u);
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(kWinRankThreads) void k_win_round0(SortBufs B, cons
       ur[q] = r;
       if (c <= tile) ui[q] = atomicAdd(&cls_loc[class_of(c)], 1u);
       else append_big_unit(B.big[LIST][0], &B.ctr->big_pk[LIST][0], B.big_cap, (uint32_t)b + gst[r], c, next_bits,
-                           &B.ctr->err);
+                           &B.ctr->err, B.chunk_log);
     }
     {
       uint32_t tot;
